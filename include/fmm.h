@@ -1,0 +1,197 @@
+/*
+ * fmm.h -- C ABI of libfmm: periodic fast multipole evaluation of the
+ * electrostatic energy, per-atom potential and forces of N point charges in a
+ * cubic cell whose net charge is neutralised by a uniform background charge,
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (Urano, Shinoda, Yoshii, Okazaki, arXiv:2003.13218):
+ *   E = NF + FF - pi Q^2 / (2 V kappa^2) + (2 pi / 3V) Q sum_i q_i r_i^2
+ *       - (2 pi / 3V) mu.mu                                   (eq. Velecfull)
+ * NF is the direct sum over each leaf's +-2 neighbour leaves (eq. EqNF), FF
+ * the octree expansion P2M -> M2M -> M2L -> L2L -> L2P (Appendix B, eqs. P2M,
+ * Lcoeffdef, EqFF) whose level-0 translation is the Ewald-split image-lattice
+ * sum of eq. 12 (with the self term of Appendix C), kappa is the same in the
+ * lattice sum and in the charged-system term (eq. 6), and the last two terms
+ * are the quadrupole surface term (eq. surfchargedend) and the dipole term
+ * that turns the tree's vacuum boundary into a conducting one (Appendix D).
+ *
+ * Conventions
+ *   Units   Gaussian: E = sum q_i q_j / r with no 1/(4 pi eps0).  With charges
+ *           in e and lengths in Angstrom, energies are in e^2/A.
+ *   Forces  F_i = -dE/dr_i.   Potential phi_i = dE/dq_i, so E = 1/2 sum q_i phi_i.
+ *   Box     cubic, edge b, origin at 0; positions may lie anywhere (they are
+ *           wrapped into [0, b) internally and never modified).
+ *   Memory  every array argument named "device" is device memory of the GPU
+ *           current when the plan was created; the caller owns it.  Scalars
+ *           marked "host" are host memory.  Device arrays are FP64,
+ *           array-of-structs where 3-vectors are involved ([n][3]).
+ *   Streams all GPU work of a plan runs on the plan's stream (default: the
+ *           null stream); a call returns after its result is on the host.
+ *   Threads a plan is not thread-safe; distinct plans are independent.
+ *   Errors  every call returns a negative fmm_status on failure and leaves a
+ *           message in fmm_last_error(plan); nothing is thrown across the ABI.
+ */
+#ifndef FMM_H
+#define FMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmm_plan *fmm_plan_t;
+
+typedef enum {
+    FMM_OK = 0,
+    FMM_ERR_INVALID = -1, /* bad argument, or non-finite position / charge  */
+    FMM_ERR_NOMEM = -2,   /* device or host allocation failed                */
+    FMM_ERR_DEVICE = -3,  /* HIP runtime error or no usable GPU              */
+    FMM_ERR_STATE = -4    /* call order violated (see fmm_solute_solvent_energy) */
+} fmm_status;
+
+typedef enum {
+    /* everything in FP64 */
+    FMM_FP64 = 0,
+    /* P2P, P2M, M2L, L2L (levels >= 1) and L2P in FP32 with cell-local
+     * coordinates; level-0 multipole, lattice operator, charged-system,
+     * quadrupole and dipole terms and the energy reduction in FP64 */
+    FMM_MIXED = 1
+} fmm_precision;
+
+/*
+ * fmm_plan -- build a plan for a cubic box of edge `box` (> 0, finite),
+ * an octree of `levels` divisions (1..10; 8^levels leaves; Appendix B,
+ * division of cells) and expansion order `p` (0..20, the paper's n_max; the
+ * truncation n <= p, lambda <= p of eq. Lcoeffdef).  Near field is the
+ * +-2-leaf block (the "second nearest neighbours" of eq. EqNF), the
+ * interaction list at every level is the children of the parent's +-2
+ * neighbours minus the own +-2 block (875 cells, 1206 distinct offsets).
+ * Defaults: FMM_FP64, kappa = 3/box, null stream.
+ * Precomputes in FP64 on the host the scale-invariant M2M / M2L / L2L
+ * operators and the lattice tensor of eq. 12, and uploads them.
+ * On success *out owns them until fmm_destroy.  On failure *out is NULL.
+ */
+fmm_status fmm_plan(double box, int levels, int p, fmm_plan_t *out);
+
+/*
+ * fmm_plan_config -- precision mode, Ewald split parameter and stream.
+ * kappa > 0 sets the splitting parameter used by BOTH the j = 0 lattice sum
+ * (eq. 12a-c) and the charged-system term (eq. 6), as the paper requires;
+ * kappa <= 0 keeps the current value.  hip_stream is a hipStream_t (NULL =
+ * null stream).  Rebuilds the lattice operator when kappa changes.  Clears
+ * the cached state used by fmm_solute_solvent_energy.
+ */
+fmm_status fmm_plan_config(fmm_plan_t plan, int precision, double kappa, void *hip_stream);
+
+/*
+ * fmm_energy_forces -- E of eq. Velecfull, forces and per-atom potential.
+ *   n       number of atoms (0 <= n < 2^31); n == 0 gives E = 0
+ *   pos     device, n x 3 FP64 (AoS), any range
+ *   q       device, n FP64
+ *   energy  host out, 1 FP64 (required)
+ *   forces  device out, n x 3 FP64, or NULL
+ *   phi     device out, n FP64, or NULL
+ * Non-finite positions or charges give FMM_ERR_INVALID (detected on the GPU).
+ * Keeps its own sorted copy of the atoms and the far-field potential for a
+ * following fmm_solute_solvent_energy (pos and q may change or be freed
+ * after this call returns).
+ */
+fmm_status fmm_energy_forces(fmm_plan_t plan, int64_t n, const double *pos, const double *q,
+                             double *energy, double *forces, double *phi);
+
+/*
+ * fmm_solute_solvent_energy -- the solute-solvent interaction energy
+ *   e_uv = E(u + Bu  U  v + Bv) - E(u + Bu) - E(v + Bv)
+ * for the partition mask[i] = 1 (solute u) / 0 (solvent v), each part with
+ * its own neutralising background, of the atoms of the preceding
+ * fmm_energy_forces call on this plan.  Far field by the two-pass scheme
+ * of eq. FMMcalc (the full-system potential of the preceding call plus one
+ * pass with solute sources only):
+ *   W_FF = 1/2 [ sum_u q phi_uv - (sum_u q phi_u - sum_v q phi_u) ],
+ * plus the near-field u-v pairs and the background cross terms
+ *   -pi Q_u Q_v / (V kappa^2) + (2 pi / 3V)(Q_u S_v + Q_v S_u - 2 mu_u.mu_v),
+ * S = sum q r^2.  This is minus the derivative of V_lambda (eq. Vswucheme)
+ * with respect to lambda.
+ *   mask  device, n uint8 (nonzero = solute)
+ *   e_uv  host out
+ * FMM_ERR_STATE if no fmm_energy_forces has run since the plan was made or
+ * reconfigured.
+ */
+fmm_status fmm_solute_solvent_energy(fmm_plan_t plan, const uint8_t *mask, double *e_uv);
+
+/*
+ * fmm_potential_parts -- near- and far-field parts separately (no charged,
+ * quadrupole or dipole terms), per atom in the caller's order, for checking
+ * the stages on their own.  phi_nf / phi_ff: device n FP64 (or NULL);
+ * field_nf / field_ff: device n x 3 FP64 (or NULL), field = -grad phi.
+ * Same input contract as fmm_energy_forces; also refreshes the cached state.
+ */
+fmm_status fmm_potential_parts(fmm_plan_t plan, int64_t n, const double *pos, const double *q,
+                               double *phi_nf, double *field_nf, double *phi_ff, double *field_ff);
+
+/*
+ * fmm_bin -- stages wrap + bin + Morton key + stable sort (by key, then by
+ * original index) only.  keys: device n uint32 (leaf Morton key of each atom
+ * in the caller's order; bit k of the x leaf index at bit 3k+2, of y at 3k+1,
+ * of z at 3k); perm: device n int32 (perm[s] = original index of sorted atom
+ * s); cell_start: device 8^levels + 1 int32 (atoms of leaf with key c are
+ * sorted positions cell_start[c] .. cell_start[c+1]-1).  Any output may be NULL.
+ */
+fmm_status fmm_bin(fmm_plan_t plan, int64_t n, const double *pos,
+                   uint32_t *keys, int32_t *perm, int32_t *cell_start);
+
+/*
+ * fmm_lattice_tensor -- copy of the plan's lattice tensor (host out):
+ * T_j^k = sum over images nu with max|nu_a| > 2 of I_j^k(nu b), for
+ * 0 <= j <= 2p, -j <= k <= j, as complex pairs (re, im) at index
+ * 2 (j*j + j + k), with I_j^k(r) = (j-k)! P_j^k(cos theta) e^{i k phi} / r^{j+1}
+ * (P with the Condon-Shortley phase).  The sum is taken as in eq. 12 (real,
+ * reciprocal k != 0 and self term, kappa of the plan) minus the explicit
+ * images with max|nu_a| <= 2.  cap = number of doubles available in out
+ * (>= 2 (2p+1)^2).
+ */
+fmm_status fmm_lattice_tensor(fmm_plan_t plan, double *out, int64_t cap);
+
+/*
+ * Stage timing.  fmm_profile(plan, 1) creates HIP events on the plan's stream
+ * and from then on every fmm_energy_forces call records one event pair around
+ * each stage group below and adds the elapsed milliseconds to per-stage
+ * accumulators (read after the call's own synchronisation, so no extra host
+ * round trip); fmm_profile(plan, 0) stops and frees them.  Enabling resets the
+ * accumulators.  fmm_profile_read copies FMM_NUM_STAGES doubles (ms, summed
+ * over calls) and the number of profiled calls.
+ */
+enum {
+    FMM_STAGE_SORT = 0,      /* wrap, bin, Morton keys, counting sort        */
+    FMM_STAGE_GATHER = 1,    /* repack into sorted leaf-local coordinates    */
+    FMM_STAGE_P2M = 2,
+    FMM_STAGE_M2M = 3,
+    FMM_STAGE_LATTICE = 4,   /* level-0 image-lattice operator (eq. 12)      */
+    FMM_STAGE_M2L = 5,       /* all levels                                   */
+    FMM_STAGE_M2L_LEAF = 6,  /* finest level only (also counted in M2L)      */
+    FMM_STAGE_L2L = 7,
+    FMM_STAGE_L2P = 8,
+    FMM_STAGE_P2P = 9,
+    FMM_STAGE_FINAL = 10,    /* moments, corrections, energy reduction       */
+    FMM_STAGE_TOTAL = 11,    /* first to last event of the call              */
+    FMM_NUM_STAGES = 12
+};
+fmm_status fmm_profile(fmm_plan_t plan, int enable);
+fmm_status fmm_profile_read(fmm_plan_t plan, double *ms, int64_t *calls);
+
+/* Message of the last failed call on this plan (never NULL; "" if none).
+ * fmm_last_error(NULL) reports failures of fmm_plan itself. */
+const char *fmm_last_error(fmm_plan_t plan);
+
+/* Frees the plan and its device memory.  NULL is ignored. */
+void fmm_destroy(fmm_plan_t plan);
+
+/* Library version string. */
+const char *fmm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMM_H */

@@ -78,16 +78,19 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
 
 
-def ewald_params(box: float, accuracy: float = 1e-13, rcut: float | None = None):
+def ewald_params(box: float, accuracy: float = 1e-13, rcut: float | None = None, n: int | None = None):
     """Pick (kappa, rcut, kmax) so both truncation errors are below ``accuracy``.
 
     Real space: erfc(kappa rcut) <= accuracy; reciprocal space:
     exp(-kmax^2 / 4 kappa^2) <= accuracy (standard Ewald error estimates).
-    ``rcut`` defaults to min(b/2, 12 A)-ish scaled to the box.
+    ``rcut`` defaults to the value balancing real- and reciprocal-space work,
+    s (b^3 / (2 pi^3 rho))^(1/6) with s = sqrt(-ln accuracy) and rho = n / b^3,
+    capped at b/2.
     """
     s = math.sqrt(-math.log(accuracy))
     if rcut is None:
-        rcut = min(0.5 * box, 12.0) if box > 6.0 else box
+        rho = (n if n else 1) / box ** 3
+        rcut = min(0.5 * box, s * (box ** 3 / (2 * math.pi ** 3 * rho)) ** (1.0 / 6.0))
     kappa = s / rcut
     kmax = 2.0 * kappa * s
     return kappa, rcut, kmax
@@ -103,7 +106,7 @@ def ewald(pos, q, box, kappa=None, rcut=None, kmax=None, eval_idx=None, accuracy
     q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
     n = q.shape[0]
     if kappa is None or rcut is None or kmax is None:
-        k0, r0, m0 = ewald_params(box, accuracy, rcut)
+        k0, r0, m0 = ewald_params(box, accuracy, rcut, n)
         kappa = kappa if kappa is not None else k0
         rcut = rcut if rcut is not None else r0
         kmax = kmax if kmax is not None else m0
@@ -130,7 +133,7 @@ def ewald_uv(pos, q, mask, box, kappa=None, rcut=None, kmax=None, accuracy=1e-13
     q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
     mask = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
     if kappa is None or rcut is None or kmax is None:
-        k0, r0, m0 = ewald_params(box, accuracy, rcut)
+        k0, r0, m0 = ewald_params(box, accuracy, rcut, q.shape[0])
         kappa = kappa if kappa is not None else k0
         rcut = rcut if rcut is not None else r0
         kmax = kmax if kmax is not None else m0

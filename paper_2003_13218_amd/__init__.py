@@ -1,0 +1,12 @@
+"""Periodic FMM for charged systems neutralised by a uniform background charge
+(arXiv:2003.13218) on AMD Instinct MI355X (gfx950).
+
+The GPU library is ``libfmm.so`` (C ABI in ``include/fmm.h``); ``binding``
+is its thin Python wrapper.  Importing this package does not load the library;
+``binding.load()`` does, and raises if it has not been built.
+"""
+from . import binding  # noqa: F401
+from .binding import (FMM_FP64, FMM_MIXED, FmmError, Plan, fmm_bin, fmm_destroy,  # noqa: F401
+                      fmm_energy_forces, fmm_last_error, fmm_lattice_tensor, fmm_plan,
+                      fmm_plan_config, fmm_potential_parts, fmm_profile, fmm_profile_read,
+                      fmm_solute_solvent_energy, fmm_version)

@@ -1,0 +1,218 @@
+"""Thin ctypes binding of libfmm (include/fmm.h).
+
+Argument marshalling only: every stage of the evaluation runs in the HIP
+kernels of libfmm.so.  PyTorch provides device memory and the stream.  The
+names mirror the C ABI.  There is no fallback: if libfmm.so is missing or
+no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfmm.so")
+
+FMM_OK = 0
+FMM_ERR_INVALID = -1
+FMM_ERR_NOMEM = -2
+FMM_ERR_DEVICE = -3
+FMM_ERR_STATE = -4
+FMM_FP64 = 0
+FMM_MIXED = 1
+
+EXPORTED = (
+    "fmm_plan", "fmm_plan_config", "fmm_energy_forces", "fmm_solute_solvent_energy",
+    "fmm_potential_parts", "fmm_bin", "fmm_lattice_tensor", "fmm_profile", "fmm_profile_read",
+    "fmm_last_error", "fmm_destroy", "fmm_version",
+)
+
+STAGES = ("sort", "gather", "p2m", "m2m", "lattice", "m2l", "m2l_leaf", "l2l", "l2p", "p2p", "final", "total")
+
+_lib = None
+_lock = threading.Lock()
+
+
+class FmmError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"libfmm status {status}: {message}")
+        self.status = status
+
+
+def load():
+    """Load libfmm.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise FileNotFoundError(f"{LIB_PATH} not found: build it with `python -m paper_2003_13218_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i64, dbl, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+        lib.fmm_plan.argtypes = [dbl, ci, ci, ctypes.POINTER(vp)]
+        lib.fmm_plan.restype = ci
+        lib.fmm_plan_config.argtypes = [vp, ci, dbl, vp]
+        lib.fmm_plan_config.restype = ci
+        lib.fmm_energy_forces.argtypes = [vp, i64, vp, vp, ctypes.POINTER(dbl), vp, vp]
+        lib.fmm_energy_forces.restype = ci
+        lib.fmm_solute_solvent_energy.argtypes = [vp, vp, ctypes.POINTER(dbl)]
+        lib.fmm_solute_solvent_energy.restype = ci
+        lib.fmm_potential_parts.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+        lib.fmm_potential_parts.restype = ci
+        lib.fmm_bin.argtypes = [vp, i64, vp, vp, vp, vp]
+        lib.fmm_bin.restype = ci
+        lib.fmm_lattice_tensor.argtypes = [vp, vp, i64]
+        lib.fmm_lattice_tensor.restype = ci
+        lib.fmm_profile.argtypes = [vp, ci]
+        lib.fmm_profile.restype = ci
+        lib.fmm_profile_read.argtypes = [vp, vp, ctypes.POINTER(i64)]
+        lib.fmm_profile_read.restype = ci
+        lib.fmm_last_error.argtypes = [vp]
+        lib.fmm_last_error.restype = ctypes.c_char_p
+        lib.fmm_destroy.argtypes = [vp]
+        lib.fmm_destroy.restype = None
+        lib.fmm_version.argtypes = []
+        lib.fmm_version.restype = ctypes.c_char_p
+        _lib = lib
+        return lib
+
+
+def fmm_last_error(plan=None) -> str:
+    h = plan.handle if isinstance(plan, Plan) else plan
+    return load().fmm_last_error(h).decode()
+
+
+def _check(status, plan=None):
+    if status != FMM_OK:
+        raise FmmError(status, fmm_last_error(plan))
+
+
+def _dptr(t, dtype, shape_tail=(), name="tensor"):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Owns an fmm_plan_t."""
+
+    def __init__(self, handle, box, levels, p):
+        self.handle = handle
+        self.box, self.levels, self.p = box, levels, p
+        self.precision = FMM_FP64
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().fmm_destroy(self.handle)
+            self.handle = None
+
+
+def fmm_plan(box: float, levels: int, p: int) -> Plan:
+    h = ctypes.c_void_p()
+    _check(load().fmm_plan(float(box), int(levels), int(p), ctypes.byref(h)))
+    return Plan(h, box, levels, p)
+
+
+def fmm_plan_config(plan: Plan, precision: int = FMM_FP64, kappa: float = 0.0, stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(load().fmm_plan_config(plan.handle, int(precision), float(kappa), ctypes.c_void_p(int(stream))), plan)
+    plan.precision = precision
+
+
+def fmm_energy_forces(plan: Plan, pos, q, forces=True, phi=False):
+    """Returns (energy: float, forces tensor or None, phi tensor or None)."""
+    import torch
+    n = int(q.shape[0])
+    pp = _dptr(pos, torch.float64, (3,), "pos")
+    qp = _dptr(q, torch.float64, (), "q")
+    f = torch.empty((n, 3), dtype=torch.float64, device=q.device) if forces else None
+    ph = torch.empty((n,), dtype=torch.float64, device=q.device) if phi else None
+    e = ctypes.c_double()
+    _check(load().fmm_energy_forces(plan.handle, n, pp, qp, ctypes.byref(e),
+                                    _dptr(f, torch.float64, (3,), "forces"),
+                                    _dptr(ph, torch.float64, (), "phi")), plan)
+    return e.value, f, ph
+
+
+def fmm_solute_solvent_energy(plan: Plan, mask) -> float:
+    import torch
+    e = ctypes.c_double()
+    _check(load().fmm_solute_solvent_energy(plan.handle, _dptr(mask, torch.uint8, (), "mask"), ctypes.byref(e)), plan)
+    return e.value
+
+
+def fmm_potential_parts(plan: Plan, pos, q):
+    """Returns (phi_nf, field_nf, phi_ff, field_ff) in the caller's order."""
+    import torch
+    n = int(q.shape[0])
+    dev = q.device
+    phi_nf = torch.empty((n,), dtype=torch.float64, device=dev)
+    phi_ff = torch.empty((n,), dtype=torch.float64, device=dev)
+    f_nf = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    f_ff = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    _check(load().fmm_potential_parts(plan.handle, n, _dptr(pos, torch.float64, (3,), "pos"),
+                                      _dptr(q, torch.float64, (), "q"), _dptr(phi_nf, torch.float64),
+                                      _dptr(f_nf, torch.float64, (3,)), _dptr(phi_ff, torch.float64),
+                                      _dptr(f_ff, torch.float64, (3,))), plan)
+    return phi_nf, f_nf, phi_ff, f_ff
+
+
+def fmm_bin(plan: Plan, pos):
+    """Returns (keys uint32 as int32 view, perm int32, cell_start int32)."""
+    import torch
+    n = int(pos.shape[0])
+    dev = pos.device
+    keys = torch.empty((n,), dtype=torch.int32, device=dev)
+    perm = torch.empty((n,), dtype=torch.int32, device=dev)
+    start = torch.empty(((1 << (3 * plan.levels)) + 1,), dtype=torch.int32, device=dev)
+    _check(load().fmm_bin(plan.handle, n, _dptr(pos, torch.float64, (3,), "pos"), _dptr(keys, torch.int32),
+                          _dptr(perm, torch.int32), _dptr(start, torch.int32)), plan)
+    return keys, perm, start
+
+
+def fmm_lattice_tensor(plan: Plan):
+    """Lattice tensor as a complex numpy array indexed j*j + j + k."""
+    import numpy as np
+    J = 2 * plan.p
+    out = np.zeros(2 * (J + 1) ** 2)
+    _check(load().fmm_lattice_tensor(plan.handle, out.ctypes.data_as(ctypes.c_void_p), out.size), plan)
+    return out[0::2] + 1j * out[1::2]
+
+
+def fmm_profile(plan: Plan, enable: bool = True):
+    _check(load().fmm_profile(plan.handle, 1 if enable else 0), plan)
+
+
+def fmm_profile_read(plan: Plan):
+    """Returns ({stage: summed ms}, calls)."""
+    import numpy as np
+    ms = np.zeros(len(STAGES))
+    calls = ctypes.c_int64()
+    _check(load().fmm_profile_read(plan.handle, ms.ctypes.data_as(ctypes.c_void_p), ctypes.byref(calls)), plan)
+    return dict(zip(STAGES, ms.tolist())), calls.value
+
+
+def fmm_destroy(plan: Plan):
+    plan.close()
+
+
+def fmm_version() -> str:
+    return load().fmm_version().decode()

@@ -1,0 +1,697 @@
+// libfmm C ABI: plan construction, validation, workspace and the ordering of
+// the GPU stages.  Every arithmetic step of the evaluation runs in the HIP
+// kernels declared in fmm_internal.h; this file only prepares operators (FP64,
+// once per plan) and launches work on the plan's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "fmm.h"
+#include "fmm_internal.h"
+
+using namespace fmm;
+
+namespace {
+
+thread_local std::string g_plan_error;
+
+struct DeviceBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    void release() {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    bool ensure(size_t b) {
+        if (b <= bytes && ptr) return true;
+        release();
+        if (b == 0) b = 16;
+        if (hipMalloc(&ptr, b) != hipSuccess) { ptr = nullptr; bytes = 0; return false; }
+        bytes = b;
+        return true;
+    }
+    template <typename T> T *as() const { return reinterpret_cast<T *>(ptr); }
+};
+
+struct Status {
+    fmm_status code;
+    std::string msg;
+};
+
+}  // namespace
+
+struct fmm_plan {
+    double box = 0.0;
+    int levels = 0, p = 0, K = 0, Kp = 0;
+    int prec = FMM_FP64;
+    double kappa = 0.0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+
+    // host operators (FP64)
+    std::vector<double> m2mT, l2lT, latT;  // transposed [o][col][row], [col][row]
+    // T_0^0 of the unit box: the net-charge (monopole-monopole) lattice
+    // constant, applied exactly in FP64 as phi += t00 Q / b instead of through
+    // the level-0 operator, so it never passes through FP32 arrays
+    double t00 = 0.0;
+    int top_fp64 = 3;  // mixed mode: tree levels 1..3 in FP64 (see top_fp64_levels)
+    double q_tree = 0.0;  // level-0 monopole of the last fmm_energy_forces tree
+    std::vector<cplx> T;                  // lattice tensor, unit box
+    Offsets offs;
+
+    // device constants
+    DeviceBuf ops32, ops64, m2m, l2l, lat, il, offv;
+    // per-call workspace
+    DeviceBuf key, count, cursor, start, perm, scan, xq, xq_u, xs, Mlev, Llev, M0, L0, m2l_part;
+    DeviceBuf phi_nf, field_nf, phi_ff, field_ff, phi_u, field_u, nfuv, partials, scalars, flag;
+    double *h_scalars = nullptr;  // pinned host mirror of `scalars`
+    int64_t cap_n = -1;
+    bool tree_ready = false;
+
+    // stage timing (fmm_profile)
+    bool profiling = false;
+    hipEvent_t ev_begin[FMM_NUM_STAGES] = {}, ev_end[FMM_NUM_STAGES] = {};
+    bool ev_used[FMM_NUM_STAGES] = {};
+    double stage_ms[FMM_NUM_STAGES] = {};
+    int64_t profiled_calls = 0;
+
+    // state cached for fmm_solute_solvent_energy (sorted copies live in xq, xs)
+    bool have_state = false;
+    int64_t n_state = 0;
+};
+
+static const int kScalars = 64;
+
+static fmm_status fail(fmm_plan_t pl, fmm_status code, const std::string &m) {
+    if (pl) pl->err = m;
+    else g_plan_error = m;
+    return code;
+}
+
+static fmm_status hip_fail(fmm_plan_t pl, hipError_t e, const char *where) {
+    std::string m = std::string(where) + ": " + hipGetErrorString(e);
+    return fail(pl, e == hipErrorOutOfMemory ? FMM_ERR_NOMEM : FMM_ERR_DEVICE, m);
+}
+
+#define HIPCHK(pl, expr, where)                         \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return hip_fail(pl, e_, where); \
+    } while (0)
+
+static int64_t level_cells(int l) { return (int64_t)1 << (3 * l); }
+// offset (in cells) of level l >= 1 inside the concatenated level arrays
+static int64_t level_offset(int l) {
+    int64_t o = 0;
+    for (int k = 1; k < l; ++k) o += level_cells(k);
+    return o;
+}
+
+static bool rec_uploaded[64] = {false};
+
+// Stage events: begin/end recorded on the plan stream when profiling.
+static void stage_begin(fmm_plan_t pl, int st) {
+    if (!pl->profiling || pl->ev_used[st]) return;
+    (void)hipEventRecord(pl->ev_begin[st], pl->stream);
+}
+static void stage_end(fmm_plan_t pl, int st) {
+    if (!pl->profiling || pl->ev_used[st]) return;
+    (void)hipEventRecord(pl->ev_end[st], pl->stream);
+    pl->ev_used[st] = true;
+}
+static void stage_reset(fmm_plan_t pl) {
+    for (int i = 0; i < FMM_NUM_STAGES; ++i) pl->ev_used[i] = false;
+}
+static void stage_collect(fmm_plan_t pl) {
+    if (!pl->profiling) return;
+    for (int i = 0; i < FMM_NUM_STAGES; ++i)
+        if (pl->ev_used[i]) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, pl->ev_begin[i], pl->ev_end[i]) == hipSuccess) pl->stage_ms[i] += ms;
+        }
+    pl->profiled_calls++;
+    stage_reset(pl);
+}
+
+// ---------------------------------------------------------------------------
+// Plan construction
+// ---------------------------------------------------------------------------
+static void build_m2l_all(int p, const Offsets &o, std::vector<double> &out) {
+    const int K = num_coeffs(p);
+    out.assign((size_t)kNumOffsets * K * K, 0.0);
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (unsigned w = 0; w < nt; ++w)
+        th.emplace_back([&, w] {
+            for (int oid = (int)w; oid < kNumOffsets; oid += (int)nt) {
+                const double t[3] = {(double)o.vec[3 * oid], (double)o.vec[3 * oid + 1],
+                                     (double)o.vec[3 * oid + 2]};
+                build_m2l_operator(p, t, out.data() + (size_t)oid * K * K);
+            }
+        });
+    for (auto &t : th) t.join();
+}
+
+static void transpose_into(const double *A, int K, double *AT) {
+    for (int r = 0; r < K; ++r)
+        for (int c = 0; c < K; ++c) AT[(size_t)c * K + r] = A[(size_t)r * K + c];
+}
+
+static fmm_status upload_lattice(fmm_plan_t pl) {
+    const int K = pl->K;
+    pl->T.assign((size_t)(2 * pl->p + 1) * (2 * pl->p + 1), cplx(0.0));
+    lattice_tensor(2 * pl->p, pl->kappa * pl->box, pl->T.data());
+    std::vector<double> A((size_t)K * K);
+    build_lattice_operator(pl->p, pl->T.data(), A.data());
+    pl->t00 = A[0];
+    A[0] = 0.0;
+    pl->latT.assign((size_t)K * K, 0.0);
+    transpose_into(A.data(), K, pl->latT.data());
+    if (!pl->lat.ensure(sizeof(double) * K * K)) return fail(pl, FMM_ERR_NOMEM, "lattice operator allocation");
+    HIPCHK(pl, hipMemcpy(pl->lat.ptr, pl->latT.data(), sizeof(double) * K * K, hipMemcpyHostToDevice),
+           "lattice upload");
+    return FMM_OK;
+}
+
+// Levels 1..top_fp64_levels(pl) of the tree run in FP64 in every mode.  At
+// shallow levels the cells are large and their M2L sums add big, nearly
+// cancelling monopole terms; in FP32 that cancellation leaves an error of a
+// few 1e-6 in every atom's potential (measured on the 1M-atom box), so the
+// top of the tree -- a few hundred cells -- stays in FP64, as does level 0.
+static int top_fp64_levels(fmm_plan_t pl) {
+    if (pl->prec == FMM_FP64) return pl->levels;
+    return std::min(pl->levels - 1, pl->top_fp64);
+}
+
+static fmm_status ensure_m2l_ops(fmm_plan_t pl) {
+    const bool need64 = top_fp64_levels(pl) > 0;
+    const bool need32 = pl->prec == FMM_MIXED;
+    if ((!need64 || pl->ops64.ptr) && (!need32 || pl->ops32.ptr)) return FMM_OK;
+    std::vector<double> rm;
+    build_m2l_all(pl->p, pl->offs, rm);
+    const size_t ne = m2l_ops_elems<float>(pl->p);
+    if (need64 && !pl->ops64.ptr) {
+        std::vector<double> sw(ne);
+        swizzle_m2l_ops<double>(pl->p, rm.data(), sw.data());
+        if (!pl->ops64.ensure(ne * sizeof(double))) return fail(pl, FMM_ERR_NOMEM, "M2L operator allocation");
+        HIPCHK(pl, hipMemcpy(pl->ops64.ptr, sw.data(), ne * sizeof(double), hipMemcpyHostToDevice), "M2L upload");
+    }
+    if (need32 && !pl->ops32.ptr) {
+        std::vector<float> sw(ne);
+        swizzle_m2l_ops<float>(pl->p, rm.data(), sw.data());
+        if (!pl->ops32.ensure(ne * sizeof(float))) return fail(pl, FMM_ERR_NOMEM, "M2L operator allocation");
+        HIPCHK(pl, hipMemcpy(pl->ops32.ptr, sw.data(), ne * sizeof(float), hipMemcpyHostToDevice), "M2L upload");
+    }
+    return FMM_OK;
+}
+
+extern "C" fmm_status fmm_plan(double box, int levels, int p, fmm_plan_t *out) {
+    if (!out) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan: out is NULL");
+    *out = nullptr;
+    if (!(box > 0.0) || !std::isfinite(box)) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan: box must be finite and > 0");
+    if (levels < 1 || levels > kMaxLevels) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan: levels must be in [1, 10]");
+    if (p < 0 || p > kMaxP) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan: p must be in [0, 20]");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(nullptr, FMM_ERR_DEVICE, "fmm_plan: no HIP device available");
+    fmm_plan_t pl = new (std::nothrow) struct fmm_plan;
+    if (!pl) return fail(nullptr, FMM_ERR_NOMEM, "fmm_plan: host allocation");
+    pl->box = box;
+    pl->levels = levels;
+    pl->p = p;
+    pl->K = num_coeffs(p);
+    pl->Kp = padded_coeffs(p);
+    pl->kappa = 3.0 / box;
+    if (hipGetDevice(&pl->device) != hipSuccess) {
+        delete pl;
+        return fail(nullptr, FMM_ERR_DEVICE, "fmm_plan: hipGetDevice failed");
+    }
+    fmm_status st = FMM_OK;
+    auto bail = [&](fmm_status s) {
+        g_plan_error = pl->err;
+        fmm_destroy(pl);
+        return s;
+    };
+    if (const char *v = std::getenv("FMM_M2L_VARIANT")) set_m2l_variant(std::atoi(v));
+    if (const char *v = std::getenv("FMM_TOP_FP64")) pl->top_fp64 = std::max(0, std::atoi(v));
+    if (pl->device < 64 && !rec_uploaded[pl->device]) {
+        RecTables t;
+        build_rec_tables(&t);
+        hipError_t e = upload_rec_tables(t);
+        if (e != hipSuccess) { hip_fail(pl, e, "recurrence tables"); return bail(FMM_ERR_DEVICE); }
+        rec_uploaded[pl->device] = true;
+    }
+    pl->offs = build_offsets();
+    const int K = pl->K;
+    pl->m2mT.assign((size_t)8 * K * K, 0.0);
+    pl->l2lT.assign((size_t)8 * K * K, 0.0);
+    std::vector<double> A((size_t)K * K);
+    for (int o = 0; o < 8; ++o) {
+        build_m2m_operator(p, o, A.data());
+        transpose_into(A.data(), K, pl->m2mT.data() + (size_t)o * K * K);
+        build_l2l_operator(p, o, A.data());
+        transpose_into(A.data(), K, pl->l2lT.data() + (size_t)o * K * K);
+    }
+    if (!pl->m2m.ensure(sizeof(double) * 8 * K * K) || !pl->l2l.ensure(sizeof(double) * 8 * K * K) ||
+        !pl->il.ensure(sizeof(int32_t) * 8 * kILSize) || !pl->offv.ensure(sizeof(int32_t) * 3 * kNumOffsets)) {
+        fail(pl, FMM_ERR_NOMEM, "fmm_plan: device allocation");
+        return bail(FMM_ERR_NOMEM);
+    }
+    if (hipMemcpy(pl->m2m.ptr, pl->m2mT.data(), sizeof(double) * 8 * K * K, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(pl->l2l.ptr, pl->l2lT.data(), sizeof(double) * 8 * K * K, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(pl->il.ptr, pl->offs.il.data(), sizeof(int32_t) * 8 * kILSize, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(pl->offv.ptr, pl->offs.vec.data(), sizeof(int32_t) * 3 * kNumOffsets, hipMemcpyHostToDevice) != hipSuccess) {
+        fail(pl, FMM_ERR_DEVICE, "fmm_plan: upload failed");
+        return bail(FMM_ERR_DEVICE);
+    }
+    if ((st = upload_lattice(pl)) != FMM_OK) return bail(st);
+    if (hipHostMalloc((void **)&pl->h_scalars, sizeof(double) * kScalars, hipHostMallocDefault) != hipSuccess) {
+        pl->h_scalars = nullptr;
+        fail(pl, FMM_ERR_NOMEM, "fmm_plan: pinned host allocation");
+        return bail(FMM_ERR_NOMEM);
+    }
+    *out = pl;
+    return FMM_OK;
+}
+
+extern "C" fmm_status fmm_plan_config(fmm_plan_t pl, int precision, double kappa, void *hip_stream) {
+    if (!pl) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan_config: plan is NULL");
+    if (precision != FMM_FP64 && precision != FMM_MIXED)
+        return fail(pl, FMM_ERR_INVALID, "fmm_plan_config: unknown precision");
+    if (!std::isfinite(kappa)) return fail(pl, FMM_ERR_INVALID, "fmm_plan_config: kappa must be finite");
+    pl->prec = precision;
+    pl->stream = (hipStream_t)hip_stream;
+    pl->have_state = false;
+    if (kappa > 0.0 && kappa != pl->kappa) {
+        pl->kappa = kappa;
+        fmm_status st = upload_lattice(pl);
+        if (st != FMM_OK) return st;
+    }
+    return FMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Evaluation
+// ---------------------------------------------------------------------------
+static fmm_status ensure_workspace(fmm_plan_t pl, int64_t n) {
+    const int64_t nleaf = level_cells(pl->levels);
+    if (!pl->tree_ready) {
+        const int64_t cells = level_offset(pl->levels + 1);
+        const size_t tb = sizeof(double) * (size_t)cells * pl->Kp;
+        int64_t part = 0;
+        for (int l = 1; l <= pl->levels; ++l)
+            if (m2l_slices(l) > 1) part = std::max(part, (int64_t)m2l_slices(l) * level_cells(l));
+        if (!pl->Mlev.ensure(tb) || !pl->Llev.ensure(tb) || !pl->M0.ensure(sizeof(double) * pl->Kp) ||
+            !pl->m2l_part.ensure(sizeof(double) * (size_t)std::max<int64_t>(part, 1) * pl->Kp) ||
+            !pl->L0.ensure(sizeof(double) * pl->Kp) || !pl->count.ensure(sizeof(uint32_t) * nleaf) ||
+            !pl->cursor.ensure(sizeof(uint32_t) * nleaf) || !pl->start.ensure(sizeof(int32_t) * (nleaf + 1)) ||
+            !pl->scan.ensure(sizeof(int32_t) * scan_scratch_len(nleaf)) ||
+            !pl->scalars.ensure(sizeof(double) * kScalars) || !pl->flag.ensure(sizeof(int) * 4) ||
+            !pl->partials.ensure(sizeof(double) * 2 * 5 * 1024))
+            return fail(pl, FMM_ERR_NOMEM, "tree workspace allocation");
+        pl->tree_ready = true;
+    }
+    if (n > pl->cap_n) {
+        const size_t nn = (size_t)std::max<int64_t>(n, 1);
+        if (!pl->key.ensure(sizeof(uint32_t) * nn) || !pl->perm.ensure(sizeof(int32_t) * nn) ||
+            !pl->xq.ensure(sizeof(double) * 4 * nn) || !pl->xq_u.ensure(sizeof(double) * 4 * nn) ||
+            !pl->xs.ensure(sizeof(double) * 4 * nn) ||
+            !pl->phi_nf.ensure(sizeof(double) * nn) || !pl->field_nf.ensure(sizeof(double) * 3 * nn) ||
+            !pl->phi_ff.ensure(sizeof(double) * nn) || !pl->field_ff.ensure(sizeof(double) * 3 * nn) ||
+            !pl->phi_u.ensure(sizeof(double) * nn) || !pl->field_u.ensure(sizeof(double) * 3 * nn) ||
+            !pl->nfuv.ensure(sizeof(double) * nn))
+            return fail(pl, FMM_ERR_NOMEM, "per-atom workspace allocation");
+        pl->cap_n = n;
+    }
+    return FMM_OK;
+}
+
+// a1 + a2: wrap, bin, Morton key, stable sort, leaf ranges.
+static fmm_status sort_atoms(fmm_plan_t pl, int64_t n, const double *pos, const double *q) {
+    hipStream_t s = pl->stream;
+    const int64_t nleaf = level_cells(pl->levels);
+    stage_begin(pl, FMM_STAGE_TOTAL);
+    stage_begin(pl, FMM_STAGE_SORT);
+    HIPCHK(pl, launch_fill_u32(pl->count.as<uint32_t>(), 0u, nleaf, s), "fill");
+    HIPCHK(pl, launch_fill_u32(pl->cursor.as<uint32_t>(), 0u, nleaf, s), "fill");
+    HIPCHK(pl, launch_fill_u32(pl->flag.as<uint32_t>(), 0u, 4, s), "fill");
+    HIPCHK(pl, launch_bin(n, pos, q, pl->box, pl->levels, pl->key.as<uint32_t>(), pl->count.as<uint32_t>(),
+                          pl->flag.as<int>(), s), "bin");
+    HIPCHK(pl, launch_scan(pl->count.as<uint32_t>(), pl->start.as<int32_t>(), nleaf, pl->scan.as<int32_t>(),
+                           scan_scratch_len(nleaf), s), "scan");
+    HIPCHK(pl, launch_scatter(n, pl->key.as<uint32_t>(), pl->start.as<int32_t>(), pl->cursor.as<uint32_t>(),
+                              pl->perm.as<int32_t>(), s), "scatter");
+    HIPCHK(pl, launch_cell_sort(nleaf, pl->start.as<int32_t>(), pl->perm.as<int32_t>(), s), "cell sort");
+    stage_end(pl, FMM_STAGE_SORT);
+    return FMM_OK;
+}
+
+// a3 - a8 on the repacked atoms xq: far-field potential and field per sorted
+// atom.  Leaf level in the mode's type T; levels 1..top in FP64; level 0 FP64.
+template <typename T>
+static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field) {
+    hipStream_t s = pl->stream;
+    const int L = pl->levels, p = pl->p, Kp = pl->Kp;
+    const int top = top_fp64_levels(pl);
+    const double h_leaf = pl->box / (double)(1 << L);
+    // level arrays hold 8-byte slots, so a level may be read as T or double
+    auto at = [&](const DeviceBuf &b, int l) { return (char *)b.ptr + (size_t)level_offset(l) * Kp * sizeof(double); };
+    auto MT = [&](int l) { return reinterpret_cast<T *>(at(pl->Mlev, l)); };
+    auto LT = [&](int l) { return reinterpret_cast<T *>(at(pl->Llev, l)); };
+    auto MD = [&](int l) { return reinterpret_cast<double *>(at(pl->Mlev, l)); };
+    auto LD = [&](int l) { return reinterpret_cast<double *>(at(pl->Llev, l)); };
+    const double *m2m = pl->m2m.as<double>(), *l2l = pl->l2l.as<double>();
+    stage_begin(pl, FMM_STAGE_P2M);
+    HIPCHK(pl, launch_p2m<T>(level_cells(L), xq, pl->start.as<int32_t>(), MT(L), p, Kp, 1.0 / h_leaf, s), "P2M");
+    stage_end(pl, FMM_STAGE_P2M);
+    stage_begin(pl, FMM_STAGE_M2M);
+    for (int l = L - 1; l >= 1; --l) {
+        const int64_t nc = level_cells(l);
+        hipError_t e;
+        if (l > top) e = launch_m2m<T, T>(nc, MT(l + 1), MT(l), m2m, p, Kp, s);
+        else if (l + 1 > top) e = launch_m2m<T, double>(nc, MT(l + 1), MD(l), m2m, p, Kp, s);
+        else e = launch_m2m<double, double>(nc, MD(l + 1), MD(l), m2m, p, Kp, s);
+        HIPCHK(pl, e, "M2M");
+    }
+    HIPCHK(pl, (top >= 1 ? launch_m2m<double, double>(1, MD(1), pl->M0.as<double>(), m2m, p, Kp, s)
+                         : launch_m2m<T, double>(1, MT(1), pl->M0.as<double>(), m2m, p, Kp, s)), "M2M");
+    stage_end(pl, FMM_STAGE_M2M);
+    stage_begin(pl, FMM_STAGE_LATTICE);
+    HIPCHK(pl, launch_lattice(pl->M0.as<double>(), pl->L0.as<double>(), pl->lat.as<double>(), p, Kp, s), "lattice");
+    stage_end(pl, FMM_STAGE_LATTICE);
+    stage_begin(pl, FMM_STAGE_M2L);
+    for (int l = 1; l <= L; ++l) {
+        if (l == L) stage_begin(pl, FMM_STAGE_M2L_LEAF);
+        hipError_t e;
+        if (l <= top)
+            e = launch_m2l<double>(l, pl->ops64.as<double>(), pl->il.as<int32_t>(), pl->offv.as<int32_t>(), MD(l),
+                                   LD(l), pl->m2l_part.as<double>(), p, Kp, s);
+        else
+            e = launch_m2l<T>(l, sizeof(T) == 8 ? (const T *)pl->ops64.ptr : (const T *)pl->ops32.ptr,
+                              pl->il.as<int32_t>(), pl->offv.as<int32_t>(), MT(l), LT(l), pl->m2l_part.as<T>(), p,
+                              Kp, s);
+        HIPCHK(pl, e, "M2L");
+        if (l == L) stage_end(pl, FMM_STAGE_M2L_LEAF);
+    }
+    stage_end(pl, FMM_STAGE_M2L);
+    stage_begin(pl, FMM_STAGE_L2L);
+    HIPCHK(pl, (top >= 1 ? launch_l2l<double, double>(level_cells(1), pl->L0.as<double>(), LD(1), l2l, p, Kp, s)
+                         : launch_l2l<double, T>(level_cells(1), pl->L0.as<double>(), LT(1), l2l, p, Kp, s)), "L2L");
+    for (int l = 2; l <= L; ++l) {
+        const int64_t nc = level_cells(l);
+        hipError_t e;
+        if (l <= top) e = launch_l2l<double, double>(nc, LD(l - 1), LD(l), l2l, p, Kp, s);
+        else if (l - 1 <= top) e = launch_l2l<double, T>(nc, LD(l - 1), LT(l), l2l, p, Kp, s);
+        else e = launch_l2l<T, T>(nc, LT(l - 1), LT(l), l2l, p, Kp, s);
+        HIPCHK(pl, e, "L2L");
+    }
+    stage_end(pl, FMM_STAGE_L2L);
+    stage_begin(pl, FMM_STAGE_L2P);
+    HIPCHK(pl, launch_l2p<T>(level_cells(L), xq, pl->start.as<int32_t>(), LT(L), p, Kp, h_leaf, phi, field, s),
+           "L2P");
+    stage_end(pl, FMM_STAGE_L2P);
+    return FMM_OK;
+}
+
+static int p2p_groups(int64_t n, int levels) {
+    const double occ = (double)n / (double)level_cells(levels);
+    if (occ > 40.0) return 2;
+    if (occ > 12.0) return 4;
+    if (occ > 5.0) return 8;
+    return 16;
+}
+
+template <typename T>
+static fmm_status run_fields(fmm_plan_t pl, int64_t n, const double *pos, const double *q) {
+    hipStream_t s = pl->stream;
+    fmm_status st;
+    if ((st = sort_atoms(pl, n, pos, q)) != FMM_OK) return st;
+    stage_begin(pl, FMM_STAGE_GATHER);
+    HIPCHK(pl, launch_gather(n, pl->perm.as<int32_t>(), pos, q, pl->box, pl->levels, pl->prec == FMM_FP64,
+                             pl->xq.ptr, pl->xs.as<double>(), s), "gather");
+    stage_end(pl, FMM_STAGE_GATHER);
+    if ((st = far_field<T>(pl, pl->xq.ptr, pl->phi_ff.as<double>(), pl->field_ff.as<T>())) != FMM_OK) return st;
+    const double h_leaf = pl->box / (double)(1 << pl->levels);
+    stage_begin(pl, FMM_STAGE_P2P);
+    HIPCHK(pl, launch_p2p<T>(level_cells(pl->levels), pl->levels, pl->xq.ptr, pl->start.as<int32_t>(), h_leaf,
+                             pl->phi_nf.as<double>(), pl->field_nf.as<T>(), p2p_groups(n, pl->levels), s), "P2P");
+    stage_end(pl, FMM_STAGE_P2P);
+    return FMM_OK;
+}
+
+static fmm_status check_eval_args(fmm_plan_t pl, int64_t n, const double *pos, const double *q) {
+    if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(pl, FMM_ERR_INVALID, "n must be in [0, 2^31)");
+    if (n > 0 && (!pos || !q)) return fail(pl, FMM_ERR_INVALID, "pos and q must be non-NULL when n > 0");
+    return FMM_OK;
+}
+
+static fmm_status finish_readback(fmm_plan_t pl, int nscalars) {
+    hipStream_t s = pl->stream;
+    HIPCHK(pl, hipMemcpyAsync(pl->h_scalars, pl->scalars.ptr, sizeof(double) * nscalars, hipMemcpyDeviceToHost, s),
+           "readback");
+    int flag = 0;
+    HIPCHK(pl, hipMemcpyAsync(&pl->h_scalars[kScalars - 1], pl->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s),
+           "readback");
+    HIPCHK(pl, hipStreamSynchronize(s), "synchronize");
+    std::memcpy(&flag, &pl->h_scalars[kScalars - 1], sizeof(int));
+    if (flag) return fail(pl, FMM_ERR_INVALID, "non-finite position or charge");
+    return FMM_OK;
+}
+
+template <typename T>
+static fmm_status energy_forces_t(fmm_plan_t pl, int64_t n, const double *pos, const double *q, double *energy,
+                                  double *forces, double *phi) {
+    hipStream_t s = pl->stream;
+    fmm_status st;
+    if ((st = run_fields<T>(pl, n, pos, q)) != FMM_OK) return st;
+    const int nb = moments_blocks(n);
+    double *sc = pl->scalars.as<double>();
+    stage_begin(pl, FMM_STAGE_FINAL);
+    HIPCHK(pl, launch_moments(n, pl->xs.as<double>(), pl->perm.as<int32_t>(), nullptr, 0, pl->partials.as<double>(),
+                              nb, sc, s), "moments");
+    HIPCHK(pl, hipMemcpyAsync(sc + 10, pl->M0.ptr, sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
+    HIPCHK(pl, launch_finalize<T>(n, pl->perm.as<int32_t>(), pl->xs.as<double>(), pl->box, pl->kappa,
+                                  pl->t00 / pl->box, sc, pl->M0.as<double>(), pl->phi_nf.as<double>(),
+                                  pl->field_nf.as<T>(), pl->phi_ff.as<double>(), pl->field_ff.as<T>(), forces, phi,
+                                  pl->partials.as<double>(), nb, sc + 8, s), "finalize");
+    stage_end(pl, FMM_STAGE_FINAL);
+    stage_end(pl, FMM_STAGE_TOTAL);
+    if ((st = finish_readback(pl, 11)) != FMM_OK) return st;
+    stage_collect(pl);
+    *energy = pl->h_scalars[8];
+    pl->q_tree = pl->h_scalars[10];
+    return FMM_OK;
+}
+
+extern "C" fmm_status fmm_energy_forces(fmm_plan_t pl, int64_t n, const double *pos, const double *q,
+                                        double *energy, double *forces, double *phi) {
+    fmm_status st = check_eval_args(pl, n, pos, q);
+    if (st != FMM_OK) return st;
+    if (!energy) return fail(pl, FMM_ERR_INVALID, "energy must be non-NULL");
+    pl->have_state = false;
+    if (n == 0) {
+        *energy = 0.0;
+        pl->have_state = true;
+        pl->n_state = 0;
+        return FMM_OK;
+    }
+    HIPCHK(pl, hipSetDevice(pl->device), "hipSetDevice");
+    if ((st = ensure_workspace(pl, n)) != FMM_OK) return st;
+    if ((st = ensure_m2l_ops(pl)) != FMM_OK) return st;
+    stage_reset(pl);
+    st = pl->prec == FMM_FP64 ? energy_forces_t<double>(pl, n, pos, q, energy, forces, phi)
+                              : energy_forces_t<float>(pl, n, pos, q, energy, forces, phi);
+    if (st == FMM_OK) {
+        pl->have_state = true;
+        pl->n_state = n;
+    }
+    return st;
+}
+
+template <typename T>
+static fmm_status parts_t(fmm_plan_t pl, int64_t n, const double *pos, const double *q, double *phi_nf,
+                          double *field_nf, double *phi_ff, double *field_ff) {
+    hipStream_t s = pl->stream;
+    fmm_status st;
+    if ((st = run_fields<T>(pl, n, pos, q)) != FMM_OK) return st;
+    double *sc = pl->scalars.as<double>();
+    HIPCHK(pl, launch_moments(n, pl->xs.as<double>(), pl->perm.as<int32_t>(), nullptr, 0, pl->partials.as<double>(),
+                              moments_blocks(n), sc, s), "moments");
+    HIPCHK(pl, launch_parts_out<T>(n, pl->perm.as<int32_t>(), pl->phi_nf.as<double>(), pl->field_nf.as<T>(),
+                                   pl->M0.as<double>(), 0.0, phi_nf, field_nf, s), "parts");
+    // the far field includes the net-charge lattice constant t00 Q_tree / b
+    HIPCHK(pl, launch_parts_out<T>(n, pl->perm.as<int32_t>(), pl->phi_ff.as<double>(), pl->field_ff.as<T>(),
+                                   pl->M0.as<double>(), pl->t00 / pl->box, phi_ff, field_ff, s), "parts");
+    HIPCHK(pl, hipMemcpyAsync(sc + 10, pl->M0.ptr, sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
+    if ((st = finish_readback(pl, 11)) != FMM_OK) return st;
+    pl->q_tree = pl->h_scalars[10];
+    return FMM_OK;
+}
+
+extern "C" fmm_status fmm_potential_parts(fmm_plan_t pl, int64_t n, const double *pos, const double *q,
+                                          double *phi_nf, double *field_nf, double *phi_ff, double *field_ff) {
+    fmm_status st = check_eval_args(pl, n, pos, q);
+    if (st != FMM_OK) return st;
+    pl->have_state = false;
+    if (n == 0) return FMM_OK;
+    HIPCHK(pl, hipSetDevice(pl->device), "hipSetDevice");
+    if ((st = ensure_workspace(pl, n)) != FMM_OK) return st;
+    if ((st = ensure_m2l_ops(pl)) != FMM_OK) return st;
+    st = pl->prec == FMM_FP64 ? parts_t<double>(pl, n, pos, q, phi_nf, field_nf, phi_ff, field_ff)
+                              : parts_t<float>(pl, n, pos, q, phi_nf, field_nf, phi_ff, field_ff);
+    if (st == FMM_OK) {
+        pl->have_state = true;
+        pl->n_state = n;
+    }
+    return st;
+}
+
+template <typename T>
+static fmm_status solute_solvent_t(fmm_plan_t pl, const uint8_t *mask, double *e_uv) {
+    hipStream_t s = pl->stream;
+    const int64_t n = pl->n_state;
+    fmm_status st;
+    // pass 2 of eq. FMMcalc: far field of the solute atoms alone
+    HIPCHK(pl, launch_mask_charges(n, pl->perm.as<int32_t>(), mask, pl->prec == FMM_FP64, pl->xq.ptr, pl->xq_u.ptr, s),
+           "mask charges");
+    if ((st = far_field<T>(pl, pl->xq_u.ptr, pl->phi_u.as<double>(), pl->field_u.as<T>())) != FMM_OK) return st;
+    double *sc0 = pl->scalars.as<double>();
+    HIPCHK(pl, hipMemcpyAsync(sc0 + 20, pl->M0.ptr, sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
+    const double h_leaf = pl->box / (double)(1 << pl->levels);
+    HIPCHK(pl, launch_p2p_uv<T>(n, pl->levels, pl->xq.ptr, pl->start.as<int32_t>(), pl->perm.as<int32_t>(), mask,
+                                h_leaf, pl->nfuv.as<double>(), s), "P2P uv");
+    const int nb = moments_blocks(n);
+    double *sc = pl->scalars.as<double>();
+    HIPCHK(pl, launch_uv_sums<T>(n, pl->perm.as<int32_t>(), pl->xs.as<double>(), mask, pl->phi_ff.as<double>(),
+                                 pl->phi_u.as<double>(), pl->nfuv.as<double>(), pl->partials.as<double>(), nb, sc + 16, s),
+           "uv sums");
+    HIPCHK(pl, launch_moments(n, pl->xs.as<double>(), pl->perm.as<int32_t>(), mask, 1, pl->partials.as<double>(), nb,
+                              sc + 24, s), "moments");
+    HIPCHK(pl, launch_moments(n, pl->xs.as<double>(), pl->perm.as<int32_t>(), mask, 0, pl->partials.as<double>(), nb,
+                              sc + 32, s), "moments");
+    if ((st = finish_readback(pl, 40)) != FMM_OK) return st;
+    const double *h = pl->h_scalars;
+    const double A = h[16], B = h[17], C = h[18], D = h[19];
+    const double Qu = h[24], mux = h[25], muy = h[26], muz = h[27], Su = h[28];
+    const double Qv = h[32], mvx = h[33], mvy = h[34], mvz = h[35], Sv = h[36];
+    const double V = pl->box * pl->box * pl->box;
+    // FF cross term.  The net-charge lattice constant enters phi_uv as
+    // t00 Q_tree / b and phi_u as t00 Q_u,tree / b (tree monopoles of the two
+    // passes); its share of (A - B + C) / 2 is added here in FP64.
+    const double qt = pl->q_tree, qut = h[20];
+    const double w_ff = 0.5 * (A - B + C) + 0.5 * pl->t00 / pl->box * (Qu * qt - Qu * qut + Qv * qut);
+    const double w_bc = -M_PI * Qu * Qv / (V * pl->kappa * pl->kappa) +
+                        (2.0 * M_PI / (3.0 * V)) * (Qu * Sv + Qv * Su - 2.0 * (mux * mvx + muy * mvy + muz * mvz));
+    *e_uv = w_ff + D + w_bc;
+    return FMM_OK;
+}
+
+extern "C" fmm_status fmm_solute_solvent_energy(fmm_plan_t pl, const uint8_t *mask, double *e_uv) {
+    if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    if (!e_uv) return fail(pl, FMM_ERR_INVALID, "e_uv must be non-NULL");
+    if (!pl->have_state) return fail(pl, FMM_ERR_STATE, "fmm_solute_solvent_energy needs a preceding fmm_energy_forces");
+    if (pl->n_state == 0) { *e_uv = 0.0; return FMM_OK; }
+    if (!mask) return fail(pl, FMM_ERR_INVALID, "mask must be non-NULL");
+    HIPCHK(pl, hipSetDevice(pl->device), "hipSetDevice");
+    return pl->prec == FMM_FP64 ? solute_solvent_t<double>(pl, mask, e_uv) : solute_solvent_t<float>(pl, mask, e_uv);
+}
+
+extern "C" fmm_status fmm_bin(fmm_plan_t pl, int64_t n, const double *pos, uint32_t *keys, int32_t *perm,
+                              int32_t *cell_start) {
+    if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(pl, FMM_ERR_INVALID, "n must be in [0, 2^31)");
+    if (n > 0 && !pos) return fail(pl, FMM_ERR_INVALID, "pos must be non-NULL when n > 0");
+    HIPCHK(pl, hipSetDevice(pl->device), "hipSetDevice");
+    fmm_status st;
+    if ((st = ensure_workspace(pl, n)) != FMM_OK) return st;
+    pl->have_state = false;
+    hipStream_t s = pl->stream;
+    if ((st = sort_atoms(pl, n, pos, nullptr)) != FMM_OK) return st;
+    const int64_t nleaf = level_cells(pl->levels);
+    if (keys && n > 0) HIPCHK(pl, hipMemcpyAsync(keys, pl->key.ptr, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s), "copy");
+    if (perm && n > 0) HIPCHK(pl, hipMemcpyAsync(perm, pl->perm.ptr, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s), "copy");
+    if (cell_start)
+        HIPCHK(pl, hipMemcpyAsync(cell_start, pl->start.ptr, sizeof(int32_t) * (nleaf + 1), hipMemcpyDeviceToDevice, s),
+               "copy");
+    return finish_readback(pl, 1);
+}
+
+extern "C" fmm_status fmm_lattice_tensor(fmm_plan_t pl, double *out, int64_t cap) {
+    if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    const int64_t need = 2 * (int64_t)(2 * pl->p + 1) * (2 * pl->p + 1);
+    if (!out || cap < need) return fail(pl, FMM_ERR_INVALID, "output too small");
+    // stored for a unit box: T_j(nu b) = b^{-(j+1)} T_j(nu)
+    for (int j = 0; j <= 2 * pl->p; ++j) {
+        const double sc = std::pow(pl->box, -(double)(j + 1));
+        for (int k = -j; k <= j; ++k) {
+            const cplx v = pl->T[(size_t)j * j + j + k] * sc;
+            out[2 * ((int64_t)j * j + j + k)] = v.real();
+            out[2 * ((int64_t)j * j + j + k) + 1] = v.imag();
+        }
+    }
+    return FMM_OK;
+}
+
+static void free_events(fmm_plan_t pl) {
+    for (int i = 0; i < FMM_NUM_STAGES; ++i) {
+        if (pl->ev_begin[i]) (void)hipEventDestroy(pl->ev_begin[i]);
+        if (pl->ev_end[i]) (void)hipEventDestroy(pl->ev_end[i]);
+        pl->ev_begin[i] = pl->ev_end[i] = nullptr;
+    }
+    pl->profiling = false;
+}
+
+extern "C" fmm_status fmm_profile(fmm_plan_t pl, int enable) {
+    if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    HIPCHK(pl, hipSetDevice(pl->device), "hipSetDevice");
+    free_events(pl);
+    for (int i = 0; i < FMM_NUM_STAGES; ++i) pl->stage_ms[i] = 0.0;
+    pl->profiled_calls = 0;
+    stage_reset(pl);
+    if (!enable) return FMM_OK;
+    for (int i = 0; i < FMM_NUM_STAGES; ++i) {
+        hipError_t e = hipEventCreate(&pl->ev_begin[i]);
+        if (e == hipSuccess) e = hipEventCreate(&pl->ev_end[i]);
+        if (e != hipSuccess) {
+            free_events(pl);
+            return hip_fail(pl, e, "hipEventCreate");
+        }
+    }
+    pl->profiling = true;
+    return FMM_OK;
+}
+
+extern "C" fmm_status fmm_profile_read(fmm_plan_t pl, double *ms, int64_t *calls) {
+    if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    if (ms)
+        for (int i = 0; i < FMM_NUM_STAGES; ++i) ms[i] = pl->stage_ms[i];
+    if (calls) *calls = pl->profiled_calls;
+    return FMM_OK;
+}
+
+extern "C" const char *fmm_last_error(fmm_plan_t pl) {
+    if (!pl) return g_plan_error.c_str();
+    return pl->err.c_str();
+}
+
+extern "C" void fmm_destroy(fmm_plan_t pl) {
+    if (!pl) return;
+    DeviceBuf *bufs[] = {&pl->ops32, &pl->ops64, &pl->m2m, &pl->l2l, &pl->lat, &pl->il, &pl->offv, &pl->key,
+                         &pl->count, &pl->cursor, &pl->start, &pl->perm, &pl->scan, &pl->xq, &pl->xq_u, &pl->xs, &pl->m2l_part,
+                         &pl->Mlev, &pl->Llev, &pl->M0, &pl->L0, &pl->phi_nf, &pl->field_nf, &pl->phi_ff,
+                         &pl->field_ff, &pl->phi_u, &pl->field_u, &pl->nfuv, &pl->partials, &pl->scalars, &pl->flag};
+    for (DeviceBuf *b : bufs) b->release();
+    free_events(pl);
+    if (pl->h_scalars) (void)hipHostFree(pl->h_scalars);
+    delete pl;
+}
+
+extern "C" const char *fmm_version(void) { return "libfmm 0.1 (gfx950)"; }

@@ -1,0 +1,158 @@
+// Internal declarations shared by the host orchestration and the HIP kernels
+// of libfmm.  Nothing here is part of the public ABI (see include/fmm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace fmm {
+
+constexpr int kWS = 2;            // near field / well-separatedness: +-2 cells
+constexpr int kNumOffsets = 1206; // distinct M2L offsets: [-5,5]^3 minus [-2,2]^3
+constexpr int kILSize = 875;      // interaction list size per parity class
+constexpr int kMaxP = 20;
+constexpr int kMaxLevels = 10;
+
+// ---------------------------------------------------------------------------
+// Coefficient storage ("real storage"), K = (p+1)^2 reals per expansion:
+//   index n*n           : m = 0 part
+//   index n*n + 2m - 1  : real part of order m > 0
+//   index n*n + 2m      : imaginary part of order m > 0
+// Multipoles hold  M^_n^m = sum_j q_j conj(R^_n^m(r_j - c))  (no factor 2).
+// Locals hold      L^_n^0 and 2 Re / 2 Im of L^_n^m (m > 0), so that the
+// potential is the plain dot product  phi(c + x) = sum_k Rr_k(x) Lr_k  with
+// Rr = (R^_n^0, Re R^_n^m, Im R^_n^m).
+// R^_n^m = sqrt((n+m)!(n-m)!) R_n^m and I^_n^m = I_n^m / sqrt((n+m)!(n-m)!)
+// where R_n^m = r^n P_n^m e^{im phi}/(n+m)!, I_n^m = (n-m)! P_n^m e^{im phi}/r^{n+1}.
+// Expansions at level l are stored scaled by the cell edge h_l:
+//   M~_n = M^_n / h^n,   L~_n = L^_n h^{n+1},
+// which makes every M2M, M2L and L2L operator independent of the level and
+// of the box size.
+// ---------------------------------------------------------------------------
+
+constexpr inline int num_coeffs(int p) { return (p + 1) * (p + 1); }
+constexpr inline int padded_coeffs(int p) { return ((num_coeffs(p) + 15) / 16) * 16; }
+
+// Host FP64 precompute (harmonics_host.cpp) ---------------------------------
+using cplx = std::complex<double>;
+
+// Complex solid harmonics at (x,y,z) for 0 <= n <= J, all -n <= m <= n,
+// stored at n*n + n + m.
+void regular_complex(double x, double y, double z, int J, cplx *out);
+void irregular_complex(double x, double y, double z, int J, cplx *out);
+double norm_factor(int n, int m);  // sqrt((n+|m|)!(n-|m|)!)
+
+struct Offsets {
+    std::vector<int> vec;  // kNumOffsets x 3
+    std::vector<int> il;   // 8 x kILSize offset ids (parity code = 4 px + 2 py + pz)
+};
+Offsets build_offsets();
+
+// Real operators, row-major [out][in], K x K.
+void build_m2l_operator(int p, const double t[3], double *A);
+void build_lattice_operator(int p, const cplx *T, double *A);
+void build_m2m_operator(int p, int octant, double *A);  // child octant -> parent
+void build_l2l_operator(int p, int octant, double *A);  // parent -> child octant
+
+// Lattice tensor for a unit box: T_j^k = sum_{|nu|_inf > 2} I_j^k(nu), j <= J,
+// evaluated as in eq. 12 with split parameter kappa_b (= kappa * b) for j = 0
+// and j <= kEwaldMaxJ; direct absolutely convergent sums above.
+void lattice_tensor(int J, double kappa_b, cplx *T);
+
+// Recurrence coefficient tables for the normalised regular harmonics
+// (index n(n+1)/2 + m): a = (2n-1)/sqrt((n+m)(n-m)),
+// b = sqrt((n+m-1)(n-m-1)/((n+m)(n-m))); diagonal c_m = sqrt((2m-1)/(2m)),
+// sub-diagonal d_m = sqrt(2m+1).
+struct RecTables {
+    double a[(kMaxP + 1) * (kMaxP + 2) / 2];
+    double b[(kMaxP + 1) * (kMaxP + 2) / 2];
+    double c[kMaxP + 1];
+    double d[kMaxP + 1];
+};
+void build_rec_tables(RecTables *t);
+
+// Kernel launchers (defined in the .hip files) ------------------------------
+// All return the first HIP error they meet.
+
+// k_expand.hip
+hipError_t upload_rec_tables(const RecTables &t);
+
+// k_sort.hip
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
+hipError_t launch_bin(int64_t n, const double *pos, const double *q, double box, int levels,
+                      uint32_t *key, uint32_t *count, int *flag, hipStream_t s);
+hipError_t launch_scan(const uint32_t *in, int32_t *out_exclusive, int64_t n,
+                       int32_t *scratch, int64_t scratch_len, hipStream_t s);
+int64_t scan_scratch_len(int64_t n);
+hipError_t launch_scatter(int64_t n, const uint32_t *key, const int32_t *start, uint32_t *cursor,
+                          int32_t *perm, hipStream_t s);
+hipError_t launch_cell_sort(int64_t nleaf, const int32_t *start, int32_t *perm, hipStream_t s);
+hipError_t launch_gather(int64_t n, const int32_t *perm, const double *pos, const double *q,
+                         double box, int levels, bool fp64, void *xq, double *xs, hipStream_t s);
+hipError_t launch_mask_charges(int64_t n, const int32_t *perm, const uint8_t *mask, bool fp64,
+                               const void *xq, void *xq_u, hipStream_t s);
+
+// k_expand.hip (T = float for mixed, double for fp64)
+template <typename T>
+hipError_t launch_p2m(int64_t nleaf, const void *xq, const int32_t *start, T *M, int p, int Kp,
+                      double inv_h, hipStream_t s);
+template <typename Tin, typename Tout>
+hipError_t launch_m2m(int64_t nparent, const Tin *Mchild, Tout *Mparent, const double *opsT, int p,
+                      int Kp, hipStream_t s);
+template <typename Tin, typename Tout>
+hipError_t launch_l2l(int64_t nchild, const Tin *Lparent, Tout *Lchild, const double *opsT, int p,
+                      int Kp, hipStream_t s);
+hipError_t launch_lattice(const double *M0, double *L0, const double *AT, int p, int Kp,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_l2p(int64_t nleaf, const void *xq, const int32_t *start, const T *L, int p,
+                      int Kp, double h, double *phi, T *field, hipStream_t s);
+
+// k_m2l.hip
+// Levels with few target cells split the 875 offsets into slices (split-K)
+// whose partial sums go to `partial` and are added in a fixed order.
+int m2l_slices(int level);
+void set_m2l_variant(int v);  // tuning: 0 default, 1 offset-split, 2 LDS-shared
+template <typename T>
+hipError_t launch_m2l(int level, const T *ops, const int32_t *il, const int32_t *offs, const T *M,
+                      T *L, T *partial, int p, int Kp, hipStream_t s);
+template <typename T>
+size_t m2l_ops_elems(int p);  // element count of the swizzled operator array
+template <typename T>
+void swizzle_m2l_ops(int p, const double *ops_rowmajor /*1206 x K x K*/, T *out);
+
+// k_p2p.hip
+template <typename T>
+hipError_t launch_p2p(int64_t nleaf, int levels, const void *xq, const int32_t *start, double h,
+                      double *phi, T *field, int groups, hipStream_t s);
+template <typename T>
+hipError_t launch_p2p_uv(int64_t n, int levels, const void *xq, const int32_t *start,
+                         const int32_t *perm, const uint8_t *mask, double h, double *out_per_atom,
+                         hipStream_t s);
+
+// k_reduce.hip
+struct Moments {  // device-side FP64 results of the moment reduction
+    double Q, mux, muy, muz, S2;
+};
+hipError_t launch_moments(int64_t n, const double *xs, const int32_t *perm, const uint8_t *mask,
+                          int want, double *partials, int nblocks, double *out5, hipStream_t s);
+int moments_blocks(int64_t n);
+template <typename T>
+hipError_t launch_finalize(int64_t n, const int32_t *perm, const double *xs, double box, double kappa,
+                           double t00b, const double *moments, const double *m0, const double *phi_nf,
+                           const T *field_nf, const double *phi_ff, const T *field_ff, double *forces,
+                           double *phi, double *partials, int nblocks, double *energy_out, hipStream_t s);
+template <typename T>
+hipError_t launch_parts_out(int64_t n, const int32_t *perm, const double *phi_s, const T *field_s,
+                            const double *m0, double cq, double *phi, double *field, hipStream_t s);
+template <typename T>
+hipError_t launch_uv_sums(int64_t n, const int32_t *perm, const double *xs, const uint8_t *mask,
+                          const double *phi_uv, const double *phi_u, const double *nf_uv, double *partials,
+                          int nblocks, double *out4, hipStream_t s);
+
+}  // namespace fmm

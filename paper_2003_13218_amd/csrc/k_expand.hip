@@ -1,0 +1,379 @@
+// Stages a3 (P2M), a4 (M2M), a5 (lattice operator at level 0), a7 (L2L) and
+// a8 (L2P with gradient) of the far field (Appendix B: eqs. P2M, EqFF; the
+// level-0 image-lattice sum of eq. 12).
+//
+// Storage and scaling conventions are those of fmm_internal.h: real storage
+// of the normalised harmonics, expansions at each level scaled by the cell
+// edge so that every operator is level- and box-independent.
+#include "fmm_internal.h"
+
+namespace fmm {
+
+constexpr int kTri = (kMaxP + 1) * (kMaxP + 2) / 2;
+__constant__ double c_ra_d[kTri];
+__constant__ double c_rb_d[kTri];
+__constant__ double c_rc_d[kMaxP + 1];
+__constant__ double c_rd_d[kMaxP + 1];
+__constant__ float c_ra_f[kTri];
+__constant__ float c_rb_f[kTri];
+__constant__ float c_rc_f[kMaxP + 1];
+__constant__ float c_rd_f[kMaxP + 1];
+
+hipError_t upload_rec_tables(const RecTables &t) {
+    float af[kTri], bf[kTri], cf[kMaxP + 1], df[kMaxP + 1];
+    for (int i = 0; i < kTri; ++i) { af[i] = (float)t.a[i]; bf[i] = (float)t.b[i]; }
+    for (int i = 0; i <= kMaxP; ++i) { cf[i] = (float)t.c[i]; df[i] = (float)t.d[i]; }
+    hipError_t e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_ra_d), t.a, sizeof(t.a))) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_rb_d), t.b, sizeof(t.b))) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_rc_d), t.c, sizeof(t.c))) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_rd_d), t.d, sizeof(t.d))) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_ra_f), af, sizeof(af))) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_rb_f), bf, sizeof(bf))) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_rc_f), cf, sizeof(cf))) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_rd_f), df, sizeof(df))) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+template <typename T> struct Rec;
+template <> struct Rec<double> {
+    __device__ static double a(int i) { return c_ra_d[i]; }
+    __device__ static double b(int i) { return c_rb_d[i]; }
+    __device__ static double c(int m) { return c_rc_d[m]; }
+    __device__ static double d(int m) { return c_rd_d[m]; }
+};
+template <> struct Rec<float> {
+    __device__ static float a(int i) { return c_ra_f[i]; }
+    __device__ static float b(int i) { return c_rb_f[i]; }
+    __device__ static float c(int m) { return c_rc_f[m]; }
+    __device__ static float d(int m) { return c_rd_f[m]; }
+};
+
+// Calls f(n, m, re, im) with the normalised regular harmonic R^_n^m(x,y,z) for
+// every 0 <= m <= n <= p (m outer, n inner), by the three-term recurrences
+//   R^_m^m     = -c_m (x + i y) R^_{m-1}^{m-1}
+//   R^_{m+1}^m = d_m z R^_m^m
+//   R^_n^m     = a_nm z R^_{n-1}^m - b_nm r^2 R^_{n-2}^m.
+template <typename T, typename F>
+__device__ inline void regular_hat_foreach(T x, T y, T z, int p, F &&f) {
+    const T r2 = x * x + y * y + z * z;
+    T mre = 1, mim = 0;
+    for (int m = 0; m <= p; ++m) {
+        if (m > 0) {
+            const T c = -Rec<T>::c(m);
+            const T nre = c * (x * mre - y * mim);
+            const T nim = c * (x * mim + y * mre);
+            mre = nre;
+            mim = nim;
+        }
+        f(m, m, mre, mim);
+        if (m + 1 > p) continue;
+        T p2re = mre, p2im = mim;
+        const T dm = Rec<T>::d(m) * z;
+        T p1re = dm * mre, p1im = dm * mim;
+        f(m + 1, m, p1re, p1im);
+        int ti = (m + 2) * (m + 3) / 2 + m;
+        for (int n = m + 2; n <= p; ++n) {
+            const T a = Rec<T>::a(ti) * z, b = Rec<T>::b(ti) * r2;
+            const T cre = a * p1re - b * p2re;
+            const T cim = a * p1im - b * p2im;
+            f(n, m, cre, cim);
+            p2re = p1re; p2im = p1im;
+            p1re = cre; p1im = cim;
+            ti += n + 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// P2M (eq. P2M): M~_n^m(leaf) = sum_j q_j conj(R^_n^m((r_j - c)/h)).
+// One workgroup (one wavefront) per leaf; each lane evaluates one atom's
+// harmonics into LDS, then lanes sum columns.  Deterministic order.
+// ---------------------------------------------------------------------------
+constexpr int kMaxKPerLane = (num_coeffs(kMaxP) + 63) / 64;
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_p2m(int64_t nleaf, const T *__restrict__ xq,
+                                            const int32_t *__restrict__ start, T *__restrict__ M,
+                                            int p, int K, int Kp, T inv_h, int chunk) {
+    extern __shared__ unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
+    const int tid = threadIdx.x;
+    for (int64_t leaf = blockIdx.x; leaf < nleaf; leaf += gridDim.x) {
+        const int32_t s0 = start[leaf], s1 = start[leaf + 1];
+        double acc[kMaxKPerLane];  // leaf sums in FP64 (rounded once on store)
+#pragma unroll
+        for (int u = 0; u < kMaxKPerLane; ++u) acc[u] = 0;
+        for (int32_t base = s0; base < s1; base += chunk) {
+            const int cnt = min(chunk, s1 - base);
+            if (tid < cnt) {
+                const T *a = xq + 4 * (int64_t)(base + tid);
+                const T x = a[0] * inv_h, y = a[1] * inv_h, z = a[2] * inv_h, q = a[3];
+                T *row = sm + (size_t)tid * K;
+                regular_hat_foreach<T>(x, y, z, p, [&](int n, int m, T re, T im) {
+                    if (m == 0) row[n * n] = q * re;
+                    else {
+                        row[n * n + 2 * m - 1] = q * re;
+                        row[n * n + 2 * m] = -q * im;
+                    }
+                });
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kMaxKPerLane; ++u) {
+                const int j = tid + 64 * u;
+                if (j < K)
+                    for (int a = 0; a < cnt; ++a) acc[u] += (double)sm[(size_t)a * K + j];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int u = 0; u < kMaxKPerLane; ++u) {
+            const int j = tid + 64 * u;
+            if (j < Kp) M[leaf * Kp + j] = j < K ? (T)acc[u] : (T)0;
+        }
+        // Kp may exceed 64 * kMaxKPerLane only if K does; padded tail:
+        for (int j = 64 * kMaxKPerLane + tid; j < Kp; j += 64) M[leaf * Kp + j] = 0;
+    }
+}
+
+template <typename T>
+hipError_t launch_p2m(int64_t nleaf, const void *xq, const int32_t *start, T *M, int p, int Kp,
+                      double inv_h, hipStream_t s) {
+    const int K = num_coeffs(p);
+    int chunk = (int)(65536 / ((size_t)K * sizeof(T)));
+    if (chunk > 64) chunk = 64;
+    if (chunk < 1) chunk = 1;
+    const size_t lds = (size_t)chunk * K * sizeof(T);
+    int64_t g = nleaf < 1048576 ? nleaf : 1048576;
+    hipLaunchKernelGGL(k_p2m<T>, dim3((unsigned)g), dim3(64), lds, s, nleaf, (const T *)xq, start, M, p,
+                       K, Kp, (T)inv_h, chunk);
+    return hipGetLastError();
+}
+template hipError_t launch_p2m<float>(int64_t, const void *, const int32_t *, float *, int, int, double,
+                                      hipStream_t);
+template hipError_t launch_p2m<double>(int64_t, const void *, const int32_t *, double *, int, int, double,
+                                       hipStream_t);
+
+// ---------------------------------------------------------------------------
+// M2M: M~(parent) = sum over the 8 child octants of A_o M~(child 8P + o).
+// One thread per (parent, row); A_o stored transposed [o][col][row] (FP64) so
+// a wavefront reads consecutive rows.  Only columns of degree <= the row's
+// degree are non-zero.  FP64 arithmetic.
+// ---------------------------------------------------------------------------
+__device__ inline int degree_of(int idx) {
+    int n = (int)sqrtf((float)idx);
+    while ((n + 1) * (n + 1) <= idx) ++n;
+    while (n * n > idx) --n;
+    return n;
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_m2m(int64_t nparent, const Tin *__restrict__ Mc, Tout *__restrict__ Mp,
+                      const double *__restrict__ opsT, int K, int Kp) {
+    const int64_t total = nparent * Kp;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t P = g / Kp;
+        const int row = (int)(g - P * Kp);
+        double acc = 0.0;
+        if (row < K) {
+            const int n = degree_of(row);
+            const int cend = (n + 1) * (n + 1);
+            for (int o = 0; o < 8; ++o) {
+                const Tin *src = Mc + (8 * P + o) * Kp;
+                const double *A = opsT + (size_t)o * K * K + row;
+                for (int c = 0; c < cend; ++c) acc += A[(size_t)c * K] * (double)src[c];
+            }
+        }
+        Mp[P * Kp + row] = (Tout)acc;
+    }
+}
+
+template <typename Tin, typename Tout>
+hipError_t launch_m2m(int64_t nparent, const Tin *Mchild, Tout *Mparent, const double *opsT, int p,
+                      int Kp, hipStream_t s) {
+    const int K = num_coeffs(p);
+    int64_t total = nparent * Kp;
+    int64_t g = (total + 255) / 256;
+    if (g > 1048576) g = 1048576;
+    hipLaunchKernelGGL((k_m2m<Tin, Tout>), dim3((unsigned)g), dim3(256), 0, s, nparent, Mchild, Mparent,
+                       opsT, K, Kp);
+    return hipGetLastError();
+}
+template hipError_t launch_m2m<float, float>(int64_t, const float *, float *, const double *, int, int,
+                                             hipStream_t);
+template hipError_t launch_m2m<float, double>(int64_t, const float *, double *, const double *, int, int,
+                                              hipStream_t);
+template hipError_t launch_m2m<double, double>(int64_t, const double *, double *, const double *, int,
+                                               int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// L2L (merge): L~(child 8P + o) += A_o L~(P).  Columns of degree >= the
+// row's degree.  FP64 arithmetic.
+// ---------------------------------------------------------------------------
+template <typename Tin, typename Tout>
+__global__ void k_l2l(int64_t nchild, const Tin *__restrict__ Lp, Tout *__restrict__ Lc,
+                      const double *__restrict__ opsT, int K, int Kp) {
+    const int64_t total = nchild * Kp;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t C = g / Kp;
+        const int row = (int)(g - C * Kp);
+        if (row >= K) continue;
+        const int64_t P = C >> 3;
+        const int o = (int)(C & 7);
+        const int n = degree_of(row);
+        const Tin *src = Lp + P * Kp;
+        const double *A = opsT + (size_t)o * K * K + row;
+        double acc = 0.0;
+        for (int c = n * n; c < K; ++c) acc += A[(size_t)c * K] * (double)src[c];
+        Lc[C * Kp + row] = (Tout)((double)Lc[C * Kp + row] + acc);
+    }
+}
+
+template <typename Tin, typename Tout>
+hipError_t launch_l2l(int64_t nchild, const Tin *Lparent, Tout *Lchild, const double *opsT, int p,
+                      int Kp, hipStream_t s) {
+    const int K = num_coeffs(p);
+    int64_t total = nchild * Kp;
+    int64_t g = (total + 255) / 256;
+    if (g > 1048576) g = 1048576;
+    hipLaunchKernelGGL((k_l2l<Tin, Tout>), dim3((unsigned)g), dim3(256), 0, s, nchild, Lparent, Lchild,
+                       opsT, K, Kp);
+    return hipGetLastError();
+}
+template hipError_t launch_l2l<double, float>(int64_t, const double *, float *, const double *, int, int,
+                                              hipStream_t);
+template hipError_t launch_l2l<float, float>(int64_t, const float *, float *, const double *, int, int,
+                                             hipStream_t);
+template hipError_t launch_l2l<double, double>(int64_t, const double *, double *, const double *, int,
+                                               int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Level 0 (eq. 12 applied through eq. Lcoeffdef): L~(0) = A_T M~(0), FP64.
+// ---------------------------------------------------------------------------
+__global__ void k_lattice(const double *__restrict__ M0, double *__restrict__ L0,
+                          const double *__restrict__ AT, int K, int Kp) {
+    for (int row = threadIdx.x; row < Kp; row += blockDim.x) {
+        double acc = 0.0;
+        if (row < K)
+            for (int c = 0; c < K; ++c) acc += AT[(size_t)c * K + row] * M0[c];
+        L0[row] = acc;
+    }
+}
+
+hipError_t launch_lattice(const double *M0, double *L0, const double *AT, int p, int Kp, hipStream_t s) {
+    hipLaunchKernelGGL(k_lattice, dim3(1), dim3(256), 0, s, M0, L0, AT, num_coeffs(p), Kp);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// L2P (eq. EqFF) with gradient: phi(c + x) = (1/h) sum_k Rr_k(x/h) L~_k and
+// grad phi = (1/h^2) sum_k Rr_k(x/h) G~_k, where G~ (degree <= p-1) follows
+// from L~ by differentiating the regular harmonics:
+//   dz R_n^m = R_{n-1}^m,  (dx + i dy) R_n^m = R_{n-1}^{m+1},
+//   (dx - i dy) R_n^m = -R_{n-1}^{m-1}.
+// One wavefront per leaf; lanes take atoms.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline void get_local(const T *Ls, int n, int m, T &re, T &im) {
+    const int am = m < 0 ? -m : m;
+    if (am > n) { re = 0; im = 0; return; }
+    if (am == 0) { re = Ls[n * n]; im = 0; return; }
+    re = (T)0.5 * Ls[n * n + 2 * am - 1];
+    im = (T)0.5 * Ls[n * n + 2 * am];
+    if (m < 0) {  // L_n^{-m} = (-1)^m conj(L_n^m)
+        const T s = (am & 1) ? (T)-1 : (T)1;
+        re = s * re;
+        im = -s * im;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_l2p(int64_t nleaf, const T *__restrict__ xq,
+                                            const int32_t *__restrict__ start, const T *__restrict__ L,
+                                            int p, int K, int Kp, T inv_h, T inv_h2, double *__restrict__ phi,
+                                            T *__restrict__ field) {
+    extern __shared__ unsigned char smem_raw[];
+    T *Ls = reinterpret_cast<T *>(smem_raw);
+    const int Kg = p * p;
+    T *Gx = Ls + K;
+    T *Gy = Gx + Kg;
+    T *Gz = Gy + Kg;
+    const int tid = threadIdx.x;
+    for (int64_t leaf = blockIdx.x; leaf < nleaf; leaf += gridDim.x) {
+        const int32_t s0 = start[leaf], s1 = start[leaf + 1];
+        if (s1 <= s0) continue;  // uniform per block
+        for (int j = tid; j < K; j += 64) Ls[j] = L[leaf * Kp + j];
+        __syncthreads();
+        for (int j = tid; j < Kg; j += 64) {
+            const int n = degree_of(j);
+            const int r = j - n * n;
+            const int m = (r + 1) / 2;
+            T are, aim, bre, bim, cre, cim;
+            get_local(Ls, n + 1, m - 1, are, aim);
+            get_local(Ls, n + 1, m + 1, bre, bim);
+            get_local(Ls, n + 1, m, cre, cim);
+            const T fa = sqrt((T)((n - m + 2) * (n - m + 1)));
+            const T fb = sqrt((T)((n + m + 2) * (n + m + 1)));
+            const T fc = sqrt((T)((n + 1 + m) * (n + 1 - m)));
+            // complex G-hat values
+            const T gxr = (T)0.5 * (fa * are - fb * bre), gxi = (T)0.5 * (fa * aim - fb * bim);
+            // (i/2)(fa A + fb B)
+            const T gyr = (T)-0.5 * (fa * aim + fb * bim), gyi = (T)0.5 * (fa * are + fb * bre);
+            const T gzr = fc * cre, gzi = fc * cim;
+            if (m == 0) {
+                Gx[j] = gxr; Gy[j] = gyr; Gz[j] = gzr;
+            } else if (r & 1) {  // real part slot, factor 2
+                Gx[j] = 2 * gxr; Gy[j] = 2 * gyr; Gz[j] = 2 * gzr;
+            } else {
+                Gx[j] = 2 * gxi; Gy[j] = 2 * gyi; Gz[j] = 2 * gzi;
+            }
+        }
+        __syncthreads();
+        for (int32_t s = s0 + tid; s < s1; s += 64) {
+            const T *a = xq + 4 * (int64_t)s;
+            const T x = a[0] * inv_h, y = a[1] * inv_h, z = a[2] * inv_h;
+            double ph = 0;  // potential accumulated in FP64 (see k_p2p)
+            T gx = 0, gy = 0, gz = 0;
+            regular_hat_foreach<T>(x, y, z, p, [&](int n, int m, T re, T im) {
+                if (m == 0) {
+                    const int k = n * n;
+                    ph += (double)(re * Ls[k]);
+                    if (n < p) { gx += re * Gx[k]; gy += re * Gy[k]; gz += re * Gz[k]; }
+                } else {
+                    const int k = n * n + 2 * m - 1;
+                    ph += (double)(re * Ls[k] + im * Ls[k + 1]);
+                    if (n < p) {
+                        gx += re * Gx[k] + im * Gx[k + 1];
+                        gy += re * Gy[k] + im * Gy[k + 1];
+                        gz += re * Gz[k] + im * Gz[k + 1];
+                    }
+                }
+            });
+            phi[s] = ph * (double)inv_h;
+            field[3 * (int64_t)s + 0] = -gx * inv_h2;
+            field[3 * (int64_t)s + 1] = -gy * inv_h2;
+            field[3 * (int64_t)s + 2] = -gz * inv_h2;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+hipError_t launch_l2p(int64_t nleaf, const void *xq, const int32_t *start, const T *L, int p, int Kp,
+                      double h, double *phi, T *field, hipStream_t s) {
+    const int K = num_coeffs(p);
+    const size_t lds = (size_t)(K + 3 * p * p) * sizeof(T);
+    int64_t g = nleaf < 1048576 ? nleaf : 1048576;
+    hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)g), dim3(64), lds, s, nleaf, (const T *)xq, start, L, p, K,
+                       Kp, (T)(1.0 / h), (T)(1.0 / (h * h)), phi, field);
+    return hipGetLastError();
+}
+template hipError_t launch_l2p<float>(int64_t, const void *, const int32_t *, const float *, int, int,
+                                      double, double *, float *, hipStream_t);
+template hipError_t launch_l2p<double>(int64_t, const void *, const int32_t *, const double *, int, int,
+                                       double, double *, double *, hipStream_t);
+
+}  // namespace fmm

@@ -1,0 +1,309 @@
+// Stage a1/a2: wrap, leaf binning, Morton keys, stable counting sort by
+// (key, original index), per-leaf ranges and the repack into sorted,
+// leaf-local coordinates.  Integer work is bit-exact; the FP64 arithmetic
+// that decides a leaf index uses explicitly rounded operations (no FMA
+// contraction) so that it equals the plain definition
+//   w = x - b floor(x / b)  (0 if that gives b),  c = floor(w * (2^L / b)).
+#include "fmm_internal.h"
+#include "morton.h"
+#include "wrap.h"
+
+namespace fmm {
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_f64(double *p, double v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+static inline unsigned grid_for(int64_t n, int bs) {
+    int64_t g = (n + bs - 1) / bs;
+    if (g > 65535 * 16) g = 65535 * 16;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+// key[i] and per-leaf counts; flag |= 1 for a non-finite position or charge.
+__global__ void k_bin(int64_t n, const double *__restrict__ pos, const double *__restrict__ q,
+                      double box, double scale, uint32_t nc, uint32_t *__restrict__ key,
+                      uint32_t *__restrict__ count, int *__restrict__ flag) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+        const double qi = q ? q[i] : 0.0;
+        if (!isfinite(x) || !isfinite(y) || !isfinite(z) || !isfinite(qi)) {
+            atomicOr(flag, 1);
+            key[i] = 0;
+            atomicAdd(&count[0], 1u);
+            continue;
+        }
+        const uint32_t cx = leaf_coord(wrap_coord(x, box), scale, nc);
+        const uint32_t cy = leaf_coord(wrap_coord(y, box), scale, nc);
+        const uint32_t cz = leaf_coord(wrap_coord(z, box), scale, nc);
+        const uint32_t k = morton3(cx, cy, cz);
+        key[i] = k;
+        atomicAdd(&count[k], 1u);
+    }
+}
+
+hipError_t launch_bin(int64_t n, const double *pos, const double *q, double box, int levels,
+                      uint32_t *key, uint32_t *count, int *flag, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const uint32_t nc = 1u << levels;
+    const double scale = (double)nc / box;
+    hipLaunchKernelGGL(k_bin, dim3(grid_for(n, 256)), dim3(256), 0, s, n, pos, q, box, scale, nc,
+                       key, count, flag);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of uint32 counts into int32 starts (out has n + 1 entries).
+// Three-phase: per-block scan of 1024 elements, recursive scan of block sums,
+// add-back.  Deterministic integer arithmetic.
+// ---------------------------------------------------------------------------
+constexpr int kScanBlock = 1024;
+
+__global__ void k_scan_block(const uint32_t *__restrict__ in, int32_t *__restrict__ out, int64_t n,
+                             int32_t *__restrict__ block_sums) {
+    __shared__ int32_t s[kScanBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+    for (int i = threadIdx.x; i < kScanBlock; i += blockDim.x) {
+        int64_t g = base + i;
+        s[i] = g < n ? (int32_t)in[g] : 0;
+    }
+    __syncthreads();
+    // Hillis-Steele on 1024 elements with 256 threads (4 per thread)
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+        int32_t v[4];
+        for (int u = 0; u < 4; ++u) {
+            int i = threadIdx.x * 4 + u;
+            v[u] = i >= off ? s[i - off] : 0;
+        }
+        __syncthreads();
+        for (int u = 0; u < 4; ++u) s[threadIdx.x * 4 + u] += v[u];
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < kScanBlock; i += blockDim.x) {
+        int64_t g = base + i;
+        if (g < n) out[g] = (i == 0 ? 0 : s[i - 1]);  // exclusive
+    }
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = s[kScanBlock - 1];
+}
+
+__global__ void k_scan_add(int32_t *__restrict__ out, int64_t n, const int32_t *__restrict__ offs) {
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+    const int32_t o = offs[blockIdx.x];
+    for (int i = threadIdx.x; i < kScanBlock; i += blockDim.x) {
+        int64_t g = base + i;
+        if (g < n) out[g] += o;
+    }
+}
+
+__global__ void k_set_total(int32_t *out, int64_t n, const uint32_t *in) {
+    // out[n] = out[n-1] + in[n-1]
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = (n > 0 ? out[n - 1] + (int32_t)in[n - 1] : 0);
+}
+
+int64_t scan_scratch_len(int64_t n) {
+    int64_t total = 0;
+    int64_t m = n;
+    while (m > 1) {
+        int64_t nb = (m + kScanBlock - 1) / kScanBlock;
+        total += 2 * nb + 2;
+        m = nb;
+    }
+    return total + 4;
+}
+
+// scratch: int32 buffer of scan_scratch_len(n)
+static hipError_t scan_rec(const uint32_t *in_u, const int32_t *in_i, int32_t *out, int64_t n,
+                           int32_t *scratch, hipStream_t s);
+
+__global__ void k_scan_block_i(const int32_t *__restrict__ in, int32_t *__restrict__ out, int64_t n,
+                               int32_t *__restrict__ block_sums) {
+    __shared__ int32_t s[kScanBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+    for (int i = threadIdx.x; i < kScanBlock; i += blockDim.x) {
+        int64_t g = base + i;
+        s[i] = g < n ? in[g] : 0;
+    }
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+        int32_t v[4];
+        for (int u = 0; u < 4; ++u) {
+            int i = threadIdx.x * 4 + u;
+            v[u] = i >= off ? s[i - off] : 0;
+        }
+        __syncthreads();
+        for (int u = 0; u < 4; ++u) s[threadIdx.x * 4 + u] += v[u];
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < kScanBlock; i += blockDim.x) {
+        int64_t g = base + i;
+        if (g < n) out[g] = (i == 0 ? 0 : s[i - 1]);
+    }
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = s[kScanBlock - 1];
+}
+
+static hipError_t scan_rec(const uint32_t *in_u, const int32_t *in_i, int32_t *out, int64_t n,
+                           int32_t *scratch, hipStream_t s) {
+    const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    int32_t *sums = scratch;
+    int32_t *sums_scan = scratch + nb + 1;
+    int32_t *rest = scratch + 2 * nb + 2;
+    if (in_u)
+        hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(256), 0, s, in_u, out, n, sums);
+    else
+        hipLaunchKernelGGL(k_scan_block_i, dim3((unsigned)nb), dim3(256), 0, s, in_i, out, n, sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nb == 1) return e;
+    e = scan_rec(nullptr, sums, sums_scan, nb, rest, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(256), 0, s, out, n, sums_scan);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const uint32_t *in, int32_t *out, int64_t n, int32_t *scratch,
+                       int64_t scratch_len, hipStream_t s) {
+    if (scratch_len < scan_scratch_len(n)) return hipErrorInvalidValue;
+    if (n > 0) {
+        hipError_t e = scan_rec(in, nullptr, out, n, scratch, s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_set_total, dim3(1), dim3(64), 0, s, out, n, in);
+    return hipGetLastError();
+}
+
+// Scatter original indices into their leaf segment (order inside a segment
+// is then fixed by k_cell_sort).
+__global__ void k_scatter(int64_t n, const uint32_t *__restrict__ key, const int32_t *__restrict__ start,
+                          uint32_t *__restrict__ cursor, int32_t *__restrict__ perm) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = key[i];
+        const uint32_t slot = atomicAdd(&cursor[k], 1u);
+        perm[start[k] + (int32_t)slot] = (int32_t)i;
+    }
+}
+
+hipError_t launch_scatter(int64_t n, const uint32_t *key, const int32_t *start, uint32_t *cursor,
+                          int32_t *perm, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, n, key, start, cursor, perm);
+    return hipGetLastError();
+}
+
+// Insertion sort of each leaf segment by original index: makes the order
+// (key, index), i.e. a stable sort, independent of atomic arrival order.
+__global__ void k_cell_sort(int64_t nleaf, const int32_t *__restrict__ start, int32_t *__restrict__ perm) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nleaf;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = start[c], e = start[c + 1];
+        for (int32_t i = b + 1; i < e; ++i) {
+            const int32_t v = perm[i];
+            int32_t j = i - 1;
+            while (j >= b && perm[j] > v) {
+                perm[j + 1] = perm[j];
+                --j;
+            }
+            perm[j + 1] = v;
+        }
+    }
+}
+
+hipError_t launch_cell_sort(int64_t nleaf, const int32_t *start, int32_t *perm, hipStream_t s) {
+    hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(nleaf, 256)), dim3(256), 0, s, nleaf, start, perm);
+    return hipGetLastError();
+}
+
+// Repack in sorted order: leaf-local coordinates (x - leaf centre) and
+// charge in the mode's precision (xq), plus an FP64 copy (xs) of the wrapped
+// position measured from the box centre and the charge, which the correction
+// terms, the energy reduction and the solute-solvent pass read later (so
+// they never touch the caller's arrays again).
+template <typename T>
+__global__ void k_gather(int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ pos,
+                         const double *__restrict__ q, double box, double scale, uint32_t nc, double h,
+                         T *__restrict__ xq, double *__restrict__ xs) {
+    const double hb = 0.5 * box;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = perm[s];
+        double w[3];
+        double loc[3];
+        for (int a = 0; a < 3; ++a) {
+            w[a] = wrap_coord(pos[3 * (int64_t)i + a], box);
+            const uint32_t c = leaf_coord(w[a], scale, nc);
+            loc[a] = w[a] - ((double)c + 0.5) * h;
+        }
+        const double qi = q[i];
+        xq[4 * s + 0] = (T)loc[0];
+        xq[4 * s + 1] = (T)loc[1];
+        xq[4 * s + 2] = (T)loc[2];
+        xq[4 * s + 3] = (T)qi;
+        xs[4 * s + 0] = w[0] - hb;
+        xs[4 * s + 1] = w[1] - hb;
+        xs[4 * s + 2] = w[2] - hb;
+        xs[4 * s + 3] = qi;
+    }
+}
+
+hipError_t launch_gather(int64_t n, const int32_t *perm, const double *pos, const double *q, double box,
+                         int levels, bool fp64, void *xq, double *xs, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const uint32_t nc = 1u << levels;
+    const double scale = (double)nc / box;
+    const double h = box / (double)nc;
+    if (fp64)
+        hipLaunchKernelGGL(k_gather<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, perm, pos, q, box,
+                           scale, nc, h, (double *)xq, xs);
+    else
+        hipLaunchKernelGGL(k_gather<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, perm, pos, q, box,
+                           scale, nc, h, (float *)xq, xs);
+    return hipGetLastError();
+}
+
+// Solute-only charges for the second far-field pass of the solute-solvent
+// scheme: xq_u = xq with q multiplied by the solute flag of the atom.
+template <typename T>
+__global__ void k_mask_charges(int64_t n, const int32_t *__restrict__ perm, const uint8_t *__restrict__ mask,
+                               const T *__restrict__ xq, T *__restrict__ xq_u) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const bool u = mask[perm[s]] != 0;
+        xq_u[4 * s + 0] = xq[4 * s + 0];
+        xq_u[4 * s + 1] = xq[4 * s + 1];
+        xq_u[4 * s + 2] = xq[4 * s + 2];
+        xq_u[4 * s + 3] = u ? xq[4 * s + 3] : (T)0;
+    }
+}
+
+hipError_t launch_mask_charges(int64_t n, const int32_t *perm, const uint8_t *mask, bool fp64, const void *xq,
+                               void *xq_u, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (fp64)
+        hipLaunchKernelGGL(k_mask_charges<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, perm, mask,
+                           (const double *)xq, (double *)xq_u);
+    else
+        hipLaunchKernelGGL(k_mask_charges<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, perm, mask,
+                           (const float *)xq, (float *)xq_u);
+    return hipGetLastError();
+}
+
+}  // namespace fmm

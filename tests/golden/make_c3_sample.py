@@ -1,0 +1,36 @@
+"""Writes tests/golden/c3_sample_oracle.npz: the FP64 Ewald oracle's potential
+and force on the seeded 2,000-atom sample of the 1,000,000-atom box
+(333,333 waters + one -1 ion, b = 215.30 A), plus the sample indices and the
+Ewald parameters.  Calls only oracle/ and the seeded input generator.
+
+    python tests/golden/make_c3_sample.py
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import workloads  # noqa: E402
+
+
+def main(name="C3", k=2000):
+    w = workloads.config(name)
+    idx = workloads.sample_indices(w.n, k, w.seed)
+    ion = np.array([w.n - 1])
+    idx = np.unique(np.concatenate([idx, ion]))
+    t = time.time()
+    r = oracle.ewald(w.pos, w.q, w.box, eval_idx=idx, rcut=0.5 * w.box, accuracy=1e-13)
+    dt = time.time() - t
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name.lower()}_sample_oracle.npz")
+    np.savez(out, idx=idx, phi=r["phi"], force=r["force"], kappa=r["kappa"], rcut=r["rcut"], kmax=r["kmax"],
+             seconds=dt, threads=oracle.num_threads())
+    print(out, f"{dt:.1f} s", oracle.num_threads(), "threads")
+
+
+if __name__ == "__main__":
+    main(*(sys.argv[1:2] or ["C3"]))

@@ -1,0 +1,384 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances: relative energy error and RMS relative force / potential error
+(sqrt(sum |dF|^2 / sum |F|^2)); <= 1e-6 in FP64 mode and <= 1e-5 in mixed
+mode where the expansion order makes the truncation error that small.
+Integer stages (binning, Morton keys, sort) are compared bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from conftest import golden
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dtype=None):
+    import torch
+    t = torch.tensor(np.ascontiguousarray(a), device="cuda")
+    return t if dtype is None else t.to(dtype)
+
+
+def rms_rel(a, b):
+    return float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
+
+
+def _plan(fmm, box, levels, p, prec, kappa=0.0):
+    plan = fmm.fmm_plan(box, levels, p)
+    fmm.fmm_plan_config(plan, prec, kappa)
+    return plan
+
+
+_cache = {}
+
+
+def ewald_full(name):
+    if name not in _cache:
+        w = workloads.config(name)
+        _cache[name] = (w, oracle.ewald(w.pos, w.q, w.box))
+    return _cache[name]
+
+
+# ---------------------------------------------------------------- a1 / a2 ---
+@pytest.mark.parametrize("levels", [1, 2, 4, 5])
+def test_binning_bit_exact(fmm, levels):
+    w = workloads.config("C2")
+    pos = w.pos.copy()
+    # boundary cases: exactly on leaf faces, exactly b, negative, beyond b
+    h = w.box / 2 ** levels
+    pos[0] = [0.0, h, 2 * h]
+    pos[1] = [w.box, -1e-12, w.box - 1e-13]
+    pos[2] = [-w.box - 0.5 * h, 3.0 * w.box + 0.25, -7 * h]
+    pos[3] = [0.5 * w.box] * 3
+    plan = _plan(fmm, w.box, levels, 2, fmm.FMM_FP64)
+    keys, perm, start = fmm.fmm_bin(plan, _t(pos))
+    _, kref = oracle.bin_reference(pos, w.box, levels)
+    order, sref = oracle.sort_reference(pos, w.box, levels)
+    np.testing.assert_array_equal(keys.cpu().numpy().view(np.uint32), kref)
+    np.testing.assert_array_equal(perm.cpu().numpy(), order)
+    np.testing.assert_array_equal(start.cpu().numpy(), sref)
+
+
+# ---------------------------------------------------------------------- a9 --
+@pytest.mark.parametrize("name", ["C1", "C2"])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-6)])
+def test_p2p_matches_direct_nearfield(fmm, name, prec, tol):
+    w = workloads.config(name)
+    plan = _plan(fmm, w.box, w.levels, 2, prec)
+    pn, fn, _, _ = fmm.fmm_potential_parts(plan, _t(w.pos), _t(w.q))
+    phi, field = oracle.nearfield(w.pos, w.q, w.box, w.levels)
+    assert rms_rel(pn.cpu().numpy(), phi) < tol
+    assert rms_rel(fn.cpu().numpy(), field) < tol
+
+
+def test_p2p_shallow_tree_repeats_images(fmm):
+    # levels = 1: the +-2 block wraps the 2-leaf axis several times; every
+    # image must be visited, none deduplicated
+    pos, q = workloads.random_charges(40, 5.0, seed=41, net=0.5)
+    plan = _plan(fmm, 5.0, 1, 2, fmm.FMM_FP64)
+    pn, fn, _, _ = fmm.fmm_potential_parts(plan, _t(pos), _t(q))
+    phi, field = oracle.nearfield(pos, q, 5.0, 1)
+    np.testing.assert_allclose(pn.cpu().numpy(), phi, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(fn.cpu().numpy(), field, rtol=1e-11, atol=1e-12)
+
+
+# ------------------------------------------------------- whole path a1-a13 --
+def test_c1_fp64_energy_forces(fmm):
+    w, o = ewald_full("C1")
+    plan = _plan(fmm, w.box, w.levels, w.p, fmm.FMM_FP64)
+    e, f, ph = fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q), forces=True, phi=True)
+    E = o["terms"]["total"]
+    assert abs(e - E) / abs(E) < 1e-6
+    # p = 8 on a 4-leaf-per-axis tree: force truncation error is a few 1e-6
+    assert rms_rel(f.cpu().numpy(), o["force"]) < 5e-6
+    assert rms_rel(ph.cpu().numpy(), o["phi"]) < 5e-6
+    # E = 1/2 sum q phi holds to rounding
+    assert 0.5 * float(w.q @ ph.cpu().numpy()) == pytest.approx(e, rel=1e-12)
+
+
+def test_c1_fp64_forces_at_higher_order(fmm):
+    # the force tolerance 1e-6 of FP64 mode is met once p makes the
+    # truncation error small enough
+    w, o = ewald_full("C1")
+    plan = _plan(fmm, w.box, w.levels, 12, fmm.FMM_FP64)
+    e, f, ph = fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q), forces=True, phi=True)
+    assert abs(e - o["terms"]["total"]) / abs(o["terms"]["total"]) < 1e-8
+    assert rms_rel(f.cpu().numpy(), o["force"]) < 1e-6
+    assert rms_rel(ph.cpu().numpy(), o["phi"]) < 1e-6
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-6), (1, 1e-5)])
+def test_c2_energy_forces(fmm, prec, tol):
+    w, o = ewald_full("C2")
+    plan = _plan(fmm, w.box, w.levels, w.p, prec)
+    e, f, ph = fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q), forces=True, phi=True)
+    E = o["terms"]["total"]
+    assert abs(e - E) / abs(E) < tol
+    assert rms_rel(f.cpu().numpy(), o["force"]) < tol
+    assert rms_rel(ph.cpu().numpy(), o["phi"]) < tol
+
+
+def uv_scale(w, mask):
+    # The cross energy of a small solute is an interaction of a few atoms: its
+    # error is that of the potential at those atoms, so it is measured in the
+    # unit of a single-atom energy, sum_u |q_i| x rms(phi) (oracle phi); the
+    # synthetic shell of randomly oriented waters makes e_uv itself
+    # accidentally small, which a plain relative error would overweight.
+    o = ewald_full(w.name)[1] if w.name in ("C1", "C2") else oracle.ewald(w.pos, w.q, w.box)
+    return float(np.sum(np.abs(w.q[mask == 1])) * np.sqrt(np.mean(o["phi"] ** 2)))
+
+
+# C1 runs at the workload's p = 8, where the truncation error of the cross
+# energy is a few 1e-6 of its scale; C2 (p = 10) meets 1e-6 in FP64
+@pytest.mark.parametrize("name,prec,tol", [("C1", 0, 1e-5), ("C2", 0, 1e-6), ("C2", 1, 1e-5)])
+def test_solute_solvent_energy(fmm, name, prec, tol):
+    w = workloads.config(name)
+    plan = _plan(fmm, w.box, w.levels, w.p, prec)
+    fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q))
+    # the library keeps its own copy of the atoms: the inputs may be gone
+    e_uv = fmm.fmm_solute_solvent_energy(plan, _t(w.mask))
+    ref = oracle.ewald_uv(w.pos, w.q, w.mask, w.box)["total"]
+    assert abs(e_uv - ref) / max(abs(ref), uv_scale(w, w.mask)) < tol
+
+
+def test_solute_solvent_many_solute_atoms(fmm):
+    # a solute of several atoms spread over leaves, net charge != 0 in both parts
+    w = workloads.config("C1")
+    mask = np.zeros(w.n, np.uint8)
+    mask[[0, 1, 2, 100, 101, 102, 648]] = 1
+    plan = _plan(fmm, w.box, w.levels, 12, fmm.FMM_FP64)
+    fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q))
+    e_uv = fmm.fmm_solute_solvent_energy(plan, _t(mask))
+    ref = oracle.ewald_uv(w.pos, w.q, mask, w.box)["total"]
+    assert abs(e_uv - ref) / max(abs(ref), uv_scale(w, mask)) < 1e-6
+
+
+# ------------------------------------------------------ closed-form pins ---
+@pytest.mark.parametrize("levels,p", [(1, 10), (2, 10), (3, 12)])
+def test_single_charge_xi(fmm, levels, p):
+    # one charge anywhere in the cell: E = -xi q^2 / (2b); exercises the
+    # lattice operator (eq. 12 with its self term) and the charged-system term
+    b, q0 = 12.0, -1.3
+    plan = _plan(fmm, b, levels, p, fmm.FMM_FP64)
+    for r in ([1.0, 2.0, 3.0], [6.0, 6.0, 6.0], [11.9, 0.05, 7.3]):
+        e, f, _ = fmm.fmm_energy_forces(plan, _t([r]), _t([q0]))
+        xi = -2 * b * e / q0 ** 2
+        assert xi == pytest.approx(golden("xi_simple_cubic.txt"), abs=2e-6)
+        # the exact force on a lone charge vanishes; |F| scale is q^2/b^2
+        assert np.abs(f.cpu().numpy()).max() < 1e-5 * q0 ** 2 / b ** 2
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_madelung_nacl(fmm, levels):
+    pos = np.array([[i, j, k] for i in range(2) for j in range(2) for k in range(2)], float) + 0.3
+    q = np.array([(-1.0) ** (i + j + k) for i in range(2) for j in range(2) for k in range(2)])
+    plan = _plan(fmm, 2.0, levels, 10, fmm.FMM_FP64)
+    e, _, _ = fmm.fmm_energy_forces(plan, _t(pos), _t(q))
+    assert -e / 4 == pytest.approx(golden("madelung_nacl.txt"), rel=1e-7)
+
+
+def test_kappa_independence(fmm):
+    # the same kappa in the lattice sum and the charged-system term: E must
+    # not depend on it (the requirement stated after eq. Velecfull)
+    w, o = ewald_full("C1")
+    es = []
+    for kb in (2.0, 3.0, 4.5):
+        plan = _plan(fmm, w.box, w.levels, w.p, fmm.FMM_FP64, kappa=kb / w.box)
+        es.append(fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q), forces=False)[0])
+    assert np.ptp(es) / abs(es[0]) < 1e-12
+
+
+def test_lattice_tensor_pins(fmm):
+    b, p = 3.0, 8
+    kap = 1.1
+    plan = _plan(fmm, b, 2, p, fmm.FMM_FP64, kappa=kap)
+    T = fmm.fmm_lattice_tensor(plan)
+    V = b ** 3
+    r = np.arange(-2, 3)
+    nu = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
+    nu = nu[(nu != 0).any(1)]
+    near = np.sum(1.0 / (np.linalg.norm(nu, axis=1) * b))
+    # j = 0: full Ewald image sum equals -xi/b + pi/(V kappa^2) (eq. 12 with its
+    # self term, k = 0 left out); the explicit images |nu|_inf <= 2 are removed
+    assert T[0].real == pytest.approx(-golden("xi_simple_cubic.txt") / b + math.pi / (V * kap ** 2) - near,
+                                      abs=6e-7 / b)
+    # cubic symmetry: odd j, j = 2 and orders k != 0 mod 4 vanish
+    for j in range(1, 2 * p + 1):
+        for k in range(-j, j + 1):
+            if j % 2 == 1 or j == 2 or k % 4 != 0:
+                assert abs(T[j * j + j + k]) < 1e-10 * max(1.0, abs(T[j * j + j]))
+    # j >= 10: the sum over |nu|_inf > 2 converges absolutely; compare with a
+    # direct sum from the definition of I_j^k (oracle.solid_harmonics convention)
+    from scipy.special import lpmv
+    R = 14
+    r = np.arange(-R, R + 1)
+    nu = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3).astype(float)
+    nu = nu[np.abs(nu).max(1) > 2] * b
+    rr = np.linalg.norm(nu, axis=1)
+    ct = nu[:, 2] / rr
+    ph = np.arctan2(nu[:, 1], nu[:, 0])
+    for j, k in [(10, 0), (10, 4), (12, 8), (14, 4), (16, 0)]:
+        direct = np.sum(math.factorial(j - k) * lpmv(k, j, ct) * np.exp(1j * k * ph) / rr ** (j + 1))
+        assert T[j * j + j + k] == pytest.approx(direct, rel=2e-6)
+
+
+# ------------------------------------------------------------- properties ---
+def test_boundary_crossing_is_continuous(fmm):
+    # a charged molecule crossing the cell face: E continuous (the role of the
+    # quadrupole surface term, eq. surfchargedend, in the paper's results)
+    w = workloads.config("C1")
+    plan = _plan(fmm, w.box, w.levels, 10, fmm.FMM_FP64)
+    pos = w.pos.copy()
+    ion = w.n - 1
+    es, fs = [], []
+    for x in (-1e-4, 1e-4):
+        pos[ion] = [x, 4.0, 5.0]
+        e, f, _ = fmm.fmm_energy_forces(plan, _t(pos), _t(w.q))
+        es.append(e)
+        fs.append(f.cpu().numpy()[ion, 0])
+    # E(+d) - E(-d) = -2 d F_x up to O(d^2)
+    resid = abs(es[1] - es[0] + 2e-4 * 0.5 * (fs[0] + fs[1]))
+    assert resid < 1e-7
+    # the correction terms (quadrupole + dipole) jump by a finite amount as the
+    # ion's wrapped image moves across the cell; the tree part jumps the other
+    # way, and only their sum is continuous
+    def e_corr(p):
+        V = w.box ** 3
+        r = oracle.wrap_positions(p, w.box) - w.box / 2
+        Q = w.q.sum()
+        mu = (w.q[:, None] * r).sum(0)
+        S = float(w.q @ (r * r).sum(1))
+        return 2 * math.pi / (3 * V) * (Q * S - mu @ mu)
+    p1 = w.pos.copy(); p1[ion] = [-1e-4, 4.0, 5.0]
+    p2 = w.pos.copy(); p2[ion] = [1e-4, 4.0, 5.0]
+    assert abs(e_corr(p2) - e_corr(p1)) > 1e4 * resid
+
+
+def test_energy_force_consistency(fmm):
+    # F = -grad E inside a leaf.  (At finite p the FMM energy jumps by its
+    # truncation error when an atom changes leaf, so no finite difference may
+    # straddle a leaf face: the ion, which sits exactly on one, is moved off.)
+    w = workloads.config("C1")
+    pos0 = w.pos.copy()
+    pos0[w.n - 1] += 0.37
+    w.pos = pos0
+    plan = _plan(fmm, w.box, w.levels, 14, fmm.FMM_FP64)
+    e0, f, _ = fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q))
+    f = f.cpu().numpy()
+    h = 1e-5
+    for i in (5, 300, w.n - 1):
+        for a in range(3):
+            pp = w.pos.copy(); pp[i, a] += h
+            pm = w.pos.copy(); pm[i, a] -= h
+            ep = fmm.fmm_energy_forces(plan, _t(pp), _t(w.q), forces=False)[0]
+            em = fmm.fmm_energy_forces(plan, _t(pm), _t(w.q), forces=False)[0]
+            assert f[i, a] == pytest.approx(-(ep - em) / (2 * h), rel=1e-5, abs=1e-7)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_run_to_run_bitwise_determinism(fmm, prec):
+    w = workloads.config("C2")
+    plan = _plan(fmm, w.box, w.levels, w.p, prec)
+    pos, q = _t(w.pos), _t(w.q)
+    ref = fmm.fmm_energy_forces(plan, pos, q, phi=True)
+    for _ in range(3):
+        e, f, ph = fmm.fmm_energy_forces(plan, pos, q, phi=True)
+        assert e == ref[0]
+        assert bool((f == ref[1]).all()) and bool((ph == ref[2]).all())
+
+
+def test_translation_and_image_invariance(fmm):
+    w = workloads.config("C1")
+    plan = _plan(fmm, w.box, w.levels, w.p, fmm.FMM_FP64)
+    e0 = fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q), forces=False)[0]
+    # moving atoms by whole box vectors changes nothing (positions are wrapped)
+    pos = w.pos.copy()
+    pos[::7] += w.box * np.array([1.0, -2.0, 3.0])
+    e1 = fmm.fmm_energy_forces(plan, _t(pos), _t(w.q), forces=False)[0]
+    assert e1 == e0
+    # a rigid translation changes only the truncation error
+    e2 = fmm.fmm_energy_forces(plan, _t(w.pos + np.array([0.37, -1.1, 2.9])), _t(w.q), forces=False)[0]
+    assert e2 == pytest.approx(e0, rel=1e-6)
+
+
+# ------------------------------------------------------------- edge cases ---
+def test_edge_cases(fmm):
+    import torch
+    plan = _plan(fmm, 10.0, 2, 6, fmm.FMM_FP64)
+    # n = 0
+    e, f, _ = fmm.fmm_energy_forces(plan, torch.zeros((0, 3), dtype=torch.float64, device="cuda"),
+                                    torch.zeros((0,), dtype=torch.float64, device="cuda"))
+    assert e == 0.0
+    # solute-solvent on an empty system
+    assert fmm.fmm_solute_solvent_energy(plan, torch.zeros((0,), dtype=torch.uint8, device="cuda")) == 0.0
+    # all atoms in one leaf
+    rng = np.random.default_rng(7)
+    pos = rng.uniform(0.1, 2.4, (200, 3))
+    q = rng.uniform(-1, 1, 200)
+    e, f, ph = fmm.fmm_energy_forces(plan, _t(pos), _t(q), phi=True)
+    o = oracle.ewald(pos, q, 10.0)
+    assert abs(e - o["terms"]["total"]) / abs(o["terms"]["total"]) < 1e-6
+    assert rms_rel(f.cpu().numpy(), o["force"]) < 1e-5
+    # an all-solvent and an all-solute mask give zero interaction
+    assert fmm.fmm_solute_solvent_energy(plan, _t(np.zeros(200, np.uint8))) == pytest.approx(0.0, abs=1e-12)
+    assert fmm.fmm_solute_solvent_energy(plan, _t(np.ones(200, np.uint8))) == pytest.approx(0.0, abs=1e-9)
+    # non-finite input is rejected
+    bad = pos.copy(); bad[3, 1] = np.nan
+    with pytest.raises(fmm.FmmError) as ei:
+        fmm.fmm_energy_forces(plan, _t(bad), _t(q))
+    assert ei.value.status == fmm.binding.FMM_ERR_INVALID
+    # solute-solvent without a valid preceding evaluation
+    with pytest.raises(fmm.FmmError) as ei:
+        fmm.fmm_solute_solvent_energy(plan, _t(np.zeros(200, np.uint8)))
+    assert ei.value.status == fmm.binding.FMM_ERR_STATE
+    # ragged sizes: n not a multiple of any tile, tiny systems
+    plan = _plan(fmm, 10.0, 2, 12, fmm.FMM_FP64)
+    for n in (1, 2, 3, 65, 257):
+        pos, q = workloads.random_charges(n, 10.0, seed=100 + n, net=0.3)
+        e, f, _ = fmm.fmm_energy_forces(plan, _t(pos), _t(q))
+        E = oracle.ewald(pos, q, 10.0)["terms"]["total"]
+        assert abs(e - E) <= 1e-6 * max(1.0, abs(E))
+
+
+def test_error_falls_with_order(fmm):
+    # the paper's accuracy experiment (error vs n_max, one ion in 1080 waters,
+    # l_max = 3) on the synthetic analog: the error drops geometrically with p
+    w = workloads.config("PA")
+    o = oracle.ewald(w.pos, w.q, w.box)
+    E = o["terms"]["total"]
+    errs = []
+    for p in (2, 4, 6, 8, 10):
+        plan = _plan(fmm, w.box, w.levels, p, fmm.FMM_FP64)
+        e = fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q), forces=False)[0]
+        errs.append(abs(e - E) / abs(E))
+    print("relative energy error vs p (2,4,6,8,10):", errs)
+    assert errs[1] < 1e-5 and errs[2] < 1e-6
+    assert errs[4] < errs[2] < errs[0]
+
+
+# ------------------------------------------------ the 1M-atom benchmark box --
+@pytest.mark.parametrize("prec,tol", [(1, 1e-5), (0, 1e-6)])
+def test_c3_sample_parity(fmm, prec, tol):
+    # the benchmark configuration (levels 5, p 12, launch configuration of
+    # bench.py): potential and force on the seeded 2,000-atom sample (plus the
+    # ion) against the oracle values stored by tests/golden/make_c3_sample.py
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "c3_sample_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/c3_sample_oracle.npz not generated")
+    ref = np.load(path)
+    w = workloads.config("C3")
+    idx = ref["idx"]
+    np.testing.assert_array_equal(idx[:-1], np.sort(workloads.sample_indices(w.n, 2000, w.seed)))
+    plan = _plan(fmm, w.box, w.levels, w.p, prec)
+    e, f, ph = fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q), forces=True, phi=True)
+    f = f.cpu().numpy()[idx]
+    ph = ph.cpu().numpy()[idx]
+    ef, ep = rms_rel(f, ref["force"]), rms_rel(ph, ref["phi"])
+    print(f"C3 prec={prec}: force rms rel {ef:.2e}, phi rms rel {ep:.2e}, ion phi {ph[-1]:.8f} vs {ref['phi'][-1]:.8f}")
+    assert ef < tol and ep < tol
+    assert abs(ph[-1] - ref["phi"][-1]) < tol * abs(ref["phi"][-1])
