@@ -56,7 +56,7 @@ struct fmm_plan {
     std::string err;
 
     // host operators (FP64)
-    std::vector<double> m2mT, l2lT, latT;  // transposed [o][col][row], [col][row]
+    std::vector<double> latT;  // transposed [col][row]
     // T_0^0 of the unit box: the net-charge (monopole-monopole) lattice
     // constant, applied exactly in FP64 as phi += t00 Q / b instead of through
     // the level-0 operator, so it never passes through FP32 arrays
@@ -67,7 +67,8 @@ struct fmm_plan {
     Offsets offs;
 
     // device constants
-    DeviceBuf ops32, ops64, m2m, l2l, lat, il, offv;
+    DeviceBuf ops32, ops64, lat, il, offv;
+    DeviceBuf tree32, tree64;  // swizzled M2M (8) then L2L (8) octant operators
     // per-call workspace
     DeviceBuf key, count, cursor, start, perm, scan, xq, xq_u, xs, Mlev, Llev, M0, L0, m2l_part;
     DeviceBuf phi_nf, field_nf, phi_ff, field_ff, phi_u, field_u, nfuv, partials, scalars, flag;
@@ -250,26 +251,30 @@ extern "C" fmm_status fmm_plan(double box, int levels, int p, fmm_plan_t *out) {
     }
     pl->offs = build_offsets();
     const int K = pl->K;
-    pl->m2mT.assign((size_t)8 * K * K, 0.0);
-    pl->l2lT.assign((size_t)8 * K * K, 0.0);
-    std::vector<double> A((size_t)K * K);
-    for (int o = 0; o < 8; ++o) {
-        build_m2m_operator(p, o, A.data());
-        transpose_into(A.data(), K, pl->m2mT.data() + (size_t)o * K * K);
-        build_l2l_operator(p, o, A.data());
-        transpose_into(A.data(), K, pl->l2lT.data() + (size_t)o * K * K);
-    }
-    if (!pl->m2m.ensure(sizeof(double) * 8 * K * K) || !pl->l2l.ensure(sizeof(double) * 8 * K * K) ||
-        !pl->il.ensure(sizeof(int32_t) * 8 * kILSize) || !pl->offv.ensure(sizeof(int32_t) * 3 * kNumOffsets)) {
-        fail(pl, FMM_ERR_NOMEM, "fmm_plan: device allocation");
-        return bail(FMM_ERR_NOMEM);
-    }
-    if (hipMemcpy(pl->m2m.ptr, pl->m2mT.data(), sizeof(double) * 8 * K * K, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(pl->l2l.ptr, pl->l2lT.data(), sizeof(double) * 8 * K * K, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(pl->il.ptr, pl->offs.il.data(), sizeof(int32_t) * 8 * kILSize, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(pl->offv.ptr, pl->offs.vec.data(), sizeof(int32_t) * 3 * kNumOffsets, hipMemcpyHostToDevice) != hipSuccess) {
-        fail(pl, FMM_ERR_DEVICE, "fmm_plan: upload failed");
-        return bail(FMM_ERR_DEVICE);
+    {
+        // octant operators, row-major, M2M then L2L, swizzled for the matrix cores
+        std::vector<double> rm((size_t)16 * K * K);
+        for (int o = 0; o < 8; ++o) {
+            build_m2m_operator(p, o, rm.data() + (size_t)o * K * K);
+            build_l2l_operator(p, o, rm.data() + (size_t)(8 + o) * K * K);
+        }
+        const size_t ne = (size_t)16 * pl->Kp * pl->Kp;
+        std::vector<float> s32(ne);
+        std::vector<double> s64(ne);
+        swizzle_ops<float>(p, 16, rm.data(), s32.data());
+        swizzle_ops<double>(p, 16, rm.data(), s64.data());
+        if (!pl->tree32.ensure(ne * sizeof(float)) || !pl->tree64.ensure(ne * sizeof(double)) ||
+            !pl->il.ensure(sizeof(int32_t) * 8 * kILSize) || !pl->offv.ensure(sizeof(int32_t) * 3 * kNumOffsets)) {
+            fail(pl, FMM_ERR_NOMEM, "fmm_plan: device allocation");
+            return bail(FMM_ERR_NOMEM);
+        }
+        if (hipMemcpy(pl->tree32.ptr, s32.data(), ne * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(pl->tree64.ptr, s64.data(), ne * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(pl->il.ptr, pl->offs.il.data(), sizeof(int32_t) * 8 * kILSize, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(pl->offv.ptr, pl->offs.vec.data(), sizeof(int32_t) * 3 * kNumOffsets, hipMemcpyHostToDevice) != hipSuccess) {
+            fail(pl, FMM_ERR_DEVICE, "fmm_plan: upload failed");
+            return bail(FMM_ERR_DEVICE);
+        }
     }
     if ((st = upload_lattice(pl)) != FMM_OK) return bail(st);
     if (hipHostMalloc((void **)&pl->h_scalars, sizeof(double) * kScalars, hipHostMallocDefault) != hipSuccess) {
@@ -367,7 +372,13 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
     auto LT = [&](int l) { return reinterpret_cast<T *>(at(pl->Llev, l)); };
     auto MD = [&](int l) { return reinterpret_cast<double *>(at(pl->Mlev, l)); };
     auto LD = [&](int l) { return reinterpret_cast<double *>(at(pl->Llev, l)); };
-    const double *m2m = pl->m2m.as<double>(), *l2l = pl->l2l.as<double>();
+    // octant operators: M2M block first, L2L block second, in FP32 and FP64
+    const size_t blk = (size_t)8 * Kp * Kp;
+    const void *m2m32 = pl->tree32.as<float>(), *l2l32 = pl->tree32.as<float>() + blk;
+    const void *m2m64 = pl->tree64.as<double>(), *l2l64 = pl->tree64.as<double>() + blk;
+    auto m2m_ops = [&](bool fp64) { return fp64 ? m2m64 : m2m32; };
+    auto l2l_ops = [&](bool fp64) { return fp64 ? l2l64 : l2l32; };
+    constexpr bool TD = sizeof(T) == 8;
     stage_begin(pl, FMM_STAGE_P2M);
     HIPCHK(pl, launch_p2m<T>(level_cells(L), xq, pl->start.as<int32_t>(), MT(L), p, Kp, 1.0 / h_leaf, s), "P2M");
     stage_end(pl, FMM_STAGE_P2M);
@@ -375,13 +386,14 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
     for (int l = L - 1; l >= 1; --l) {
         const int64_t nc = level_cells(l);
         hipError_t e;
-        if (l > top) e = launch_m2m<T, T>(nc, MT(l + 1), MT(l), m2m, p, Kp, s);
-        else if (l + 1 > top) e = launch_m2m<T, double>(nc, MT(l + 1), MD(l), m2m, p, Kp, s);
-        else e = launch_m2m<double, double>(nc, MD(l + 1), MD(l), m2m, p, Kp, s);
+        if (l > top) e = launch_m2m_mfma<T, T>(nc, MT(l + 1), MT(l), m2m_ops(TD), p, Kp, s);
+        else if (l + 1 > top) e = launch_m2m_mfma<T, double>(nc, MT(l + 1), MD(l), m2m_ops(true), p, Kp, s);
+        else e = launch_m2m_mfma<double, double>(nc, MD(l + 1), MD(l), m2m_ops(true), p, Kp, s);
         HIPCHK(pl, e, "M2M");
     }
-    HIPCHK(pl, (top >= 1 ? launch_m2m<double, double>(1, MD(1), pl->M0.as<double>(), m2m, p, Kp, s)
-                         : launch_m2m<T, double>(1, MT(1), pl->M0.as<double>(), m2m, p, Kp, s)), "M2M");
+    HIPCHK(pl, (top >= 1 ? launch_m2m_mfma<double, double>(1, MD(1), pl->M0.as<double>(), m2m_ops(true), p, Kp, s)
+                         : launch_m2m_mfma<T, double>(1, MT(1), pl->M0.as<double>(), m2m_ops(true), p, Kp, s)),
+           "M2M");
     stage_end(pl, FMM_STAGE_M2M);
     stage_begin(pl, FMM_STAGE_LATTICE);
     HIPCHK(pl, launch_lattice(pl->M0.as<double>(), pl->L0.as<double>(), pl->lat.as<double>(), p, Kp, s), "lattice");
@@ -402,14 +414,15 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
     }
     stage_end(pl, FMM_STAGE_M2L);
     stage_begin(pl, FMM_STAGE_L2L);
-    HIPCHK(pl, (top >= 1 ? launch_l2l<double, double>(level_cells(1), pl->L0.as<double>(), LD(1), l2l, p, Kp, s)
-                         : launch_l2l<double, T>(level_cells(1), pl->L0.as<double>(), LT(1), l2l, p, Kp, s)), "L2L");
+    HIPCHK(pl, (top >= 1 ? launch_l2l_mfma<double, double>(1, pl->L0.as<double>(), LD(1), l2l_ops(true), p, Kp, s)
+                         : launch_l2l_mfma<double, T>(1, pl->L0.as<double>(), LT(1), l2l_ops(true), p, Kp, s)),
+           "L2L");
     for (int l = 2; l <= L; ++l) {
-        const int64_t nc = level_cells(l);
+        const int64_t np = level_cells(l - 1);  // parents
         hipError_t e;
-        if (l <= top) e = launch_l2l<double, double>(nc, LD(l - 1), LD(l), l2l, p, Kp, s);
-        else if (l - 1 <= top) e = launch_l2l<double, T>(nc, LD(l - 1), LT(l), l2l, p, Kp, s);
-        else e = launch_l2l<T, T>(nc, LT(l - 1), LT(l), l2l, p, Kp, s);
+        if (l <= top) e = launch_l2l_mfma<double, double>(np, LD(l - 1), LD(l), l2l_ops(true), p, Kp, s);
+        else if (l - 1 <= top) e = launch_l2l_mfma<double, T>(np, LD(l - 1), LT(l), l2l_ops(true), p, Kp, s);
+        else e = launch_l2l_mfma<T, T>(np, LT(l - 1), LT(l), l2l_ops(TD), p, Kp, s);
         HIPCHK(pl, e, "L2L");
     }
     stage_end(pl, FMM_STAGE_L2L);
@@ -421,6 +434,11 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
 }
 
 static int p2p_groups(int64_t n, int levels) {
+    static const int forced = [] {
+        const char *v = std::getenv("FMM_P2P_GROUPS");
+        return v ? std::atoi(v) : 0;
+    }();
+    if (forced == 1 || forced == 2 || forced == 4 || forced == 8 || forced == 16) return forced;
     const double occ = (double)n / (double)level_cells(levels);
     if (occ > 40.0) return 2;
     if (occ > 12.0) return 4;
@@ -684,7 +702,7 @@ extern "C" const char *fmm_last_error(fmm_plan_t pl) {
 
 extern "C" void fmm_destroy(fmm_plan_t pl) {
     if (!pl) return;
-    DeviceBuf *bufs[] = {&pl->ops32, &pl->ops64, &pl->m2m, &pl->l2l, &pl->lat, &pl->il, &pl->offv, &pl->key,
+    DeviceBuf *bufs[] = {&pl->ops32, &pl->ops64, &pl->tree32, &pl->tree64, &pl->lat, &pl->il, &pl->offv, &pl->key,
                          &pl->count, &pl->cursor, &pl->start, &pl->perm, &pl->scan, &pl->xq, &pl->xq_u, &pl->xs, &pl->m2l_part,
                          &pl->Mlev, &pl->Llev, &pl->M0, &pl->L0, &pl->phi_nf, &pl->field_nf, &pl->phi_ff,
                          &pl->field_ff, &pl->phi_u, &pl->field_u, &pl->nfuv, &pl->partials, &pl->scalars, &pl->flag};

@@ -101,12 +101,6 @@ hipError_t launch_mask_charges(int64_t n, const int32_t *perm, const uint8_t *ma
 template <typename T>
 hipError_t launch_p2m(int64_t nleaf, const void *xq, const int32_t *start, T *M, int p, int Kp,
                       double inv_h, hipStream_t s);
-template <typename Tin, typename Tout>
-hipError_t launch_m2m(int64_t nparent, const Tin *Mchild, Tout *Mparent, const double *opsT, int p,
-                      int Kp, hipStream_t s);
-template <typename Tin, typename Tout>
-hipError_t launch_l2l(int64_t nchild, const Tin *Lparent, Tout *Lchild, const double *opsT, int p,
-                      int Kp, hipStream_t s);
 hipError_t launch_lattice(const double *M0, double *L0, const double *AT, int p, int Kp,
                           hipStream_t s);
 template <typename T>
@@ -125,6 +119,18 @@ template <typename T>
 size_t m2l_ops_elems(int p);  // element count of the swizzled operator array
 template <typename T>
 void swizzle_m2l_ops(int p, const double *ops_rowmajor /*1206 x K x K*/, T *out);
+// any nops row-major K x K operators into the matrix-core lane order
+template <typename T>
+void swizzle_ops(int p, int nops, const double *ops_rowmajor, T *out);
+
+// k_tree.hip: M2M / L2L on the matrix cores; ops = 8 swizzled octant
+// operators in the compute precision (FP64 if either side is FP64)
+template <typename Tin, typename Tout>
+hipError_t launch_m2m_mfma(int64_t nparent, const Tin *Mchild, Tout *Mparent, const void *ops, int p,
+                           int Kp, hipStream_t s);
+template <typename Tin, typename Tout>
+hipError_t launch_l2l_mfma(int64_t nparent, const Tin *Lparent, Tout *Lchild, const void *ops, int p,
+                           int Kp, hipStream_t s);
 
 // k_p2p.hip
 template <typename T>

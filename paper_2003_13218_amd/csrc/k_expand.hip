@@ -1,6 +1,7 @@
-// Stages a3 (P2M), a4 (M2M), a5 (lattice operator at level 0), a7 (L2L) and
-// a8 (L2P with gradient) of the far field (Appendix B: eqs. P2M, EqFF; the
-// level-0 image-lattice sum of eq. 12).
+// Stages a3 (P2M), a5 (lattice operator at level 0) and a8 (L2P with
+// gradient) of the far field (Appendix B: eqs. P2M, EqFF; the level-0
+// image-lattice sum of eq. 12).  M2M and L2L run on the matrix cores
+// (k_tree.hip).
 //
 // Storage and scaling conventions are those of fmm_internal.h: real storage
 // of the normalised harmonics, expansions at each level scaled by the cell
@@ -155,100 +156,13 @@ template hipError_t launch_p2m<float>(int64_t, const void *, const int32_t *, fl
 template hipError_t launch_p2m<double>(int64_t, const void *, const int32_t *, double *, int, int, double,
                                        hipStream_t);
 
-// ---------------------------------------------------------------------------
-// M2M: M~(parent) = sum over the 8 child octants of A_o M~(child 8P + o).
-// One thread per (parent, row); A_o stored transposed [o][col][row] (FP64) so
-// a wavefront reads consecutive rows.  Only columns of degree <= the row's
-// degree are non-zero.  FP64 arithmetic.
-// ---------------------------------------------------------------------------
+// degree n of the real storage index idx (n^2 <= idx < (n+1)^2)
 __device__ inline int degree_of(int idx) {
     int n = (int)sqrtf((float)idx);
     while ((n + 1) * (n + 1) <= idx) ++n;
     while (n * n > idx) --n;
     return n;
 }
-
-template <typename Tin, typename Tout>
-__global__ void k_m2m(int64_t nparent, const Tin *__restrict__ Mc, Tout *__restrict__ Mp,
-                      const double *__restrict__ opsT, int K, int Kp) {
-    const int64_t total = nparent * Kp;
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
-         g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t P = g / Kp;
-        const int row = (int)(g - P * Kp);
-        double acc = 0.0;
-        if (row < K) {
-            const int n = degree_of(row);
-            const int cend = (n + 1) * (n + 1);
-            for (int o = 0; o < 8; ++o) {
-                const Tin *src = Mc + (8 * P + o) * Kp;
-                const double *A = opsT + (size_t)o * K * K + row;
-                for (int c = 0; c < cend; ++c) acc += A[(size_t)c * K] * (double)src[c];
-            }
-        }
-        Mp[P * Kp + row] = (Tout)acc;
-    }
-}
-
-template <typename Tin, typename Tout>
-hipError_t launch_m2m(int64_t nparent, const Tin *Mchild, Tout *Mparent, const double *opsT, int p,
-                      int Kp, hipStream_t s) {
-    const int K = num_coeffs(p);
-    int64_t total = nparent * Kp;
-    int64_t g = (total + 255) / 256;
-    if (g > 1048576) g = 1048576;
-    hipLaunchKernelGGL((k_m2m<Tin, Tout>), dim3((unsigned)g), dim3(256), 0, s, nparent, Mchild, Mparent,
-                       opsT, K, Kp);
-    return hipGetLastError();
-}
-template hipError_t launch_m2m<float, float>(int64_t, const float *, float *, const double *, int, int,
-                                             hipStream_t);
-template hipError_t launch_m2m<float, double>(int64_t, const float *, double *, const double *, int, int,
-                                              hipStream_t);
-template hipError_t launch_m2m<double, double>(int64_t, const double *, double *, const double *, int,
-                                               int, hipStream_t);
-
-// ---------------------------------------------------------------------------
-// L2L (merge): L~(child 8P + o) += A_o L~(P).  Columns of degree >= the
-// row's degree.  FP64 arithmetic.
-// ---------------------------------------------------------------------------
-template <typename Tin, typename Tout>
-__global__ void k_l2l(int64_t nchild, const Tin *__restrict__ Lp, Tout *__restrict__ Lc,
-                      const double *__restrict__ opsT, int K, int Kp) {
-    const int64_t total = nchild * Kp;
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total;
-         g += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t C = g / Kp;
-        const int row = (int)(g - C * Kp);
-        if (row >= K) continue;
-        const int64_t P = C >> 3;
-        const int o = (int)(C & 7);
-        const int n = degree_of(row);
-        const Tin *src = Lp + P * Kp;
-        const double *A = opsT + (size_t)o * K * K + row;
-        double acc = 0.0;
-        for (int c = n * n; c < K; ++c) acc += A[(size_t)c * K] * (double)src[c];
-        Lc[C * Kp + row] = (Tout)((double)Lc[C * Kp + row] + acc);
-    }
-}
-
-template <typename Tin, typename Tout>
-hipError_t launch_l2l(int64_t nchild, const Tin *Lparent, Tout *Lchild, const double *opsT, int p,
-                      int Kp, hipStream_t s) {
-    const int K = num_coeffs(p);
-    int64_t total = nchild * Kp;
-    int64_t g = (total + 255) / 256;
-    if (g > 1048576) g = 1048576;
-    hipLaunchKernelGGL((k_l2l<Tin, Tout>), dim3((unsigned)g), dim3(256), 0, s, nchild, Lparent, Lchild,
-                       opsT, K, Kp);
-    return hipGetLastError();
-}
-template hipError_t launch_l2l<double, float>(int64_t, const double *, float *, const double *, int, int,
-                                              hipStream_t);
-template hipError_t launch_l2l<float, float>(int64_t, const float *, float *, const double *, int, int,
-                                             hipStream_t);
-template hipError_t launch_l2l<double, double>(int64_t, const double *, double *, const double *, int,
-                                               int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Level 0 (eq. 12 applied through eq. Lcoeffdef): L~(0) = A_T M~(0), FP64.

@@ -22,32 +22,10 @@
 //     dispatch of workgroups to the 8 XCDs every XCD streams one class's 875
 //     operators through its own L2.
 #include "fmm_internal.h"
+#include "mfma.h"
 #include "morton.h"
 
 namespace fmm {
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-template <typename T> struct Mfma;
-template <> struct Mfma<float> {
-    using V = f32x4;
-    static constexpr int CB = 2;  // column blocks of 16 target cells per workgroup
-    __device__ static inline V mma(float a, float b, V c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    // row of the 16x16 result held by (lane, register r); the column is lane % 16
-    __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-};
-template <> struct Mfma<double> {
-    using V = f64x4;
-    static constexpr int CB = 1;
-    __device__ static inline V mma(double a, double b, V c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    // the f64 variant interleaves result rows across registers
-    __device__ static inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
-};
 
 constexpr int kRowBlocksPerWave = 11;  // 176 rows: K <= 169 (p <= 12) in one row group
 
@@ -62,10 +40,10 @@ template size_t m2l_ops_elems<double>(int);
 // out[(((oid * NKC + kc) * NRB + rb) * 64 + lane) * 4 + j] =
 //     O_oid[row = 16 rb + lane % 16][col = 16 kc + 4 (lane / 16) + j]
 template <typename T>
-void swizzle_m2l_ops(int p, const double *ops, T *out) {
+void swizzle_ops(int p, int nops, const double *ops, T *out) {
     const int K = num_coeffs(p), Kp = padded_coeffs(p);
     const int NB = Kp / 16;
-    for (int oid = 0; oid < kNumOffsets; ++oid) {
+    for (int oid = 0; oid < nops; ++oid) {
         const double *A = ops + (size_t)oid * K * K;
         for (int kc = 0; kc < NB; ++kc)
             for (int rb = 0; rb < NB; ++rb)
@@ -77,6 +55,13 @@ void swizzle_m2l_ops(int p, const double *ops, T *out) {
                         out[((((size_t)oid * NB + kc) * NB + rb) * 64 + lane) * 4 + j] = (T)v;
                     }
     }
+}
+template void swizzle_ops<float>(int, int, const double *, float *);
+template void swizzle_ops<double>(int, int, const double *, double *);
+
+template <typename T>
+void swizzle_m2l_ops(int p, const double *ops, T *out) {
+    swizzle_ops<T>(p, kNumOffsets, ops, out);
 }
 template void swizzle_m2l_ops<float>(int, const double *, float *);
 template void swizzle_m2l_ops<double>(int, const double *, double *);
