@@ -71,6 +71,7 @@ struct fmm_plan {
     DeviceBuf tree32, tree64;  // swizzled M2M (8) then L2L (8) octant operators
     // per-call workspace
     DeviceBuf key, count, cursor, start, perm, scan, xq, xq_u, xs, Mlev, Llev, M0, L0, m2l_part;
+    DeviceBuf pstart, xqp;  // near-field copy of xq, leaves padded to the P2P group count
     DeviceBuf phi_nf, field_nf, phi_ff, field_ff, phi_u, field_u, nfuv, partials, scalars, flag;
     double *h_scalars = nullptr;  // pinned host mirror of `scalars`
     int64_t cap_n = -1;
@@ -317,6 +318,7 @@ static fmm_status ensure_workspace(fmm_plan_t pl, int64_t n) {
             !pl->m2l_part.ensure(sizeof(double) * (size_t)std::max<int64_t>(part, 1) * pl->Kp) ||
             !pl->L0.ensure(sizeof(double) * pl->Kp) || !pl->count.ensure(sizeof(uint32_t) * nleaf) ||
             !pl->cursor.ensure(sizeof(uint32_t) * nleaf) || !pl->start.ensure(sizeof(int32_t) * (nleaf + 1)) ||
+            !pl->pstart.ensure(sizeof(int32_t) * (nleaf + 1)) ||
             !pl->scan.ensure(sizeof(int32_t) * scan_scratch_len(nleaf)) ||
             !pl->scalars.ensure(sizeof(double) * kScalars) || !pl->flag.ensure(sizeof(int) * 4) ||
             !pl->partials.ensure(sizeof(double) * 2 * 5 * 1024))
@@ -328,6 +330,7 @@ static fmm_status ensure_workspace(fmm_plan_t pl, int64_t n) {
         if (!pl->key.ensure(sizeof(uint32_t) * nn) || !pl->perm.ensure(sizeof(int32_t) * nn) ||
             !pl->xq.ensure(sizeof(double) * 4 * nn) || !pl->xq_u.ensure(sizeof(double) * 4 * nn) ||
             !pl->xs.ensure(sizeof(double) * 4 * nn) ||
+            !pl->xqp.ensure(sizeof(double) * 4 * (nn + (size_t)kMaxP2PGroups * nleaf)) ||
             !pl->phi_nf.ensure(sizeof(double) * nn) || !pl->field_nf.ensure(sizeof(double) * 3 * nn) ||
             !pl->phi_ff.ensure(sizeof(double) * nn) || !pl->field_ff.ensure(sizeof(double) * 3 * nn) ||
             !pl->phi_u.ensure(sizeof(double) * nn) || !pl->field_u.ensure(sizeof(double) * 3 * nn) ||
@@ -438,7 +441,7 @@ static int p2p_groups(int64_t n, int levels) {
         const char *v = std::getenv("FMM_P2P_GROUPS");
         return v ? std::atoi(v) : 0;
     }();
-    if (forced == 1 || forced == 2 || forced == 4 || forced == 8 || forced == 16) return forced;
+    if (forced == 1 || forced == 2 || forced == 4 || forced == 8 || forced == kMaxP2PGroups) return forced;
     const double occ = (double)n / (double)level_cells(levels);
     if (occ > 40.0) return 2;
     if (occ > 12.0) return 4;
@@ -454,12 +457,21 @@ static fmm_status run_fields(fmm_plan_t pl, int64_t n, const double *pos, const 
     stage_begin(pl, FMM_STAGE_GATHER);
     HIPCHK(pl, launch_gather(n, pl->perm.as<int32_t>(), pos, q, pl->box, pl->levels, pl->prec == FMM_FP64,
                              pl->xq.ptr, pl->xs.as<double>(), s), "gather");
+    // near-field copy with leaves padded to a multiple of the P2P group count
+    // (the sort's cursor array is free again and holds the padded counts)
+    const int64_t nleaf = level_cells(pl->levels);
+    const int groups = p2p_groups(n, pl->levels);
+    HIPCHK(pl, launch_pad_counts(nleaf, pl->count.as<uint32_t>(), groups, pl->cursor.as<uint32_t>(), s), "pad");
+    HIPCHK(pl, launch_scan(pl->cursor.as<uint32_t>(), pl->pstart.as<int32_t>(), nleaf, pl->scan.as<int32_t>(),
+                           scan_scratch_len(nleaf), s), "scan");
+    HIPCHK(pl, launch_pad_gather(nleaf, pl->start.as<int32_t>(), pl->pstart.as<int32_t>(), pl->prec == FMM_FP64,
+                                 pl->xq.ptr, 16.0 * pl->box, pl->xqp.ptr, s), "pad gather");
     stage_end(pl, FMM_STAGE_GATHER);
     if ((st = far_field<T>(pl, pl->xq.ptr, pl->phi_ff.as<double>(), pl->field_ff.as<T>())) != FMM_OK) return st;
     const double h_leaf = pl->box / (double)(1 << pl->levels);
     stage_begin(pl, FMM_STAGE_P2P);
-    HIPCHK(pl, launch_p2p<T>(level_cells(pl->levels), pl->levels, pl->xq.ptr, pl->start.as<int32_t>(), h_leaf,
-                             pl->phi_nf.as<double>(), pl->field_nf.as<T>(), p2p_groups(n, pl->levels), s), "P2P");
+    HIPCHK(pl, launch_p2p<T>(nleaf, pl->levels, pl->xqp.ptr, pl->pstart.as<int32_t>(), pl->start.as<int32_t>(),
+                             h_leaf, pl->phi_nf.as<double>(), pl->field_nf.as<T>(), groups, s), "P2P");
     stage_end(pl, FMM_STAGE_P2P);
     return FMM_OK;
 }
@@ -703,7 +715,7 @@ extern "C" const char *fmm_last_error(fmm_plan_t pl) {
 extern "C" void fmm_destroy(fmm_plan_t pl) {
     if (!pl) return;
     DeviceBuf *bufs[] = {&pl->ops32, &pl->ops64, &pl->tree32, &pl->tree64, &pl->lat, &pl->il, &pl->offv, &pl->key,
-                         &pl->count, &pl->cursor, &pl->start, &pl->perm, &pl->scan, &pl->xq, &pl->xq_u, &pl->xs, &pl->m2l_part,
+                         &pl->count, &pl->cursor, &pl->start, &pl->pstart, &pl->xqp, &pl->perm, &pl->scan, &pl->xq, &pl->xq_u, &pl->xs, &pl->m2l_part,
                          &pl->Mlev, &pl->Llev, &pl->M0, &pl->L0, &pl->phi_nf, &pl->field_nf, &pl->phi_ff,
                          &pl->field_ff, &pl->phi_u, &pl->field_u, &pl->nfuv, &pl->partials, &pl->scalars, &pl->flag};
     for (DeviceBuf *b : bufs) b->release();

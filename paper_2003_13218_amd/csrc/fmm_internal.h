@@ -15,6 +15,7 @@ constexpr int kWS = 2;            // near field / well-separatedness: +-2 cells
 constexpr int kNumOffsets = 1206; // distinct M2L offsets: [-5,5]^3 minus [-2,2]^3
 constexpr int kILSize = 875;      // interaction list size per parity class
 constexpr int kMaxP = 20;
+constexpr int kMaxP2PGroups = 16;  // largest source-group count of the P2P kernel
 constexpr int kMaxLevels = 10;
 
 // ---------------------------------------------------------------------------
@@ -92,6 +93,9 @@ int64_t scan_scratch_len(int64_t n);
 hipError_t launch_scatter(int64_t n, const uint32_t *key, const int32_t *start, uint32_t *cursor,
                           int32_t *perm, hipStream_t s);
 hipError_t launch_cell_sort(int64_t nleaf, const int32_t *start, int32_t *perm, hipStream_t s);
+hipError_t launch_pad_counts(int64_t nleaf, const uint32_t *count, int G, uint32_t *pcount, hipStream_t s);
+hipError_t launch_pad_gather(int64_t nleaf, const int32_t *start, const int32_t *pstart, bool fp64,
+                             const void *xq, double far, void *xqp, hipStream_t s);
 hipError_t launch_gather(int64_t n, const int32_t *perm, const double *pos, const double *q,
                          double box, int levels, bool fp64, void *xq, double *xs, hipStream_t s);
 hipError_t launch_mask_charges(int64_t n, const int32_t *perm, const uint8_t *mask, bool fp64,
@@ -134,8 +138,8 @@ hipError_t launch_l2l_mfma(int64_t nparent, const Tin *Lparent, Tout *Lchild, co
 
 // k_p2p.hip
 template <typename T>
-hipError_t launch_p2p(int64_t nleaf, int levels, const void *xq, const int32_t *start, double h,
-                      double *phi, T *field, int groups, hipStream_t s);
+hipError_t launch_p2p(int64_t nleaf, int levels, const void *xqp, const int32_t *pstart, const int32_t *start,
+                      double h, double *phi, T *field, int groups, hipStream_t s);
 template <typename T>
 hipError_t launch_p2p_uv(int64_t n, int levels, const void *xq, const int32_t *start,
                          const int32_t *perm, const uint8_t *mask, double h, double *out_per_atom,

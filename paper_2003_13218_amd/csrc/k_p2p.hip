@@ -9,11 +9,16 @@
 // arithmetic stays at the scale of a few leaf edges.
 //
 // One wavefront per leaf.  The 64 lanes are split into TS = 64/G target
-// slots x G source groups: lane (a, g) takes target atom a of the current
-// target chunk and the source atoms j = g, g+G, ... of every neighbour leaf.
-// The G partial sums of a target are combined with cross-lane shuffles at the
-// end.  G is chosen from the mean leaf occupancy so both the target chunk and
-// the source stride stay nearly full.
+// slots x G source groups: lane (a, g) = lane (a G + g) takes target atom a
+// of the current target chunk and the source atoms j = g, g+G, ... of every
+// neighbour leaf.  Sources come from the padded copy xqp, in which every
+// leaf holds a multiple of G atoms (q = 0 padding far away), so all lanes
+// run the same trip count and the loop has no per-lane bounds test.  Each
+// lane sums a leaf's (about n/G) potential terms in the mode's precision
+// and adds that partial to an FP64 total, so rounding never accumulates over
+// the ~125 n terms of a potential; the field terms fall off as 1/r^2 and are
+// summed in the mode's precision.  The G partial sums of a target are
+// combined with cross-lane shuffles at the end.
 #include "fmm_internal.h"
 #include "morton.h"
 
@@ -23,58 +28,65 @@ template <typename T> __device__ inline T rsqrt_t(T x);
 template <> __device__ inline float rsqrt_t<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 template <> __device__ inline double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
 
+template <typename T> struct Vec4 { typedef T type __attribute__((ext_vector_type(4))); };
+
+// Potential and field at (ox, oy, oz) from the nk sources bp[0], bp[G], ...
+// SELF: the sources are the target's own leaf; skip the source at index self.
+template <typename T, int G, bool SELF>
+__device__ inline void p2p_leaf(const typename Vec4<T>::type *__restrict__ bp, int nk, T ox, T oy, T oz,
+                                const typename Vec4<T>::type *selfp, double &ph, T &fx, T &fy, T &fz) {
+    T pc = 0;
+#pragma unroll 4
+    for (int k = 0; k < nk; ++k) {
+        const typename Vec4<T>::type b = bp[k * G];
+        const T dx = ox - b.x, dy = oy - b.y, dz = oz - b.z;
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        T rinv = rsqrt_t<T>(r2);
+        if (SELF) rinv = (bp + k * G == selfp) ? (T)0 : rinv;
+        const T qr = b.w * rinv;
+        const T qr3 = qr * rinv * rinv;
+        pc += qr;
+        fx += qr3 * dx;
+        fy += qr3 * dy;
+        fz += qr3 * dz;
+    }
+    ph += (double)pc;
+}
+
 template <typename T, int G>
-__global__ __launch_bounds__(256) void k_p2p(int64_t nleaf, int levels, const T *__restrict__ xq,
-                                             const int32_t *__restrict__ start, T h,
-                                             double *__restrict__ phi, T *__restrict__ field) {
+__global__ __launch_bounds__(256) void k_p2p(int64_t nleaf, int levels, const T *__restrict__ xqp,
+                                             const int32_t *__restrict__ pstart, const int32_t *__restrict__ start,
+                                             T h, double *__restrict__ phi, T *__restrict__ field) {
+    using V4 = typename Vec4<T>::type;
     constexpr int TS = 64 / G;
     const int lane = threadIdx.x & 63;
-    const int64_t leaf = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    // wavefront-uniform leaf index: keeps the neighbour walk on the scalar unit
+    const int64_t leaf = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
     if (leaf >= nleaf) return;  // whole wavefront; no block barriers below
     const int g = lane % G;
     const int a = lane / G;
     uint32_t cx, cy, cz;
     demorton3((uint32_t)leaf, cx, cy, cz);
     const uint32_t nmask = (1u << levels) - 1u;
-    const int32_t s0 = start[leaf], s1 = start[leaf + 1];
-    for (int32_t base = s0; base < s1; base += TS) {
-        const int32_t si = base + a;
-        const bool act = si < s1;
-        T xi = 0, yi = 0, zi = 0;
-        if (act) {
-            xi = xq[4 * (int64_t)si + 0];
-            yi = xq[4 * (int64_t)si + 1];
-            zi = xq[4 * (int64_t)si + 2];
-        }
-        // the potential sums ~125 x (atoms per leaf) terms whose partial sums
-        // are O(1): it is accumulated in FP64 (an FP64 add costs one VALU
-        // slot, like an FP32 add); the field terms fall off as 1/r^2 and stay
-        // in the mode's precision
+    const V4 *X = reinterpret_cast<const V4 *>(xqp);
+    const int32_t s0 = start[leaf], cnt = start[leaf + 1] - s0;
+    const int32_t p0 = pstart[leaf], pcnt = pstart[leaf + 1] - p0;
+    for (int32_t tb = 0; tb < cnt; tb += TS) {
+        const int32_t t = tb + a;
+        const int32_t tl = min(t, pcnt - 1);  // lanes past the leaf redo its last slot, unstored
+        const V4 ti = X[p0 + tl];
         double ph = 0;
         T fx = 0, fy = 0, fz = 0;
-        for (int dx = -kWS; dx <= kWS; ++dx)
-            for (int dy = -kWS; dy <= kWS; ++dy)
-                for (int dz = -kWS; dz <= kWS; ++dz) {
-                    const uint32_t sc = morton3((cx + dx) & nmask, (cy + dy) & nmask, (cz + dz) & nmask);
-                    const int32_t j0 = start[sc], j1 = start[sc + 1];
-                    const T ox = xi - (T)dx * h, oy = yi - (T)dy * h, oz = zi - (T)dz * h;
-                    const bool center = (dx == 0 && dy == 0 && dz == 0);
-                    for (int32_t j = j0 + g; j < j1; j += G) {
-                        const T *b = xq + 4 * (int64_t)j;
-                        const T ddx = ox - b[0], ddy = oy - b[1], ddz = oz - b[2];
-                        const bool self = center && (j == si);
-                        const T qj = (self || !act) ? (T)0 : b[3];
-                        T r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-                        r2 = self ? (T)1 : r2;
-                        const T rinv = rsqrt_t<T>(r2);
-                        const T qr = qj * rinv;
-                        const T qr3 = qr * rinv * rinv;
-                        ph += (double)qr;
-                        fx += qr3 * ddx;
-                        fy += qr3 * ddy;
-                        fz += qr3 * ddz;
-                    }
-                }
+        p2p_leaf<T, G, true>(X + p0 + g, pcnt / G, ti.x, ti.y, ti.z, X + p0 + tl, ph, fx, fy, fz);
+        for (int c = 0; c < 125; ++c) {
+            if (c == 62) continue;  // offset (0, 0, 0): done above
+            const int dx = c / 25 - kWS, dy = (c / 5) % 5 - kWS, dz = c % 5 - kWS;
+            const uint32_t sc = morton3((cx + dx) & nmask, (cy + dy) & nmask, (cz + dz) & nmask);
+            const int32_t j0 = pstart[sc];
+            const int nk = (pstart[sc + 1] - j0) / G;
+            p2p_leaf<T, G, false>(X + j0 + g, nk, ti.x - (T)dx * h, ti.y - (T)dy * h, ti.z - (T)dz * h, nullptr,
+                                  ph, fx, fy, fz);
+        }
 #pragma unroll
         for (int m = 1; m < G; m <<= 1) {
             ph += __shfl_xor(ph, m);
@@ -82,34 +94,35 @@ __global__ __launch_bounds__(256) void k_p2p(int64_t nleaf, int levels, const T 
             fy += __shfl_xor(fy, m);
             fz += __shfl_xor(fz, m);
         }
-        if (act && g == 0) {
+        if (t < cnt && g == 0) {
+            const int64_t si = s0 + t;
             phi[si] = ph;
-            field[3 * (int64_t)si + 0] = fx;
-            field[3 * (int64_t)si + 1] = fy;
-            field[3 * (int64_t)si + 2] = fz;
+            field[3 * si + 0] = fx;
+            field[3 * si + 1] = fy;
+            field[3 * si + 2] = fz;
         }
     }
 }
 
 template <typename T>
-hipError_t launch_p2p(int64_t nleaf, int levels, const void *xq, const int32_t *start, double h, double *phi,
-                      T *field, int groups, hipStream_t s) {
+hipError_t launch_p2p(int64_t nleaf, int levels, const void *xqp, const int32_t *pstart, const int32_t *start,
+                      double h, double *phi, T *field, int groups, hipStream_t s) {
     const int64_t grid = (nleaf + 3) / 4;
-    const T *x = (const T *)xq;
+    const T *x = (const T *)xqp;
     switch (groups) {
-        case 1: hipLaunchKernelGGL((k_p2p<T, 1>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x, start, (T)h, phi, field); break;
-        case 2: hipLaunchKernelGGL((k_p2p<T, 2>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x, start, (T)h, phi, field); break;
-        case 4: hipLaunchKernelGGL((k_p2p<T, 4>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x, start, (T)h, phi, field); break;
-        case 8: hipLaunchKernelGGL((k_p2p<T, 8>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x, start, (T)h, phi, field); break;
-        case 16: hipLaunchKernelGGL((k_p2p<T, 16>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x, start, (T)h, phi, field); break;
+        case 1: hipLaunchKernelGGL((k_p2p<T, 1>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x, pstart, start, (T)h, phi, field); break;
+        case 2: hipLaunchKernelGGL((k_p2p<T, 2>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x, pstart, start, (T)h, phi, field); break;
+        case 4: hipLaunchKernelGGL((k_p2p<T, 4>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x, pstart, start, (T)h, phi, field); break;
+        case 8: hipLaunchKernelGGL((k_p2p<T, 8>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x, pstart, start, (T)h, phi, field); break;
+        case 16: hipLaunchKernelGGL((k_p2p<T, 16>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x, pstart, start, (T)h, phi, field); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
-template hipError_t launch_p2p<float>(int64_t, int, const void *, const int32_t *, double, double *, float *,
-                                      int, hipStream_t);
-template hipError_t launch_p2p<double>(int64_t, int, const void *, const int32_t *, double, double *,
-                                       double *, int, hipStream_t);
+template hipError_t launch_p2p<float>(int64_t, int, const void *, const int32_t *, const int32_t *, double,
+                                      double *, float *, int, hipStream_t);
+template hipError_t launch_p2p<double>(int64_t, int, const void *, const int32_t *, const int32_t *, double,
+                                       double *, double *, int, hipStream_t);
 
 // Near-field solute-solvent pairs: out[s] = q_s sum_{j in NF(s), solvent} q_j / r
 // for solute atoms s (0 for solvent).  One thread per sorted atom; FP64 sum

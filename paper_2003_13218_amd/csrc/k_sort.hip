@@ -279,6 +279,67 @@ hipError_t launch_gather(int64_t n, const int32_t *perm, const double *pos, cons
     return hipGetLastError();
 }
 
+// Near-field copy of xq with every leaf padded to a multiple of G atoms
+// (G = source groups of the P2P kernel), so the P2P inner loop needs no
+// per-lane bounds test.  Padding atoms have q = 0 and sit far outside the
+// leaf, where their terms vanish
+// without forming 0/0 (leaf-local coordinate `far` per axis, chosen by the
+// caller well beyond the reach of any shifted neighbour).
+// pcount[c] = round_up(count[c], G).
+__global__ void k_pad_counts(int64_t nleaf, const uint32_t *__restrict__ count, uint32_t G,
+                             uint32_t *__restrict__ pcount) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nleaf;
+         c += (int64_t)gridDim.x * blockDim.x)
+        pcount[c] = (count[c] + G - 1) / G * G;
+}
+
+hipError_t launch_pad_counts(int64_t nleaf, const uint32_t *count, int G, uint32_t *pcount, hipStream_t s) {
+    if (nleaf <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pad_counts, dim3(grid_for(nleaf, 256)), dim3(256), 0, s, nleaf, count, (uint32_t)G,
+                       pcount);
+    return hipGetLastError();
+}
+
+// one wavefront per leaf; lanes copy the leaf's slots
+template <typename T>
+__global__ __launch_bounds__(256) void k_pad_gather(int64_t nleaf, const int32_t *__restrict__ start,
+                                                    const int32_t *__restrict__ pstart, const T *__restrict__ xq,
+                                                    T far, T *__restrict__ xqp) {
+    const int64_t leaf = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (leaf >= nleaf) return;
+    const int lane = threadIdx.x & 63;
+    const int32_t s0 = start[leaf], cnt = start[leaf + 1] - s0;
+    const int32_t p0 = pstart[leaf], pcnt = pstart[leaf + 1] - p0;
+    for (int32_t t = lane; t < pcnt; t += 64) {
+        T *d = xqp + 4 * (int64_t)(p0 + t);
+        if (t < cnt) {
+            const T *src = xq + 4 * (int64_t)(s0 + t);
+            d[0] = src[0];
+            d[1] = src[1];
+            d[2] = src[2];
+            d[3] = src[3];
+        } else {
+            d[0] = far;
+            d[1] = far;
+            d[2] = far;
+            d[3] = (T)0;
+        }
+    }
+}
+
+hipError_t launch_pad_gather(int64_t nleaf, const int32_t *start, const int32_t *pstart, bool fp64,
+                             const void *xq, double far, void *xqp, hipStream_t s) {
+    if (nleaf <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)((nleaf + 3) / 4);
+    if (fp64)
+        hipLaunchKernelGGL(k_pad_gather<double>, dim3(grid), dim3(256), 0, s, nleaf, start, pstart,
+                           (const double *)xq, far, (double *)xqp);
+    else
+        hipLaunchKernelGGL(k_pad_gather<float>, dim3(grid), dim3(256), 0, s, nleaf, start, pstart,
+                           (const float *)xq, (float)far, (float *)xqp);
+    return hipGetLastError();
+}
+
 // Solute-only charges for the second far-field pass of the solute-solvent
 // scheme: xq_u = xq with q multiplied by the solute flag of the atom.
 template <typename T>
