@@ -53,10 +53,17 @@ typedef enum {
 typedef enum {
     /* everything in FP64 */
     FMM_FP64 = 0,
-    /* P2P, P2M, M2L, L2L (levels >= 1) and L2P in FP32 with cell-local
-     * coordinates; level-0 multipole, lattice operator, charged-system,
-     * quadrupole and dipole terms and the energy reduction in FP64 */
-    FMM_MIXED = 1
+    /* P2P, P2M, L2P and the expansions of levels >= 4 (their M2M, M2L and
+     * L2L) in FP32 with cell-local coordinates; the P2P potential and the
+     * leaf multipoles summed in FP64; levels 0-3, the lattice operator, the
+     * charged-system, quadrupole and dipole terms and the energy reduction
+     * in FP64 */
+    FMM_MIXED = 1,
+    /* as FMM_MIXED, but the FP32 levels' M2L takes BF16 operands (operators
+     * and multipoles rounded to bfloat16, 8 significant bits) with FP32
+     * accumulation on the matrix cores: a precision/speed trade-off whose
+     * far-field error is of the order of the BF16 unit roundoff 2^-8 */
+    FMM_MIXED_BF16_M2L = 2
 } fmm_precision;
 
 /*

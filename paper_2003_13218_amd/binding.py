@@ -21,6 +21,7 @@ FMM_ERR_DEVICE = -3
 FMM_ERR_STATE = -4
 FMM_FP64 = 0
 FMM_MIXED = 1
+FMM_MIXED_BF16_M2L = 2
 
 EXPORTED = (
     "fmm_plan", "fmm_plan_config", "fmm_energy_forces", "fmm_solute_solvent_energy",

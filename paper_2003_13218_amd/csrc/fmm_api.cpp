@@ -67,7 +67,7 @@ struct fmm_plan {
     Offsets offs;
 
     // device constants
-    DeviceBuf ops32, ops64, lat, il, offv;
+    DeviceBuf ops32, ops64, opsbf, lat, il, offv;  // opsbf: M2L operators as bfloat16
     DeviceBuf tree32, tree64;  // swizzled M2M (8) then L2L (8) octant operators
     // per-call workspace
     DeviceBuf key, count, cursor, start, perm, scan, xq, xq_u, xs, Mlev, Llev, M0, L0, m2l_part;
@@ -195,10 +195,18 @@ static int top_fp64_levels(fmm_plan_t pl) {
 static fmm_status ensure_m2l_ops(fmm_plan_t pl) {
     const bool need64 = top_fp64_levels(pl) > 0;
     const bool need32 = pl->prec == FMM_MIXED;
-    if ((!need64 || pl->ops64.ptr) && (!need32 || pl->ops32.ptr)) return FMM_OK;
+    const bool needbf = pl->prec == FMM_MIXED_BF16_M2L;
+    if ((!need64 || pl->ops64.ptr) && (!need32 || pl->ops32.ptr) && (!needbf || pl->opsbf.ptr)) return FMM_OK;
     std::vector<double> rm;
     build_m2l_all(pl->p, pl->offs, rm);
     const size_t ne = m2l_ops_elems<float>(pl->p);
+    if (needbf && !pl->opsbf.ptr) {
+        const size_t nb = m2l_bf16_ops_elems(pl->p);
+        std::vector<uint16_t> sw(nb);
+        swizzle_m2l_ops_bf16(pl->p, rm.data(), sw.data());
+        if (!pl->opsbf.ensure(nb * sizeof(uint16_t))) return fail(pl, FMM_ERR_NOMEM, "M2L operator allocation");
+        HIPCHK(pl, hipMemcpy(pl->opsbf.ptr, sw.data(), nb * sizeof(uint16_t), hipMemcpyHostToDevice), "M2L upload");
+    }
     if (need64 && !pl->ops64.ptr) {
         std::vector<double> sw(ne);
         swizzle_m2l_ops<double>(pl->p, rm.data(), sw.data());
@@ -289,7 +297,7 @@ extern "C" fmm_status fmm_plan(double box, int levels, int p, fmm_plan_t *out) {
 
 extern "C" fmm_status fmm_plan_config(fmm_plan_t pl, int precision, double kappa, void *hip_stream) {
     if (!pl) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan_config: plan is NULL");
-    if (precision != FMM_FP64 && precision != FMM_MIXED)
+    if (precision != FMM_FP64 && precision != FMM_MIXED && precision != FMM_MIXED_BF16_M2L)
         return fail(pl, FMM_ERR_INVALID, "fmm_plan_config: unknown precision");
     if (!std::isfinite(kappa)) return fail(pl, FMM_ERR_INVALID, "fmm_plan_config: kappa must be finite");
     pl->prec = precision;
@@ -408,6 +416,10 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
         if (l <= top)
             e = launch_m2l<double>(l, pl->ops64.as<double>(), pl->il.as<int32_t>(), pl->offv.as<int32_t>(), MD(l),
                                    LD(l), pl->m2l_part.as<double>(), p, Kp, s);
+        else if (!TD && pl->prec == FMM_MIXED_BF16_M2L)
+            e = launch_m2l_bf16(l, pl->opsbf.ptr, pl->il.as<int32_t>(), pl->offv.as<int32_t>(),
+                                reinterpret_cast<const float *>(MT(l)), reinterpret_cast<float *>(LT(l)),
+                                pl->m2l_part.as<float>(), p, Kp, s);
         else
             e = launch_m2l<T>(l, sizeof(T) == 8 ? (const T *)pl->ops64.ptr : (const T *)pl->ops32.ptr,
                               pl->il.as<int32_t>(), pl->offv.as<int32_t>(), MT(l), LT(l), pl->m2l_part.as<T>(), p,
@@ -714,7 +726,7 @@ extern "C" const char *fmm_last_error(fmm_plan_t pl) {
 
 extern "C" void fmm_destroy(fmm_plan_t pl) {
     if (!pl) return;
-    DeviceBuf *bufs[] = {&pl->ops32, &pl->ops64, &pl->tree32, &pl->tree64, &pl->lat, &pl->il, &pl->offv, &pl->key,
+    DeviceBuf *bufs[] = {&pl->ops32, &pl->ops64, &pl->opsbf, &pl->tree32, &pl->tree64, &pl->lat, &pl->il, &pl->offv, &pl->key,
                          &pl->count, &pl->cursor, &pl->start, &pl->pstart, &pl->xqp, &pl->perm, &pl->scan, &pl->xq, &pl->xq_u, &pl->xs, &pl->m2l_part,
                          &pl->Mlev, &pl->Llev, &pl->M0, &pl->L0, &pl->phi_nf, &pl->field_nf, &pl->phi_ff,
                          &pl->field_ff, &pl->phi_u, &pl->field_u, &pl->nfuv, &pl->partials, &pl->scalars, &pl->flag};

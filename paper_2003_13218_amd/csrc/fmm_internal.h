@@ -123,6 +123,12 @@ template <typename T>
 size_t m2l_ops_elems(int p);  // element count of the swizzled operator array
 template <typename T>
 void swizzle_m2l_ops(int p, const double *ops_rowmajor /*1206 x K x K*/, T *out);
+// M2L operators as bfloat16 (round to nearest even) in the lane order of
+// v_mfma_f32_16x16x32_bf16: [1206][NKC][NB][64 lanes][8], NKC = ceil(K/32)
+size_t m2l_bf16_ops_elems(int p);
+void swizzle_m2l_ops_bf16(int p, const double *ops_rowmajor, uint16_t *out);
+hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const int32_t *offs, const float *M,
+                           float *L, float *partial, int p, int Kp, hipStream_t s);
 // any nops row-major K x K operators into the matrix-core lane order
 template <typename T>
 void swizzle_ops(int p, int nops, const double *ops_rowmajor, T *out);

@@ -21,6 +21,8 @@
 //   * blockIdx mod 8 selects the parity class, so with the round-robin
 //     dispatch of workgroups to the 8 XCDs every XCD streams one class's 875
 //     operators through its own L2.
+#include <cstring>
+
 #include "fmm_internal.h"
 #include "mfma.h"
 #include "morton.h"
@@ -417,6 +419,240 @@ template <typename T> static bool use_lds_kernel(int level) {
     if (g_m2l_variant == 1) return false;
     if (g_m2l_variant == 2) return true;
     return true;  // default: LDS-shared kernel from level 4 on
+}
+
+// ---------------------------------------------------------------------------
+// M2L with BF16 operands (precision mode FMM_MIXED_BF16_M2L): the same
+// contraction L~_c += sum_t O_t M~_{c+t} on v_mfma_f32_16x16x32_bf16, which
+// takes 8 consecutive k values per lane: lane l holds
+//   A[l % 16][8 (l / 16) + i]  (operator rows, k)   and
+//   B[8 (l / 16) + i][l % 16]  (k, target columns),  i = 0..7,
+// and returns the 16x16 FP32 block with the layout of the FP32 instruction.
+// K is walked in chunks of 32 (NKC = ceil(K / 32)); the FP32 multipoles are
+// rounded to BF16 as they are loaded (coefficients past Kp read as 0).
+// Workgroup layout, LDS staging (U chunks per stage, double buffered) and
+// split-K are those of k_m2l_lds; accumulation stays in FP32 because the
+// BF16 operand rounding (2^-9 relative) dominates the error.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+static inline uint16_t bf16_round(double v) {
+    const float f = (float)v;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+static int bf16_chunks(int p) { return (num_coeffs(p) + 31) / 32; }
+
+size_t m2l_bf16_ops_elems(int p) {
+    return (size_t)kNumOffsets * bf16_chunks(p) * (padded_coeffs(p) / 16) * 64 * 8;
+}
+
+void swizzle_m2l_ops_bf16(int p, const double *ops, uint16_t *out) {
+    const int K = num_coeffs(p), NB = padded_coeffs(p) / 16, NKC = bf16_chunks(p);
+    for (int oid = 0; oid < kNumOffsets; ++oid) {
+        const double *A = ops + (size_t)oid * K * K;
+        for (int kc = 0; kc < NKC; ++kc)
+            for (int rb = 0; rb < NB; ++rb)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int i = 0; i < 8; ++i) {
+                        const int row = 16 * rb + (lane & 15);
+                        const int col = 32 * kc + 8 * (lane >> 4) + i;
+                        const double v = (row < K && col < K) ? A[(size_t)row * K + col] : 0.0;
+                        out[((((size_t)oid * NKC + kc) * NB + rb) * 64 + lane) * 8 + i] = bf16_round(v);
+                    }
+    }
+}
+
+constexpr int kBf16Stage = 3;  // K chunks per LDS stage
+
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void k_m2l_bf16(const bf16x8 *__restrict__ ops, const int32_t *__restrict__ il,
+                                                  const int32_t *__restrict__ offs, const float *__restrict__ M,
+                                                  float *__restrict__ L, int nh_bits, int NB, int NKC, int Kp,
+                                                  int nrg, int nslices_arg) {
+    const int nslices = SPLIT ? nslices_arg : 1;
+    constexpr int NRW = kRowBlocksPerWave;
+    constexpr int CHUNK = NRW * 64;  // 16-byte entries per chunk slot
+    constexpr int U = kBf16Stage;
+    constexpr int PER_T = (U * CHUNK + 255) / 256;
+    __shared__ bf16x8 lds[2][U * CHUNK];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    const int parity = blockIdx.x & 7;
+    int rest = blockIdx.x >> 3;
+    const int rg = rest % nrg;
+    rest /= nrg;
+    const int slice = rest % nslices;
+    const int tile = rest / nslices;
+    const int rb0 = rg * NRW;
+    const int nrb = min(NRW, NB - rb0);
+    const uint32_t ntarget = 1u << (3 * nh_bits);
+    const uint32_t nmask = (2u << nh_bits) - 1u;
+
+    const uint32_t P = (uint32_t)tile * 64 + (uint32_t)wid * 16 + (lane & 15);
+    const bool valid = P < ntarget;
+    uint32_t tx, ty, tz;
+    demorton3(valid ? P : 0u, tx, ty, tz);
+    tx = 2 * tx + ((parity >> 2) & 1);
+    ty = 2 * ty + ((parity >> 1) & 1);
+    tz = 2 * tz + (parity & 1);
+    const uint32_t tcell = 8 * P + (uint32_t)parity;
+
+    const int t0 = slice * kILSize / nslices, t1 = (slice + 1) * kILSize / nslices;
+    const int nchunk = (t1 - t0) * NKC;
+    const int nstage = (nchunk + U - 1) / U;
+    const size_t op_stride = (size_t)NKC * NB * 64;  // 16-byte entries per offset
+    const int32_t *ilp = il + parity * kILSize;
+    const int kq = 8 * (lane >> 4);  // this lane's k offset inside a chunk
+
+    struct Cursor {
+        int t, kc, oid;
+        const float *src;
+    };
+    auto set_t = [&](Cursor &c, int t) {
+        c.t = t;
+        c.kc = 0;
+        if (t >= t1) return;
+        c.oid = ilp[t];
+        const uint32_t sx = (tx + (uint32_t)offs[3 * c.oid]) & nmask;
+        const uint32_t sy = (ty + (uint32_t)offs[3 * c.oid + 1]) & nmask;
+        const uint32_t sz = (tz + (uint32_t)offs[3 * c.oid + 2]) & nmask;
+        c.src = M + (size_t)morton3(sx, sy, sz) * Kp + kq;
+    };
+    auto advance = [&](Cursor &c) {
+        if (++c.kc == NKC) set_t(c, c.t + 1);
+    };
+    auto load_b = [&](const Cursor &c) -> bf16x8 {
+        bf16x8 b;
+        if (32 * c.kc + kq < Kp) {
+            const f32x4 x = *reinterpret_cast<const f32x4 *>(c.src + 32 * c.kc);
+            const f32x4 y = *reinterpret_cast<const f32x4 *>(c.src + 32 * c.kc + 4);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                b[i] = (__bf16)x[i];
+                b[4 + i] = (__bf16)y[i];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) b[i] = (__bf16)0.0f;
+        }
+        return b;
+    };
+
+    f32x4 acc[NRW];
+#pragma unroll
+    for (int rb = 0; rb < NRW; ++rb) acc[rb] = f32x4{0, 0, 0, 0};
+
+    Cursor cc, pc;  // compute cursor, prefetch cursor
+    set_t(cc, t0);
+    set_t(pc, t0);
+    bf16x8 pre[PER_T];
+    bf16x8 bcur[U], bnext[U];
+    size_t base[U];  // first operator entry of each chunk of the prefetched stage
+    bool have[U];
+
+    // entry idx = tid + 256 v of a stage belongs to chunk slot idx / CHUNK
+    auto fetch_stage = [&](bf16x8 *dst_regs, bf16x8 *dst_lds, bf16x8 *bdst) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            have[u] = pc.t < t1;
+            if (have[u]) {
+                base[u] = (size_t)pc.oid * op_stride + ((size_t)pc.kc * NB + rb0) * 64;
+                bdst[u] = load_b(pc);
+                advance(pc);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < PER_T; ++v) {
+            const int idx = tid + 256 * v;
+            const int u = idx / CHUNK, e = idx % CHUNK;
+            if (u < U && e < nrb * 64 && have[u]) {
+                const bf16x8 x = ops[base[u] + e];
+                if (dst_lds) dst_lds[idx] = x;
+                else dst_regs[v] = x;
+            }
+        }
+    };
+
+    fetch_stage(nullptr, lds[0], bcur);
+    __syncthreads();
+
+    for (int st = 0; st < nstage; ++st) {
+        const int cur = st & 1;
+        const bool more = st + 1 < nstage;
+        bool hv[U];
+        if (more) {
+            fetch_stage(pre, nullptr, bnext);
+#pragma unroll
+            for (int u = 0; u < U; ++u) hv[u] = have[u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (cc.t < t1) {
+                bf16x8 a[NRW];
+#pragma unroll
+                for (int rb = 0; rb < NRW; ++rb)
+                    if (rb < nrb) a[rb] = lds[cur][u * CHUNK + rb * 64 + lane];
+#pragma unroll
+                for (int rb = 0; rb < NRW; ++rb)
+                    if (rb < nrb) acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], bcur[u], acc[rb], 0, 0, 0);
+                advance(cc);
+            }
+        }
+        if (more) {
+#pragma unroll
+            for (int v = 0; v < PER_T; ++v) {
+                const int idx = tid + 256 * v;
+                const int u = idx / CHUNK, e = idx % CHUNK;
+                if (u < U && e < nrb * 64 && hv[u]) lds[cur ^ 1][idx] = pre[v];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) bcur[u] = bnext[u];
+        }
+        __syncthreads();
+    }
+
+    if (!valid) return;
+    float *out = L + (size_t)slice * ((size_t)8 << (3 * nh_bits)) * Kp;
+#pragma unroll
+    for (int rb = 0; rb < NRW; ++rb)
+        if (rb < nrb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * (rb0 + rb) + Mfma<float>::row(lane, r);
+                out[(size_t)tcell * Kp + row] = acc[rb][r];
+            }
+}
+
+hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const int32_t *offs, const float *M,
+                           float *L, float *partial, int p, int Kp, hipStream_t s) {
+    const int NB = Kp / 16;
+    const int NKC = bf16_chunks(p);
+    const int nh_bits = level - 1;
+    const int64_t ntarget = (int64_t)1 << (3 * nh_bits);
+    const int nslices = partial ? m2l_slices(level) : 1;
+    const int nrg = (NB + kRowBlocksPerWave - 1) / kRowBlocksPerWave;
+    const int64_t ntile = (ntarget + 63) / 64;
+    const int64_t grid = 8 * ntile * nslices * nrg;
+    const bf16x8 *o = reinterpret_cast<const bf16x8 *>(ops);
+    if (nslices > 1)
+        hipLaunchKernelGGL((k_m2l_bf16<true>), dim3((unsigned)grid), dim3(256), 0, s, o, il, offs, M, partial,
+                           nh_bits, NB, NKC, Kp, nrg, nslices);
+    else
+        hipLaunchKernelGGL((k_m2l_bf16<false>), dim3((unsigned)grid), dim3(256), 0, s, o, il, offs, M, L, nh_bits,
+                           NB, NKC, Kp, nrg, 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nslices == 1) return e;
+    const int64_t elems = ((int64_t)8 << (3 * nh_bits)) * Kp;
+    int64_t g = (elems + 255) / 256;
+    if (g > 65535) g = 65535;
+    hipLaunchKernelGGL(k_m2l_reduce<float>, dim3((unsigned)g), dim3(256), 0, s, partial, L, nslices, elems);
+    return hipGetLastError();
 }
 
 template <typename T>

@@ -1,9 +1,10 @@
-"""Writes tests/golden/c3_sample_oracle.npz: the FP64 Ewald oracle's potential
-and force on the seeded 2,000-atom sample of the 1,000,000-atom box
-(333,333 waters + one -1 ion, b = 215.30 A), plus the sample indices and the
-Ewald parameters.  Calls only oracle/ and the seeded input generator.
+"""Writes tests/golden/<config>_sample_oracle.npz: the FP64 Ewald oracle's
+potential and force on the seeded 2,000-atom sample of a large box plus its
+ions, the sample indices and the Ewald parameters.  Calls only oracle/ and the
+seeded input generator.
 
-    python tests/golden/make_c3_sample.py
+    python tests/golden/make_c3_sample.py        # C3: 1,000,000 atoms, one -1 ion
+    python tests/golden/make_c3_sample.py C5     # C5: 3,000,008 atoms, 8 ions
 """
 import os
 import sys
@@ -21,8 +22,8 @@ import workloads  # noqa: E402
 def main(name="C3", k=2000):
     w = workloads.config(name)
     idx = workloads.sample_indices(w.n, k, w.seed)
-    ion = np.array([w.n - 1])
-    idx = np.unique(np.concatenate([idx, ion]))
+    ions = np.nonzero(w.mask)[0]
+    idx = np.unique(np.concatenate([idx, ions]))
     t = time.time()
     r = oracle.ewald(w.pos, w.q, w.box, eval_idx=idx, rcut=0.5 * w.box, accuracy=1e-13)
     dt = time.time() - t

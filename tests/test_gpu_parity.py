@@ -122,6 +122,22 @@ def test_c2_energy_forces(fmm, prec, tol):
     assert rms_rel(ph.cpu().numpy(), o["phi"]) < tol
 
 
+@pytest.mark.parametrize("prec,tol", [(0, 1e-6), (1, 1e-5)])
+def test_c2_order_16(fmm, prec, tol):
+    # p = 16 (the top order of the precision/order sweep): K = 289 spans two
+    # row groups of the M2L kernels and 19 row blocks in M2M / L2L, and the
+    # lattice tensor reaches degree 32
+    w, o = ewald_full("C2")
+    plan = _plan(fmm, w.box, w.levels, 16, prec)
+    e, f, ph = fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q), forces=True, phi=True)
+    E = o["terms"]["total"]
+    print(f"C2 p=16 prec={prec}: E rel {abs(e - E) / abs(E):.2e}, force {rms_rel(f.cpu().numpy(), o['force']):.2e}, "
+          f"phi {rms_rel(ph.cpu().numpy(), o['phi']):.2e}")
+    assert abs(e - E) / abs(E) < tol
+    assert rms_rel(f.cpu().numpy(), o["force"]) < tol
+    assert rms_rel(ph.cpu().numpy(), o["phi"]) < tol
+
+
 def uv_scale(w, mask):
     # The cross energy of a small solute is an interaction of a few atoms: its
     # error is that of the potential at those atoms, so it is measured in the
@@ -383,3 +399,29 @@ def test_c3_sample_parity(fmm, prec, tol):
     print(f"C3 prec={prec}: force rms rel {ef:.2e}, phi rms rel {ep:.2e}, ion phi {ph[-1]:.8f} vs {ref['phi'][-1]:.8f}")
     assert ef < tol and ep < tol
     assert abs(ph[-1] - ref["phi"][-1]) < tol * abs(ref["phi"][-1])
+
+
+def test_c3_sample_bf16_m2l(fmm):
+    # BF16-operand M2L at the FP32 levels (4 and 5): operators and multipoles
+    # are rounded to 8 significant bits (unit roundoff u = 2^-9) before the
+    # matrix-core products.  The potential is a sum of O(10^4) far-field
+    # terms of both signs per atom, so its error is u times their absolute
+    # sum rather than u times the potential; the bounds below (2^-5 for the
+    # potential, 2^-10 for the force, whose terms fall off one power faster)
+    # fix the order of magnitude, and the FP32 path must stay two orders
+    # below them.
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "c3_sample_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/c3_sample_oracle.npz not generated")
+    ref = np.load(path)
+    w = workloads.config("C3")
+    idx = ref["idx"]
+    plan = _plan(fmm, w.box, w.levels, w.p, fmm.FMM_MIXED_BF16_M2L)
+    e, f, ph = fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q), forces=True, phi=True)
+    ef = rms_rel(f.cpu().numpy()[idx], ref["force"])
+    ep = rms_rel(ph.cpu().numpy()[idx], ref["phi"])
+    print(f"C3 BF16 M2L: force rms rel {ef:.2e}, phi rms rel {ep:.2e}")
+    assert ef < 2.0 ** -10 and ep < 2.0 ** -5
+    # the BF16 error is a real rounding effect, not noise on top of FP32
+    assert ep > 1e-4
