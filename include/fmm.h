@@ -161,6 +161,54 @@ fmm_status fmm_bin(fmm_plan_t plan, int64_t n, const double *pos,
 fmm_status fmm_lattice_tensor(fmm_plan_t plan, double *out, int64_t cap);
 
 /*
+ * Batches of independent boxes -- e.g. the charging windows lambda_w of a
+ * free-energy calculation (the lambda-scaled solute-solvent interaction of
+ * eq. Vswucheme), each window its own periodic box with its own atom count
+ * and edge.  All boxes share the order p, the precision and the
+ * box-independent operators; each has its own tree depth.
+ *
+ * fmm_plan_batch -- nbox boxes of edges box[w] (host, nbox doubles).
+ *   levels: host nbox ints (1..10), or NULL to choose each depth from a cost
+ *           model of this library's P2P and M2L rates and natoms[w];
+ *   natoms: host nbox expected atom counts (used only when levels is NULL).
+ *   Default precision FMM_FP64; kappa is 3/box[w] per box (fmm_plan_config on
+ *   a batch plan takes kappa = 0).  The plan owns one HIP stream per box and
+ *   one of its own (used when the configured stream is NULL).
+ *
+ * fmm_energy_forces_batch -- energies of all boxes.  Box w holds the atoms
+ *   offsets[w] .. offsets[w+1]-1 (host, nbox + 1 non-decreasing int64) of
+ *   pos (device, x 3 FP64) and q (device FP64); energies: host out, nbox;
+ *   forces: device out (same rows as pos) or NULL.  The boxes run as
+ *   parallel branches of one HIP graph launch on the plan stream; the graph
+ *   is captured on the first call and replayed while offsets, the three
+ *   pointers and the precision stay the same (inputs may change in place).
+ *   Empty boxes give 0.  Caches the per-box state for
+ *
+ * fmm_solute_solvent_energy_batch -- e_uv[w] (host out, nbox) of every box
+ *   (see fmm_solute_solvent_energy) for mask (device, same rows as pos),
+ *   one graph launch.  FMM_ERR_STATE without a preceding
+ *   fmm_energy_forces_batch on this plan.
+ *
+ * fmm_autotune_batch -- times, on the given inputs, whole evaluations of
+ *   every box at depths L-1, L, L+1 around its current one and with 2, 4 and
+ *   8 P2P source groups, and keeps the fastest; forces_scratch: device, same
+ *   rows as pos x 3, or NULL.  fmm_batch_levels reports the chosen depths and
+ *   P2P group counts (0 = from the leaf occupancy), host nbox ints each, either
+ *   may be NULL.
+ *
+ * Single-box calls (fmm_energy_forces, fmm_bin, ...) reject a batch plan and
+ * the *_batch calls reject a single-box plan (FMM_ERR_INVALID).
+ */
+fmm_status fmm_plan_batch(int nbox, const double *box, const int64_t *natoms, const int *levels, int p,
+                          fmm_plan_t *out);
+fmm_status fmm_energy_forces_batch(fmm_plan_t plan, const int64_t *offsets, const double *pos, const double *q,
+                                   double *energies, double *forces);
+fmm_status fmm_solute_solvent_energy_batch(fmm_plan_t plan, const uint8_t *mask, double *e_uv);
+fmm_status fmm_autotune_batch(fmm_plan_t plan, const int64_t *offsets, const double *pos, const double *q,
+                              double *forces_scratch);
+fmm_status fmm_batch_levels(fmm_plan_t plan, int *levels, int *p2p_groups);
+
+/*
  * Stage timing.  fmm_profile(plan, 1) creates HIP events on the plan's stream
  * and from then on every fmm_energy_forces call records one event pair around
  * each stage group below and adds the elapsed milliseconds to per-stage

@@ -26,7 +26,8 @@ FMM_MIXED_BF16_M2L = 2
 EXPORTED = (
     "fmm_plan", "fmm_plan_config", "fmm_energy_forces", "fmm_solute_solvent_energy",
     "fmm_potential_parts", "fmm_bin", "fmm_lattice_tensor", "fmm_profile", "fmm_profile_read",
-    "fmm_last_error", "fmm_destroy", "fmm_version",
+    "fmm_last_error", "fmm_destroy", "fmm_version", "fmm_plan_batch", "fmm_energy_forces_batch",
+    "fmm_solute_solvent_energy_batch", "fmm_autotune_batch", "fmm_batch_levels",
 )
 
 STAGES = ("sort", "gather", "p2m", "m2m", "lattice", "m2l", "m2l_leaf", "l2l", "l2p", "p2p", "final", "total")
@@ -73,6 +74,16 @@ def load():
         lib.fmm_last_error.restype = ctypes.c_char_p
         lib.fmm_destroy.argtypes = [vp]
         lib.fmm_destroy.restype = None
+        lib.fmm_plan_batch.argtypes = [ci, vp, vp, vp, ci, ctypes.POINTER(vp)]
+        lib.fmm_plan_batch.restype = ci
+        lib.fmm_energy_forces_batch.argtypes = [vp, vp, vp, vp, vp, vp]
+        lib.fmm_energy_forces_batch.restype = ci
+        lib.fmm_solute_solvent_energy_batch.argtypes = [vp, vp, vp]
+        lib.fmm_solute_solvent_energy_batch.restype = ci
+        lib.fmm_autotune_batch.argtypes = [vp, vp, vp, vp, vp]
+        lib.fmm_autotune_batch.restype = ci
+        lib.fmm_batch_levels.argtypes = [vp, vp, vp]
+        lib.fmm_batch_levels.restype = ci
         lib.fmm_version.argtypes = []
         lib.fmm_version.restype = ctypes.c_char_p
         _lib = lib
@@ -111,6 +122,7 @@ class Plan:
         self.handle = handle
         self.box, self.levels, self.p = box, levels, p
         self.precision = FMM_FP64
+        self.nbox = 1  # boxes of a batch plan
 
     def __del__(self):
         try:
@@ -209,6 +221,73 @@ def fmm_profile_read(plan: Plan):
     calls = ctypes.c_int64()
     _check(load().fmm_profile_read(plan.handle, ms.ctypes.data_as(ctypes.c_void_p), ctypes.byref(calls)), plan)
     return dict(zip(STAGES, ms.tolist())), calls.value
+
+
+def _host(a, dtype):
+    import numpy as np
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def fmm_plan_batch(boxes, p: int, levels=None, natoms=None) -> Plan:
+    """Batch plan over len(boxes) independent boxes (see include/fmm.h)."""
+    import numpy as np
+    b = _host(boxes, np.float64)
+    lv = None if levels is None else _host(levels, np.int32)
+    na = None if natoms is None else _host(natoms, np.int64)
+    h = ctypes.c_void_p()
+    ptr = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    _check(load().fmm_plan_batch(int(b.size), ptr(b), ptr(na), ptr(lv), int(p), ctypes.byref(h)))
+    plan = Plan(h, b, None, p)
+    plan.nbox = int(b.size)
+    return plan
+
+
+def fmm_energy_forces_batch(plan: Plan, offsets, pos, q, forces=True):
+    """Returns (energies: numpy nbox, forces tensor or None)."""
+    import numpy as np
+    import torch
+    off = _host(offsets, np.int64)
+    if off.size != plan.nbox + 1:
+        raise ValueError(f"offsets needs {plan.nbox + 1} entries")
+    n = int(q.shape[0])
+    f = torch.empty((n, 3), dtype=torch.float64, device=q.device) if forces else None
+    e = np.zeros(plan.nbox)
+    _check(load().fmm_energy_forces_batch(plan.handle, off.ctypes.data_as(ctypes.c_void_p),
+                                          _dptr(pos, torch.float64, (3,), "pos"), _dptr(q, torch.float64, (), "q"),
+                                          e.ctypes.data_as(ctypes.c_void_p),
+                                          _dptr(f, torch.float64, (3,), "forces")), plan)
+    return e, f
+
+
+def fmm_solute_solvent_energy_batch(plan: Plan, mask):
+    import numpy as np
+    import torch
+    e = np.zeros(plan.nbox)
+    _check(load().fmm_solute_solvent_energy_batch(plan.handle, _dptr(mask, torch.uint8, (), "mask"),
+                                                  e.ctypes.data_as(ctypes.c_void_p)), plan)
+    return e
+
+
+def fmm_batch_levels(plan: Plan):
+    """Returns (tree depth per box, P2P source groups per box (0 = automatic))."""
+    import numpy as np
+    lv = np.zeros(plan.nbox, np.int32)
+    g = np.zeros(plan.nbox, np.int32)
+    _check(load().fmm_batch_levels(plan.handle, lv.ctypes.data_as(ctypes.c_void_p),
+                                   g.ctypes.data_as(ctypes.c_void_p)), plan)
+    return lv, g
+
+
+def fmm_autotune_batch(plan: Plan, offsets, pos, q):
+    """Times depth and P2P-group candidates per box; returns fmm_batch_levels."""
+    import numpy as np
+    import torch
+    off = _host(offsets, np.int64)
+    scratch = torch.empty((int(q.shape[0]), 3), dtype=torch.float64, device=q.device)
+    _check(load().fmm_autotune_batch(plan.handle, off.ctypes.data_as(ctypes.c_void_p),
+                                     _dptr(pos, torch.float64, (3,), "pos"), _dptr(q, torch.float64, (), "q"),
+                                     _dptr(scratch, torch.float64, (3,))), plan)
+    return fmm_batch_levels(plan)
 
 
 def fmm_destroy(plan: Plan):

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <memory>
 #include <thread>
 #include <vector>
 
@@ -39,6 +40,18 @@ struct DeviceBuf {
     template <typename T> T *as() const { return reinterpret_cast<T *>(ptr); }
 };
 
+// Device copies of the order-p operators that do not depend on the box.
+struct OpSet {
+    int p = 0;
+    Offsets offs;
+    DeviceBuf ops32, ops64, opsbf, il, offv;  // M2L (FP32 / FP64 / bfloat16), interaction lists
+    DeviceBuf tree32, tree64;                 // swizzled M2M (8) then L2L (8) octant operators
+    ~OpSet() {
+        DeviceBuf *b[] = {&ops32, &ops64, &opsbf, &il, &offv, &tree32, &tree64};
+        for (DeviceBuf *x : b) x->release();
+    }
+};
+
 struct Status {
     fmm_status code;
     std::string msg;
@@ -64,11 +77,11 @@ struct fmm_plan {
     int top_fp64 = 3;  // mixed mode: tree levels 1..3 in FP64 (see top_fp64_levels)
     double q_tree = 0.0;  // level-0 monopole of the last fmm_energy_forces tree
     std::vector<cplx> T;                  // lattice tensor, unit box
-    Offsets offs;
 
-    // device constants
-    DeviceBuf ops32, ops64, opsbf, lat, il, offv;  // opsbf: M2L operators as bfloat16
-    DeviceBuf tree32, tree64;  // swizzled M2M (8) then L2L (8) octant operators
+    // scale-invariant translation operators of order p, shared by every plan
+    // of a batch (they do not depend on the box)
+    std::shared_ptr<OpSet> op;
+    DeviceBuf lat;  // level-0 lattice operator (depends on kappa b)
     // per-call workspace
     DeviceBuf key, count, cursor, start, perm, scan, xq, xq_u, xs, Mlev, Llev, M0, L0, m2l_part;
     DeviceBuf pstart, xqp;  // near-field copy of xq, leaves padded to the P2P group count
@@ -87,6 +100,23 @@ struct fmm_plan {
     // state cached for fmm_solute_solvent_energy (sorted copies live in xq, xs)
     bool have_state = false;
     int64_t n_state = 0;
+    int p2p_g = 0;  // P2P source groups; 0 = chosen from the leaf occupancy
+
+    // batch plans (fmm_plan_batch): one sub-plan per box, run as parallel
+    // branches of one captured HIP graph per call signature
+    bool is_batch = false;
+    std::vector<fmm_plan_t> sub;
+    std::vector<int64_t> sub_natoms;  // atom counts the levels were chosen for
+    std::vector<hipStream_t> sub_stream;
+    std::vector<hipEvent_t> sub_done;
+    hipEvent_t fork = nullptr, input_ready = nullptr;
+    hipStream_t own_stream = nullptr;
+    struct Graph {
+        hipGraphExec_t exec = nullptr;
+        std::vector<int64_t> key;
+    } g_ef, g_uv;
+    std::vector<int64_t> batch_off;  // offsets of the last batch evaluation
+    bool batch_state = false;
 };
 
 static const int kScalars = 64;
@@ -117,6 +147,14 @@ static int64_t level_offset(int l) {
 }
 
 static bool rec_uploaded[64] = {false};
+
+static void batch_drop_graphs(fmm_plan_t pl) {
+    for (auto *g : {&pl->g_ef, &pl->g_uv}) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        g->exec = nullptr;
+        g->key.clear();
+    }
+}
 
 // Stage events: begin/end recorded on the plan stream when profiling.
 static void stage_begin(fmm_plan_t pl, int st) {
@@ -166,6 +204,41 @@ static void transpose_into(const double *A, int K, double *AT) {
         for (int c = 0; c < K; ++c) AT[(size_t)c * K + r] = A[(size_t)r * K + c];
 }
 
+// Offsets, interaction lists and the M2M / L2L operators of order p; the
+// M2L operators are added on first use (ensure_m2l_ops).
+static fmm_status make_opset(int p, std::shared_ptr<OpSet> &out, std::string &msg) {
+    auto op = std::make_shared<OpSet>();
+    op->p = p;
+    op->offs = build_offsets();
+    const int K = num_coeffs(p), Kp = padded_coeffs(p);
+    // octant operators, row-major, M2M then L2L, swizzled for the matrix cores
+    std::vector<double> rm((size_t)16 * K * K);
+    for (int o = 0; o < 8; ++o) {
+        build_m2m_operator(p, o, rm.data() + (size_t)o * K * K);
+        build_l2l_operator(p, o, rm.data() + (size_t)(8 + o) * K * K);
+    }
+    const size_t ne = (size_t)16 * Kp * Kp;
+    std::vector<float> s32(ne);
+    std::vector<double> s64(ne);
+    swizzle_ops<float>(p, 16, rm.data(), s32.data());
+    swizzle_ops<double>(p, 16, rm.data(), s64.data());
+    if (!op->tree32.ensure(ne * sizeof(float)) || !op->tree64.ensure(ne * sizeof(double)) ||
+        !op->il.ensure(sizeof(int32_t) * 8 * kILSize) || !op->offv.ensure(sizeof(int32_t) * 3 * kNumOffsets)) {
+        msg = "fmm_plan: device allocation";
+        return FMM_ERR_NOMEM;
+    }
+    if (hipMemcpy(op->tree32.ptr, s32.data(), ne * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(op->tree64.ptr, s64.data(), ne * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(op->il.ptr, op->offs.il.data(), sizeof(int32_t) * 8 * kILSize, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(op->offv.ptr, op->offs.vec.data(), sizeof(int32_t) * 3 * kNumOffsets, hipMemcpyHostToDevice) !=
+            hipSuccess) {
+        msg = "fmm_plan: upload failed";
+        return FMM_ERR_DEVICE;
+    }
+    out = op;
+    return FMM_OK;
+}
+
 static fmm_status upload_lattice(fmm_plan_t pl) {
     const int K = pl->K;
     pl->T.assign((size_t)(2 * pl->p + 1) * (2 * pl->p + 1), cplx(0.0));
@@ -196,34 +269,34 @@ static fmm_status ensure_m2l_ops(fmm_plan_t pl) {
     const bool need64 = top_fp64_levels(pl) > 0;
     const bool need32 = pl->prec == FMM_MIXED;
     const bool needbf = pl->prec == FMM_MIXED_BF16_M2L;
-    if ((!need64 || pl->ops64.ptr) && (!need32 || pl->ops32.ptr) && (!needbf || pl->opsbf.ptr)) return FMM_OK;
+    if ((!need64 || pl->op->ops64.ptr) && (!need32 || pl->op->ops32.ptr) && (!needbf || pl->op->opsbf.ptr)) return FMM_OK;
     std::vector<double> rm;
-    build_m2l_all(pl->p, pl->offs, rm);
+    build_m2l_all(pl->p, pl->op->offs, rm);
     const size_t ne = m2l_ops_elems<float>(pl->p);
-    if (needbf && !pl->opsbf.ptr) {
+    if (needbf && !pl->op->opsbf.ptr) {
         const size_t nb = m2l_bf16_ops_elems(pl->p);
         std::vector<uint16_t> sw(nb);
         swizzle_m2l_ops_bf16(pl->p, rm.data(), sw.data());
-        if (!pl->opsbf.ensure(nb * sizeof(uint16_t))) return fail(pl, FMM_ERR_NOMEM, "M2L operator allocation");
-        HIPCHK(pl, hipMemcpy(pl->opsbf.ptr, sw.data(), nb * sizeof(uint16_t), hipMemcpyHostToDevice), "M2L upload");
+        if (!pl->op->opsbf.ensure(nb * sizeof(uint16_t))) return fail(pl, FMM_ERR_NOMEM, "M2L operator allocation");
+        HIPCHK(pl, hipMemcpy(pl->op->opsbf.ptr, sw.data(), nb * sizeof(uint16_t), hipMemcpyHostToDevice), "M2L upload");
     }
-    if (need64 && !pl->ops64.ptr) {
+    if (need64 && !pl->op->ops64.ptr) {
         std::vector<double> sw(ne);
         swizzle_m2l_ops<double>(pl->p, rm.data(), sw.data());
-        if (!pl->ops64.ensure(ne * sizeof(double))) return fail(pl, FMM_ERR_NOMEM, "M2L operator allocation");
-        HIPCHK(pl, hipMemcpy(pl->ops64.ptr, sw.data(), ne * sizeof(double), hipMemcpyHostToDevice), "M2L upload");
+        if (!pl->op->ops64.ensure(ne * sizeof(double))) return fail(pl, FMM_ERR_NOMEM, "M2L operator allocation");
+        HIPCHK(pl, hipMemcpy(pl->op->ops64.ptr, sw.data(), ne * sizeof(double), hipMemcpyHostToDevice), "M2L upload");
     }
-    if (need32 && !pl->ops32.ptr) {
+    if (need32 && !pl->op->ops32.ptr) {
         std::vector<float> sw(ne);
         swizzle_m2l_ops<float>(pl->p, rm.data(), sw.data());
-        if (!pl->ops32.ensure(ne * sizeof(float))) return fail(pl, FMM_ERR_NOMEM, "M2L operator allocation");
-        HIPCHK(pl, hipMemcpy(pl->ops32.ptr, sw.data(), ne * sizeof(float), hipMemcpyHostToDevice), "M2L upload");
+        if (!pl->op->ops32.ensure(ne * sizeof(float))) return fail(pl, FMM_ERR_NOMEM, "M2L operator allocation");
+        HIPCHK(pl, hipMemcpy(pl->op->ops32.ptr, sw.data(), ne * sizeof(float), hipMemcpyHostToDevice), "M2L upload");
     }
     return FMM_OK;
 }
 
-extern "C" fmm_status fmm_plan(double box, int levels, int p, fmm_plan_t *out) {
-    if (!out) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan: out is NULL");
+static fmm_status plan_create(double box, int levels, int p, const std::shared_ptr<OpSet> &shared,
+                              fmm_plan_t *out) {
     *out = nullptr;
     if (!(box > 0.0) || !std::isfinite(box)) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan: box must be finite and > 0");
     if (levels < 1 || levels > kMaxLevels) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan: levels must be in [1, 10]");
@@ -258,31 +331,14 @@ extern "C" fmm_status fmm_plan(double box, int levels, int p, fmm_plan_t *out) {
         if (e != hipSuccess) { hip_fail(pl, e, "recurrence tables"); return bail(FMM_ERR_DEVICE); }
         rec_uploaded[pl->device] = true;
     }
-    pl->offs = build_offsets();
-    const int K = pl->K;
-    {
-        // octant operators, row-major, M2M then L2L, swizzled for the matrix cores
-        std::vector<double> rm((size_t)16 * K * K);
-        for (int o = 0; o < 8; ++o) {
-            build_m2m_operator(p, o, rm.data() + (size_t)o * K * K);
-            build_l2l_operator(p, o, rm.data() + (size_t)(8 + o) * K * K);
-        }
-        const size_t ne = (size_t)16 * pl->Kp * pl->Kp;
-        std::vector<float> s32(ne);
-        std::vector<double> s64(ne);
-        swizzle_ops<float>(p, 16, rm.data(), s32.data());
-        swizzle_ops<double>(p, 16, rm.data(), s64.data());
-        if (!pl->tree32.ensure(ne * sizeof(float)) || !pl->tree64.ensure(ne * sizeof(double)) ||
-            !pl->il.ensure(sizeof(int32_t) * 8 * kILSize) || !pl->offv.ensure(sizeof(int32_t) * 3 * kNumOffsets)) {
-            fail(pl, FMM_ERR_NOMEM, "fmm_plan: device allocation");
-            return bail(FMM_ERR_NOMEM);
-        }
-        if (hipMemcpy(pl->tree32.ptr, s32.data(), ne * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(pl->tree64.ptr, s64.data(), ne * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(pl->il.ptr, pl->offs.il.data(), sizeof(int32_t) * 8 * kILSize, hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(pl->offv.ptr, pl->offs.vec.data(), sizeof(int32_t) * 3 * kNumOffsets, hipMemcpyHostToDevice) != hipSuccess) {
-            fail(pl, FMM_ERR_DEVICE, "fmm_plan: upload failed");
-            return bail(FMM_ERR_DEVICE);
+    if (shared) {
+        pl->op = shared;
+    } else {
+        std::string msg;
+        fmm_status os = make_opset(p, pl->op, msg);
+        if (os != FMM_OK) {
+            fail(pl, os, msg);
+            return bail(os);
         }
     }
     if ((st = upload_lattice(pl)) != FMM_OK) return bail(st);
@@ -295,11 +351,28 @@ extern "C" fmm_status fmm_plan(double box, int levels, int p, fmm_plan_t *out) {
     return FMM_OK;
 }
 
+extern "C" fmm_status fmm_plan(double box, int levels, int p, fmm_plan_t *out) {
+    if (!out) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan: out is NULL");
+    return plan_create(box, levels, p, nullptr, out);
+}
+
 extern "C" fmm_status fmm_plan_config(fmm_plan_t pl, int precision, double kappa, void *hip_stream) {
     if (!pl) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan_config: plan is NULL");
     if (precision != FMM_FP64 && precision != FMM_MIXED && precision != FMM_MIXED_BF16_M2L)
         return fail(pl, FMM_ERR_INVALID, "fmm_plan_config: unknown precision");
     if (!std::isfinite(kappa)) return fail(pl, FMM_ERR_INVALID, "fmm_plan_config: kappa must be finite");
+    if (pl->is_batch) {
+        if (kappa != 0.0) return fail(pl, FMM_ERR_INVALID, "fmm_plan_config: a batch plan takes kappa = 0 (3/b per box)");
+        pl->prec = precision;
+        pl->stream = hip_stream ? (hipStream_t)hip_stream : pl->own_stream;
+        pl->batch_state = false;
+        for (fmm_plan_t b : pl->sub) {
+            b->prec = precision;
+            b->have_state = false;
+        }
+        batch_drop_graphs(pl);
+        return FMM_OK;
+    }
     pl->prec = precision;
     pl->stream = (hipStream_t)hip_stream;
     pl->have_state = false;
@@ -385,8 +458,8 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
     auto LD = [&](int l) { return reinterpret_cast<double *>(at(pl->Llev, l)); };
     // octant operators: M2M block first, L2L block second, in FP32 and FP64
     const size_t blk = (size_t)8 * Kp * Kp;
-    const void *m2m32 = pl->tree32.as<float>(), *l2l32 = pl->tree32.as<float>() + blk;
-    const void *m2m64 = pl->tree64.as<double>(), *l2l64 = pl->tree64.as<double>() + blk;
+    const void *m2m32 = pl->op->tree32.as<float>(), *l2l32 = pl->op->tree32.as<float>() + blk;
+    const void *m2m64 = pl->op->tree64.as<double>(), *l2l64 = pl->op->tree64.as<double>() + blk;
     auto m2m_ops = [&](bool fp64) { return fp64 ? m2m64 : m2m32; };
     auto l2l_ops = [&](bool fp64) { return fp64 ? l2l64 : l2l32; };
     constexpr bool TD = sizeof(T) == 8;
@@ -414,15 +487,15 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
         if (l == L) stage_begin(pl, FMM_STAGE_M2L_LEAF);
         hipError_t e;
         if (l <= top)
-            e = launch_m2l<double>(l, pl->ops64.as<double>(), pl->il.as<int32_t>(), pl->offv.as<int32_t>(), MD(l),
+            e = launch_m2l<double>(l, pl->op->ops64.as<double>(), pl->op->il.as<int32_t>(), pl->op->offv.as<int32_t>(), MD(l),
                                    LD(l), pl->m2l_part.as<double>(), p, Kp, s);
         else if (!TD && pl->prec == FMM_MIXED_BF16_M2L)
-            e = launch_m2l_bf16(l, pl->opsbf.ptr, pl->il.as<int32_t>(), pl->offv.as<int32_t>(),
+            e = launch_m2l_bf16(l, pl->op->opsbf.ptr, pl->op->il.as<int32_t>(), pl->op->offv.as<int32_t>(),
                                 reinterpret_cast<const float *>(MT(l)), reinterpret_cast<float *>(LT(l)),
                                 pl->m2l_part.as<float>(), p, Kp, s);
         else
-            e = launch_m2l<T>(l, sizeof(T) == 8 ? (const T *)pl->ops64.ptr : (const T *)pl->ops32.ptr,
-                              pl->il.as<int32_t>(), pl->offv.as<int32_t>(), MT(l), LT(l), pl->m2l_part.as<T>(), p,
+            e = launch_m2l<T>(l, sizeof(T) == 8 ? (const T *)pl->op->ops64.ptr : (const T *)pl->op->ops32.ptr,
+                              pl->op->il.as<int32_t>(), pl->op->offv.as<int32_t>(), MT(l), LT(l), pl->m2l_part.as<T>(), p,
                               Kp, s);
         HIPCHK(pl, e, "M2L");
         if (l == L) stage_end(pl, FMM_STAGE_M2L_LEAF);
@@ -472,7 +545,7 @@ static fmm_status run_fields(fmm_plan_t pl, int64_t n, const double *pos, const 
     // near-field copy with leaves padded to a multiple of the P2P group count
     // (the sort's cursor array is free again and holds the padded counts)
     const int64_t nleaf = level_cells(pl->levels);
-    const int groups = p2p_groups(n, pl->levels);
+    const int groups = pl->p2p_g ? pl->p2p_g : p2p_groups(n, pl->levels);
     HIPCHK(pl, launch_pad_counts(nleaf, pl->count.as<uint32_t>(), groups, pl->cursor.as<uint32_t>(), s), "pad");
     HIPCHK(pl, launch_scan(pl->cursor.as<uint32_t>(), pl->pstart.as<int32_t>(), nleaf, pl->scan.as<int32_t>(),
                            scan_scratch_len(nleaf), s), "scan");
@@ -490,27 +563,40 @@ static fmm_status run_fields(fmm_plan_t pl, int64_t n, const double *pos, const 
 
 static fmm_status check_eval_args(fmm_plan_t pl, int64_t n, const double *pos, const double *q) {
     if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    if (pl->is_batch) return fail(pl, FMM_ERR_INVALID, "batch plan: use the *_batch calls");
     if (n < 0 || n >= ((int64_t)1 << 31)) return fail(pl, FMM_ERR_INVALID, "n must be in [0, 2^31)");
     if (n > 0 && (!pos || !q)) return fail(pl, FMM_ERR_INVALID, "pos and q must be non-NULL when n > 0");
     return FMM_OK;
 }
 
-static fmm_status finish_readback(fmm_plan_t pl, int nscalars) {
+// Device scalars (and the input-check flag) to the pinned host mirror, on the
+// plan stream; check_readback runs once that stream has been synchronised.
+static fmm_status enqueue_readback(fmm_plan_t pl, int nscalars) {
     hipStream_t s = pl->stream;
     HIPCHK(pl, hipMemcpyAsync(pl->h_scalars, pl->scalars.ptr, sizeof(double) * nscalars, hipMemcpyDeviceToHost, s),
            "readback");
-    int flag = 0;
     HIPCHK(pl, hipMemcpyAsync(&pl->h_scalars[kScalars - 1], pl->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, s),
            "readback");
-    HIPCHK(pl, hipStreamSynchronize(s), "synchronize");
+    return FMM_OK;
+}
+static fmm_status check_readback(fmm_plan_t pl) {
+    int flag = 0;
     std::memcpy(&flag, &pl->h_scalars[kScalars - 1], sizeof(int));
     if (flag) return fail(pl, FMM_ERR_INVALID, "non-finite position or charge");
     return FMM_OK;
 }
+static fmm_status finish_readback(fmm_plan_t pl, int nscalars) {
+    fmm_status st = enqueue_readback(pl, nscalars);
+    if (st != FMM_OK) return st;
+    HIPCHK(pl, hipStreamSynchronize(pl->stream), "synchronize");
+    return check_readback(pl);
+}
 
+// All device work of one evaluation plus the readback copies, enqueued on the
+// plan stream without synchronising (also used under stream capture).
 template <typename T>
-static fmm_status energy_forces_t(fmm_plan_t pl, int64_t n, const double *pos, const double *q, double *energy,
-                                  double *forces, double *phi) {
+static fmm_status enqueue_energy_forces(fmm_plan_t pl, int64_t n, const double *pos, const double *q,
+                                        double *forces, double *phi) {
     hipStream_t s = pl->stream;
     fmm_status st;
     if ((st = run_fields<T>(pl, n, pos, q)) != FMM_OK) return st;
@@ -526,11 +612,26 @@ static fmm_status energy_forces_t(fmm_plan_t pl, int64_t n, const double *pos, c
                                   pl->partials.as<double>(), nb, sc + 8, s), "finalize");
     stage_end(pl, FMM_STAGE_FINAL);
     stage_end(pl, FMM_STAGE_TOTAL);
-    if ((st = finish_readback(pl, 11)) != FMM_OK) return st;
+    return enqueue_readback(pl, 11);
+}
+
+// after the plan stream has been synchronised
+static fmm_status finish_energy(fmm_plan_t pl, double *energy) {
+    fmm_status st = check_readback(pl);
+    if (st != FMM_OK) return st;
     stage_collect(pl);
     *energy = pl->h_scalars[8];
     pl->q_tree = pl->h_scalars[10];
     return FMM_OK;
+}
+
+template <typename T>
+static fmm_status energy_forces_t(fmm_plan_t pl, int64_t n, const double *pos, const double *q, double *energy,
+                                  double *forces, double *phi) {
+    fmm_status st = enqueue_energy_forces<T>(pl, n, pos, q, forces, phi);
+    if (st != FMM_OK) return st;
+    HIPCHK(pl, hipStreamSynchronize(pl->stream), "synchronize");
+    return finish_energy(pl, energy);
 }
 
 extern "C" fmm_status fmm_energy_forces(fmm_plan_t pl, int64_t n, const double *pos, const double *q,
@@ -597,7 +698,7 @@ extern "C" fmm_status fmm_potential_parts(fmm_plan_t pl, int64_t n, const double
 }
 
 template <typename T>
-static fmm_status solute_solvent_t(fmm_plan_t pl, const uint8_t *mask, double *e_uv) {
+static fmm_status enqueue_solute_solvent(fmm_plan_t pl, const uint8_t *mask) {
     hipStream_t s = pl->stream;
     const int64_t n = pl->n_state;
     fmm_status st;
@@ -619,7 +720,13 @@ static fmm_status solute_solvent_t(fmm_plan_t pl, const uint8_t *mask, double *e
                               sc + 24, s), "moments");
     HIPCHK(pl, launch_moments(n, pl->xs.as<double>(), pl->perm.as<int32_t>(), mask, 0, pl->partials.as<double>(), nb,
                               sc + 32, s), "moments");
-    if ((st = finish_readback(pl, 40)) != FMM_OK) return st;
+    return enqueue_readback(pl, 40);
+}
+
+// W_uv from the pass-2 scalars, after the plan stream has been synchronised
+static fmm_status finish_solute_solvent(fmm_plan_t pl, double *e_uv) {
+    fmm_status st = check_readback(pl);
+    if (st != FMM_OK) return st;
     const double *h = pl->h_scalars;
     const double A = h[16], B = h[17], C = h[18], D = h[19];
     const double Qu = h[24], mux = h[25], muy = h[26], muz = h[27], Su = h[28];
@@ -636,8 +743,17 @@ static fmm_status solute_solvent_t(fmm_plan_t pl, const uint8_t *mask, double *e
     return FMM_OK;
 }
 
+template <typename T>
+static fmm_status solute_solvent_t(fmm_plan_t pl, const uint8_t *mask, double *e_uv) {
+    fmm_status st = enqueue_solute_solvent<T>(pl, mask);
+    if (st != FMM_OK) return st;
+    HIPCHK(pl, hipStreamSynchronize(pl->stream), "synchronize");
+    return finish_solute_solvent(pl, e_uv);
+}
+
 extern "C" fmm_status fmm_solute_solvent_energy(fmm_plan_t pl, const uint8_t *mask, double *e_uv) {
     if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    if (pl->is_batch) return fail(pl, FMM_ERR_INVALID, "batch plan: use fmm_solute_solvent_energy_batch");
     if (!e_uv) return fail(pl, FMM_ERR_INVALID, "e_uv must be non-NULL");
     if (!pl->have_state) return fail(pl, FMM_ERR_STATE, "fmm_solute_solvent_energy needs a preceding fmm_energy_forces");
     if (pl->n_state == 0) { *e_uv = 0.0; return FMM_OK; }
@@ -649,6 +765,7 @@ extern "C" fmm_status fmm_solute_solvent_energy(fmm_plan_t pl, const uint8_t *ma
 extern "C" fmm_status fmm_bin(fmm_plan_t pl, int64_t n, const double *pos, uint32_t *keys, int32_t *perm,
                               int32_t *cell_start) {
     if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    if (pl->is_batch) return fail(pl, FMM_ERR_INVALID, "batch plan: fmm_bin takes a single-box plan");
     if (n < 0 || n >= ((int64_t)1 << 31)) return fail(pl, FMM_ERR_INVALID, "n must be in [0, 2^31)");
     if (n > 0 && !pos) return fail(pl, FMM_ERR_INVALID, "pos must be non-NULL when n > 0");
     HIPCHK(pl, hipSetDevice(pl->device), "hipSetDevice");
@@ -668,6 +785,7 @@ extern "C" fmm_status fmm_bin(fmm_plan_t pl, int64_t n, const double *pos, uint3
 
 extern "C" fmm_status fmm_lattice_tensor(fmm_plan_t pl, double *out, int64_t cap) {
     if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    if (pl->is_batch) return fail(pl, FMM_ERR_INVALID, "batch plan: fmm_lattice_tensor takes a single-box plan");
     const int64_t need = 2 * (int64_t)(2 * pl->p + 1) * (2 * pl->p + 1);
     if (!out || cap < need) return fail(pl, FMM_ERR_INVALID, "output too small");
     // stored for a unit box: T_j(nu b) = b^{-(j+1)} T_j(nu)
@@ -693,6 +811,7 @@ static void free_events(fmm_plan_t pl) {
 
 extern "C" fmm_status fmm_profile(fmm_plan_t pl, int enable) {
     if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    if (pl->is_batch && enable) return fail(pl, FMM_ERR_INVALID, "batch plan: stage profiling takes a single-box plan");
     HIPCHK(pl, hipSetDevice(pl->device), "hipSetDevice");
     free_events(pl);
     for (int i = 0; i < FMM_NUM_STAGES; ++i) pl->stage_ms[i] = 0.0;
@@ -726,14 +845,351 @@ extern "C" const char *fmm_last_error(fmm_plan_t pl) {
 
 extern "C" void fmm_destroy(fmm_plan_t pl) {
     if (!pl) return;
-    DeviceBuf *bufs[] = {&pl->ops32, &pl->ops64, &pl->opsbf, &pl->tree32, &pl->tree64, &pl->lat, &pl->il, &pl->offv, &pl->key,
+    if (pl->is_batch) {
+        batch_drop_graphs(pl);
+        for (fmm_plan_t b : pl->sub) fmm_destroy(b);
+        for (hipStream_t x : pl->sub_stream)
+            if (x) (void)hipStreamDestroy(x);
+        for (hipEvent_t e : pl->sub_done)
+            if (e) (void)hipEventDestroy(e);
+        if (pl->fork) (void)hipEventDestroy(pl->fork);
+        if (pl->input_ready) (void)hipEventDestroy(pl->input_ready);
+        if (pl->own_stream) (void)hipStreamDestroy(pl->own_stream);
+        delete pl;
+        return;
+    }
+    DeviceBuf *bufs[] = {&pl->lat, &pl->key,
                          &pl->count, &pl->cursor, &pl->start, &pl->pstart, &pl->xqp, &pl->perm, &pl->scan, &pl->xq, &pl->xq_u, &pl->xs, &pl->m2l_part,
                          &pl->Mlev, &pl->Llev, &pl->M0, &pl->L0, &pl->phi_nf, &pl->field_nf, &pl->phi_ff,
                          &pl->field_ff, &pl->phi_u, &pl->field_u, &pl->nfuv, &pl->partials, &pl->scalars, &pl->flag};
     for (DeviceBuf *b : bufs) b->release();
     free_events(pl);
     if (pl->h_scalars) (void)hipHostFree(pl->h_scalars);
+    pl->op.reset();
     delete pl;
+}
+
+// ---------------------------------------------------------------------------
+// Batches of independent boxes (charging windows of different size)
+// ---------------------------------------------------------------------------
+
+// Cost model for the tree depth of one box (seconds, MI355X): P2P pairs
+// N * 125 N / 8^L, M2L flops 2 Kp^2 * 875 per cell summed over levels 1..L,
+// a fixed per-level launch cost, and the per-atom expansion work.  The rates
+// were measured with the kernels of this library on the 1M-atom box; the
+// autotuner (fmm_autotune_batch) replaces the model's choice by timings.
+static double depth_cost(int64_t n, int levels, int p, int prec) {
+    const double Kp = padded_coeffs(p);
+    const double pair_s = prec == FMM_FP64 ? 1.2e-12 : 6.5e-13;
+    const double flop_s = prec == FMM_FP64 ? 2.0e-14 : 1.0e-14;
+    double cells = 0.0;
+    for (int l = 1; l <= levels; ++l) cells += (double)level_cells(l);
+    const double pairs = (double)n * 125.0 * (double)n / (double)level_cells(levels);
+    return pair_s * pairs + flop_s * 2.0 * Kp * Kp * 875.0 * cells + 2.5e-5 * levels + 2.0e-11 * n * Kp;
+}
+
+static int model_levels(int64_t n, int p, int prec) {
+    int best = 1;
+    double bc = depth_cost(n, 1, p, prec);
+    for (int L = 2; L <= 7; ++L) {
+        const double c = depth_cost(n, L, p, prec);
+        if (c < bc) { bc = c; best = L; }
+    }
+    return best;
+}
+
+extern "C" fmm_status fmm_plan_batch(int nbox, const double *box, const int64_t *natoms, const int *levels, int p,
+                                     fmm_plan_t *out) {
+    if (!out) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan_batch: out is NULL");
+    *out = nullptr;
+    if (nbox < 1 || nbox > 4096) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan_batch: nbox must be in [1, 4096]");
+    if (!box) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan_batch: box is NULL");
+    if (!levels && !natoms) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan_batch: give levels or natoms");
+    if (p < 0 || p > kMaxP) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan_batch: p must be in [0, 20]");
+    fmm_plan_t pl = new (std::nothrow) struct fmm_plan;
+    if (!pl) return fail(nullptr, FMM_ERR_NOMEM, "fmm_plan_batch: host allocation");
+    pl->is_batch = true;
+    pl->p = p;
+    pl->K = num_coeffs(p);
+    pl->Kp = padded_coeffs(p);
+    auto bail = [&](fmm_status st, const std::string &m) {
+        g_plan_error = m;
+        fmm_destroy(pl);
+        return st;
+    };
+    if (hipGetDevice(&pl->device) != hipSuccess) return bail(FMM_ERR_DEVICE, "fmm_plan_batch: hipGetDevice failed");
+    if (hipStreamCreateWithFlags(&pl->own_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&pl->input_ready, hipEventDisableTiming) != hipSuccess)
+        return bail(FMM_ERR_DEVICE, "fmm_plan_batch: stream or event creation failed");
+    pl->stream = pl->own_stream;
+    std::shared_ptr<OpSet> ops;
+    for (int w = 0; w < nbox; ++w) {
+        if (natoms && natoms[w] < 0) return bail(FMM_ERR_INVALID, "fmm_plan_batch: natoms must be >= 0");
+        const int L = levels ? levels[w] : model_levels(natoms[w], p, FMM_MIXED);
+        fmm_plan_t b = nullptr;
+        fmm_status st = plan_create(box[w], L, p, ops, &b);
+        if (st != FMM_OK) return bail(st, "fmm_plan_batch: box " + std::to_string(w) + ": " + g_plan_error);
+        ops = b->op;
+        pl->sub.push_back(b);
+        pl->sub_natoms.push_back(natoms ? natoms[w] : -1);
+        hipStream_t x = nullptr;
+        hipEvent_t e = nullptr;
+        if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            if (x) (void)hipStreamDestroy(x);
+            return bail(FMM_ERR_DEVICE, "fmm_plan_batch: stream or event creation failed");
+        }
+        pl->sub_stream.push_back(x);
+        pl->sub_done.push_back(e);
+        b->stream = x;
+    }
+    pl->op = ops;
+    *out = pl;
+    return FMM_OK;
+}
+
+extern "C" fmm_status fmm_batch_levels(fmm_plan_t pl, int *levels, int *p2p_groups_out) {
+    if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    if (!pl->is_batch) return fail(pl, FMM_ERR_INVALID, "fmm_batch_levels: not a batch plan");
+    for (size_t w = 0; w < pl->sub.size(); ++w) {
+        if (levels) levels[w] = pl->sub[w]->levels;
+        if (p2p_groups_out) p2p_groups_out[w] = pl->sub[w]->p2p_g;
+    }
+    return FMM_OK;
+}
+
+static fmm_status check_batch_offsets(fmm_plan_t pl, const int64_t *off) {
+    if (!off) return fail(pl, FMM_ERR_INVALID, "offsets is NULL");
+    if (off[0] < 0) return fail(pl, FMM_ERR_INVALID, "offsets[0] must be >= 0");
+    for (size_t w = 0; w < pl->sub.size(); ++w) {
+        const int64_t n = off[w + 1] - off[w];
+        if (n < 0 || n >= ((int64_t)1 << 31)) return fail(pl, FMM_ERR_INVALID, "offsets must be non-decreasing, boxes < 2^31 atoms");
+    }
+    return FMM_OK;
+}
+
+// Capture `enqueue(w)` for every non-empty box as parallel branches of one
+// graph (fork from and join into the batch stream), or reuse the graph that
+// was captured for the same key.  Launches it; the caller synchronises.
+template <typename F>
+static fmm_status batch_run(fmm_plan_t pl, fmm_plan::Graph &g, const std::vector<int64_t> &key,
+                            const int64_t *off, F enqueue) {
+    hipStream_t cs = pl->stream;
+    if (!g.exec || g.key != key) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
+        g.key.clear();
+        HIPCHK(pl, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "graph capture");
+        fmm_status st = FMM_OK;
+        hipError_t e = hipEventRecord(pl->fork, cs);
+        for (size_t w = 0; w < pl->sub.size() && st == FMM_OK && e == hipSuccess; ++w) {
+            if (off[w + 1] == off[w]) continue;
+            fmm_plan_t b = pl->sub[w];
+            b->stream = pl->sub_stream[w];
+            e = hipStreamWaitEvent(b->stream, pl->fork, 0);
+            if (e != hipSuccess) break;
+            st = enqueue(w);
+            if (st != FMM_OK) {
+                pl->err = "box " + std::to_string(w) + ": " + b->err;
+                break;
+            }
+            e = hipEventRecord(pl->sub_done[w], b->stream);
+            if (e == hipSuccess) e = hipStreamWaitEvent(cs, pl->sub_done[w], 0);
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(cs, &graph);
+        if (st != FMM_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess || ec != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(pl, e != hipSuccess ? e : ec, "graph capture");
+        }
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(pl, e, "graph instantiate");
+        g.exec = exec;
+        g.key = key;
+    }
+    if (cs == pl->own_stream) {
+        // the plan's own stream does not order itself after the null stream,
+        // on which the caller's inputs may still be in flight
+        HIPCHK(pl, hipEventRecord(pl->input_ready, nullptr), "event record");
+        HIPCHK(pl, hipStreamWaitEvent(cs, pl->input_ready, 0), "stream wait");
+    }
+    HIPCHK(pl, hipGraphLaunch(g.exec, cs), "graph launch");
+    return FMM_OK;
+}
+
+extern "C" fmm_status fmm_energy_forces_batch(fmm_plan_t pl, const int64_t *offsets, const double *pos,
+                                              const double *q, double *energies, double *forces) {
+    if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    if (!pl->is_batch) return fail(pl, FMM_ERR_INVALID, "fmm_energy_forces_batch: not a batch plan");
+    fmm_status st = check_batch_offsets(pl, offsets);
+    if (st != FMM_OK) return st;
+    if (!energies) return fail(pl, FMM_ERR_INVALID, "energies is NULL");
+    const size_t nb = pl->sub.size();
+    if (offsets[nb] > offsets[0] && (!pos || !q)) return fail(pl, FMM_ERR_INVALID, "pos and q must be non-NULL");
+    HIPCHK(pl, hipSetDevice(pl->device), "hipSetDevice");
+    pl->batch_state = false;
+    for (size_t w = 0; w < nb; ++w) {
+        fmm_plan_t b = pl->sub[w];
+        b->have_state = false;
+        const int64_t n = offsets[w + 1] - offsets[w];
+        if (n == 0) continue;
+        if ((st = ensure_workspace(b, n)) != FMM_OK || (st = ensure_m2l_ops(b)) != FMM_OK) {
+            pl->err = "box " + std::to_string(w) + ": " + b->err;
+            return st;
+        }
+    }
+    std::vector<int64_t> key(offsets, offsets + nb + 1);
+    key.push_back((int64_t)(uintptr_t)pos);
+    key.push_back((int64_t)(uintptr_t)q);
+    key.push_back((int64_t)(uintptr_t)forces);
+    key.push_back(pl->prec);
+    st = batch_run(pl, pl->g_ef, key, offsets, [&](size_t w) -> fmm_status {
+        fmm_plan_t b = pl->sub[w];
+        const int64_t o = offsets[w], n = offsets[w + 1] - o;
+        double *f = forces ? forces + 3 * o : nullptr;
+        return b->prec == FMM_FP64 ? enqueue_energy_forces<double>(b, n, pos + 3 * o, q + o, f, nullptr)
+                                   : enqueue_energy_forces<float>(b, n, pos + 3 * o, q + o, f, nullptr);
+    });
+    if (st != FMM_OK) return st;
+    HIPCHK(pl, hipStreamSynchronize(pl->stream), "synchronize");
+    for (size_t w = 0; w < nb; ++w) {
+        fmm_plan_t b = pl->sub[w];
+        const int64_t n = offsets[w + 1] - offsets[w];
+        energies[w] = 0.0;
+        if (n > 0 && (st = finish_energy(b, &energies[w])) != FMM_OK) {
+            pl->err = "box " + std::to_string(w) + ": " + b->err;
+            return st;
+        }
+        b->have_state = true;
+        b->n_state = n;
+    }
+    pl->batch_off.assign(offsets, offsets + nb + 1);
+    pl->batch_state = true;
+    return FMM_OK;
+}
+
+extern "C" fmm_status fmm_solute_solvent_energy_batch(fmm_plan_t pl, const uint8_t *mask, double *e_uv) {
+    if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    if (!pl->is_batch) return fail(pl, FMM_ERR_INVALID, "fmm_solute_solvent_energy_batch: not a batch plan");
+    if (!e_uv) return fail(pl, FMM_ERR_INVALID, "e_uv is NULL");
+    if (!pl->batch_state)
+        return fail(pl, FMM_ERR_STATE, "fmm_solute_solvent_energy_batch needs a preceding fmm_energy_forces_batch");
+    const size_t nb = pl->sub.size();
+    const int64_t *off = pl->batch_off.data();
+    if (off[nb] > off[0] && !mask) return fail(pl, FMM_ERR_INVALID, "mask is NULL");
+    HIPCHK(pl, hipSetDevice(pl->device), "hipSetDevice");
+    std::vector<int64_t> key(pl->batch_off);
+    key.push_back((int64_t)(uintptr_t)mask);
+    key.push_back(pl->prec);
+    fmm_status st = batch_run(pl, pl->g_uv, key, off, [&](size_t w) -> fmm_status {
+        fmm_plan_t b = pl->sub[w];
+        return b->prec == FMM_FP64 ? enqueue_solute_solvent<double>(b, mask + off[w])
+                                   : enqueue_solute_solvent<float>(b, mask + off[w]);
+    });
+    if (st != FMM_OK) return st;
+    HIPCHK(pl, hipStreamSynchronize(pl->stream), "synchronize");
+    for (size_t w = 0; w < nb; ++w) {
+        e_uv[w] = 0.0;
+        if (off[w + 1] == off[w]) continue;
+        if ((st = finish_solute_solvent(pl->sub[w], &e_uv[w])) != FMM_OK) {
+            pl->err = "box " + std::to_string(w) + ": " + pl->sub[w]->err;
+            return st;
+        }
+    }
+    return FMM_OK;
+}
+
+// Autotuner: for every non-empty box, time whole evaluations (energy and
+// forces, hipEvent-timed on the box's stream after one warm-up) for the tree
+// depths L-1, L, L+1 around the current one and the P2P source-group counts
+// 2, 4, 8, and keep the fastest configuration.  Scratch plans share the
+// box-independent operators.
+extern "C" fmm_status fmm_autotune_batch(fmm_plan_t pl, const int64_t *offsets, const double *pos, const double *q,
+                                         double *forces_scratch) {
+    if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    if (!pl->is_batch) return fail(pl, FMM_ERR_INVALID, "fmm_autotune_batch: not a batch plan");
+    fmm_status st = check_batch_offsets(pl, offsets);
+    if (st != FMM_OK) return st;
+    HIPCHK(pl, hipSetDevice(pl->device), "hipSetDevice");
+    HIPCHK(pl, hipDeviceSynchronize(), "synchronize");  // inputs written on any stream
+    batch_drop_graphs(pl);
+    pl->batch_state = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(pl, hipEventCreate(&e0), "hipEventCreate");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(pl, FMM_ERR_DEVICE, "hipEventCreate");
+    }
+    auto time_eval = [&](fmm_plan_t b, int64_t o, int64_t n, float &ms) -> fmm_status {
+        fmm_status s2;
+        if ((s2 = ensure_workspace(b, n)) != FMM_OK || (s2 = ensure_m2l_ops(b)) != FMM_OK) return s2;
+        double e = 0.0;
+        double *f = forces_scratch ? forces_scratch + 3 * o : nullptr;
+        ms = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            if (hipEventRecord(e0, b->stream) != hipSuccess) return FMM_ERR_DEVICE;
+            s2 = b->prec == FMM_FP64 ? energy_forces_t<double>(b, n, pos + 3 * o, q + o, &e, f, nullptr)
+                                     : energy_forces_t<float>(b, n, pos + 3 * o, q + o, &e, f, nullptr);
+            if (s2 != FMM_OK) return s2;
+            if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return FMM_ERR_DEVICE;
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            if (rep > 0) ms = std::min(ms, t);  // rep 0 is the warm-up
+        }
+        return FMM_OK;
+    };
+    for (size_t w = 0; w < pl->sub.size() && st == FMM_OK; ++w) {
+        const int64_t o = offsets[w], n = offsets[w + 1] - o;
+        if (n == 0) continue;
+        fmm_plan_t cur = pl->sub[w];
+        float best_ms = 1e30f;
+        int best_L = cur->levels, best_g = 0;
+        for (int L = std::max(1, cur->levels - 1); L <= std::min(kMaxLevels, cur->levels + 1) && st == FMM_OK; ++L) {
+            fmm_plan_t b = nullptr;
+            if (L == cur->levels) b = cur;
+            else if ((st = plan_create(cur->box, L, pl->p, pl->op, &b)) != FMM_OK) {
+                pl->err = "autotune box " + std::to_string(w) + ": " + g_plan_error;
+                break;
+            }
+            b->prec = pl->prec;
+            b->stream = pl->sub_stream[w];
+            for (int g : {2, 4, 8}) {
+                b->p2p_g = g;
+                float ms = 0.f;
+                if ((st = time_eval(b, o, n, ms)) != FMM_OK) {
+                    pl->err = "autotune box " + std::to_string(w) + ": " + b->err;
+                    break;
+                }
+                if (ms < best_ms) { best_ms = ms; best_L = L; best_g = g; }
+            }
+            if (b != cur) fmm_destroy(b);
+        }
+        if (st != FMM_OK) break;
+        if (best_L != cur->levels) {
+            fmm_plan_t b = nullptr;
+            if ((st = plan_create(cur->box, best_L, pl->p, pl->op, &b)) != FMM_OK) {
+                pl->err = "autotune box " + std::to_string(w) + ": " + g_plan_error;
+                break;
+            }
+            b->prec = pl->prec;
+            b->stream = pl->sub_stream[w];
+            fmm_destroy(cur);
+            pl->sub[w] = b;
+            cur = b;
+        }
+        cur->p2p_g = best_g;
+        cur->have_state = false;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
 }
 
 extern "C" const char *fmm_version(void) { return "libfmm 0.1 (gfx950)"; }
