@@ -1,20 +1,30 @@
 """Throughput of the periodic background-charge FMM on one MI355X.
 
-One step = one fmm_energy_forces call (all of stages a1-a13: sort, P2M, M2M,
-lattice operator, M2L, L2L, L2P, P2P, correction terms, compensated energy
-reduction, forces scattered to the caller's order, energy on the host) on the
-1,000,000-atom box (333,333 rigid waters + one -1 ion, b = 215.30 A,
-levels 5, p = 12) with inputs resident in HBM.  Metric: atom-evals/s =
-N * steps / time, mixed precision (FP32 P2P and M2L, FP64 lattice,
-corrections and reduction); the FP64 FMM on the same box is timed beside it.
+Default (the headline): one step = one fmm_energy_forces call (all of stages
+a1-a13: sort, P2M, M2M, lattice operator, M2L, L2L, L2P, P2P, correction
+terms, compensated energy reduction, forces scattered to the caller's order,
+energy on the host) on the 1,000,000-atom box (333,333 rigid waters + one -1
+ion, b = 215.30 A, levels 5, p = 12) with inputs resident in HBM.  Metric:
+atom-evals/s = N * steps / time in mixed precision (FP32 P2P and M2L at the
+fine levels; FP64 top levels, lattice, corrections and reduction); the FP64
+FMM on the same box is timed beside it, and the oracle on a bounded sample on
+the host cores.  Prints ONE JSON line.
 
-Prints ONE JSON line.  --gpus > 1 is refused: this build runs on one GPU.
+Other workloads (each one JSON line):
+  --config C5 [--p P] [--prec fp64|mixed|bf16]   3,000,008 atoms, levels 6
+  --config C5 --sweep       p in (4, 8, 12, 16) x (fp64, mixed, bf16), one line each
+  --config C4               32 charging windows (6k-48k atoms), one graph launch
+                            of energies + forces and one of solute-solvent
+                            energies per step, depths and P2P groups autotuned
+--gpus > 1 is refused: this build runs on one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -22,12 +32,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 M2L_IL = 875  # interaction-list size per cell
+PEAK_TFLOPS = {"mixed": 157.3, "bf16": 2500.0, "fp64": 78.6}  # dense MFMA peaks of MI355X (FP32, BF16, FP64)
+PREC_NAMES = {"fp64": 0, "mixed": 1, "bf16": 2}
+LEAF_KERNEL = {"mixed": "k_m2l_lds<float, false>", "fp64": "k_m2l_lds<double, false>", "bf16": "k_m2l_bf16<false>"}
 
 
-def m2l_flops(levels, p, level=None):
+def m2l_flops(p, level):
+    """Algorithmic M2L flops of one level: 2 K^2 per (target, source) pair."""
     K = (p + 1) ** 2
-    cells = (8 ** level) if level is not None else sum(8 ** l for l in range(1, levels + 1))
-    return 2.0 * K * K * M2L_IL * cells
+    return 2.0 * K * K * M2L_IL * 8 ** level
+
+
+def recorded_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when there is none or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "m2l_leaf_c3_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_src = re.search(r"source sha256 of k_m2l\.hip: ([0-9a-f]{64})", text)
+    m_b = re.search(r"HBM bytes per launch \(calibrated\): ([0-9.eE+]+)", text)
+    m_k = re.search(r"kernel: (.+)", text)
+    m_w = re.search(r"workload: (.+)", text)
+    if not (m_src and m_b and m_k and m_w) or m_k.group(1).strip() != kernel or m_w.group(1).strip() != workload:
+        return None
+    src = os.path.join(ROOT, "paper_2003_13218_amd", "csrc", "k_m2l.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m_src.group(1):
+        return None
+    return float(m_b.group(1))
 
 
 def cpu_baseline(w, accuracy=1e-6):
@@ -58,29 +90,25 @@ def cpu_baseline(w, accuracy=1e-6):
                        f"fixed + per-atom * N = {t_full:.0f} s")}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C3")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not part of "
-              "this build", file=sys.stderr)
-        sys.exit(2)
-
+def sample_error(name, f, ph):
+    """RMS relative force / potential error on the stored oracle sample."""
     import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"{name.lower()}_sample_oracle.npz")
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path)
+    idx = ref["idx"]
+    fs, ps = f.cpu().numpy()[idx], ph.cpu().numpy()[idx]
+    rel = lambda a, b: float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))  # noqa: E731
+    return {"force_rms_rel": rel(fs, ref["force"]), "phi_rms_rel": rel(ps, ref["phi"]), "atoms": int(idx.size)}
+
+
+def run_single(args, w, p, prec_name, steps, warmup, fp64_leg, cpu_leg):
     import torch
     import paper_2003_13218_amd as F
-    import workloads
-
-    w = workloads.config(args.config)
     pos = torch.tensor(w.pos, device="cuda")
     q = torch.tensor(w.q, device="cuda")
-    plan = F.fmm_plan(w.box, w.levels, w.p)
+    plan = F.fmm_plan(w.box, w.levels, p)
 
     def timed(prec, steps, warmup):
         F.fmm_plan_config(plan, prec)
@@ -98,43 +126,135 @@ def main():
         F.fmm_profile(plan, False)
         return dt, e, {k: v / max(calls, 1) for k, v in stages.items()}
 
-    dt, e_mixed, st = timed(F.FMM_MIXED, args.steps, args.warmup)
-    ms = 1e3 * dt / args.steps
-    value = w.n * args.steps / dt
-    print(f"[bench] mixed: {ms:.3f} ms/step, E = {e_mixed:.10f}", file=sys.stderr, flush=True)
+    prec = PREC_NAMES[prec_name]
+    dt, e_main, st = timed(prec, steps, warmup)
+    ms = 1e3 * dt / steps
+    value = w.n * steps / dt
+    print(f"[bench] {w.name} p={p} {prec_name}: {ms:.3f} ms/step, E = {e_main:.10f}", file=sys.stderr, flush=True)
+    _, f, ph = F.fmm_energy_forces(plan, pos, q, forces=True, phi=True)
+    err = sample_error(w.name, f, ph)
 
     # dominant kernel: M2L at the finest level; algorithmic flops per launch
-    flops_leaf = m2l_flops(w.levels, w.p, w.levels)
+    # divided by its event-timed average duration on the plan's stream
+    flops_leaf = m2l_flops(p, w.levels)
     m2l_ms = st["m2l_leaf"]
     achieved = flops_leaf / (m2l_ms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": 157.3, "unit": "TFLOP/s",
-                "frac": round(achieved / 157.3, 4), "traffic": None,
-                "kernel": f"k_m2l_lds<float, false> (M2L, level {w.levels})", "avg_ms": round(m2l_ms, 4),
+    peak = PEAK_TFLOPS[prec_name]
+    kernel = LEAF_KERNEL[prec_name]
+    workload = f"{w.name} levels {w.levels} p {p}"
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": recorded_traffic(kernel, workload),
+                "kernel": f"{kernel} (M2L, level {w.levels})", "avg_ms": round(m2l_ms, 4),
                 "flops_per_launch": flops_leaf}
-
+    desc = {"C3": "333,333 waters + one -1 ion", "C5": "1,000,000 waters + 8 ions (net +3)"}.get(w.name, w.name)
+    metric = ("atom-evals/s (energy+forces) at 1M atoms, mixed vs FP64 FMM, rel err <=1e-5" if w.name == "C3"
+              else f"atom-evals/s (energy+forces) on {w.name} ({w.n} atoms)")
     out = {
-        "metric": "atom-evals/s (energy+forces) at 1M atoms, mixed vs FP64 FMM, rel err <=1e-5",
-        "value": value, "unit": "atom-evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "metric": metric,
+        "value": value, "unit": "atom-evals/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": f"{args.config}: {w.n} atoms (333,333 waters + one -1 ion), b = {w.box} A, "
-                               f"levels {w.levels}, p {w.p}, mixed precision",
-                   "n_atoms": w.n, "box": w.box, "levels": w.levels, "p": w.p},
+        "dtype": {"mixed": "f32+f64", "fp64": "f64", "bf16": "bf16-m2l+f32+f64"}[prec_name], "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.n} atoms ({desc}), b = {w.box} A, levels {w.levels}, p {p}, "
+                               f"{prec_name} precision",
+                   "n_atoms": w.n, "box": w.box, "levels": w.levels, "p": p, "precision": prec_name},
         "stages_ms": {k: round(v, 4) for k, v in st.items()},
+        "sample_error": err,
         "roofline": roofline,
     }
-    if not args.no_fp64:
-        dt64, e64, st64 = timed(F.FMM_FP64, max(3, args.steps // 4), 1)
-        n64 = max(3, args.steps // 4)
+    if fp64_leg and prec_name != "fp64":
+        n64 = max(3, steps // 4)
+        dt64, e64, st64 = timed(F.FMM_FP64, n64, 1)
         out["fp64"] = {"value": w.n * n64 / dt64, "ms_per_step": 1e3 * dt64 / n64,
                        "stages_ms": {k: round(v, 4) for k, v in st64.items()}, "energy": e64}
         out["mixed_vs_fp64"] = value / out["fp64"]["value"]
-        out["energy_mixed_minus_fp64_rel"] = abs(e_mixed - e64) / abs(e64)
+        out["energy_rel_diff_vs_fp64"] = abs(e_main - e64) / abs(e64)
         print(f"[bench] fp64: {out['fp64']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
-    if not args.no_cpu:
+    if cpu_leg:
         print("[bench] timing the CPU oracle on a sample ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)
-    print(json.dumps(out), flush=True)
+    F.fmm_destroy(plan)
+    return out
+
+
+def run_batch(args):
+    """C4: 32 charging windows, energies + forces and e_uv per step."""
+    import numpy as np
+    import torch
+    import paper_2003_13218_amd as F
+    import workloads
+    ws = workloads.batch_windows()
+    off = np.zeros(len(ws) + 1, np.int64)
+    off[1:] = np.cumsum([w.n for w in ws])
+    pos = torch.tensor(np.concatenate([w.pos for w in ws]), device="cuda")
+    q = torch.tensor(np.concatenate([w.q for w in ws]), device="cuda")
+    mask = torch.tensor(np.concatenate([w.mask for w in ws]), device="cuda")
+    p = args.p or 10
+    plan = F.fmm_plan_batch([w.box for w in ws], p, natoms=[w.n for w in ws])
+    F.fmm_plan_config(plan, PREC_NAMES[args.prec])
+    model_levels, _ = F.fmm_batch_levels(plan)
+    t0 = time.perf_counter()
+    levels, groups = F.fmm_autotune_batch(plan, off, pos, q)
+    t_tune = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        F.fmm_energy_forces_batch(plan, off, pos, q)
+        F.fmm_solute_solvent_energy_batch(plan, mask)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        E, _ = F.fmm_energy_forces_batch(plan, off, pos, q)
+        U = F.fmm_solute_solvent_energy_batch(plan, mask)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n = int(off[-1])
+    print(f"[bench] C4: {1e3 * dt / args.steps:.3f} ms/step over {len(ws)} windows, {n} atoms",
+          file=sys.stderr, flush=True)
+    return {
+        "metric": "atom-evals/s (energy+forces+solute-solvent energy), 32 charging windows, one graph launch each",
+        "value": n * args.steps / dt, "unit": "atom-evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"mixed": "f32+f64", "fp64": "f64", "bf16": "bf16-m2l+f32+f64"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": f"C4: {len(ws)} windows, {n} atoms (6k-48k per box), p {p}, {args.prec} precision",
+                   "n_atoms": n, "windows": len(ws), "p": p, "precision": args.prec,
+                   "model_levels": model_levels.tolist(), "tuned_levels": levels.tolist(),
+                   "tuned_p2p_groups": groups.tolist(), "autotune_s": round(t_tune, 2)},
+        "energies": E.tolist(), "e_uv": U.tolist(),
+        "roofline": None,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="C3", choices=["C3", "C5", "C4"])
+    ap.add_argument("--p", type=int, default=0, help="expansion order (default: the workload's)")
+    ap.add_argument("--prec", default="mixed", choices=list(PREC_NAMES))
+    ap.add_argument("--sweep", action="store_true", help="C5: p x precision sweep")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not part of "
+              "this build", file=sys.stderr)
+        sys.exit(2)
+
+    import workloads
+    if args.config == "C4":
+        print(json.dumps(run_batch(args)), flush=True)
+        return
+    w = workloads.config(args.config)
+    if args.sweep:
+        for p in (4, 8, 12, 16):
+            for prec in ("fp64", "mixed", "bf16"):
+                out = run_single(args, w, p, prec, args.steps, args.warmup, False, False)
+                print(json.dumps(out), flush=True)
+        return
+    p = args.p or w.p
+    cpu_leg = not args.no_cpu and args.config == "C3"
+    print(json.dumps(run_single(args, w, p, args.prec, args.steps, args.warmup, not args.no_fp64, cpu_leg)),
+          flush=True)
 
 
 if __name__ == "__main__":

@@ -527,10 +527,13 @@ static int p2p_groups(int64_t n, int levels) {
         return v ? std::atoi(v) : 0;
     }();
     if (forced == 1 || forced == 2 || forced == 4 || forced == 8 || forced == kMaxP2PGroups) return forced;
+    // 4 groups of 16 target slots fit the 10-40 atom leaves of water boxes at
+    // 4-7 A leaf edges best (measured: 30 atoms/leaf G 4 < 2 < 8; 11 atoms/leaf
+    // G 4 < 8); sparse leaves take more groups, crowded ones fewer
     const double occ = (double)n / (double)level_cells(levels);
-    if (occ > 40.0) return 2;
-    if (occ > 12.0) return 4;
-    if (occ > 5.0) return 8;
+    if (occ > 48.0) return 2;
+    if (occ > 5.0) return 4;
+    if (occ > 2.5) return 8;
     return 16;
 }
 

@@ -425,3 +425,33 @@ def test_c3_sample_bf16_m2l(fmm):
     assert ef < 2.0 ** -10 and ep < 2.0 ** -5
     # the BF16 error is a real rounding effect, not noise on top of FP32
     assert ep > 1e-4
+
+
+# ------------------------------------- the 3M-atom precision / order sweep box --
+def test_c5_sample_order_sweep(fmm):
+    # 1,000,000 waters + 8 ions (net +3), levels 6: the error against the
+    # oracle sample falls with the order in FP64 (truncation only) and reaches
+    # the mixed-precision floor (~2e-6) from p = 8 on
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "c5_sample_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/c5_sample_oracle.npz not generated")
+    ref = np.load(path)
+    w = workloads.config("C5")
+    idx = ref["idx"]
+    np.testing.assert_array_equal(np.nonzero(w.mask)[0], idx[-8:])
+    pos, q = _t(w.pos), _t(w.q)
+    errs = {}
+    for p in (4, 8, 12):
+        plan = fmm.fmm_plan(w.box, w.levels, p)
+        for prec in (fmm.FMM_FP64, fmm.FMM_MIXED):
+            fmm.fmm_plan_config(plan, prec)
+            _, f, ph = fmm.fmm_energy_forces(plan, pos, q, forces=True, phi=True)
+            errs[p, prec] = (rms_rel(f.cpu().numpy()[idx], ref["force"]), rms_rel(ph.cpu().numpy()[idx], ref["phi"]))
+        fmm.fmm_destroy(plan)
+    print("C5 (force, phi) rms rel errors:", {k: tuple(f"{x:.2e}" for x in v) for k, v in errs.items()})
+    f64 = [max(errs[p, 0]) for p in (4, 8, 12)]
+    assert f64[2] < f64[1] / 10 < f64[0] / 100
+    assert f64[2] < 1e-6
+    for p in (8, 12):
+        assert max(errs[p, 1]) < 1e-5
