@@ -234,12 +234,25 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="C5: p x precision sweep")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many bytes 5 times (the reference "
+                         "kernel that scales the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is not part of "
               "this build", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_bytes:
+        import torch
+        n = args.copy_bytes // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n, "launches": 5}), flush=True)
+        return
     import workloads
     if args.config == "C4":
         print(json.dumps(run_batch(args)), flush=True)

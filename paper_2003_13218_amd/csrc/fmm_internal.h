@@ -112,13 +112,16 @@ hipError_t launch_l2p(int64_t nleaf, const void *xq, const int32_t *start, const
                       int Kp, double h, double *phi, T *field, hipStream_t s);
 
 // k_m2l.hip
-// Levels with few target cells split the 875 offsets into slices (split-K)
-// whose partial sums go to `partial` and are added in a fixed order.
+// Levels with few target cells split the interaction list into slices
+// (split-K) whose partial sums go to `partial` and are added in a fixed order.
+// il: 8 parity classes x nil operator ids; offs: 3 ints per operator id (the
+// source cell is the target cell + offset, wrapped on the level's grid).
+// nil = 875 for the interaction list itself, fewer for the aliased levels.
 int m2l_slices(int level);
 void set_m2l_variant(int v);  // tuning: 0 default, 1 offset-split, 2 LDS-shared
 template <typename T>
 hipError_t launch_m2l(int level, const T *ops, const int32_t *il, const int32_t *offs, const T *M,
-                      T *L, T *partial, int p, int Kp, hipStream_t s);
+                      T *L, T *partial, int p, int Kp, hipStream_t s, int nil = kILSize);
 template <typename T>
 size_t m2l_ops_elems(int p);  // element count of the swizzled operator array
 template <typename T>

@@ -142,8 +142,11 @@ template <typename T>
 hipError_t launch_p2m(int64_t nleaf, const void *xq, const int32_t *start, T *M, int p, int Kp,
                       double inv_h, hipStream_t s) {
     const int K = num_coeffs(p);
-    int chunk = (int)(65536 / ((size_t)K * sizeof(T)));
-    if (chunk > 64) chunk = 64;
+    // atoms staged per pass: at most 32 (one pass for the 10-30 atoms of a
+    // typical leaf) and at most 32 KB of LDS, so that several single-wave
+    // workgroups share a CU and hide each other's latency
+    int chunk = (int)(32768 / ((size_t)K * sizeof(T)));
+    if (chunk > 32) chunk = 32;
     if (chunk < 1) chunk = 1;
     const size_t lds = (size_t)chunk * K * sizeof(T);
     int64_t g = nleaf < 1048576 ? nleaf : 1048576;

@@ -21,6 +21,7 @@
 //   * blockIdx mod 8 selects the parity class, so with the round-robin
 //     dispatch of workgroups to the 8 XCDs every XCD streams one class's 875
 //     operators through its own L2.
+#include <algorithm>
 #include <cstring>
 
 #include "fmm_internal.h"
@@ -72,7 +73,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ ops, const int32_t *__restrict__ il,
                                              const int32_t *__restrict__ offs, const T *__restrict__ M,
                                              T *__restrict__ L, int nh_bits, int NB, int Kp, int R,
-                                             int nslices) {
+                                             int nslices, int nil) {
     constexpr int CB = Mfma<T>::CB;
     constexpr int NRW = kRowBlocksPerWave;
     using V = typename Mfma<T>::V;
@@ -114,12 +115,12 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ ops, const in
         for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = V{0, 0, 0, 0};
 
     // offsets of this workgroup's slice, then of this wavefront's share of it
-    const int s0 = slice * kILSize / nslices, s1 = (slice + 1) * kILSize / nslices;
+    const int s0 = slice * nil / nslices, s1 = (slice + 1) * nil / nslices;
     const int t0 = s0 + ts * (s1 - s0) / nts, t1 = s0 + (ts + 1) * (s1 - s0) / nts;
     const size_t op_stride = (size_t)NB * NB * 64 * 4;  // elements per offset
     if (nrb > 0) {
         for (int t = t0; t < t1; ++t) {
-            const int oid = il[parity * kILSize + t];
+            const int oid = il[parity * nil + t];
             const int ox = offs[3 * oid], oy = offs[3 * oid + 1], oz = offs[3 * oid + 2];
             const T *bp[CB];
 #pragma unroll
@@ -657,7 +658,7 @@ hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const 
 
 template <typename T>
 hipError_t launch_m2l(int level, const T *ops, const int32_t *il, const int32_t *offs, const T *M, T *L,
-                      T *partial, int p, int Kp, hipStream_t s) {
+                      T *partial, int p, int Kp, hipStream_t s, int nil) {
     constexpr int CB = Mfma<T>::CB;
     const int NB = Kp / 16;
     int R = 1;
@@ -666,8 +667,9 @@ hipError_t launch_m2l(int level, const T *ops, const int32_t *il, const int32_t 
     if (NB > 4 * kRowBlocksPerWave) return hipErrorInvalidValue;
     const int nh_bits = level - 1;
     const int64_t ntarget = (int64_t)1 << (3 * nh_bits);
-    const int nslices = partial ? m2l_slices(level) : 1;
+    const int nslices = partial ? std::min(m2l_slices(level), nil) : 1;
     if (use_lds_kernel<T>(level)) {
+        if (nil != kILSize) return hipErrorInvalidValue;  // the LDS kernel walks the full list
         const int nrg = (NB + kRowBlocksPerWave - 1) / kRowBlocksPerWave;
         const int64_t ntile = (ntarget + 63) / 64;
         const int64_t grid = 8 * ntile * nslices * nrg;
@@ -681,7 +683,7 @@ hipError_t launch_m2l(int level, const T *ops, const int32_t *il, const int32_t 
         const int64_t ntile = (ntarget + 16 * CB - 1) / (16 * CB);
         const int64_t grid = 8 * ntile * nslices;
         hipLaunchKernelGGL(k_m2l<T>, dim3((unsigned)grid), dim3(256), 0, s, ops, il, offs, M,
-                           nslices > 1 ? partial : L, nh_bits, NB, Kp, R, nslices);
+                           nslices > 1 ? partial : L, nh_bits, NB, Kp, R, nslices, nil);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nslices == 1) return e;
@@ -692,8 +694,8 @@ hipError_t launch_m2l(int level, const T *ops, const int32_t *il, const int32_t 
     return hipGetLastError();
 }
 template hipError_t launch_m2l<float>(int, const float *, const int32_t *, const int32_t *, const float *,
-                                      float *, float *, int, int, hipStream_t);
+                                      float *, float *, int, int, hipStream_t, int);
 template hipError_t launch_m2l<double>(int, const double *, const int32_t *, const int32_t *, const double *,
-                                       double *, double *, int, int, hipStream_t);
+                                       double *, double *, int, int, hipStream_t, int);
 
 }  // namespace fmm
