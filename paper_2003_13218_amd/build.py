@@ -24,8 +24,12 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-result"]
-# device code: no packed FP32 instructions (v_pk_*_f32)
-DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# device code: no packed FP32 instructions (v_pk_*_f32); matrix-core
+# accumulators in ordinary VGPRs (gfx950 MFMA reads and writes them directly),
+# which keeps the compiler from copying every accumulator into AGPRs and back
+# around each batch of MFMAs in the M2L loop
+DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 
 
 def sources():

@@ -219,32 +219,29 @@ template <> struct LdsTile<double> {
 
 // SPLIT: compiled separately for split-K launches (offset slices written to a
 // partial buffer) and whole launches, so profiles tell the finest level apart.
-template <typename T, bool SPLIT>
+// NRB: row blocks of this launch (rows 16 rb0 .. 16 (rb0 + NRB) - 1), a
+// compile-time constant so that the chunk loop is straight-line code (a
+// run-time row count turned every MFMA into a branch and forced full
+// memory waits inside the compute section).
+template <typename T, bool SPLIT, int NRB>
 __global__ __launch_bounds__(256) void k_m2l_lds(const T *__restrict__ ops, const int32_t *__restrict__ il,
                                                  const int32_t *__restrict__ offs, const T *__restrict__ M,
-                                                 T *__restrict__ L, int nh_bits, int NB, int Kp, int nrg,
+                                                 T *__restrict__ L, int nh_bits, int NB, int Kp, int rb0,
                                                  int nslices_arg) {
     const int nslices = SPLIT ? nslices_arg : 1;
-    constexpr int NRW = kRowBlocksPerWave;
-    constexpr int CHUNK = NRW * 64;  // vec4 entries per chunk slot
-    constexpr int U = LdsTile<T>::U;
-    constexpr bool F64 = LdsTile<T>::kFlush64;
+    constexpr int CHUNK = NRB * 64;             // vec4 entries per operator chunk
     constexpr int PER_T = (CHUNK + 255) / 256;  // vec4 loads per thread per chunk
+    constexpr bool F64 = LdsTile<T>::kFlush64;
     using V = typename Mfma<T>::V;
-    __shared__ V lds[2][U][CHUNK];
+    __shared__ V lds[2][CHUNK];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
     const int parity = blockIdx.x & 7;
-    int rest = blockIdx.x >> 3;
-    const int rg = rest % nrg;
-    rest /= nrg;
+    const int rest = blockIdx.x >> 3;
     const int slice = rest % nslices;
     const int tile = rest / nslices;
-    const int rb0 = rg * NRW;
-    const int nrb = min(NRW, NB - rb0);
-    const int nent = nrb * 64;
     const uint32_t ntarget = 1u << (3 * nh_bits);
     const uint32_t nmask = (2u << nh_bits) - 1u;
 
@@ -258,131 +255,114 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const T *__restrict__ ops, cons
     const uint32_t tcell = 8 * P + (uint32_t)parity;
 
     const int t0 = slice * kILSize / nslices, t1 = (slice + 1) * kILSize / nslices;
-    const int nchunk = (t1 - t0) * NB;
-    const int nstage = (nchunk + U - 1) / U;
+    const int nstage = (t1 - t0) * NB;  // one (offset, 16-coefficient chunk) per stage
     const size_t op_stride = (size_t)NB * NB * 64;  // vec4 entries per offset
     const V *opsv = reinterpret_cast<const V *>(ops);
     const int32_t *ilp = il + parity * kILSize;
+    // entries of a chunk this thread stages: tid + 256 v; only the last v can
+    // fall past the chunk, and that load is clamped into it (stored only when
+    // inside)
+    const int e_last = min(tid + 256 * (PER_T - 1), CHUNK - 1);
+    const bool last_in = tid + 256 * (PER_T - 1) < CHUNK;
 
-    // chunk cursor (t, kc) advanced one chunk at a time; oid and the
-    // multipole row of this lane's source cell change only with t
+    // chunk cursor (t, kc) advanced one chunk at a time; the operator id and
+    // the multipole row of this lane's source cell change only with t
     struct Cursor {
-        int t, kc, oid;
-        const T *src;
+        int t, kc;
+        size_t base;     // first vec4 entry of the chunk
+        const T *src;    // this lane's 4 coefficients of the source multipole
     };
     auto set_t = [&](Cursor &c, int t) {
         c.t = t;
         c.kc = 0;
-        if (t >= t1) return;
-        c.oid = ilp[t];
-        const uint32_t sx = (tx + (uint32_t)offs[3 * c.oid]) & nmask;
-        const uint32_t sy = (ty + (uint32_t)offs[3 * c.oid + 1]) & nmask;
-        const uint32_t sz = (tz + (uint32_t)offs[3 * c.oid + 2]) & nmask;
+        const int oid = ilp[min(t, t1 - 1)];  // past the end: stay on a valid chunk
+        const uint32_t sx = (tx + (uint32_t)offs[3 * oid]) & nmask;
+        const uint32_t sy = (ty + (uint32_t)offs[3 * oid + 1]) & nmask;
+        const uint32_t sz = (tz + (uint32_t)offs[3 * oid + 2]) & nmask;
         c.src = M + (size_t)morton3(sx, sy, sz) * Kp + 4 * (lane >> 4);
+        c.base = (size_t)oid * op_stride + (size_t)rb0 * 64;
     };
     auto advance = [&](Cursor &c) {
         if (++c.kc == NB) set_t(c, c.t + 1);
+        else c.base += (size_t)NB * 64;
     };
 
-    V acc[NRW];
-    double hi[NRW][4];
+    V acc[NRB];
+    double hi[F64 ? NRB : 1][4];
 #pragma unroll
-    for (int rb = 0; rb < NRW; ++rb) {
-        acc[rb] = V{0, 0, 0, 0};
+    for (int rb = 0; rb < NRB; ++rb) acc[rb] = V{0, 0, 0, 0};
+    if constexpr (F64)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) hi[rb][r] = 0.0;
-    }
+        for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) hi[rb][r] = 0.0;
 
-    Cursor cc, pc;  // compute cursor, prefetch cursor
-    set_t(cc, t0);
+    Cursor pc;  // prefetch cursor; the compute side only needs kc
     set_t(pc, t0);
-    V pre[U][PER_T];
-    V bcur[U], bnext[U];
-    bool last_of_t[U];
+    int kc = 0;
 
-    // prologue: stage 0
+    // prologue: stage 0 into LDS buffer 0
+    V bcur;
+    {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        if (pc.t < t1) {
-            const size_t base = (size_t)pc.oid * op_stride + ((size_t)pc.kc * NB + rb0) * 64;
-#pragma unroll
-            for (int v = 0; v < PER_T; ++v) {
-                const int e = tid + 256 * v;
-                if (e < nent) lds[0][u][e] = opsv[base + e];
-            }
-            bcur[u] = *reinterpret_cast<const V *>(pc.src + 16 * pc.kc);
-            advance(pc);
-        }
+        for (int v = 0; v < PER_T - 1; ++v) lds[0][tid + 256 * v] = opsv[pc.base + tid + 256 * v];
+        const V x = opsv[pc.base + e_last];
+        if (last_in) lds[0][e_last] = x;
+        bcur = *reinterpret_cast<const V *>(pc.src + 16 * pc.kc);
+        advance(pc);
     }
+    // Drain every prologue load: the compiler's wait bookkeeping would
+    // otherwise carry the pending bcur load into the loop and put a full
+    // memory wait in front of each stage's first MFMA.
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
     for (int st = 0; st < nstage; ++st) {
         const int cur = st & 1;
-        // prefetch the next stage's operator chunks and multipole fragments
+        // prefetch the next chunk (on the last stage: a harmless re-read of a
+        // valid chunk) into registers
+        V pre[PER_T];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (pc.t < t1) {
-                const size_t base = (size_t)pc.oid * op_stride + ((size_t)pc.kc * NB + rb0) * 64;
+        for (int v = 0; v < PER_T - 1; ++v) pre[v] = opsv[pc.base + tid + 256 * v];
+        pre[PER_T - 1] = opsv[pc.base + e_last];
+        const V bnext = *reinterpret_cast<const V *>(pc.src + 16 * pc.kc);
+        advance(pc);
+        // this stage on the matrix cores
+        V a[NRB];
 #pragma unroll
-                for (int v = 0; v < PER_T; ++v) {
-                    const int e = tid + 256 * v;
-                    if (e < nent) pre[u][v] = opsv[base + e];
-                }
-                bnext[u] = *reinterpret_cast<const V *>(pc.src + 16 * pc.kc);
-                advance(pc);
-            }
-        }
-        // compute this stage
+        for (int rb = 0; rb < NRB; ++rb) a[rb] = lds[cur][rb * 64 + lane];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            last_of_t[u] = false;
-            if (cc.t < t1) {
-                V a[NRW];
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int rb = 0; rb < NRW; ++rb)
-                    if (rb < nrb) a[rb] = lds[cur][u][rb * 64 + lane];
+            for (int rb = 0; rb < NRB; ++rb) acc[rb] = Mfma<T>::mma(a[rb][j], bcur[j], acc[rb]);
+        if (++kc == NB) {
+            kc = 0;
+            if constexpr (F64) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-#pragma unroll
-                    for (int rb = 0; rb < NRW; ++rb)
-                        if (rb < nrb) acc[rb] = Mfma<T>::mma(a[rb][j], bcur[u][j], acc[rb]);
-                last_of_t[u] = (cc.kc == NB - 1);
-                advance(cc);
-            }
-            if (F64 && last_of_t[u]) {
-#pragma unroll
-                for (int rb = 0; rb < NRW; ++rb) {
+                for (int rb = 0; rb < NRB; ++rb) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) hi[rb][r] += (double)acc[rb][r];
                     acc[rb] = V{0, 0, 0, 0};
                 }
             }
         }
-        // publish the prefetched stage
-        if (st + 1 < nstage) {
+        // publish the prefetched chunk for the next stage
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-#pragma unroll
-                for (int v = 0; v < PER_T; ++v) {
-                    const int e = tid + 256 * v;
-                    if (e < nent) lds[cur ^ 1][u][e] = pre[u][v];
-                }
-                bcur[u] = bnext[u];
-            }
-        }
+        for (int v = 0; v < PER_T - 1; ++v) lds[cur ^ 1][tid + 256 * v] = pre[v];
+        if (last_in) lds[cur ^ 1][e_last] = pre[PER_T - 1];
+        bcur = bnext;
         __syncthreads();
     }
 
     if (!valid) return;
     T *out = L + (size_t)slice * ((size_t)8 << (3 * nh_bits)) * Kp;
 #pragma unroll
-    for (int rb = 0; rb < NRW; ++rb)
-        if (rb < nrb)
+    for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = 16 * (rb0 + rb) + Mfma<T>::row(lane, r);
-                out[(size_t)tcell * Kp + row] = F64 ? (T)(hi[rb][r] + (double)acc[rb][r]) : acc[rb][r];
-            }
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * (rb0 + rb) + Mfma<T>::row(lane, r);
+            out[(size_t)tcell * Kp + row] = F64 ? (T)(hi[rb][r] + (double)acc[rb][r]) : acc[rb][r];
+        }
 }
 
 // Sum of the split-K partial results in slice order (deterministic).
@@ -396,30 +376,29 @@ __global__ void k_m2l_reduce(const T *__restrict__ partial, T *__restrict__ L, i
     }
 }
 
-// Slices per level: enough workgroups (>= ~1024) to fill 256 CUs at two
+// Slices per level: enough workgroups (>= ~512) to fill 256 CUs at two
 // resident workgroups each; levels >= 5 have enough targets on their own.
 int m2l_slices(int level) {
     switch (level) {
         case 1: return 64;
         case 2: return 64;
-        case 3: return 32;
+        case 3: return 64;
         case 4: return 32;
         default: return 1;
     }
 }
 
-// Levels from this one on use the LDS-shared kernel (many target cells);
-// for FP32 the per-wave offset-split kernel is kept at every level unless
-// m2l_variant selects otherwise (0 = default, 1 = offset-split kernel at
-// every level, 2 = LDS-shared kernel from level 4 on).
-constexpr int kLdsLevel = 4;
+// Levels from this one on use the LDS-shared kernel (measured on the 1M-atom
+// box: level 3 in FP64 with 64 slices 0.4 ms faster than the offset-split
+// kernel); the two coarsest levels (aliased lists of 8 and 64 entries) use the
+// offset-split kernel.  m2l_variant 1 forces the offset-split kernel everywhere
+// (tuning and cross-checks).
+constexpr int kLdsLevel = 3;
 static int g_m2l_variant = 0;
 void set_m2l_variant(int v) { g_m2l_variant = v; }
 template <typename T> static bool use_lds_kernel(int level) {
     if (level < kLdsLevel) return false;
-    if (g_m2l_variant == 1) return false;
-    if (g_m2l_variant == 2) return true;
-    return true;  // default: LDS-shared kernel from level 4 on
+    return g_m2l_variant != 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -670,15 +649,31 @@ hipError_t launch_m2l(int level, const T *ops, const int32_t *il, const int32_t 
     const int nslices = partial ? std::min(m2l_slices(level), nil) : 1;
     if (use_lds_kernel<T>(level)) {
         if (nil != kILSize) return hipErrorInvalidValue;  // the LDS kernel walks the full list
-        const int nrg = (NB + kRowBlocksPerWave - 1) / kRowBlocksPerWave;
         const int64_t ntile = (ntarget + 63) / 64;
-        const int64_t grid = 8 * ntile * nslices * nrg;
-        if (nslices > 1)
-            hipLaunchKernelGGL((k_m2l_lds<T, true>), dim3((unsigned)grid), dim3(256), 0, s, ops, il, offs, M, partial,
-                               nh_bits, NB, Kp, nrg, nslices);
-        else
-            hipLaunchKernelGGL((k_m2l_lds<T, false>), dim3((unsigned)grid), dim3(256), 0, s, ops, il, offs, M, L,
-                               nh_bits, NB, Kp, nrg, 1);
+        const int64_t grid = 8 * ntile * nslices;
+        T *out = nslices > 1 ? partial : L;
+        // one launch per group of up to kRowBlocksPerWave row blocks
+        for (int rb0 = 0; rb0 < NB; rb0 += kRowBlocksPerWave) {
+            const int nrb = std::min(kRowBlocksPerWave, NB - rb0);
+            hipError_t e = hipSuccess;
+            switch (nrb) {
+#define FMM_M2L_LDS_CASE(N)                                                                                     \
+    case N:                                                                                                     \
+        if (nslices > 1)                                                                                        \
+            hipLaunchKernelGGL((k_m2l_lds<T, true, N>), dim3((unsigned)grid), dim3(256), 0, s, ops, il, offs, M, \
+                               out, nh_bits, NB, Kp, rb0, nslices);                                             \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_m2l_lds<T, false, N>), dim3((unsigned)grid), dim3(256), 0, s, ops, il, offs, \
+                               M, out, nh_bits, NB, Kp, rb0, 1);                                                \
+        break;
+                FMM_M2L_LDS_CASE(1) FMM_M2L_LDS_CASE(2) FMM_M2L_LDS_CASE(3) FMM_M2L_LDS_CASE(4)
+                FMM_M2L_LDS_CASE(5) FMM_M2L_LDS_CASE(6) FMM_M2L_LDS_CASE(7) FMM_M2L_LDS_CASE(8)
+                FMM_M2L_LDS_CASE(9) FMM_M2L_LDS_CASE(10) FMM_M2L_LDS_CASE(11)
+#undef FMM_M2L_LDS_CASE
+                default: return hipErrorInvalidValue;
+            }
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     } else {
         const int64_t ntile = (ntarget + 16 * CB - 1) / (16 * CB);
         const int64_t grid = 8 * ntile * nslices;
