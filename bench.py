@@ -34,7 +34,12 @@ sys.path.insert(0, ROOT)
 M2L_IL = 875  # interaction-list size per cell
 PEAK_TFLOPS = {"mixed": 157.3, "bf16": 2500.0, "fp64": 78.6}  # dense MFMA peaks of MI355X (FP32, BF16, FP64)
 PREC_NAMES = {"fp64": 0, "mixed": 1, "bf16": 2}
-LEAF_KERNEL = {"mixed": "k_m2l_lds<float, false>", "fp64": "k_m2l_lds<double, false>", "bf16": "k_m2l_bf16<false>"}
+def leaf_kernel(prec_name, p):
+    """Name of the finest-level M2L kernel (first row group) for this order."""
+    if prec_name == "bf16":
+        return "k_m2l_bf16<false>"
+    nb = ((p + 1) ** 2 + 15) // 16
+    return f"k_m2l_lds<{'double' if prec_name == 'fp64' else 'float'}, false, {min(11, nb)}>"
 
 
 def m2l_flops(p, level):
@@ -140,7 +145,7 @@ def run_single(args, w, p, prec_name, steps, warmup, fp64_leg, cpu_leg):
     m2l_ms = st["m2l_leaf"]
     achieved = flops_leaf / (m2l_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec_name]
-    kernel = LEAF_KERNEL[prec_name]
+    kernel = leaf_kernel(prec_name, p)
     workload = f"{w.name} levels {w.levels} p {p}"
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": recorded_traffic(kernel, workload),
