@@ -170,18 +170,25 @@ __device__ inline int degree_of(int idx) {
 // ---------------------------------------------------------------------------
 // Level 0 (eq. 12 applied through eq. Lcoeffdef): L~(0) = A_T M~(0), FP64.
 // ---------------------------------------------------------------------------
-__global__ void k_lattice(const double *__restrict__ M0, double *__restrict__ L0,
-                          const double *__restrict__ AT, int K, int Kp) {
-    for (int row = threadIdx.x; row < Kp; row += blockDim.x) {
-        double acc = 0.0;
-        if (row < K)
-            for (int c = 0; c < K; ++c) acc += AT[(size_t)c * K + row] * M0[c];
-        L0[row] = acc;
-    }
+// Rows in blocks of 64 (one per thread of a wavefront); the four wavefronts
+// of a workgroup take interleaved quarters of the columns and their partial
+// sums are added through LDS in a fixed order.  AT is stored transposed
+// ([col][row]), so a wavefront reads 64 consecutive doubles per column.
+__global__ __launch_bounds__(256) void k_lattice(const double *__restrict__ M0, double *__restrict__ L0,
+                                                 const double *__restrict__ AT, int K, int Kp) {
+    __shared__ double part[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int row = blockIdx.x * 64 + lane;
+    double acc = 0.0;
+    if (row < K)
+        for (int c = w; c < K; c += 4) acc += AT[(size_t)c * K + row] * M0[c];
+    part[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && row < Kp) L0[row] = row < K ? ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane] : 0.0;
 }
 
 hipError_t launch_lattice(const double *M0, double *L0, const double *AT, int p, int Kp, hipStream_t s) {
-    hipLaunchKernelGGL(k_lattice, dim3(1), dim3(256), 0, s, M0, L0, AT, num_coeffs(p), Kp);
+    hipLaunchKernelGGL(k_lattice, dim3((unsigned)((Kp + 63) / 64)), dim3(256), 0, s, M0, L0, AT, num_coeffs(p), Kp);
     return hipGetLastError();
 }
 

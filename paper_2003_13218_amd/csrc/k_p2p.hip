@@ -125,41 +125,51 @@ template hipError_t launch_p2p<double>(int64_t, int, const void *, const int32_t
                                        double *, double *, int, hipStream_t);
 
 // Near-field solute-solvent pairs: out[s] = q_s sum_{j in NF(s), solvent} q_j / r
-// for solute atoms s (0 for solvent).  One thread per sorted atom; FP64 sum
-// of terms evaluated in the mode's precision.
+// for solute atoms s (0 for solvent).  One wavefront per leaf: the lanes flag
+// the leaf's solute atoms; for each of them (wave-uniform loop) the lanes
+// split the solvent sources of the 125 neighbour leaves, each lane summing its
+// terms in FP64, then a fixed shuffle tree adds the lane sums.  Leaves without
+// solute atoms only write zeros.
 template <typename T>
-__global__ void k_p2p_uv(int64_t n, int levels, const T *__restrict__ xq, const int32_t *__restrict__ start,
-                         const int32_t *__restrict__ perm, const uint8_t *__restrict__ mask, T h,
-                         double *__restrict__ out) {
-    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
-         s += (int64_t)gridDim.x * blockDim.x) {
-        if (!mask[perm[s]]) { out[s] = 0.0; continue; }
-        // locate the leaf of s: binary search in start[]
-        const int64_t nleaf = (int64_t)1 << (3 * levels);
-        int64_t lo = 0, hi = nleaf;  // start[lo] <= s < start[hi]
-        while (hi - lo > 1) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (start[mid] <= s) lo = mid; else hi = mid;
-        }
-        uint32_t cx, cy, cz;
-        demorton3((uint32_t)lo, cx, cy, cz);
-        const uint32_t nmask = (1u << levels) - 1u;
-        const T xi = xq[4 * s], yi = xq[4 * s + 1], zi = xq[4 * s + 2], qi = xq[4 * s + 3];
-        double acc = 0.0;
-        for (int dx = -kWS; dx <= kWS; ++dx)
-            for (int dy = -kWS; dy <= kWS; ++dy)
-                for (int dz = -kWS; dz <= kWS; ++dz) {
-                    const uint32_t sc = morton3((cx + dx) & nmask, (cy + dy) & nmask, (cz + dz) & nmask);
-                    for (int32_t j = start[sc]; j < start[sc + 1]; ++j) {
-                        if (mask[perm[j]]) continue;
-                        const T ddx = xi - ((T)dx * h + xq[4 * (int64_t)j]);
-                        const T ddy = yi - ((T)dy * h + xq[4 * (int64_t)j + 1]);
-                        const T ddz = zi - ((T)dz * h + xq[4 * (int64_t)j + 2]);
-                        const T r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-                        acc += (double)(xq[4 * (int64_t)j + 3] * rsqrt_t<T>(r2));
+__global__ __launch_bounds__(256) void k_p2p_uv(int64_t nleaf, int levels, const T *__restrict__ xq,
+                                                const int32_t *__restrict__ start,
+                                                const int32_t *__restrict__ perm, const uint8_t *__restrict__ mask,
+                                                T h, double *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t leaf = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    if (leaf >= nleaf) return;  // whole wavefront; no block barriers below
+    uint32_t cx, cy, cz;
+    demorton3((uint32_t)leaf, cx, cy, cz);
+    const uint32_t nmask = (1u << levels) - 1u;
+    const int32_t s0 = start[leaf], s1 = start[leaf + 1];
+    for (int32_t base = s0; base < s1; base += 64) {
+        const int32_t i = base + lane;
+        const bool is_u = i < s1 && mask[perm[i]] != 0;
+        if (i < s1 && !is_u) out[i] = 0.0;
+        uint64_t todo = __ballot(is_u);
+        while (todo) {
+            const int k = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int32_t a = base + k;  // wave-uniform solute atom
+            const T xi = xq[4 * (int64_t)a], yi = xq[4 * (int64_t)a + 1], zi = xq[4 * (int64_t)a + 2];
+            double acc = 0.0;
+            for (int dx = -kWS; dx <= kWS; ++dx)
+                for (int dy = -kWS; dy <= kWS; ++dy)
+                    for (int dz = -kWS; dz <= kWS; ++dz) {
+                        const uint32_t sc = morton3((cx + dx) & nmask, (cy + dy) & nmask, (cz + dz) & nmask);
+                        const T ox = xi - (T)dx * h, oy = yi - (T)dy * h, oz = zi - (T)dz * h;
+                        for (int32_t j = start[sc] + lane; j < start[sc + 1]; j += 64) {
+                            if (mask[perm[j]]) continue;
+                            const T *bj = xq + 4 * (int64_t)j;
+                            const T ddx = ox - bj[0], ddy = oy - bj[1], ddz = oz - bj[2];
+                            const T r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                            acc += (double)(bj[3] * rsqrt_t<T>(r2));
+                        }
                     }
-                }
-        out[s] = (double)qi * acc;
+#pragma unroll
+            for (int m = 1; m < 64; m <<= 1) acc += __shfl_xor(acc, m);
+            if (lane == 0) out[a] = (double)xq[4 * (int64_t)a + 3] * acc;
+        }
     }
 }
 
@@ -167,10 +177,9 @@ template <typename T>
 hipError_t launch_p2p_uv(int64_t n, int levels, const void *xq, const int32_t *start, const int32_t *perm,
                          const uint8_t *mask, double h, double *out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    int64_t g = (n + 255) / 256;
-    if (g > 65535) g = 65535;
-    hipLaunchKernelGGL(k_p2p_uv<T>, dim3((unsigned)g), dim3(256), 0, s, n, levels, (const T *)xq, start, perm,
-                       mask, (T)h, out);
+    const int64_t nleaf = (int64_t)1 << (3 * levels);
+    hipLaunchKernelGGL(k_p2p_uv<T>, dim3((unsigned)((nleaf + 3) / 4)), dim3(256), 0, s, nleaf, levels,
+                       (const T *)xq, start, perm, mask, (T)h, out);
     return hipGetLastError();
 }
 template hipError_t launch_p2p_uv<float>(int64_t, int, const void *, const int32_t *, const int32_t *,
