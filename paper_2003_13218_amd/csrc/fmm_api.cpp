@@ -634,8 +634,15 @@ static fmm_status run_fields(fmm_plan_t pl, int64_t n, const double *pos, const 
                                scan_scratch_len(nleaf), ns), "scan");
         HIPCHK(pl, launch_pad_gather(nleaf, pl->start.as<int32_t>(), pl->pstart.as<int32_t>(), pl->prec == FMM_FP64,
                                      pl->xq.ptr, 16.0 * pl->box, pl->xqp.ptr, ns), "pad gather");
+        // target chunks of TS = 64 / groups atoms; enough wavefronts per leaf
+        // to cover the mean occupancy once, and at least 64k wavefronts
+        const double occ = (double)n / (double)nleaf;
+        int nsplit = (int)std::ceil(occ / (64.0 / groups));
+        while (nsplit < 8 && nleaf * nsplit < 65536) nsplit *= 2;
+        nsplit = std::max(1, std::min(nsplit, 8));
+        while (nsplit > 1 && nleaf * nsplit >= ((int64_t)1 << 31)) nsplit /= 2;  // wavefront ids stay int
         HIPCHK(pl, launch_p2p<T>(nleaf, pl->levels, pl->xqp.ptr, pl->pstart.as<int32_t>(), pl->start.as<int32_t>(),
-                                 h_leaf, pl->phi_nf.as<double>(), pl->field_nf.as<T>(), groups, ns), "P2P");
+                                 h_leaf, pl->phi_nf.as<double>(), pl->field_nf.as<T>(), groups, nsplit, ns), "P2P");
         stage_end(pl, FMM_STAGE_P2P, ns);
         if (fork) HIPCHK(pl, hipEventRecord(pl->ev_join, ns), "event record");
         return FMM_OK;

@@ -56,12 +56,16 @@ __device__ inline void p2p_leaf(const typename Vec4<T>::type *__restrict__ bp, i
 template <typename T, int G>
 __global__ __launch_bounds__(256) void k_p2p(int64_t nleaf, int levels, const T *__restrict__ xqp,
                                              const int32_t *__restrict__ pstart, const int32_t *__restrict__ start,
-                                             T h, double *__restrict__ phi, T *__restrict__ field) {
+                                             T h, double *__restrict__ phi, T *__restrict__ field, int nsplit) {
     using V4 = typename Vec4<T>::type;
     constexpr int TS = 64 / G;
     const int lane = threadIdx.x & 63;
-    // wavefront-uniform leaf index: keeps the neighbour walk on the scalar unit
-    const int64_t leaf = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    // wavefront-uniform (leaf, part): keeps the neighbour walk on the scalar
+    // unit; the target chunks of a leaf are dealt round-robin to nsplit
+    // wavefronts so that small boxes still fill the chip
+    const int wv = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    const int64_t leaf = wv / nsplit;
+    const int part = wv % nsplit;
     if (leaf >= nleaf) return;  // whole wavefront; no block barriers below
     const int g = lane % G;
     const int a = lane / G;
@@ -71,7 +75,7 @@ __global__ __launch_bounds__(256) void k_p2p(int64_t nleaf, int levels, const T 
     const V4 *X = reinterpret_cast<const V4 *>(xqp);
     const int32_t s0 = start[leaf], cnt = start[leaf + 1] - s0;
     const int32_t p0 = pstart[leaf], pcnt = pstart[leaf + 1] - p0;
-    for (int32_t tb = 0; tb < cnt; tb += TS) {
+    for (int32_t tb = part * TS; tb < cnt; tb += nsplit * TS) {
         const int32_t t = tb + a;
         const int32_t tl = min(t, pcnt - 1);  // lanes past the leaf redo its last slot, unstored
         const V4 ti = X[p0 + tl];
@@ -106,23 +110,26 @@ __global__ __launch_bounds__(256) void k_p2p(int64_t nleaf, int levels, const T 
 
 template <typename T>
 hipError_t launch_p2p(int64_t nleaf, int levels, const void *xqp, const int32_t *pstart, const int32_t *start,
-                      double h, double *phi, T *field, int groups, hipStream_t s) {
-    const int64_t grid = (nleaf + 3) / 4;
+                      double h, double *phi, T *field, int groups, int nsplit, hipStream_t s) {
+    if (nsplit < 1 || nsplit > 64) return hipErrorInvalidValue;
+    const int64_t grid = (nleaf * nsplit + 3) / 4;
     const T *x = (const T *)xqp;
     switch (groups) {
-        case 1: hipLaunchKernelGGL((k_p2p<T, 1>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x, pstart, start, (T)h, phi, field); break;
-        case 2: hipLaunchKernelGGL((k_p2p<T, 2>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x, pstart, start, (T)h, phi, field); break;
-        case 4: hipLaunchKernelGGL((k_p2p<T, 4>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x, pstart, start, (T)h, phi, field); break;
-        case 8: hipLaunchKernelGGL((k_p2p<T, 8>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x, pstart, start, (T)h, phi, field); break;
-        case 16: hipLaunchKernelGGL((k_p2p<T, 16>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x, pstart, start, (T)h, phi, field); break;
+#define FMM_P2P_CASE(G)                                                                                    \
+    case G:                                                                                                \
+        hipLaunchKernelGGL((k_p2p<T, G>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x, pstart, \
+                           start, (T)h, phi, field, nsplit);                                              \
+        break;
+        FMM_P2P_CASE(1) FMM_P2P_CASE(2) FMM_P2P_CASE(4) FMM_P2P_CASE(8) FMM_P2P_CASE(16)
+#undef FMM_P2P_CASE
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 template hipError_t launch_p2p<float>(int64_t, int, const void *, const int32_t *, const int32_t *, double,
-                                      double *, float *, int, hipStream_t);
+                                      double *, float *, int, int, hipStream_t);
 template hipError_t launch_p2p<double>(int64_t, int, const void *, const int32_t *, const int32_t *, double,
-                                       double *, double *, int, hipStream_t);
+                                       double *, double *, int, int, hipStream_t);
 
 // Near-field solute-solvent pairs: out[s] = q_s sum_{j in NF(s), solvent} q_j / r
 // for solute atoms s (0 for solvent).  One wavefront per leaf: the lanes flag
