@@ -22,6 +22,7 @@
 //     dispatch of workgroups to the 8 XCDs every XCD streams one class's 875
 //     operators through its own L2.
 #include <algorithm>
+#include <type_traits>
 #include <cstring>
 
 #include "fmm_internal.h"
@@ -207,33 +208,97 @@ __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ ops, const in
 //     (11 chunks x 4 steps) instead of 875 offsets.
 // Split-K over offset slices is available as for k_m2l.
 // ---------------------------------------------------------------------------
-template <typename T> struct LdsTile;
-template <> struct LdsTile<float> {
-    static constexpr int U = 1;  // chunks per LDS stage
-    static constexpr bool kFlush64 = true;
+// Operand policies of the LDS-shared kernel.  A chunk is one (offset,
+// KW-coefficient column block); its operator fragments are NRB row blocks x
+// 64 lanes of 16-byte A operands.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <typename T> struct PolMfma {  // FP32 or FP64 operands, v_mfma_*_16x16x4
+    using S = T;                          // storage type of M and L
+    using A = typename Mfma<T>::V;        // 16-byte (FP32) / 32-byte (FP64) operator fragment
+    using B = typename Mfma<T>::V;
+    using Acc = typename Mfma<T>::V;
+    using R = B;                          // multipole fragment as loaded
+    static constexpr int KW = 16;
+    static constexpr bool kFlush64 = sizeof(T) == 4;
+    __device__ static R load_b(const S *p, bool in) {
+        return in ? *reinterpret_cast<const R *>(p) : R{0, 0, 0, 0};
+    }
+    __device__ static B to_b(const R &r) { return r; }
+    __device__ static Acc mma(const A &a, const B &b, Acc c) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c = Mfma<T>::mma(a[j], b[j], c);
+        return c;
+    }
 };
-template <> struct LdsTile<double> {
-    static constexpr int U = 1;
+struct PolBf16 {  // BF16 operands, FP32 storage and accumulation, v_mfma_f32_16x16x32_bf16
+    using S = float;
+    using A = bf16x8;
+    using B = bf16x8;
+    using Acc = f32x4;
+    typedef float R __attribute__((ext_vector_type(8)));  // loaded as FP32, rounded at use
+    static constexpr int KW = 32;
     static constexpr bool kFlush64 = false;
+    __device__ static R load_b(const S *p, bool in) {
+        return in ? *reinterpret_cast<const R *>(p) : R{0, 0, 0, 0, 0, 0, 0, 0};
+    }
+    __device__ static B to_b(const R &r) {
+        B b;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) b[i] = (__bf16)r[i];
+        return b;
+    }
+    __device__ static Acc mma(const A &a, const B &b, Acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
 };
 
-// SPLIT: compiled separately for split-K launches (offset slices written to a
-// partial buffer) and whole launches, so profiles tell the finest level apart.
-// NRB: row blocks of this launch (rows 16 rb0 .. 16 (rb0 + NRB) - 1), a
-// compile-time constant so that the chunk loop is straight-line code (a
-// run-time row count turned every MFMA into a branch and forced full
-// memory waits inside the compute section).
-template <typename T, bool SPLIT, int NRB>
-__global__ __launch_bounds__(256) void k_m2l_lds(const T *__restrict__ ops, const int32_t *__restrict__ il,
-                                                 const int32_t *__restrict__ offs, const T *__restrict__ M,
-                                                 T *__restrict__ L, int nh_bits, int NB, int Kp, int rb0,
-                                                 int nslices_arg) {
+// Chunks per LDS stage: enough matrix-core work per barrier (about 40 FP32
+// MFMA-equivalents) within 48 KB of double-buffered LDS and a few registers.
+template <typename P, int NRB> constexpr int stage_chunks() {
+    constexpr int bytes = (int)sizeof(typename P::A);                   // per lane and row block
+    constexpr int cyc = std::is_same<P, PolBf16>::value ? 16 : (bytes == 16 ? 4 * 32 : 4 * 64);
+    constexpr int want = (1280 + cyc * NRB - 1) / (cyc * NRB);
+    constexpr int lds_cap = (48 * 1024) / (2 * NRB * 64 * bytes);
+    constexpr int u = want < lds_cap ? want : lds_cap;
+    return u < 1 ? 1 : (u > 6 ? 6 : u);
+}
+
+// ---------------------------------------------------------------------------
+// M2L for levels with many cells: operator chunks shared through LDS.
+//   * a workgroup owns 4 x 16 target cells (one parity class) and NRB row
+//     blocks (rows 16 rb0 .. 16 (rb0 + NRB) - 1); its four wavefronts walk the
+//     same chunks (offset t, column block kc) in lockstep, each on its own 16
+//     targets;
+//   * U chunks per stage are loaded once per workgroup -- already in MFMA lane
+//     order -- into double-buffered LDS, prefetched into registers one stage
+//     ahead together with the multipole fragments; one barrier per stage;
+//   * NRB and U are compile-time constants so the stage is straight-line
+//     code: a run-time row count turned every MFMA into a branch and made the
+//     compiler wait for all outstanding loads before each stage's first MFMA;
+//     past the end of the list the prefetch re-reads a valid chunk and its
+//     multipole fragment is zero, so the extra products add nothing;
+//   * FP32: after each offset the matrix-core accumulators are added into FP64
+//     accumulators, so every FP32 rounding chain is one offset long;
+//   * blockIdx mod 8 = parity class (one class's operators per XCD L2).
+// SPLIT: split-K over offset slices (partials to a buffer, added in a fixed
+// order by k_m2l_reduce), compiled separately so profiles tell levels apart.
+// ---------------------------------------------------------------------------
+template <typename P, bool SPLIT, int NRB, int U>
+__global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict__ ops,
+                                                 const int32_t *__restrict__ il, const int32_t *__restrict__ offs,
+                                                 const typename P::S *__restrict__ M, typename P::S *__restrict__ L,
+                                                 int nh_bits, int NB, int NKC, int Kp, int rb0, int nslices_arg) {
+    using S = typename P::S;
+    using A = typename P::A;
+    using B = typename P::B;
+    using Acc = typename P::Acc;
+    using R = typename P::R;
+    constexpr bool F64 = P::kFlush64;
+    constexpr int CHUNK = NRB * 64;             // fragments per chunk
+    constexpr int PC = (CHUNK + 255) / 256;     // fragment loads per thread per chunk
+    __shared__ A lds[2][U * CHUNK];
     const int nslices = SPLIT ? nslices_arg : 1;
-    constexpr int CHUNK = NRB * 64;             // vec4 entries per operator chunk
-    constexpr int PER_T = (CHUNK + 255) / 256;  // vec4 loads per thread per chunk
-    constexpr bool F64 = LdsTile<T>::kFlush64;
-    using V = typename Mfma<T>::V;
-    __shared__ V lds[2][CHUNK];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -245,32 +310,28 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const T *__restrict__ ops, cons
     const uint32_t ntarget = 1u << (3 * nh_bits);
     const uint32_t nmask = (2u << nh_bits) - 1u;
 
-    const uint32_t P = (uint32_t)tile * 64 + (uint32_t)wid * 16 + (lane & 15);
-    const bool valid = P < ntarget;
+    const uint32_t Pt = (uint32_t)tile * 64 + (uint32_t)wid * 16 + (lane & 15);
+    const bool valid = Pt < ntarget;
     uint32_t tx, ty, tz;
-    demorton3(valid ? P : 0u, tx, ty, tz);
+    demorton3(valid ? Pt : 0u, tx, ty, tz);
     tx = 2 * tx + ((parity >> 2) & 1);
     ty = 2 * ty + ((parity >> 1) & 1);
     tz = 2 * tz + (parity & 1);
-    const uint32_t tcell = 8 * P + (uint32_t)parity;
+    const uint32_t tcell = 8 * Pt + (uint32_t)parity;
 
     const int t0 = slice * kILSize / nslices, t1 = (slice + 1) * kILSize / nslices;
-    const int nstage = (t1 - t0) * NB;  // one (offset, 16-coefficient chunk) per stage
-    const size_t op_stride = (size_t)NB * NB * 64;  // vec4 entries per offset
-    const V *opsv = reinterpret_cast<const V *>(ops);
+    const int nchunk = (t1 - t0) * NKC;
+    const int nstage = (nchunk + U - 1) / U;
+    const size_t op_stride = (size_t)NKC * NB * 64;  // fragments per offset
     const int32_t *ilp = il + parity * kILSize;
-    // entries of a chunk this thread stages: tid + 256 v; only the last v can
-    // fall past the chunk, and that load is clamped into it (stored only when
-    // inside)
-    const int e_last = min(tid + 256 * (PER_T - 1), CHUNK - 1);
-    const bool last_in = tid + 256 * (PER_T - 1) < CHUNK;
+    const int kq = (P::KW / 4) * (lane >> 4);        // this lane's k offset inside a chunk
 
-    // chunk cursor (t, kc) advanced one chunk at a time; the operator id and
-    // the multipole row of this lane's source cell change only with t
+    // chunk cursor (t, kc); the operator id and the multipole row of this
+    // lane's source cell change only with t
     struct Cursor {
         int t, kc;
-        size_t base;     // first vec4 entry of the chunk
-        const T *src;    // this lane's 4 coefficients of the source multipole
+        size_t base;   // first fragment of the chunk
+        const S *src;  // this lane's coefficients of the source multipole
     };
     auto set_t = [&](Cursor &c, int t) {
         c.t = t;
@@ -279,90 +340,156 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const T *__restrict__ ops, cons
         const uint32_t sx = (tx + (uint32_t)offs[3 * oid]) & nmask;
         const uint32_t sy = (ty + (uint32_t)offs[3 * oid + 1]) & nmask;
         const uint32_t sz = (tz + (uint32_t)offs[3 * oid + 2]) & nmask;
-        c.src = M + (size_t)morton3(sx, sy, sz) * Kp + 4 * (lane >> 4);
+        c.src = M + (size_t)morton3(sx, sy, sz) * Kp + kq;
         c.base = (size_t)oid * op_stride + (size_t)rb0 * 64;
     };
     auto advance = [&](Cursor &c) {
-        if (++c.kc == NB) set_t(c, c.t + 1);
+        if (++c.kc == NKC) set_t(c, c.t + 1);
         else c.base += (size_t)NB * 64;
     };
+    // the multipole fragment of the cursor's chunk: zero past the list (only
+    // reachable inside a stage when U > 1) and past Kp (only for 32-wide
+    // chunks, whose last one may stick out of the padded row)
+    auto frag_b = [&](const Cursor &c) -> R {
+        bool in = true;
+        if constexpr (U > 1) in = c.t < t1;
+        if constexpr (P::KW > 16) in = in && P::KW * c.kc + kq < Kp;
+        return P::load_b(c.src + P::KW * c.kc, in);
+    };
 
-    V acc[NRB];
+    Acc acc[NRB];
     double hi[F64 ? NRB : 1][4];
 #pragma unroll
-    for (int rb = 0; rb < NRB; ++rb) acc[rb] = V{0, 0, 0, 0};
+    for (int rb = 0; rb < NRB; ++rb) acc[rb] = Acc{0, 0, 0, 0};
     if constexpr (F64)
 #pragma unroll
         for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) hi[rb][r] = 0.0;
 
-    Cursor pc;  // prefetch cursor; the compute side only needs kc
+    Cursor pc;  // prefetch cursor
     set_t(pc, t0);
-    int kc = 0;
+    int kc = 0;  // compute side: column block of the next chunk
+    const int e_last = min(tid + 256 * (PC - 1), CHUNK - 1);
+    const bool last_in = tid + 256 * (PC - 1) < CHUNK;
 
     // prologue: stage 0 into LDS buffer 0
-    V bcur;
-    {
+    R bcur[U];
 #pragma unroll
-        for (int v = 0; v < PER_T - 1; ++v) lds[0][tid + 256 * v] = opsv[pc.base + tid + 256 * v];
-        const V x = opsv[pc.base + e_last];
-        if (last_in) lds[0][e_last] = x;
-        bcur = *reinterpret_cast<const V *>(pc.src + 16 * pc.kc);
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int v = 0; v < PC - 1; ++v) lds[0][u * CHUNK + tid + 256 * v] = ops[pc.base + tid + 256 * v];
+        const A x = ops[pc.base + e_last];
+        if (last_in) lds[0][u * CHUNK + e_last] = x;
+        bcur[u] = frag_b(pc);
         advance(pc);
     }
-    // Drain every prologue load: the compiler's wait bookkeeping would
-    // otherwise carry the pending bcur load into the loop and put a full
-    // memory wait in front of each stage's first MFMA.
+    // drain every prologue load: otherwise the compiler's wait bookkeeping
+    // carries them into the loop and waits on all loads before the MFMAs
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
     for (int st = 0; st < nstage; ++st) {
         const int cur = st & 1;
-        // prefetch the next chunk (on the last stage: a harmless re-read of a
-        // valid chunk) into registers
-        V pre[PER_T];
+        // prefetch the next stage (past the end: harmless re-reads)
+        A pre[U][PC];
+        R bnext[U];
 #pragma unroll
-        for (int v = 0; v < PER_T - 1; ++v) pre[v] = opsv[pc.base + tid + 256 * v];
-        pre[PER_T - 1] = opsv[pc.base + e_last];
-        const V bnext = *reinterpret_cast<const V *>(pc.src + 16 * pc.kc);
-        advance(pc);
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int v = 0; v < PC - 1; ++v) pre[u][v] = ops[pc.base + tid + 256 * v];
+            pre[u][PC - 1] = ops[pc.base + e_last];
+            bnext[u] = frag_b(pc);
+            // compiler-only barrier: keeps the loads above the cursor update
+            // (otherwise they are sunk below its branch, towards their use)
+            asm volatile("" ::: "memory");
+            advance(pc);
+        }
+        // keep the prefetch loads ahead of the matrix-core work (the
+        // scheduler would otherwise sink them towards their use at the end)
+        if constexpr (sizeof(A) == 16) __builtin_amdgcn_sched_barrier(0);
         // this stage on the matrix cores
-        V a[NRB];
 #pragma unroll
-        for (int rb = 0; rb < NRB; ++rb) a[rb] = lds[cur][rb * 64 + lane];
+        for (int u = 0; u < U; ++u) {
+            A a[NRB];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+            for (int rb = 0; rb < NRB; ++rb) a[rb] = lds[cur][u * CHUNK + rb * 64 + lane];
+            // all 16-byte fragment reads issued before the first MFMA (FP64
+            // fragments are twice as large: there the compiler's interleaving
+            // of reads and MFMAs is kept, measured faster)
+            if constexpr (sizeof(A) == 16) __builtin_amdgcn_sched_barrier(0);
+            const B b = P::to_b(bcur[u]);
 #pragma unroll
-            for (int rb = 0; rb < NRB; ++rb) acc[rb] = Mfma<T>::mma(a[rb][j], bcur[j], acc[rb]);
-        if (++kc == NB) {
-            kc = 0;
-            if constexpr (F64) {
+            for (int rb = 0; rb < NRB; ++rb) acc[rb] = P::mma(a[rb], b, acc[rb]);
+            if (++kc == NKC) {
+                kc = 0;
+                if constexpr (F64) {
 #pragma unroll
-                for (int rb = 0; rb < NRB; ++rb) {
+                    for (int rb = 0; rb < NRB; ++rb) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) hi[rb][r] += (double)acc[rb][r];
-                    acc[rb] = V{0, 0, 0, 0};
+                        for (int r = 0; r < 4; ++r) hi[rb][r] += (double)acc[rb][r];
+                        acc[rb] = Acc{0, 0, 0, 0};
+                    }
                 }
             }
         }
-        // publish the prefetched chunk for the next stage
+        // publish the prefetched stage: for 16-byte fragments after all of this
+        // stage's MFMAs, so the waits for the prefetch loads come as late as
+        // possible; FP64 stages are long enough that the compiler's placement
+        // of the LDS writes among the MFMAs hides their latency (measured)
+        if constexpr (sizeof(A) == 16) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int v = 0; v < PER_T - 1; ++v) lds[cur ^ 1][tid + 256 * v] = pre[v];
-        if (last_in) lds[cur ^ 1][e_last] = pre[PER_T - 1];
-        bcur = bnext;
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int v = 0; v < PC - 1; ++v) lds[cur ^ 1][u * CHUNK + tid + 256 * v] = pre[u][v];
+            if (last_in) lds[cur ^ 1][u * CHUNK + e_last] = pre[u][PC - 1];
+            bcur[u] = bnext[u];
+        }
         __syncthreads();
     }
 
     if (!valid) return;
-    T *out = L + (size_t)slice * ((size_t)8 << (3 * nh_bits)) * Kp;
+    S *out = L + (size_t)slice * ((size_t)8 << (3 * nh_bits)) * Kp;
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int row = 16 * (rb0 + rb) + Mfma<T>::row(lane, r);
-            out[(size_t)tcell * Kp + row] = F64 ? (T)(hi[rb][r] + (double)acc[rb][r]) : acc[rb][r];
+            const int row = 16 * (rb0 + rb) + Mfma<S>::row(lane, r);
+            out[(size_t)tcell * Kp + row] = F64 ? (S)(hi[rb][r] + (double)acc[rb][r]) : (S)acc[rb][r];
         }
+}
+
+// Launches the LDS-shared kernel for every group of up to kRowBlocksPerWave
+// row blocks (one launch per group, NRB and U fixed at compile time).
+template <typename P>
+static hipError_t launch_lds(const void *ops, const int32_t *il, const int32_t *offs, const typename P::S *M,
+                             typename P::S *out, int nh_bits, int NB, int NKC, int Kp, int nslices, hipStream_t s) {
+    using A = typename P::A;
+    const int64_t ntile = (((int64_t)1 << (3 * nh_bits)) + 63) / 64;
+    const int64_t grid = 8 * ntile * nslices;
+    const A *o = reinterpret_cast<const A *>(ops);
+    for (int rb0 = 0; rb0 < NB; rb0 += kRowBlocksPerWave) {
+        const int nrb = std::min(kRowBlocksPerWave, NB - rb0);
+        switch (nrb) {
+#define FMM_M2L_LDS_CASE(N)                                                                                    \
+    case N:                                                                                                    \
+        if (nslices > 1)                                                                                       \
+            hipLaunchKernelGGL((k_m2l_lds<P, true, N, stage_chunks<P, N>()>), dim3((unsigned)grid), dim3(256), \
+                               0, s, o, il, offs, M, out, nh_bits, NB, NKC, Kp, rb0, nslices);                \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_m2l_lds<P, false, N, stage_chunks<P, N>()>), dim3((unsigned)grid),          \
+                               dim3(256), 0, s, o, il, offs, M, out, nh_bits, NB, NKC, Kp, rb0, 1);           \
+        break;
+            FMM_M2L_LDS_CASE(1) FMM_M2L_LDS_CASE(2) FMM_M2L_LDS_CASE(3) FMM_M2L_LDS_CASE(4)
+            FMM_M2L_LDS_CASE(5) FMM_M2L_LDS_CASE(6) FMM_M2L_LDS_CASE(7) FMM_M2L_LDS_CASE(8)
+            FMM_M2L_LDS_CASE(9) FMM_M2L_LDS_CASE(10) FMM_M2L_LDS_CASE(11)
+#undef FMM_M2L_LDS_CASE
+            default: return hipErrorInvalidValue;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // Sum of the split-K partial results in slice order (deterministic).
@@ -414,8 +541,6 @@ template <typename T> static bool use_lds_kernel(int level) {
 // split-K are those of k_m2l_lds; accumulation stays in FP32 because the
 // BF16 operand rounding (2^-9 relative) dominates the error.
 // ---------------------------------------------------------------------------
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
 static inline uint16_t bf16_round(double v) {
     const float f = (float)v;
     uint32_t u;
@@ -446,187 +571,13 @@ void swizzle_m2l_ops_bf16(int p, const double *ops, uint16_t *out) {
     }
 }
 
-constexpr int kBf16Stage = 3;  // K chunks per LDS stage
-
-template <bool SPLIT>
-__global__ __launch_bounds__(256) void k_m2l_bf16(const bf16x8 *__restrict__ ops, const int32_t *__restrict__ il,
-                                                  const int32_t *__restrict__ offs, const float *__restrict__ M,
-                                                  float *__restrict__ L, int nh_bits, int NB, int NKC, int Kp,
-                                                  int nrg, int nslices_arg) {
-    const int nslices = SPLIT ? nslices_arg : 1;
-    constexpr int NRW = kRowBlocksPerWave;
-    constexpr int CHUNK = NRW * 64;  // 16-byte entries per chunk slot
-    constexpr int U = kBf16Stage;
-    constexpr int PER_T = (U * CHUNK + 255) / 256;
-    __shared__ bf16x8 lds[2][U * CHUNK];
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wid = tid >> 6;
-    const int parity = blockIdx.x & 7;
-    int rest = blockIdx.x >> 3;
-    const int rg = rest % nrg;
-    rest /= nrg;
-    const int slice = rest % nslices;
-    const int tile = rest / nslices;
-    const int rb0 = rg * NRW;
-    const int nrb = min(NRW, NB - rb0);
-    const uint32_t ntarget = 1u << (3 * nh_bits);
-    const uint32_t nmask = (2u << nh_bits) - 1u;
-
-    const uint32_t P = (uint32_t)tile * 64 + (uint32_t)wid * 16 + (lane & 15);
-    const bool valid = P < ntarget;
-    uint32_t tx, ty, tz;
-    demorton3(valid ? P : 0u, tx, ty, tz);
-    tx = 2 * tx + ((parity >> 2) & 1);
-    ty = 2 * ty + ((parity >> 1) & 1);
-    tz = 2 * tz + (parity & 1);
-    const uint32_t tcell = 8 * P + (uint32_t)parity;
-
-    const int t0 = slice * kILSize / nslices, t1 = (slice + 1) * kILSize / nslices;
-    const int nchunk = (t1 - t0) * NKC;
-    const int nstage = (nchunk + U - 1) / U;
-    const size_t op_stride = (size_t)NKC * NB * 64;  // 16-byte entries per offset
-    const int32_t *ilp = il + parity * kILSize;
-    const int kq = 8 * (lane >> 4);  // this lane's k offset inside a chunk
-
-    struct Cursor {
-        int t, kc, oid;
-        const float *src;
-    };
-    auto set_t = [&](Cursor &c, int t) {
-        c.t = t;
-        c.kc = 0;
-        if (t >= t1) return;
-        c.oid = ilp[t];
-        const uint32_t sx = (tx + (uint32_t)offs[3 * c.oid]) & nmask;
-        const uint32_t sy = (ty + (uint32_t)offs[3 * c.oid + 1]) & nmask;
-        const uint32_t sz = (tz + (uint32_t)offs[3 * c.oid + 2]) & nmask;
-        c.src = M + (size_t)morton3(sx, sy, sz) * Kp + kq;
-    };
-    auto advance = [&](Cursor &c) {
-        if (++c.kc == NKC) set_t(c, c.t + 1);
-    };
-    auto load_b = [&](const Cursor &c) -> bf16x8 {
-        bf16x8 b;
-        if (32 * c.kc + kq < Kp) {
-            const f32x4 x = *reinterpret_cast<const f32x4 *>(c.src + 32 * c.kc);
-            const f32x4 y = *reinterpret_cast<const f32x4 *>(c.src + 32 * c.kc + 4);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                b[i] = (__bf16)x[i];
-                b[4 + i] = (__bf16)y[i];
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) b[i] = (__bf16)0.0f;
-        }
-        return b;
-    };
-
-    f32x4 acc[NRW];
-#pragma unroll
-    for (int rb = 0; rb < NRW; ++rb) acc[rb] = f32x4{0, 0, 0, 0};
-
-    Cursor cc, pc;  // compute cursor, prefetch cursor
-    set_t(cc, t0);
-    set_t(pc, t0);
-    bf16x8 pre[PER_T];
-    bf16x8 bcur[U], bnext[U];
-    size_t base[U];  // first operator entry of each chunk of the prefetched stage
-    bool have[U];
-
-    // entry idx = tid + 256 v of a stage belongs to chunk slot idx / CHUNK
-    auto fetch_stage = [&](bf16x8 *dst_regs, bf16x8 *dst_lds, bf16x8 *bdst) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            have[u] = pc.t < t1;
-            if (have[u]) {
-                base[u] = (size_t)pc.oid * op_stride + ((size_t)pc.kc * NB + rb0) * 64;
-                bdst[u] = load_b(pc);
-                advance(pc);
-            }
-        }
-#pragma unroll
-        for (int v = 0; v < PER_T; ++v) {
-            const int idx = tid + 256 * v;
-            const int u = idx / CHUNK, e = idx % CHUNK;
-            if (u < U && e < nrb * 64 && have[u]) {
-                const bf16x8 x = ops[base[u] + e];
-                if (dst_lds) dst_lds[idx] = x;
-                else dst_regs[v] = x;
-            }
-        }
-    };
-
-    fetch_stage(nullptr, lds[0], bcur);
-    __syncthreads();
-
-    for (int st = 0; st < nstage; ++st) {
-        const int cur = st & 1;
-        const bool more = st + 1 < nstage;
-        bool hv[U];
-        if (more) {
-            fetch_stage(pre, nullptr, bnext);
-#pragma unroll
-            for (int u = 0; u < U; ++u) hv[u] = have[u];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (cc.t < t1) {
-                bf16x8 a[NRW];
-#pragma unroll
-                for (int rb = 0; rb < NRW; ++rb)
-                    if (rb < nrb) a[rb] = lds[cur][u * CHUNK + rb * 64 + lane];
-#pragma unroll
-                for (int rb = 0; rb < NRW; ++rb)
-                    if (rb < nrb) acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb], bcur[u], acc[rb], 0, 0, 0);
-                advance(cc);
-            }
-        }
-        if (more) {
-#pragma unroll
-            for (int v = 0; v < PER_T; ++v) {
-                const int idx = tid + 256 * v;
-                const int u = idx / CHUNK, e = idx % CHUNK;
-                if (u < U && e < nrb * 64 && hv[u]) lds[cur ^ 1][idx] = pre[v];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) bcur[u] = bnext[u];
-        }
-        __syncthreads();
-    }
-
-    if (!valid) return;
-    float *out = L + (size_t)slice * ((size_t)8 << (3 * nh_bits)) * Kp;
-#pragma unroll
-    for (int rb = 0; rb < NRW; ++rb)
-        if (rb < nrb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = 16 * (rb0 + rb) + Mfma<float>::row(lane, r);
-                out[(size_t)tcell * Kp + row] = acc[rb][r];
-            }
-}
-
 hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const int32_t *offs, const float *M,
                            float *L, float *partial, int p, int Kp, hipStream_t s) {
     const int NB = Kp / 16;
-    const int NKC = bf16_chunks(p);
     const int nh_bits = level - 1;
-    const int64_t ntarget = (int64_t)1 << (3 * nh_bits);
     const int nslices = partial ? m2l_slices(level) : 1;
-    const int nrg = (NB + kRowBlocksPerWave - 1) / kRowBlocksPerWave;
-    const int64_t ntile = (ntarget + 63) / 64;
-    const int64_t grid = 8 * ntile * nslices * nrg;
-    const bf16x8 *o = reinterpret_cast<const bf16x8 *>(ops);
-    if (nslices > 1)
-        hipLaunchKernelGGL((k_m2l_bf16<true>), dim3((unsigned)grid), dim3(256), 0, s, o, il, offs, M, partial,
-                           nh_bits, NB, NKC, Kp, nrg, nslices);
-    else
-        hipLaunchKernelGGL((k_m2l_bf16<false>), dim3((unsigned)grid), dim3(256), 0, s, o, il, offs, M, L, nh_bits,
-                           NB, NKC, Kp, nrg, 1);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_lds<PolBf16>(ops, il, offs, M, nslices > 1 ? partial : L, nh_bits, NB, bf16_chunks(p), Kp,
+                                       nslices, s);
     if (e != hipSuccess || nslices == 1) return e;
     const int64_t elems = ((int64_t)8 << (3 * nh_bits)) * Kp;
     int64_t g = (elems + 255) / 256;
@@ -649,31 +600,9 @@ hipError_t launch_m2l(int level, const T *ops, const int32_t *il, const int32_t 
     const int nslices = partial ? std::min(m2l_slices(level), nil) : 1;
     if (use_lds_kernel<T>(level)) {
         if (nil != kILSize) return hipErrorInvalidValue;  // the LDS kernel walks the full list
-        const int64_t ntile = (ntarget + 63) / 64;
-        const int64_t grid = 8 * ntile * nslices;
-        T *out = nslices > 1 ? partial : L;
-        // one launch per group of up to kRowBlocksPerWave row blocks
-        for (int rb0 = 0; rb0 < NB; rb0 += kRowBlocksPerWave) {
-            const int nrb = std::min(kRowBlocksPerWave, NB - rb0);
-            hipError_t e = hipSuccess;
-            switch (nrb) {
-#define FMM_M2L_LDS_CASE(N)                                                                                     \
-    case N:                                                                                                     \
-        if (nslices > 1)                                                                                        \
-            hipLaunchKernelGGL((k_m2l_lds<T, true, N>), dim3((unsigned)grid), dim3(256), 0, s, ops, il, offs, M, \
-                               out, nh_bits, NB, Kp, rb0, nslices);                                             \
-        else                                                                                                    \
-            hipLaunchKernelGGL((k_m2l_lds<T, false, N>), dim3((unsigned)grid), dim3(256), 0, s, ops, il, offs, \
-                               M, out, nh_bits, NB, Kp, rb0, 1);                                                \
-        break;
-                FMM_M2L_LDS_CASE(1) FMM_M2L_LDS_CASE(2) FMM_M2L_LDS_CASE(3) FMM_M2L_LDS_CASE(4)
-                FMM_M2L_LDS_CASE(5) FMM_M2L_LDS_CASE(6) FMM_M2L_LDS_CASE(7) FMM_M2L_LDS_CASE(8)
-                FMM_M2L_LDS_CASE(9) FMM_M2L_LDS_CASE(10) FMM_M2L_LDS_CASE(11)
-#undef FMM_M2L_LDS_CASE
-                default: return hipErrorInvalidValue;
-            }
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
+        const hipError_t e = launch_lds<PolMfma<T>>(ops, il, offs, M, nslices > 1 ? partial : L, nh_bits, NB, NB,
+                                                     Kp, nslices, s);
+        if (e != hipSuccess) return e;
     } else {
         const int64_t ntile = (ntarget + 16 * CB - 1) / (16 * CB);
         const int64_t grid = 8 * ntile * nslices;
