@@ -148,7 +148,7 @@ hipError_t launch_l2l_mfma(int64_t nparent, const Tin *Lparent, Tout *Lchild, co
 // k_p2p.hip
 template <typename T>
 hipError_t launch_p2p(int64_t nleaf, int levels, const void *xqp, const int32_t *pstart, const int32_t *start,
-                      double h, double *phi, T *field, int groups, int nsplit, hipStream_t s);
+                      double h, double *phi, T *field, int groups, int nsplit, int max_wg, hipStream_t s);
 template <typename T>
 hipError_t launch_p2p_uv(int64_t n, int levels, const void *xq, const int32_t *start,
                          const int32_t *perm, const uint8_t *mask, double h, double *out_per_atom,

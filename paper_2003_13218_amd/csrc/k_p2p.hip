@@ -60,59 +60,69 @@ __global__ __launch_bounds__(256) void k_p2p(int64_t nleaf, int levels, const T 
     using V4 = typename Vec4<T>::type;
     constexpr int TS = 64 / G;
     const int lane = threadIdx.x & 63;
-    // wavefront-uniform (leaf, part): keeps the neighbour walk on the scalar
-    // unit; the target chunks of a leaf are dealt round-robin to nsplit
-    // wavefronts so that small boxes still fill the chip
-    const int wv = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
-    const int64_t leaf = wv / nsplit;
-    const int part = wv % nsplit;
-    if (leaf >= nleaf) return;  // whole wavefront; no block barriers below
     const int g = lane % G;
     const int a = lane / G;
-    uint32_t cx, cy, cz;
-    demorton3((uint32_t)leaf, cx, cy, cz);
     const uint32_t nmask = (1u << levels) - 1u;
     const V4 *X = reinterpret_cast<const V4 *>(xqp);
-    const int32_t s0 = start[leaf], cnt = start[leaf + 1] - s0;
-    const int32_t p0 = pstart[leaf], pcnt = pstart[leaf + 1] - p0;
-    for (int32_t tb = part * TS; tb < cnt; tb += nsplit * TS) {
-        const int32_t t = tb + a;
-        const int32_t tl = min(t, pcnt - 1);  // lanes past the leaf redo its last slot, unstored
-        const V4 ti = X[p0 + tl];
-        double ph = 0;
-        T fx = 0, fy = 0, fz = 0;
-        p2p_leaf<T, G, true>(X + p0 + g, pcnt / G, ti.x, ti.y, ti.z, X + p0 + tl, ph, fx, fy, fz);
-        for (int c = 0; c < 125; ++c) {
-            if (c == 62) continue;  // offset (0, 0, 0): done above
-            const int dx = c / 25 - kWS, dy = (c / 5) % 5 - kWS, dz = c % 5 - kWS;
-            const uint32_t sc = morton3((cx + dx) & nmask, (cy + dy) & nmask, (cz + dz) & nmask);
-            const int32_t j0 = pstart[sc];
-            const int nk = (pstart[sc + 1] - j0) / G;
-            p2p_leaf<T, G, false>(X + j0 + g, nk, ti.x - (T)dx * h, ti.y - (T)dy * h, ti.z - (T)dz * h, nullptr,
-                                  ph, fx, fy, fz);
-        }
+    // Work items (leaf, part), wavefront-uniform so that the neighbour walk
+    // stays on the scalar unit: the target chunks of a leaf are dealt
+    // round-robin to nsplit items so that small boxes still fill the chip.
+    // The grid may be smaller than the item count (each wavefront then takes
+    // every stride-th item).  Capping it so that the far-field kernels of the
+    // other stream keep room on every CU was measured slower on the 1M-atom
+    // box (2 workgroups per CU: P2P 19.7 ms, step 29.7 ms), so the callers
+    // launch the full grid.
+    const int64_t nitem = nleaf * nsplit;
+    const int first = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    const int stride = gridDim.x * 4;
+    for (int64_t wv = first; wv < nitem; wv += stride) {
+        const int64_t leaf = wv / nsplit;
+        const int part = (int)(wv % nsplit);
+        uint32_t cx, cy, cz;
+        demorton3((uint32_t)leaf, cx, cy, cz);
+        const int32_t s0 = start[leaf], cnt = start[leaf + 1] - s0;
+        const int32_t p0 = pstart[leaf], pcnt = pstart[leaf + 1] - p0;
+        for (int32_t tb = part * TS; tb < cnt; tb += nsplit * TS) {
+            const int32_t t = tb + a;
+            const int32_t tl = min(t, pcnt - 1);  // lanes past the leaf redo its last slot, unstored
+            const V4 ti = X[p0 + tl];
+            double ph = 0;
+            T fx = 0, fy = 0, fz = 0;
+            p2p_leaf<T, G, true>(X + p0 + g, pcnt / G, ti.x, ti.y, ti.z, X + p0 + tl, ph, fx, fy, fz);
+            for (int c = 0; c < 125; ++c) {
+                if (c == 62) continue;  // offset (0, 0, 0): done above
+                const int dx = c / 25 - kWS, dy = (c / 5) % 5 - kWS, dz = c % 5 - kWS;
+                const uint32_t sc = morton3((cx + dx) & nmask, (cy + dy) & nmask, (cz + dz) & nmask);
+                const int32_t j0 = pstart[sc];
+                const int nk = (pstart[sc + 1] - j0) / G;
+                p2p_leaf<T, G, false>(X + j0 + g, nk, ti.x - (T)dx * h, ti.y - (T)dy * h, ti.z - (T)dz * h,
+                                      nullptr, ph, fx, fy, fz);
+            }
 #pragma unroll
-        for (int m = 1; m < G; m <<= 1) {
-            ph += __shfl_xor(ph, m);
-            fx += __shfl_xor(fx, m);
-            fy += __shfl_xor(fy, m);
-            fz += __shfl_xor(fz, m);
-        }
-        if (t < cnt && g == 0) {
-            const int64_t si = s0 + t;
-            phi[si] = ph;
-            field[3 * si + 0] = fx;
-            field[3 * si + 1] = fy;
-            field[3 * si + 2] = fz;
+            for (int m = 1; m < G; m <<= 1) {
+                ph += __shfl_xor(ph, m);
+                fx += __shfl_xor(fx, m);
+                fy += __shfl_xor(fy, m);
+                fz += __shfl_xor(fz, m);
+            }
+            if (t < cnt && g == 0) {
+                const int64_t si = s0 + t;
+                phi[si] = ph;
+                field[3 * si + 0] = fx;
+                field[3 * si + 1] = fy;
+                field[3 * si + 2] = fz;
+            }
         }
     }
 }
 
+// max_wg > 0 caps the grid (the kernel loops over the remaining items)
 template <typename T>
 hipError_t launch_p2p(int64_t nleaf, int levels, const void *xqp, const int32_t *pstart, const int32_t *start,
-                      double h, double *phi, T *field, int groups, int nsplit, hipStream_t s) {
+                      double h, double *phi, T *field, int groups, int nsplit, int max_wg, hipStream_t s) {
     if (nsplit < 1 || nsplit > 64) return hipErrorInvalidValue;
-    const int64_t grid = (nleaf * nsplit + 3) / 4;
+    int64_t grid = (nleaf * nsplit + 3) / 4;
+    if (max_wg > 0 && grid > max_wg) grid = max_wg;
     const T *x = (const T *)xqp;
     switch (groups) {
 #define FMM_P2P_CASE(G)                                                                                    \
@@ -127,9 +137,9 @@ hipError_t launch_p2p(int64_t nleaf, int levels, const void *xqp, const int32_t 
     return hipGetLastError();
 }
 template hipError_t launch_p2p<float>(int64_t, int, const void *, const int32_t *, const int32_t *, double,
-                                      double *, float *, int, int, hipStream_t);
+                                      double *, float *, int, int, int, hipStream_t);
 template hipError_t launch_p2p<double>(int64_t, int, const void *, const int32_t *, const int32_t *, double,
-                                       double *, double *, int, int, hipStream_t);
+                                       double *, double *, int, int, int, hipStream_t);
 
 // Near-field solute-solvent pairs: out[s] = q_s sum_{j in NF(s), solvent} q_j / r
 // for solute atoms s (0 for solvent).  One wavefront per leaf: the lanes flag
