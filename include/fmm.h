@@ -128,6 +128,23 @@ fmm_status fmm_energy_forces(fmm_plan_t plan, int64_t n, const double *pos, cons
 fmm_status fmm_solute_solvent_energy(fmm_plan_t plan, const uint8_t *mask, double *e_uv);
 
 /*
+ * fmm_lambda_energy -- the lambda-coupled energy of eq. Vswucheme, in which
+ * the solute-solvent coupling (u-v, u-Bv, v-Bu, Bu-Bv) is scaled by
+ * (1 - lambda) and everything else is kept:
+ *   V_lambda = E(u+Bu) + E(v+Bv) + (1 - lambda) e_uv = E - lambda e_uv,
+ *   dV_lambda/dlambda = -e_uv,
+ * with E the energy of the preceding fmm_energy_forces call on this plan and
+ * e_uv as returned by fmm_solute_solvent_energy for the same mask (which this
+ * call computes).  lambda = 0: the solute fully in solution; lambda = 1: the
+ * solute decoupled from the solvent (each part still neutralised by its own
+ * background).  This is eq. FMMVTI with the signs of its background terms
+ * taken from eq. Velecfull and eq. 6.  v_lambda, dv_dlambda: host out (either
+ * may be NULL).  Same errors as fmm_solute_solvent_energy.
+ */
+fmm_status fmm_lambda_energy(fmm_plan_t plan, const uint8_t *mask, double lambda, double *v_lambda,
+                             double *dv_dlambda);
+
+/*
  * fmm_potential_parts -- near- and far-field parts separately (no charged,
  * quadrupole or dipole terms), per atom in the caller's order, for checking
  * the stages on their own.  phi_nf / phi_ff: device n FP64 (or NULL);
@@ -204,6 +221,10 @@ fmm_status fmm_plan_batch(int nbox, const double *box, const int64_t *natoms, co
 fmm_status fmm_energy_forces_batch(fmm_plan_t plan, const int64_t *offsets, const double *pos, const double *q,
                                    double *energies, double *forces);
 fmm_status fmm_solute_solvent_energy_batch(fmm_plan_t plan, const uint8_t *mask, double *e_uv);
+/* Batched fmm_lambda_energy: lambdas (host, nbox) in, v_lambda and dv_dlambda
+ * (host, nbox; either may be NULL) out, one graph launch. */
+fmm_status fmm_lambda_energy_batch(fmm_plan_t plan, const uint8_t *mask, const double *lambdas, double *v_lambda,
+                                   double *dv_dlambda);
 fmm_status fmm_autotune_batch(fmm_plan_t plan, const int64_t *offsets, const double *pos, const double *q,
                               double *forces_scratch);
 fmm_status fmm_batch_levels(fmm_plan_t plan, int *levels, int *p2p_groups);

@@ -145,6 +145,18 @@ def ewald_uv(pos, q, mask, box, kappa=None, rcut=None, kmax=None, accuracy=1e-13
     return dict(real=terms[0], rec=terms[1], charged=terms[2], total=terms[3])
 
 
+def lambda_energy(pos, q, mask, box, lam, accuracy=1e-13):
+    """V_lambda and dV_lambda/dlambda of eq. Vswucheme (solute: mask == 1).
+
+    The solute-solvent coupling (u-v, u-Bv, v-Bu, Bu-Bv) is scaled by
+    (1 - lam): V = E(u+Bu) + E(v+Bv) + (1 - lam) W = E - lam W, with E the
+    Ewald energy of all charges and W the two-set cross energy; dV/dlam = -W.
+    """
+    e = ewald(pos, q, box, accuracy=accuracy)["terms"]["total"]
+    w = ewald_uv(pos, q, mask, box, accuracy=accuracy)["total"]
+    return e - lam * w, -w
+
+
 def nearfield(pos, q, box, levels, ws=2):
     """Direct near-field potential and field (-grad phi) per atom, eq. EqNF."""
     pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
@@ -208,7 +220,7 @@ def sort_reference(pos, box, levels):
 XI_SC = 2.837297479480620  # simple-cubic constant; pinned in tests/golden
 
 
-def shell_sum_energy(pos, q, box, R, xi=XI_SC):
+def shell_sum_energy(pos, q, box, R, xi=XI_SC, mask=None, lam=0.0):
     """Energy of charges + uniform background, conducting boundary, by direct sums.
 
     E = 1/2 sum_{i != j} q_i q_j [S_R(r_ij) + (2 pi / 3V) r_ij^2] - xi Q^2 / (2 b)
@@ -216,6 +228,11 @@ def shell_sum_energy(pos, q, box, R, xi=XI_SC):
     complete spherical shells.  The r^2 term removes the spherical-summation
     dipole/quadrupole surface contribution (eqs. surftotal, surfchargedend);
     the last term is the lone-charge energy.
+
+    With a solute mask: the lambda-coupled energy of eq. Vswucheme, every
+    solute-solvent pair weighted by (1 - lam) and the background term
+    -xi/(2b) (Q_u^2 + Q_v^2 + 2 (1 - lam) Q_u Q_v) (u-Bv, v-Bu and Bu-Bv
+    scaled like u-v).
     """
     pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
     q = np.asarray(q, dtype=np.float64).reshape(-1)
@@ -234,9 +251,14 @@ def shell_sum_energy(pos, q, box, R, xi=XI_SC):
             d = pos[i] - pos[j]
             dd = d[None, :] + nu
             s = 1.0 / np.linalg.norm(d) + np.sum(1.0 / np.sqrt((dd * dd).sum(1)) - inv_nu)
-            e += 0.5 * q[i] * q[j] * (s + (2.0 * math.pi / (3.0 * V)) * float(d @ d))
-    Q = q.sum()
-    return e - xi * Q * Q / (2.0 * box)
+            wgt = 1.0 if mask is None or mask[i] == mask[j] else 1.0 - lam
+            e += 0.5 * wgt * q[i] * q[j] * (s + (2.0 * math.pi / (3.0 * V)) * float(d @ d))
+    if mask is None:
+        Q = q.sum()
+        return e - xi * Q * Q / (2.0 * box)
+    m = np.asarray(mask).reshape(-1) != 0
+    qu, qv = q[m].sum(), q[~m].sum()
+    return e - xi * (qu * qu + qv * qv + 2.0 * (1.0 - lam) * qu * qv) / (2.0 * box)
 
 
 def direct_potential(targets, sources, q):

@@ -10,4 +10,5 @@ from .binding import (FMM_FP64, FMM_MIXED, FMM_MIXED_BF16_M2L, FmmError, Plan, f
                       fmm_energy_forces, fmm_last_error, fmm_lattice_tensor, fmm_plan,
                       fmm_plan_config, fmm_potential_parts, fmm_profile, fmm_profile_read,
                       fmm_solute_solvent_energy, fmm_version, fmm_plan_batch, fmm_energy_forces_batch,
-                      fmm_solute_solvent_energy_batch, fmm_autotune_batch, fmm_batch_levels)
+                      fmm_solute_solvent_energy_batch, fmm_autotune_batch, fmm_batch_levels,
+                      fmm_lambda_energy, fmm_lambda_energy_batch)

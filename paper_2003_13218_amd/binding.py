@@ -27,7 +27,8 @@ EXPORTED = (
     "fmm_plan", "fmm_plan_config", "fmm_energy_forces", "fmm_solute_solvent_energy",
     "fmm_potential_parts", "fmm_bin", "fmm_lattice_tensor", "fmm_profile", "fmm_profile_read",
     "fmm_last_error", "fmm_destroy", "fmm_version", "fmm_plan_batch", "fmm_energy_forces_batch",
-    "fmm_solute_solvent_energy_batch", "fmm_autotune_batch", "fmm_batch_levels",
+    "fmm_solute_solvent_energy_batch", "fmm_autotune_batch", "fmm_batch_levels", "fmm_lambda_energy",
+    "fmm_lambda_energy_batch",
 )
 
 STAGES = ("sort", "gather", "p2m", "m2m", "lattice", "m2l", "m2l_leaf", "l2l", "l2p", "p2p", "final", "total")
@@ -84,6 +85,10 @@ def load():
         lib.fmm_autotune_batch.restype = ci
         lib.fmm_batch_levels.argtypes = [vp, vp, vp]
         lib.fmm_batch_levels.restype = ci
+        lib.fmm_lambda_energy.argtypes = [vp, vp, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+        lib.fmm_lambda_energy.restype = ci
+        lib.fmm_lambda_energy_batch.argtypes = [vp, vp, vp, vp, vp]
+        lib.fmm_lambda_energy_batch.restype = ci
         lib.fmm_version.argtypes = []
         lib.fmm_version.restype = ctypes.c_char_p
         _lib = lib
@@ -170,6 +175,15 @@ def fmm_solute_solvent_energy(plan: Plan, mask) -> float:
     e = ctypes.c_double()
     _check(load().fmm_solute_solvent_energy(plan.handle, _dptr(mask, torch.uint8, (), "mask"), ctypes.byref(e)), plan)
     return e.value
+
+
+def fmm_lambda_energy(plan: Plan, mask, lam: float):
+    """Returns (V_lambda, dV_lambda/dlambda) of eq. Vswucheme for the preceding evaluation."""
+    import torch
+    v, d = ctypes.c_double(), ctypes.c_double()
+    _check(load().fmm_lambda_energy(plan.handle, _dptr(mask, torch.uint8, (), "mask"), float(lam), ctypes.byref(v),
+                                    ctypes.byref(d)), plan)
+    return v.value, d.value
 
 
 def fmm_potential_parts(plan: Plan, pos, q):
@@ -266,6 +280,19 @@ def fmm_solute_solvent_energy_batch(plan: Plan, mask):
     _check(load().fmm_solute_solvent_energy_batch(plan.handle, _dptr(mask, torch.uint8, (), "mask"),
                                                   e.ctypes.data_as(ctypes.c_void_p)), plan)
     return e
+
+
+def fmm_lambda_energy_batch(plan: Plan, mask, lambdas):
+    """Returns (V_lambda, dV/dlambda) numpy arrays over the boxes of a batch plan."""
+    import numpy as np
+    import torch
+    lam = _host(lambdas, np.float64)
+    v = np.zeros(plan.nbox)
+    d = np.zeros(plan.nbox)
+    _check(load().fmm_lambda_energy_batch(plan.handle, _dptr(mask, torch.uint8, (), "mask"),
+                                          lam.ctypes.data_as(ctypes.c_void_p), v.ctypes.data_as(ctypes.c_void_p),
+                                          d.ctypes.data_as(ctypes.c_void_p)), plan)
+    return v, d
 
 
 def fmm_batch_levels(plan: Plan):

@@ -84,6 +84,7 @@ struct fmm_plan {
     double t00 = 0.0;
     int top_fp64 = 3;  // mixed mode: tree levels 1..3 in FP64 (see top_fp64_levels)
     double q_tree = 0.0;  // level-0 monopole of the last fmm_energy_forces tree
+    double last_energy = 0.0;  // energy of the last fmm_energy_forces call
     std::vector<cplx> T;                  // lattice tensor, unit box
 
     // scale-invariant translation operators of order p, shared by every plan
@@ -714,6 +715,7 @@ static fmm_status finish_energy(fmm_plan_t pl, double *energy) {
     if (st != FMM_OK) return st;
     stage_collect(pl);
     *energy = pl->h_scalars[8];
+    pl->last_energy = *energy;
     pl->q_tree = pl->h_scalars[10];
     return FMM_OK;
 }
@@ -735,6 +737,7 @@ extern "C" fmm_status fmm_energy_forces(fmm_plan_t pl, int64_t n, const double *
     pl->have_state = false;
     if (n == 0) {
         *energy = 0.0;
+        pl->last_energy = 0.0;
         pl->have_state = true;
         pl->n_state = 0;
         return FMM_OK;
@@ -853,6 +856,19 @@ extern "C" fmm_status fmm_solute_solvent_energy(fmm_plan_t pl, const uint8_t *ma
     if (!mask) return fail(pl, FMM_ERR_INVALID, "mask must be non-NULL");
     HIPCHK(pl, hipSetDevice(pl->device), "hipSetDevice");
     return pl->prec == FMM_FP64 ? solute_solvent_t<double>(pl, mask, e_uv) : solute_solvent_t<float>(pl, mask, e_uv);
+}
+
+extern "C" fmm_status fmm_lambda_energy(fmm_plan_t pl, const uint8_t *mask, double lambda, double *v_lambda,
+                                        double *dv_dlambda) {
+    if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    if (!std::isfinite(lambda)) return fail(pl, FMM_ERR_INVALID, "lambda must be finite");
+    double w = 0.0;
+    const fmm_status st = fmm_solute_solvent_energy(pl, mask, &w);
+    if (st != FMM_OK) return st;
+    // eq. Vswucheme: the solute-solvent coupling scaled by (1 - lambda)
+    if (v_lambda) *v_lambda = pl->last_energy - lambda * w;
+    if (dv_dlambda) *dv_dlambda = -w;
+    return FMM_OK;
 }
 
 extern "C" fmm_status fmm_bin(fmm_plan_t pl, int64_t n, const double *pos, uint32_t *keys, int32_t *perm,
@@ -1199,6 +1215,25 @@ extern "C" fmm_status fmm_solute_solvent_energy_batch(fmm_plan_t pl, const uint8
             pl->err = "box " + std::to_string(w) + ": " + pl->sub[w]->err;
             return st;
         }
+    }
+    return FMM_OK;
+}
+
+extern "C" fmm_status fmm_lambda_energy_batch(fmm_plan_t pl, const uint8_t *mask, const double *lambdas,
+                                              double *v_lambda, double *dv_dlambda) {
+    if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    if (!pl->is_batch) return fail(pl, FMM_ERR_INVALID, "fmm_lambda_energy_batch: not a batch plan");
+    if (!lambdas) return fail(pl, FMM_ERR_INVALID, "lambdas is NULL");
+    const size_t nb = pl->sub.size();
+    for (size_t w = 0; w < nb; ++w)
+        if (!std::isfinite(lambdas[w])) return fail(pl, FMM_ERR_INVALID, "lambdas must be finite");
+    std::vector<double> e_uv(nb);
+    const fmm_status st = fmm_solute_solvent_energy_batch(pl, mask, e_uv.data());
+    if (st != FMM_OK) return st;
+    for (size_t w = 0; w < nb; ++w) {
+        const double e = (pl->batch_off[w + 1] > pl->batch_off[w]) ? pl->sub[w]->last_energy : 0.0;
+        if (v_lambda) v_lambda[w] = e - lambdas[w] * e_uv[w];
+        if (dv_dlambda) dv_dlambda[w] = -e_uv[w];
     }
     return FMM_OK;
 }

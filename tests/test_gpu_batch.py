@@ -151,3 +151,21 @@ def test_batch_edge_cases(fmm, windows):
     with pytest.raises(fmm.FmmError):
         fmm.fmm_plan_config(plan, fmm.FMM_FP64, 0.3)
     del torch
+
+
+def test_batch_lambda_energy(fmm, windows):
+    # each window at its own lambda: batch values equal single-box plans
+    ws = windows[:4]
+    off, pos, q, mask = _concat(ws)
+    plan = fmm.fmm_plan_batch([w.box for w in ws], 10, natoms=[w.n for w in ws])
+    fmm.fmm_plan_config(plan, fmm.FMM_MIXED)
+    levels, _ = fmm.fmm_batch_levels(plan)
+    lams = [w.meta["lam"] for w in ws]
+    fmm.fmm_energy_forces_batch(plan, off, _t(pos), _t(q), forces=False)
+    V, D = fmm.fmm_lambda_energy_batch(plan, _t(mask), lams)
+    for k, w in enumerate(ws):
+        single = fmm.fmm_plan(w.box, int(levels[k]), 10)
+        fmm.fmm_plan_config(single, fmm.FMM_MIXED)
+        fmm.fmm_energy_forces(single, _t(w.pos), _t(w.q), forces=False)
+        v, d = fmm.fmm_lambda_energy(single, _t(w.mask), lams[k])
+        assert V[k] == v and D[k] == d

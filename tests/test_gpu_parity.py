@@ -161,6 +161,22 @@ def test_solute_solvent_energy(fmm, name, prec, tol):
     assert abs(e_uv - ref) / max(abs(ref), uv_scale(w, w.mask)) < tol
 
 
+@pytest.mark.parametrize("name,prec,tol", [("C1", 0, 1e-5), ("C2", 1, 1e-5)])
+def test_lambda_energy(fmm, name, prec, tol):
+    # eq. Vswucheme: V_lambda = E - lambda W, dV/dlambda = -W, against the
+    # oracle's lambda_energy (energy unit for V, the solute-solvent unit for W)
+    w, o = ewald_full(name)
+    plan = _plan(fmm, w.box, w.levels, w.p, prec)
+    e = fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q), forces=False)[0]
+    scale = uv_scale(w, w.mask)
+    for lam in (0.0, 0.25, 1.0):
+        v, dv = fmm.fmm_lambda_energy(plan, _t(w.mask), lam)
+        v_ref, dv_ref = oracle.lambda_energy(w.pos, w.q, w.mask, w.box, lam)
+        assert abs(dv - dv_ref) < tol * max(abs(dv_ref), scale)
+        assert abs(v - v_ref) < tol * abs(v_ref) + lam * tol * max(abs(dv_ref), scale)
+        assert v == pytest.approx(e + lam * dv, rel=1e-14, abs=1e-12)
+
+
 def test_solute_solvent_many_solute_atoms(fmm):
     # a solute of several atoms spread over leaves, net charge != 0 in both parts
     w = workloads.config("C1")

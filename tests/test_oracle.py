@@ -161,6 +161,28 @@ def test_solute_solvent_two_set_formula():
     assert w == pytest.approx(e_all - e_u - e_v, rel=1e-11, abs=1e-12)
 
 
+def test_lambda_energy_against_weighted_image_shells():
+    # eq. Vswucheme read as V = E(u+Bu) + E(v+Bv) + (1 - lam) W: the direct
+    # image-shell sum with every u-v pair weighted by (1 - lam) and the
+    # background cross terms scaled alike must equal E - lam W from the Ewald
+    # path; at lam = 1 it is the sum of the two separately neutralised parts
+    rng = np.random.default_rng(5)
+    box = 2.5
+    pos = rng.uniform(0, box, (5, 3))
+    q = np.array([1.1, -0.3, 0.8, -0.6, 0.4])
+    mask = np.array([1, 0, 1, 0, 0], np.uint8)
+    xi = oracle.ewald(np.zeros((1, 3)), np.ones(1), 1.0)["terms"]["total"] * -2.0
+    for lam in (0.0, 0.37, 1.0):
+        v, dv = oracle.lambda_energy(pos, q, mask, box, lam)
+        # shells to R = 48: truncation 2.8e-8 here (6.2e-7 at R = 24, 1.2e-7 at 36)
+        bf = oracle.shell_sum_energy(pos, q, box, 48, xi=xi, mask=mask, lam=lam)
+        assert bf == pytest.approx(v, abs=5e-8)
+    e_u = oracle.ewald(pos[mask == 1], q[mask == 1], box)["terms"]["total"]
+    e_v = oracle.ewald(pos[mask == 0], q[mask == 0], box)["terms"]["total"]
+    assert oracle.lambda_energy(pos, q, mask, box, 1.0)[0] == pytest.approx(e_u + e_v, rel=1e-11)
+    assert dv == pytest.approx(-oracle.ewald_uv(pos, q, mask, box)["total"], rel=1e-12)
+
+
 def test_solute_solvent_linear_in_solute_charge():
     pos, q = workloads.random_charges(14, 6.0, seed=26)
     mask = np.zeros(14, np.uint8); mask[3] = 1
