@@ -181,6 +181,9 @@ def run_single(args, w, p, prec_name, steps, warmup, fp64_leg, cpu_leg):
     return out
 
 
+UV_SCHEMES = {"symmetric": 0, "sparse": 1}
+
+
 def run_batch(args):
     """C4: 32 charging windows, energies + forces and e_uv per step."""
     import numpy as np
@@ -196,6 +199,8 @@ def run_batch(args):
     p = args.p or 10
     plan = F.fmm_plan_batch([w.box for w in ws], p, natoms=[w.n for w in ws])
     F.fmm_plan_config(plan, PREC_NAMES[args.prec])
+    uv_scheme = UV_SCHEMES[args.uv_scheme]
+    F.fmm_plan_options(plan, F.FMM_BOUNDARY_CONDUCTING, uv_scheme)
     model_levels, _ = F.fmm_batch_levels(plan)
     t0 = time.perf_counter()
     levels, groups = F.fmm_autotune_batch(plan, off, pos, q)
@@ -220,7 +225,7 @@ def run_batch(args):
         "vs_baseline": None, "dtype": {"mixed": "f32+f64", "fp64": "f64", "bf16": "bf16-m2l+f32+f64"}[args.prec],
         "data": "synthetic",
         "config": {"workload": f"C4: {len(ws)} windows, {n} atoms (6k-48k per box), p {p}, {args.prec} precision",
-                   "n_atoms": n, "windows": len(ws), "p": p, "precision": args.prec,
+                   "n_atoms": n, "windows": len(ws), "p": p, "precision": args.prec, "uv_scheme": args.uv_scheme,
                    "model_levels": model_levels.tolist(), "tuned_levels": levels.tolist(),
                    "tuned_p2p_groups": groups.tolist(), "autotune_s": round(t_tune, 2)},
         "energies": E.tolist(), "e_uv": U.tolist(),
@@ -237,6 +242,8 @@ def main():
     ap.add_argument("--p", type=int, default=0, help="expansion order (default: the workload's)")
     ap.add_argument("--prec", default="mixed", choices=list(PREC_NAMES))
     ap.add_argument("--sweep", action="store_true", help="C5: p x precision sweep")
+    ap.add_argument("--uv-scheme", default="symmetric", choices=list(UV_SCHEMES),
+                    help="C4: far-field scheme of the solute-solvent energy")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-bytes", type=int, default=0,

@@ -91,6 +91,49 @@ fmm_status fmm_plan(double box, int levels, int p, fmm_plan_t *out);
  */
 fmm_status fmm_plan_config(fmm_plan_t plan, int precision, double kappa, void *hip_stream);
 
+/* Boundary condition at infinity (Appendix A, eq. surfdipole). */
+typedef enum {
+    FMM_BOUNDARY_CONDUCTING = 0, /* tin-foil boundary of the Ewald sum (default) */
+    FMM_BOUNDARY_VACUUM = 1      /* adds the dipole surface term               */
+} fmm_boundary;
+
+/* Far-field scheme of fmm_solute_solvent_energy (bit flags). */
+typedef enum {
+    FMM_UV_SYMMETRIC = 0, /* eq. FMMcalc: a dense second pass over the solute charges       */
+    FMM_UV_SPARSE = 1,    /* one-sided W_FF = sum_u q (phi_uv - phi_u), phi_u at u only     */
+    FMM_UV_SWAP = 2       /* exchange the roles of u and v in the second pass               */
+} fmm_uv_scheme;
+
+/*
+ * fmm_plan_options -- boundary condition and solute-solvent scheme.
+ *   boundary   FMM_BOUNDARY_CONDUCTING or FMM_BOUNDARY_VACUUM.  Vacuum adds
+ *              the dipole surface term (2 pi / 3V) mu.mu of eq. surfdipole to
+ *              E, with mu = sum q r over the atoms wrapped into the box and
+ *              measured from its centre (the level-0 expansion centre); the
+ *              forces gain -(4 pi / 3V) q_i mu, the potential (4 pi / 3V)
+ *              mu.r_i, and e_uv the cross part (4 pi / 3V) mu_u.mu_v.
+ *              Changing it clears the cached state (as fmm_plan_config).
+ *   uv_scheme  FMM_UV_SYMMETRIC or FMM_UV_SPARSE, optionally | FMM_UV_SWAP.
+ *              SYMMETRIC is eq. FMMcalc with a full far-field pass over the
+ *              masked charges.  SPARSE uses the one-sided form the same
+ *              derivation gives, W_FF = sum_u q (phi_uv - phi_u): phi_u is
+ *              needed at the solute atoms only, and the tree of the solute
+ *              charges is non-zero only above the leaves that hold them, so
+ *              that pass runs (in FP64) over those cells alone -- the cheap
+ *              choice for a few ions in a large box.  phi_uv carries the
+ *              precision of the preceding fmm_energy_forces call: in the
+ *              mixed modes the one-sided sum over a LARGE masked set adds
+ *              that call's FP32 error at every masked atom, so SPARSE is
+ *              meant for a masked set of few atoms.  SWAP evaluates the
+ *              second pass over the solvent charges instead (the exchanged
+ *              form the paper notes after eq. FMMcalc); e_uv is symmetric in
+ *              u and v, so every scheme returns the same value up to the
+ *              truncation and rounding of the far field.
+ * On a batch plan the options apply to every box.  FMM_ERR_INVALID for
+ * values outside the enums.
+ */
+fmm_status fmm_plan_options(fmm_plan_t plan, int boundary, int uv_scheme);
+
 /*
  * fmm_energy_forces -- E of eq. Velecfull, forces and per-atom potential.
  *   n       number of atoms (0 <= n < 2^31); n == 0 gives E = 0

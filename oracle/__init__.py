@@ -96,12 +96,24 @@ def ewald_params(box: float, accuracy: float = 1e-13, rcut: float | None = None,
     return kappa, rcut, kmax
 
 
-def ewald(pos, q, box, kappa=None, rcut=None, kmax=None, eval_idx=None, accuracy=1e-13):
+def centred_dipole(pos, q, box):
+    """Positions wrapped into the box and measured from its centre, and mu = sum q r."""
+    r = wrap_positions(np.asarray(pos, dtype=np.float64).reshape(-1, 3), box) - 0.5 * box
+    return r, np.asarray(q, dtype=np.float64).reshape(-1) @ r
+
+
+def ewald(pos, q, box, kappa=None, rcut=None, kmax=None, eval_idx=None, accuracy=1e-13, boundary="conducting"):
     """Ewald energy terms, per-atom potential phi_i = dE/dq_i and force F_i = -dE/dr_i.
 
-    Returns dict(terms=dict(real, rec, self, charged, total), phi, force,
-    kappa, rcut, kmax).  ``terms`` are NaN when ``eval_idx`` selects a sample.
+    Returns dict(terms=dict(real, rec, self, charged, dipole, total), phi,
+    force, kappa, rcut, kmax).  ``terms`` are NaN when ``eval_idx`` selects a
+    sample.  boundary="vacuum" adds the dipole surface term (2 pi / 3V) mu.mu
+    of eq. surfdipole (Appendix A), mu = sum q r over the positions wrapped
+    into the box and measured from its centre, with its derivatives
+    (4 pi / 3V) mu.r_i in phi_i and -(4 pi / 3V) q_i mu in F_i.
     """
+    if boundary not in ("conducting", "vacuum"):
+        raise ValueError(f"unknown boundary {boundary!r}")
     pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
     q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
     n = q.shape[0]
@@ -123,12 +135,27 @@ def ewald(pos, q, box, kappa=None, rcut=None, kmax=None, eval_idx=None, accuracy
                               ne, _ptr(idx), _ptr(terms), _ptr(phi), _ptr(force))
     if rc != 0:
         raise RuntimeError(f"oracle_ewald failed with status {rc}")
-    return dict(terms=dict(real=terms[0], rec=terms[1], self=terms[2], charged=terms[3], total=terms[4]),
+    dip = 0.0
+    if boundary == "vacuum":
+        c23 = 2.0 * math.pi / (3.0 * box ** 3)
+        r, mu = centred_dipole(pos, q, box)
+        dip = c23 * float(mu @ mu)
+        sel = np.arange(n) if idx is None else idx
+        phi = phi + 2.0 * c23 * (r[sel] @ mu)
+        force = force - 2.0 * c23 * q[sel][:, None] * mu[None, :]
+    return dict(terms=dict(real=terms[0], rec=terms[1], self=terms[2], charged=terms[3], dipole=dip,
+                           total=terms[4] + dip),
                 phi=phi, force=force, kappa=kappa, rcut=rcut, kmax=kmax)
 
 
-def ewald_uv(pos, q, mask, box, kappa=None, rcut=None, kmax=None, accuracy=1e-13):
-    """Solute-solvent cross energy W (solute: mask == 1), with its parts."""
+def ewald_uv(pos, q, mask, box, kappa=None, rcut=None, kmax=None, accuracy=1e-13, boundary="conducting"):
+    """Solute-solvent cross energy W (solute: mask == 1), with its parts.
+
+    boundary="vacuum": W gains the cross part (4 pi / 3V) mu_u.mu_v of the
+    dipole surface term (see ``ewald``).
+    """
+    if boundary not in ("conducting", "vacuum"):
+        raise ValueError(f"unknown boundary {boundary!r}")
     pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
     q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
     mask = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
@@ -142,7 +169,13 @@ def ewald_uv(pos, q, mask, box, kappa=None, rcut=None, kmax=None, accuracy=1e-13
                                  float(rcut), float(kmax), _ptr(terms))
     if rc != 0:
         raise RuntimeError(f"oracle_ewald_uv failed with status {rc}")
-    return dict(real=terms[0], rec=terms[1], charged=terms[2], total=terms[3])
+    dip = 0.0
+    if boundary == "vacuum":
+        m = mask != 0
+        _, mu_u = centred_dipole(pos[m], q[m], box)
+        _, mu_v = centred_dipole(pos[~m], q[~m], box)
+        dip = 4.0 * math.pi / (3.0 * box ** 3) * float(mu_u @ mu_v)
+    return dict(real=terms[0], rec=terms[1], charged=terms[2], dipole=dip, total=terms[3] + dip)
 
 
 def lambda_energy(pos, q, mask, box, lam, accuracy=1e-13):
@@ -220,14 +253,16 @@ def sort_reference(pos, box, levels):
 XI_SC = 2.837297479480620  # simple-cubic constant; pinned in tests/golden
 
 
-def shell_sum_energy(pos, q, box, R, xi=XI_SC, mask=None, lam=0.0):
+def shell_sum_energy(pos, q, box, R, xi=XI_SC, mask=None, lam=0.0, surface=True):
     """Energy of charges + uniform background, conducting boundary, by direct sums.
 
     E = 1/2 sum_{i != j} q_i q_j [S_R(r_ij) + (2 pi / 3V) r_ij^2] - xi Q^2 / (2 b)
     with S_R(r) = 1/|r| + sum_{0 < |nu| <= R} (1/|r + nu b| - 1/|nu b|) over
     complete spherical shells.  The r^2 term removes the spherical-summation
     dipole/quadrupole surface contribution (eqs. surftotal, surfchargedend);
-    the last term is the lone-charge energy.
+    the last term is the lone-charge energy.  surface=False drops the r^2
+    term: the plain spherical summation, whose limit for a neutral set is the
+    energy under the vacuum boundary (the positions are used as given).
 
     With a solute mask: the lambda-coupled energy of eq. Vswucheme, every
     solute-solvent pair weighted by (1 - lam) and the background term
@@ -252,7 +287,8 @@ def shell_sum_energy(pos, q, box, R, xi=XI_SC, mask=None, lam=0.0):
             dd = d[None, :] + nu
             s = 1.0 / np.linalg.norm(d) + np.sum(1.0 / np.sqrt((dd * dd).sum(1)) - inv_nu)
             wgt = 1.0 if mask is None or mask[i] == mask[j] else 1.0 - lam
-            e += 0.5 * wgt * q[i] * q[j] * (s + (2.0 * math.pi / (3.0 * V)) * float(d @ d))
+            surf = (2.0 * math.pi / (3.0 * V)) * float(d @ d) if surface else 0.0
+            e += 0.5 * wgt * q[i] * q[j] * (s + surf)
     if mask is None:
         Q = q.sum()
         return e - xi * Q * Q / (2.0 * box)

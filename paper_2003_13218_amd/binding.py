@@ -22,13 +22,18 @@ FMM_ERR_STATE = -4
 FMM_FP64 = 0
 FMM_MIXED = 1
 FMM_MIXED_BF16_M2L = 2
+FMM_BOUNDARY_CONDUCTING = 0
+FMM_BOUNDARY_VACUUM = 1
+FMM_UV_SYMMETRIC = 0
+FMM_UV_SPARSE = 1
+FMM_UV_SWAP = 2
 
 EXPORTED = (
     "fmm_plan", "fmm_plan_config", "fmm_energy_forces", "fmm_solute_solvent_energy",
     "fmm_potential_parts", "fmm_bin", "fmm_lattice_tensor", "fmm_profile", "fmm_profile_read",
     "fmm_last_error", "fmm_destroy", "fmm_version", "fmm_plan_batch", "fmm_energy_forces_batch",
     "fmm_solute_solvent_energy_batch", "fmm_autotune_batch", "fmm_batch_levels", "fmm_lambda_energy",
-    "fmm_lambda_energy_batch",
+    "fmm_lambda_energy_batch", "fmm_plan_options",
 )
 
 STAGES = ("sort", "gather", "p2m", "m2m", "lattice", "m2l", "m2l_leaf", "l2l", "l2p", "p2p", "final", "total")
@@ -57,6 +62,8 @@ def load():
         lib.fmm_plan.restype = ci
         lib.fmm_plan_config.argtypes = [vp, ci, dbl, vp]
         lib.fmm_plan_config.restype = ci
+        lib.fmm_plan_options.argtypes = [vp, ci, ci]
+        lib.fmm_plan_options.restype = ci
         lib.fmm_energy_forces.argtypes = [vp, i64, vp, vp, ctypes.POINTER(dbl), vp, vp]
         lib.fmm_energy_forces.restype = ci
         lib.fmm_solute_solvent_energy.argtypes = [vp, vp, ctypes.POINTER(dbl)]
@@ -153,6 +160,10 @@ def fmm_plan_config(plan: Plan, precision: int = FMM_FP64, kappa: float = 0.0, s
         stream = torch.cuda.current_stream().cuda_stream
     _check(load().fmm_plan_config(plan.handle, int(precision), float(kappa), ctypes.c_void_p(int(stream))), plan)
     plan.precision = precision
+
+
+def fmm_plan_options(plan: Plan, boundary: int = FMM_BOUNDARY_CONDUCTING, uv_scheme: int = FMM_UV_SYMMETRIC):
+    _check(load().fmm_plan_options(plan.handle, int(boundary), int(uv_scheme)), plan)
 
 
 def fmm_energy_forces(plan: Plan, pos, q, forces=True, phi=False):

@@ -95,6 +95,10 @@ struct fmm_plan {
     DeviceBuf key, count, cursor, start, perm, scan, xq, xq_u, xs, Mlev, Llev, M0, L0, m2l_part;
     DeviceBuf pstart, xqp;  // near-field copy of xq, leaves padded to the P2P group count
     DeviceBuf phi_nf, field_nf, phi_ff, field_ff, phi_u, field_u, nfuv, partials, scalars, flag;
+    DeviceBuf sflag;    // sparse solute pass: one flag per cell, level 0 first, then levels 1..L
+    DeviceBuf mask_sw;  // exchanged solute mask (FMM_UV_SWAP)
+    int boundary = FMM_BOUNDARY_CONDUCTING;
+    int uv_scheme = FMM_UV_SYMMETRIC;
     double *h_scalars = nullptr;  // pinned host mirror of `scalars`
     int64_t cap_n = -1;
     bool tree_ready = false;
@@ -275,11 +279,13 @@ static int top_fp64_levels(fmm_plan_t pl) {
     return std::min(pl->levels - 1, pl->top_fp64);
 }
 
-static fmm_status ensure_m2l_ops(fmm_plan_t pl) {
-    const bool need64 = top_fp64_levels(pl) > 0;
+// want64: the FP64 operators are needed whatever the precision (sparse pass)
+static fmm_status ensure_m2l_ops(fmm_plan_t pl, bool want64 = false) {
+    const bool needalias = top_fp64_levels(pl) > 0 || want64;
+    const bool need64 = needalias || want64;
     const bool need32 = pl->prec == FMM_MIXED;
     const bool needbf = pl->prec == FMM_MIXED_BF16_M2L;
-    if ((!need64 || (pl->op->ops64.ptr && pl->op->alias_ops[0].ptr)) && (!need32 || pl->op->ops32.ptr) &&
+    if ((!need64 || pl->op->ops64.ptr) && (!needalias || pl->op->alias_ops[0].ptr) && (!need32 || pl->op->ops32.ptr) &&
         (!needbf || pl->op->opsbf.ptr))
         return FMM_OK;
     std::vector<double> rm;
@@ -292,7 +298,7 @@ static fmm_status ensure_m2l_ops(fmm_plan_t pl) {
         if (!pl->op->opsbf.ensure(nb * sizeof(uint16_t))) return fail(pl, FMM_ERR_NOMEM, "M2L operator allocation");
         HIPCHK(pl, hipMemcpy(pl->op->opsbf.ptr, sw.data(), nb * sizeof(uint16_t), hipMemcpyHostToDevice), "M2L upload");
     }
-    if (need64 && !pl->op->alias_ops[0].ptr) {
+    if (needalias && !pl->op->alias_ops[0].ptr) {
         // On a grid of n <= 4 cells per axis the 875 offsets t of a parity
         // class reach only n^3 distinct source cells (t modulo n), so
         //   sum_t O_t M(c + t) = sum_d (sum_{t = d mod n} O_t) M(c + d):
@@ -443,6 +449,28 @@ extern "C" fmm_status fmm_plan_config(fmm_plan_t pl, int precision, double kappa
     return FMM_OK;
 }
 
+extern "C" fmm_status fmm_plan_options(fmm_plan_t pl, int boundary, int uv_scheme) {
+    if (!pl) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan_options: plan is NULL");
+    if (boundary != FMM_BOUNDARY_CONDUCTING && boundary != FMM_BOUNDARY_VACUUM)
+        return fail(pl, FMM_ERR_INVALID, "fmm_plan_options: unknown boundary");
+    if (uv_scheme < 0 || uv_scheme > (FMM_UV_SPARSE | FMM_UV_SWAP))
+        return fail(pl, FMM_ERR_INVALID, "fmm_plan_options: unknown uv_scheme");
+    const bool changed = boundary != pl->boundary;
+    pl->boundary = boundary;
+    pl->uv_scheme = uv_scheme;
+    if (pl->is_batch) {
+        if (changed) pl->batch_state = false;
+        for (fmm_plan_t b : pl->sub) {
+            b->boundary = boundary;
+            b->uv_scheme = uv_scheme;
+            if (changed) b->have_state = false;
+        }
+    } else if (changed) {
+        pl->have_state = false;
+    }
+    return FMM_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Evaluation
 // ---------------------------------------------------------------------------
@@ -461,7 +489,8 @@ static fmm_status ensure_workspace(fmm_plan_t pl, int64_t n) {
             !pl->pstart.ensure(sizeof(int32_t) * (nleaf + 1)) ||
             !pl->scan.ensure(sizeof(int32_t) * scan_scratch_len(nleaf)) ||
             !pl->scalars.ensure(sizeof(double) * kScalars) || !pl->flag.ensure(sizeof(int) * 4) ||
-            !pl->partials.ensure(sizeof(double) * 2 * 5 * 1024))
+            !pl->partials.ensure(sizeof(double) * 2 * 5 * 1024) ||
+            !pl->sflag.ensure(sizeof(uint32_t) * (size_t)(1 + cells)))
             return fail(pl, FMM_ERR_NOMEM, "tree workspace allocation");
         pl->tree_ready = true;
     }
@@ -474,7 +503,7 @@ static fmm_status ensure_workspace(fmm_plan_t pl, int64_t n) {
             !pl->phi_nf.ensure(sizeof(double) * nn) || !pl->field_nf.ensure(sizeof(double) * 3 * nn) ||
             !pl->phi_ff.ensure(sizeof(double) * nn) || !pl->field_ff.ensure(sizeof(double) * 3 * nn) ||
             !pl->phi_u.ensure(sizeof(double) * nn) || !pl->field_u.ensure(sizeof(double) * 3 * nn) ||
-            !pl->nfuv.ensure(sizeof(double) * nn))
+            !pl->nfuv.ensure(sizeof(double) * nn) || !pl->mask_sw.ensure(nn))
             return fail(pl, FMM_ERR_NOMEM, "per-atom workspace allocation");
         pl->cap_n = n;
     }
@@ -701,7 +730,8 @@ static fmm_status enqueue_energy_forces(fmm_plan_t pl, int64_t n, const double *
                               nb, sc, s), "moments");
     HIPCHK(pl, hipMemcpyAsync(sc + 10, pl->M0.ptr, sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
     HIPCHK(pl, launch_finalize<T>(n, pl->perm.as<int32_t>(), pl->xs.as<double>(), pl->box, pl->kappa,
-                                  pl->t00 / pl->box, sc, pl->M0.as<double>(), pl->phi_nf.as<double>(),
+                                  pl->t00 / pl->box, pl->boundary == FMM_BOUNDARY_VACUUM ? 0.0 : 1.0, sc,
+                                  pl->M0.as<double>(), pl->phi_nf.as<double>(),
                                   pl->field_nf.as<T>(), pl->phi_ff.as<double>(), pl->field_ff.as<T>(), forces, phi,
                                   pl->partials.as<double>(), nb, sc + 8, s), "finalize");
     stage_end(pl, FMM_STAGE_FINAL);
@@ -793,15 +823,70 @@ extern "C" fmm_status fmm_potential_parts(fmm_plan_t pl, int64_t n, const double
     return st;
 }
 
+// Pass 2 of the one-sided scheme (FMM_UV_SPARSE): the far-field potential of
+// the masked charges alone, at the masked atoms alone, into phi_u (0 at the
+// others).  The tree of those charges is non-zero only in the cells above the
+// leaves that hold them, and their potential is wanted only in the same
+// leaves, so every stage runs over the flagged cells (all in FP64, in the
+// level arrays of pass 1, which are free again): the dense algorithm
+// restricted to the cells whose terms are not identically zero.
+static fmm_status sparse_solute_field(fmm_plan_t pl, const uint8_t *mask) {
+    hipStream_t s = pl->stream;
+    const int64_t n = pl->n_state;
+    const int L = pl->levels, p = pl->p, K = pl->K, Kp = pl->Kp;
+    uint32_t *fl[kMaxLevels + 1];
+    fl[0] = pl->sflag.as<uint32_t>();
+    for (int l = 1; l <= L; ++l) fl[l] = pl->sflag.as<uint32_t>() + 1 + level_offset(l);
+    auto MD = [&](int l) { return pl->Mlev.as<double>() + (size_t)level_offset(l) * Kp; };
+    auto LD = [&](int l) { return pl->Llev.as<double>() + (size_t)level_offset(l) * Kp; };
+    const void *tree = pl->op->tree64.ptr;  // swizzled FP64 M2M (ids 0..7) then L2L (8..15)
+    const uint32_t *key = pl->key.as<uint32_t>();
+    const int32_t *perm = pl->perm.as<int32_t>();
+    HIPCHK(pl, launch_fill_u32(fl[L], 0u, level_cells(L), s), "fill");
+    HIPCHK(pl, launch_flags(n, mask, key, L, fl, s), "flags");
+    HIPCHK(pl, launch_p2m_sparse(level_cells(L), pl->xs.as<double>(), pl->start.as<int32_t>(), perm, mask, fl[L],
+                                 pl->box, L, p, Kp, MD(L), s), "P2M");
+    for (int l = L - 1; l >= 1; --l)
+        HIPCHK(pl, launch_m2m_sparse(level_cells(l), fl[l], fl[l + 1], MD(l + 1), MD(l), tree, K, Kp, false, s),
+               "M2M");
+    HIPCHK(pl, launch_m2m_sparse(1, fl[0], fl[1], MD(1), pl->M0.as<double>(), tree, K, Kp, true, s), "M2M");
+    HIPCHK(pl, launch_lattice(pl->M0.as<double>(), pl->L0.as<double>(), pl->lat.as<double>(), p, Kp, s), "lattice");
+    // levels 1 and 2 with the operators summed over aliased offsets (as the
+    // dense pass), where the 875 offsets reach only 8 or 64 source cells
+    for (int l = 1; l <= L; ++l) {
+        const OpSet &o = *pl->op;
+        const bool alias = l <= 2;
+        HIPCHK(pl, launch_m2l_sparse(l, fl[l], alias ? o.alias_il[l - 1].as<int32_t>() : o.il.as<int32_t>(),
+                                     alias ? o.alias_off[l - 1].as<int32_t>() : o.offv.as<int32_t>(),
+                                     alias ? o.alias_ops[l - 1].as<double>() : o.ops64.as<double>(), MD(l), LD(l), K,
+                                     Kp, alias ? 1 << (3 * l) : kILSize, s), "M2L");
+    }
+    for (int l = 1; l <= L; ++l)
+        HIPCHK(pl, launch_l2l_sparse(level_cells(l), fl[l], l == 1 ? pl->L0.as<double>() : LD(l - 1), LD(l), tree, K,
+                                     Kp, s), "L2L");
+    HIPCHK(pl, launch_l2p_sparse(n, pl->xs.as<double>(), key, perm, mask, pl->box, L, p, Kp, LD(L),
+                                 pl->phi_u.as<double>(), s), "L2P");
+    return FMM_OK;
+}
+
 template <typename T>
 static fmm_status enqueue_solute_solvent(fmm_plan_t pl, const uint8_t *mask) {
     hipStream_t s = pl->stream;
     const int64_t n = pl->n_state;
     fmm_status st;
-    // pass 2 of eq. FMMcalc: far field of the solute atoms alone
-    HIPCHK(pl, launch_mask_charges(n, pl->perm.as<int32_t>(), mask, pl->prec == FMM_FP64, pl->xq.ptr, pl->xq_u.ptr, s),
-           "mask charges");
-    if ((st = far_field<T>(pl, pl->xq_u.ptr, pl->phi_u.as<double>(), pl->field_u.as<T>())) != FMM_OK) return st;
+    if (pl->uv_scheme & FMM_UV_SWAP) {
+        // u <-> v: the solvent becomes the masked set of the second pass
+        HIPCHK(pl, launch_invert_mask(n, mask, pl->mask_sw.as<uint8_t>(), s), "mask");
+        mask = pl->mask_sw.as<uint8_t>();
+    }
+    if (pl->uv_scheme & FMM_UV_SPARSE) {
+        if ((st = sparse_solute_field(pl, mask)) != FMM_OK) return st;
+    } else {
+        // pass 2 of eq. FMMcalc: far field of the solute atoms alone
+        HIPCHK(pl, launch_mask_charges(n, pl->perm.as<int32_t>(), mask, pl->prec == FMM_FP64, pl->xq.ptr,
+                                       pl->xq_u.ptr, s), "mask charges");
+        if ((st = far_field<T>(pl, pl->xq_u.ptr, pl->phi_u.as<double>(), pl->field_u.as<T>())) != FMM_OK) return st;
+    }
     double *sc0 = pl->scalars.as<double>();
     HIPCHK(pl, hipMemcpyAsync(sc0 + 20, pl->M0.ptr, sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
     const double h_leaf = pl->box / (double)(1 << pl->levels);
@@ -832,9 +917,16 @@ static fmm_status finish_solute_solvent(fmm_plan_t pl, double *e_uv) {
     // t00 Q_tree / b and phi_u as t00 Q_u,tree / b (tree monopoles of the two
     // passes); its share of (A - B + C) / 2 is added here in FP64.
     const double qt = pl->q_tree, qut = h[20];
-    const double w_ff = 0.5 * (A - B + C) + 0.5 * pl->t00 / pl->box * (Qu * qt - Qu * qut + Qv * qut);
+    // one-sided form: sum_u q (phi_uv - phi_u), C unused (phi_u is 0 at v)
+    const double w_ff = (pl->uv_scheme & FMM_UV_SPARSE)
+                            ? (A - B) + pl->t00 / pl->box * Qu * (qt - qut)
+                            : 0.5 * (A - B + C) + 0.5 * pl->t00 / pl->box * (Qu * qt - Qu * qut + Qv * qut);
+    // the vacuum boundary's dipole surface term adds (4 pi / 3V) mu_u.mu_v,
+    // which cancels the dipole cross part of the background terms
+    const double mu_w = pl->boundary == FMM_BOUNDARY_VACUUM ? 0.0 : 1.0;
     const double w_bc = -M_PI * Qu * Qv / (V * pl->kappa * pl->kappa) +
-                        (2.0 * M_PI / (3.0 * V)) * (Qu * Sv + Qv * Su - 2.0 * (mux * mvx + muy * mvy + muz * mvz));
+                        (2.0 * M_PI / (3.0 * V)) *
+                            (Qu * Sv + Qv * Su - 2.0 * mu_w * (mux * mvx + muy * mvy + muz * mvz));
     *e_uv = w_ff + D + w_bc;
     return FMM_OK;
 }
@@ -855,6 +947,8 @@ extern "C" fmm_status fmm_solute_solvent_energy(fmm_plan_t pl, const uint8_t *ma
     if (pl->n_state == 0) { *e_uv = 0.0; return FMM_OK; }
     if (!mask) return fail(pl, FMM_ERR_INVALID, "mask must be non-NULL");
     HIPCHK(pl, hipSetDevice(pl->device), "hipSetDevice");
+    fmm_status st = ensure_m2l_ops(pl, (pl->uv_scheme & FMM_UV_SPARSE) != 0);
+    if (st != FMM_OK) return st;
     return pl->prec == FMM_FP64 ? solute_solvent_t<double>(pl, mask, e_uv) : solute_solvent_t<float>(pl, mask, e_uv);
 }
 
@@ -970,7 +1064,8 @@ extern "C" void fmm_destroy(fmm_plan_t pl) {
     DeviceBuf *bufs[] = {&pl->lat, &pl->key,
                          &pl->count, &pl->cursor, &pl->start, &pl->pstart, &pl->xqp, &pl->perm, &pl->scan, &pl->xq, &pl->xq_u, &pl->xs, &pl->m2l_part,
                          &pl->Mlev, &pl->Llev, &pl->M0, &pl->L0, &pl->phi_nf, &pl->field_nf, &pl->phi_ff,
-                         &pl->field_ff, &pl->phi_u, &pl->field_u, &pl->nfuv, &pl->partials, &pl->scalars, &pl->flag};
+                         &pl->field_ff, &pl->phi_u, &pl->field_u, &pl->nfuv, &pl->partials, &pl->scalars, &pl->flag,
+                         &pl->sflag, &pl->mask_sw};
     for (DeviceBuf *b : bufs) b->release();
     free_events(pl);
     if (pl->h_scalars) (void)hipHostFree(pl->h_scalars);
@@ -1163,6 +1258,7 @@ extern "C" fmm_status fmm_energy_forces_batch(fmm_plan_t pl, const int64_t *offs
     key.push_back((int64_t)(uintptr_t)q);
     key.push_back((int64_t)(uintptr_t)forces);
     key.push_back(pl->prec);
+    key.push_back(pl->boundary);
     st = batch_run(pl, pl->g_ef, key, offsets, [&](size_t w) -> fmm_status {
         fmm_plan_t b = pl->sub[w];
         const int64_t o = offsets[w], n = offsets[w + 1] - o;
@@ -1198,9 +1294,18 @@ extern "C" fmm_status fmm_solute_solvent_energy_batch(fmm_plan_t pl, const uint8
     const int64_t *off = pl->batch_off.data();
     if (off[nb] > off[0] && !mask) return fail(pl, FMM_ERR_INVALID, "mask is NULL");
     HIPCHK(pl, hipSetDevice(pl->device), "hipSetDevice");
+    for (size_t w = 0; w < nb; ++w) {
+        if (off[w + 1] == off[w]) continue;
+        const fmm_status so = ensure_m2l_ops(pl->sub[w], (pl->uv_scheme & FMM_UV_SPARSE) != 0);
+        if (so != FMM_OK) {
+            pl->err = "box " + std::to_string(w) + ": " + pl->sub[w]->err;
+            return so;
+        }
+    }
     std::vector<int64_t> key(pl->batch_off);
     key.push_back((int64_t)(uintptr_t)mask);
     key.push_back(pl->prec);
+    key.push_back(pl->uv_scheme);
     fmm_status st = batch_run(pl, pl->g_uv, key, off, [&](size_t w) -> fmm_status {
         fmm_plan_t b = pl->sub[w];
         return b->prec == FMM_FP64 ? enqueue_solute_solvent<double>(b, mask + off[w])

@@ -100,6 +100,7 @@ hipError_t launch_gather(int64_t n, const int32_t *perm, const double *pos, cons
                          double box, int levels, bool fp64, void *xq, double *xs, hipStream_t s);
 hipError_t launch_mask_charges(int64_t n, const int32_t *perm, const uint8_t *mask, bool fp64,
                                const void *xq, void *xq_u, hipStream_t s);
+hipError_t launch_invert_mask(int64_t n, const uint8_t *mask, uint8_t *out, hipStream_t s);
 
 // k_expand.hip (T = float for mixed, double for fp64)
 template <typename T>
@@ -110,6 +111,30 @@ hipError_t launch_lattice(const double *M0, double *L0, const double *AT, int p,
 template <typename T>
 hipError_t launch_l2p(int64_t nleaf, const void *xq, const int32_t *start, const T *L, int p,
                       int Kp, double h, double *phi, T *field, hipStream_t s);
+
+// Sparse far field of the solute charges (one-sided solute-solvent scheme),
+// FP64, restricted to the cells above the leaves that hold solute atoms.
+// flag[l] (l = 0..levels) points at the 8^l cell flags of level l.
+hipError_t launch_flags(int64_t n, const uint8_t *mask, const uint32_t *key, int levels, uint32_t *const *flag,
+                        hipStream_t s);
+// k_expand.hip: P2M of the solute atoms of flagged leaves from the FP64
+// centred positions xs (sorted order), and L2P at the solute atoms (phi = 0
+// at the others)
+hipError_t launch_p2m_sparse(int64_t nleaf, const double *xs, const int32_t *start, const int32_t *perm,
+                             const uint8_t *mask, const uint32_t *flag, double box, int levels, int p, int Kp,
+                             double *M, hipStream_t s);
+hipError_t launch_l2p_sparse(int64_t n, const double *xs, const uint32_t *key, const int32_t *perm,
+                             const uint8_t *mask, double box, int levels, int p, int Kp, const double *L, double *phi,
+                             hipStream_t s);
+// k_sparse.hip: ops = the 16 swizzled FP64 octant operators (M2M then L2L)
+// for M2M / L2L; for M2L the swizzled FP64 operators with their lists (nil
+// entries per parity class, as launch_m2l)
+hipError_t launch_m2m_sparse(int64_t nparent, const uint32_t *fparent, const uint32_t *fchild, const double *Mc,
+                             double *Mp, const void *ops, int K, int Kp, bool all, hipStream_t s);
+hipError_t launch_m2l_sparse(int level, const uint32_t *flag, const int32_t *il, const int32_t *offs,
+                             const double *ops, const double *M, double *L, int K, int Kp, int nil, hipStream_t s);
+hipError_t launch_l2l_sparse(int64_t nchild, const uint32_t *flag, const double *Lp, double *Lc, const void *ops,
+                             int K, int Kp, hipStream_t s);
 
 // k_m2l.hip
 // Levels with few target cells split the interaction list into slices
@@ -161,9 +186,11 @@ struct Moments {  // device-side FP64 results of the moment reduction
 hipError_t launch_moments(int64_t n, const double *xs, const int32_t *perm, const uint8_t *mask,
                           int want, double *partials, int nblocks, double *out5, hipStream_t s);
 int moments_blocks(int64_t n);
+// mu_w: weight of the dipole parts of the background terms, 1 under the
+// conducting boundary, 0 under vacuum (the dipole surface term cancels them)
 template <typename T>
 hipError_t launch_finalize(int64_t n, const int32_t *perm, const double *xs, double box, double kappa,
-                           double t00b, const double *moments, const double *m0, const double *phi_nf,
+                           double t00b, double mu_w, const double *moments, const double *m0, const double *phi_nf,
                            const T *field_nf, const double *phi_ff, const T *field_ff, double *forces,
                            double *phi, double *partials, int nblocks, double *energy_out, hipStream_t s);
 template <typename T>

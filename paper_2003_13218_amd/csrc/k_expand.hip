@@ -7,6 +7,7 @@
 // of the normalised harmonics, expansions at each level scaled by the cell
 // edge so that every operator is level- and box-independent.
 #include "fmm_internal.h"
+#include "morton.h"
 
 namespace fmm {
 
@@ -158,6 +159,137 @@ template hipError_t launch_p2m<float>(int64_t, const void *, const int32_t *, fl
                                       hipStream_t);
 template hipError_t launch_p2m<double>(int64_t, const void *, const int32_t *, double *, int, int, double,
                                        hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Sparse solute pass (one-sided solute-solvent energy): P2M of the solute
+// atoms of flagged leaves and L2P at solute atoms only, in FP64 from the FP64
+// wrapped positions xs (measured from the box centre).
+// ---------------------------------------------------------------------------
+
+// R^_n^m for one order m and n = m..p, by the recurrences above (the sectoral
+// value R^_m^m from m steps of its own recurrence).
+template <typename T, typename F>
+__device__ inline void regular_hat_column(T x, T y, T z, int m, int p, F &&f) {
+    const T r2 = x * x + y * y + z * z;
+    T mre = 1, mim = 0;
+    for (int k = 1; k <= m; ++k) {
+        const T c = -Rec<T>::c(k);
+        const T nre = c * (x * mre - y * mim);
+        const T nim = c * (x * mim + y * mre);
+        mre = nre;
+        mim = nim;
+    }
+    f(m, mre, mim);
+    if (m + 1 > p) return;
+    T p2re = mre, p2im = mim;
+    const T dm = Rec<T>::d(m) * z;
+    T p1re = dm * mre, p1im = dm * mim;
+    f(m + 1, p1re, p1im);
+    int ti = (m + 2) * (m + 3) / 2 + m;
+    for (int n = m + 2; n <= p; ++n) {
+        const T a = Rec<T>::a(ti) * z, b = Rec<T>::b(ti) * r2;
+        const T cre = a * p1re - b * p2re;
+        const T cim = a * p1im - b * p2im;
+        f(n, cre, cim);
+        p2re = p1re; p2im = p1im;
+        p1re = cre; p1im = cim;
+        ti += n + 1;
+    }
+}
+
+// leaf-local FP64 coordinates (in units of the leaf edge) of sorted atom s
+__device__ inline void leaf_local(const double *xs, int64_t s, uint32_t leaf, double box, double h, double &x,
+                                  double &y, double &z) {
+    uint32_t cx, cy, cz;
+    demorton3(leaf, cx, cy, cz);
+    const double hb = 0.5 * box;
+    x = (xs[4 * s + 0] - (((double)cx + 0.5) * h - hb)) / h;
+    y = (xs[4 * s + 1] - (((double)cy + 0.5) * h - hb)) / h;
+    z = (xs[4 * s + 2] - (((double)cz + 0.5) * h - hb)) / h;
+}
+
+// One wavefront per leaf; flagged leaves only.  Lane m accumulates the order-m
+// coefficients of every solute atom of the leaf (each lane owns its entries).
+__global__ __launch_bounds__(64) void k_p2m_sparse(int64_t nleaf, const double *__restrict__ xs,
+                                                   const int32_t *__restrict__ start,
+                                                   const int32_t *__restrict__ perm,
+                                                   const uint8_t *__restrict__ mask, const uint32_t *__restrict__ flag,
+                                                   double box, double h, int p, int Kp, double *__restrict__ M) {
+    const int64_t leaf = blockIdx.x;
+    if (leaf >= nleaf || !flag[leaf]) return;
+    const int m = threadIdx.x;
+    double *Ml = M + leaf * Kp;
+    if (m <= p)
+        for (int n = m; n <= p; ++n) {
+            if (m == 0) Ml[n * n] = 0.0;
+            else {
+                Ml[n * n + 2 * m - 1] = 0.0;
+                Ml[n * n + 2 * m] = 0.0;
+            }
+        }
+    if (m == 0)
+        for (int k = (p + 1) * (p + 1); k < Kp; ++k) Ml[k] = 0.0;
+    if (m > p) return;
+    for (int32_t s = start[leaf]; s < start[leaf + 1]; ++s) {
+        if (!mask[perm[s]]) continue;
+        double x, y, z;
+        leaf_local(xs, s, (uint32_t)leaf, box, h, x, y, z);
+        const double q = xs[4 * s + 3];
+        regular_hat_column<double>(x, y, z, m, p, [&](int n, double re, double im) {
+            if (m == 0) Ml[n * n] += q * re;
+            else {
+                Ml[n * n + 2 * m - 1] += q * re;
+                Ml[n * n + 2 * m] -= q * im;
+            }
+        });
+    }
+}
+
+hipError_t launch_p2m_sparse(int64_t nleaf, const double *xs, const int32_t *start, const int32_t *perm,
+                             const uint8_t *mask, const uint32_t *flag, double box, int levels, int p, int Kp,
+                             double *M, hipStream_t s) {
+    const double h = box / (double)(1 << levels);
+    hipLaunchKernelGGL(k_p2m_sparse, dim3((unsigned)nleaf), dim3(64), 0, s, nleaf, xs, start, perm, mask, flag, box,
+                       h, p, Kp, M);
+    return hipGetLastError();
+}
+
+// Potential of the leaf's local expansion at every solute atom (0 elsewhere),
+// one thread per sorted atom.
+__global__ void k_l2p_sparse(int64_t n, const double *__restrict__ xs, const uint32_t *__restrict__ key,
+                             const int32_t *__restrict__ perm, const uint8_t *__restrict__ mask, double box,
+                             double h, int p, int Kp, const double *__restrict__ L, double *__restrict__ phi) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = perm[s];
+        if (!mask[i]) {
+            phi[s] = 0.0;
+            continue;
+        }
+        const uint32_t leaf = key[i];
+        double x, y, z;
+        leaf_local(xs, s, leaf, box, h, x, y, z);
+        const double *Ll = L + (size_t)leaf * Kp;
+        double acc = 0.0;
+        regular_hat_foreach<double>(x, y, z, p, [&](int nn, int m, double re, double im) {
+            if (m == 0) acc += re * Ll[nn * nn];
+            else acc += re * Ll[nn * nn + 2 * m - 1] + im * Ll[nn * nn + 2 * m];
+        });
+        phi[s] = acc / h;
+    }
+}
+
+hipError_t launch_l2p_sparse(int64_t n, const double *xs, const uint32_t *key, const int32_t *perm,
+                             const uint8_t *mask, double box, int levels, int p, int Kp, const double *L, double *phi,
+                             hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const double h = box / (double)(1 << levels);
+    int64_t g = (n + 255) / 256;
+    if (g > 65535) g = 65535;
+    hipLaunchKernelGGL(k_l2p_sparse, dim3((unsigned)g), dim3(256), 0, s, n, xs, key, perm, mask, box, h, p, Kp, L,
+                       phi);
+    return hipGetLastError();
+}
 
 // degree n of the real storage index idx (n^2 <= idx < (n+1)^2)
 __device__ inline int degree_of(int idx) {

@@ -110,8 +110,8 @@ hipError_t launch_moments(int64_t n, const double *xs, const int32_t *perm, cons
 template <typename T>
 __global__ __launch_bounds__(kRedBlock) void k_finalize(
     int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ xs,
-    double box, double kappa, double t00b, const double *__restrict__ mom, const double *__restrict__ m0,
-    const double *__restrict__ phi_nf,
+    double box, double kappa, double t00b, double mu_w, const double *__restrict__ mom,
+    const double *__restrict__ m0, const double *__restrict__ phi_nf,
     const T *__restrict__ field_nf, const double *__restrict__ phi_ff, const T *__restrict__ field_ff,
     double *__restrict__ forces, double *__restrict__ phi_out, double *__restrict__ partials) {
     const double V = box * box * box;
@@ -123,6 +123,9 @@ __global__ __launch_bounds__(kRedBlock) void k_finalize(
     const double c_bg = -M_PI * Q / (V * kappa * kappa) + t00b * m0[0];
     const double c23 = 2.0 * M_PI / (3.0 * V);
     const double c43 = 4.0 * M_PI / (3.0 * V);
+    // under the vacuum boundary (mu_w = 0) the dipole surface term
+    // (2 pi / 3V) mu.mu cancels the -mu.mu of the quadrupole/dipole terms
+    const double wx = mu_w * mux, wy = mu_w * muy, wz = mu_w * muz;
     NSum e[1];
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
          s += (int64_t)gridDim.x * blockDim.x) {
@@ -132,14 +135,14 @@ __global__ __launch_bounds__(kRedBlock) void k_finalize(
         e[0].add(0.5 * qi * ph);  // E_pair; the t00 part is added once below
         const double x = xs[4 * s], y = xs[4 * s + 1], z = xs[4 * s + 2];
         if (phi_out)
-            phi_out[i] = ph + c_bg + c23 * (S + Q * (x * x + y * y + z * z) - 2.0 * (mux * x + muy * y + muz * z));
+            phi_out[i] = ph + c_bg + c23 * (S + Q * (x * x + y * y + z * z) - 2.0 * (wx * x + wy * y + wz * z));
         if (forces) {
             const double ex = (double)field_nf[3 * s] + (double)field_ff[3 * s];
             const double ey = (double)field_nf[3 * s + 1] + (double)field_ff[3 * s + 1];
             const double ez = (double)field_nf[3 * s + 2] + (double)field_ff[3 * s + 2];
-            forces[3 * i + 0] = qi * ex - c43 * qi * (Q * x - mux);
-            forces[3 * i + 1] = qi * ey - c43 * qi * (Q * y - muy);
-            forces[3 * i + 2] = qi * ez - c43 * qi * (Q * z - muz);
+            forces[3 * i + 0] = qi * ex - c43 * qi * (Q * x - wx);
+            forces[3 * i + 1] = qi * ey - c43 * qi * (Q * y - wy);
+            forces[3 * i + 2] = qi * ez - c43 * qi * (Q * z - wz);
         }
     }
     block_reduce<1>(e);
@@ -152,8 +155,8 @@ __global__ __launch_bounds__(kRedBlock) void k_finalize(
 // E = E_pair + E_corr
 __global__ __launch_bounds__(kRedBlock) void k_energy_final(const double *__restrict__ partials, int nblocks,
                                                              const double *__restrict__ mom, double box,
-                                                             double kappa, double t00b, const double *__restrict__ m0,
-                                                             double *__restrict__ out) {
+                                                             double kappa, double t00b, double mu_w,
+                                                             const double *__restrict__ m0, double *__restrict__ out) {
     NSum v[1];
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v[0].merge(partials[2 * b], partials[2 * b + 1]);
     block_reduce<1>(v);
@@ -165,7 +168,7 @@ __global__ __launch_bounds__(kRedBlock) void k_energy_final(const double *__rest
         t.merge(v[0].s, v[0].c);
         t.add(-M_PI * Q * Q / (2.0 * V * kappa * kappa));
         t.add(0.5 * t00b * Q * m0[0]);
-        t.add(2.0 * M_PI / (3.0 * V) * (Q * S - mu2));
+        t.add(2.0 * M_PI / (3.0 * V) * (Q * S - mu_w * mu2));
         out[0] = t.value();
         out[1] = v[0].value();
     }
@@ -173,20 +176,20 @@ __global__ __launch_bounds__(kRedBlock) void k_energy_final(const double *__rest
 
 template <typename T>
 hipError_t launch_finalize(int64_t n, const int32_t *perm, const double *xs, double box, double kappa,
-                           double t00b, const double *moments, const double *m0, const double *phi_nf,
+                           double t00b, double mu_w, const double *moments, const double *m0, const double *phi_nf,
                            const T *field_nf, const double *phi_ff, const T *field_ff, double *forces, double *phi,
                            double *partials, int nblocks, double *energy_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize<T>, dim3(nblocks), dim3(kRedBlock), 0, s, n, perm, xs, box, kappa, t00b,
+    hipLaunchKernelGGL(k_finalize<T>, dim3(nblocks), dim3(kRedBlock), 0, s, n, perm, xs, box, kappa, t00b, mu_w,
                        moments, m0, phi_nf, field_nf, phi_ff, field_ff, forces, phi, partials);
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kRedBlock), 0, s, partials, nblocks, moments, box, kappa,
-                       t00b, m0, energy_out);
+                       t00b, mu_w, m0, energy_out);
     return hipGetLastError();
 }
-template hipError_t launch_finalize<float>(int64_t, const int32_t *, const double *, double, double, double,
+template hipError_t launch_finalize<float>(int64_t, const int32_t *, const double *, double, double, double, double,
                                            const double *, const double *, const double *, const float *,
                                            const double *, const float *, double *, double *, double *, int, double *,
                                            hipStream_t);
-template hipError_t launch_finalize<double>(int64_t, const int32_t *, const double *, double, double, double,
+template hipError_t launch_finalize<double>(int64_t, const int32_t *, const double *, double, double, double, double,
                                             const double *, const double *, const double *, const double *, const double *,
                                             const double *, double *, double *, double *, int, double *,
                                             hipStream_t);

@@ -395,4 +395,17 @@ hipError_t launch_mask_charges(int64_t n, const int32_t *perm, const uint8_t *ma
     return hipGetLastError();
 }
 
+// out[i] = 1 - (mask[i] != 0): the solvent as the masked set
+__global__ void k_invert_mask(int64_t n, const uint8_t *__restrict__ mask, uint8_t *__restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = mask[i] ? 0 : 1;
+}
+
+hipError_t launch_invert_mask(int64_t n, const uint8_t *mask, uint8_t *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_invert_mask, dim3(grid_for(n, 256)), dim3(256), 0, s, n, mask, out);
+    return hipGetLastError();
+}
+
 }  // namespace fmm

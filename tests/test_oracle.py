@@ -281,3 +281,54 @@ def test_solid_harmonics_closed_forms():
     _, Ir = oracle.solid_harmonics(v, 14)
     tot = sum(np.conj(Rs[k]) * Ir[k] for k in Rs)
     assert tot.real == pytest.approx(1 / np.linalg.norm(v - s), rel=1e-13)
+
+
+def test_vacuum_boundary_is_plain_spherical_sum():
+    # For a neutral set, the image sum over growing complete spherical shells
+    # (no surface correction) converges to the energy under the vacuum
+    # boundary: the conducting Ewald energy plus (2 pi / 3V) mu.mu (eq.
+    # surfdipole).  Positions inside the box, so "as given" = wrapped.
+    box = 5.0
+    pos, q = workloads.random_charges(5, box, seed=31, net=0.0)
+    xi = oracle.ewald(np.zeros((1, 3)), np.ones(1), 1.0)["terms"]["total"] * -2.0
+    ev = oracle.ewald(pos, q, box, boundary="vacuum")
+    ec = oracle.ewald(pos, q, box)
+    bf = oracle.shell_sum_energy(pos, q, box, 36, xi=xi, surface=False)
+    # R = 36 leaves 1.6e-8 of shell truncation; the surface term is 0.1 here
+    assert bf == pytest.approx(ev["terms"]["total"], abs=5e-8)
+    assert abs(bf - ec["terms"]["total"]) > 1e-2
+    # forces: minus the gradient of the plain shell sum
+    h = 1e-4
+    for a in range(3):
+        pp = pos.copy(); pp[2, a] += h
+        pm = pos.copy(); pm[2, a] -= h
+        fd = -(oracle.shell_sum_energy(pp, q, box, 36, xi=xi, surface=False)
+               - oracle.shell_sum_energy(pm, q, box, 36, xi=xi, surface=False)) / (2 * h)
+        assert ev["force"][2, a] == pytest.approx(fd, abs=2e-9)
+        assert abs(ec["force"][2, a] - fd) > 1e-5
+
+
+def test_vacuum_boundary_phi_and_cross_energy():
+    # charged parts: phi_i = dE/dq_i and E = 1/2 sum q phi (every term is
+    # quadratic in the charges); W = E(u+v) - E(u) - E(v) with each energy
+    # under the vacuum boundary
+    box = 6.0
+    pos, q = workloads.random_charges(9, box, seed=33, net=0.6)
+    pos[0] += [box, 0.0, -2 * box]  # an atom outside the box: mu uses the wrapped position
+    r = oracle.ewald(pos, q, box, boundary="vacuum")
+    assert 0.5 * float(q @ r["phi"]) == pytest.approx(r["terms"]["total"], rel=1e-12)
+    h = 1e-6
+    for i in (0, 4):
+        qp = q.copy(); qp[i] += h
+        qm = q.copy(); qm[i] -= h
+        fd = (oracle.ewald(pos, qp, box, boundary="vacuum")["terms"]["total"]
+              - oracle.ewald(pos, qm, box, boundary="vacuum")["terms"]["total"]) / (2 * h)
+        assert r["phi"][i] == pytest.approx(fd, rel=1e-7, abs=1e-9)
+    mask = np.zeros(9, np.uint8); mask[[0, 3, 5]] = 1
+    m = mask == 1
+    e_all = r["terms"]["total"]
+    e_u = oracle.ewald(pos[m], q[m], box, boundary="vacuum")["terms"]["total"]
+    e_v = oracle.ewald(pos[~m], q[~m], box, boundary="vacuum")["terms"]["total"]
+    w = oracle.ewald_uv(pos, q, mask, box, boundary="vacuum")
+    assert w["total"] == pytest.approx(e_all - e_u - e_v, rel=1e-10, abs=1e-10)
+    assert abs(w["dipole"]) > 1e-4
