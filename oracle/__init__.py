@@ -178,16 +178,68 @@ def ewald_uv(pos, q, mask, box, kappa=None, rcut=None, kmax=None, accuracy=1e-13
     return dict(real=terms[0], rec=terms[1], charged=terms[2], dipole=dip, total=terms[3] + dip)
 
 
-def lambda_energy(pos, q, mask, box, lam, accuracy=1e-13):
+def lambda_energy(pos, q, mask, box, lam, accuracy=1e-13, softcore=None):
     """V_lambda and dV_lambda/dlambda of eq. Vswucheme (solute: mask == 1).
 
     The solute-solvent coupling (u-v, u-Bv, v-Bu, Bu-Bv) is scaled by
     (1 - lam): V = E(u+Bu) + E(v+Bv) + (1 - lam) W = E - lam W, with E the
     Ewald energy of all charges and W the two-set cross energy; dV/dlam = -W.
+
+    softcore = dict(levels, alpha, sigma, c): the near-field u-v pairs (eq.
+    EqNF on a tree of that depth) take the soft-core form of
+    ``softcore_nf_uv``, so their (1 - lam)-scaled energy (1 - lam) D0 becomes
+    (1 - lam) Dsc(lam):
+        V = E - lam W + (1 - lam)(Dsc - D0),
+        dV/dlam = -W + D0 - Dsc + (1 - lam) dDsc/dlam.
     """
     e = ewald(pos, q, box, accuracy=accuracy)["terms"]["total"]
     w = ewald_uv(pos, q, mask, box, accuracy=accuracy)["total"]
-    return e - lam * w, -w
+    if softcore is None:
+        return e - lam * w, -w
+    d0, dsc, dl = softcore_nf_uv(pos, q, mask, box, softcore["levels"], lam, softcore["alpha"],
+                                 softcore["sigma"], softcore["c"])
+    return e - lam * w + (1.0 - lam) * (dsc - d0), -w + d0 - dsc + (1.0 - lam) * dl
+
+
+def softcore_nf_uv(pos, q, mask, box, levels, lam, alpha, sigma, c, ws=2):
+    """Near-field solute-solvent pair sums with the soft-core Coulomb form.
+
+    The near field of eq. EqNF pairs atom i with every image of atom j whose
+    unwrapped leaf lies within +-ws leaves of the leaf of i (leaves of edge
+    b / 2^levels after wrapping into [0, b)); here it is enumerated image by
+    image.  The soft-core form follows the one the paper gives for the
+    solute-solvent LJ term (section "Calculation detail") and notes to apply
+    to the electrostatic NF term: 1/r -> 1/s with
+    s = (alpha lam sigma^c + r^c)^(1/c).  Returns (D0, Dsc, Dlam): the sums of
+    q_u q_v / r, q_u q_v / s and q_u q_v d(1/s)/dlam over the u-v NF pairs.
+    """
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    q = np.asarray(q, dtype=np.float64).reshape(-1)
+    m = np.asarray(mask).reshape(-1) != 0
+    nc = 1 << levels
+    w = wrap_positions(pos, box)
+    cell, _ = bin_reference(pos, box, levels)
+    r_img = np.arange(-2, 3)
+    imgs = np.stack(np.meshgrid(r_img, r_img, r_img, indexing="ij"), -1).reshape(-1, 3)
+    v = np.nonzero(~m)[0]
+    wv, cv, qv = w[v], cell[v], q[v]
+    asc = alpha * lam * sigma ** c
+    d0 = dsc = dl = 0.0
+    for i in np.nonzero(m)[0]:
+        for img in imgs:
+            lead = cv + nc * img[None, :] - cell[i][None, :]   # unwrapped leaf offset of the image
+            sel = np.all(np.abs(lead) <= ws, axis=1)
+            if not sel.any():
+                continue
+            d = w[i][None, :] - (wv[sel] + box * img[None, :])
+            r = np.sqrt((d * d).sum(1))
+            x = asc + r ** c
+            inv_s = x ** (-1.0 / c)
+            qq = q[i] * qv[sel]
+            d0 += float(np.sum(qq / r))
+            dsc += float(np.sum(qq * inv_s))
+            dl += float(np.sum(qq * (-(alpha * sigma ** c / c) * inv_s / x)))
+    return d0, dsc, dl
 
 
 def nearfield(pos, q, box, levels, ws=2):

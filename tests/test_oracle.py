@@ -332,3 +332,54 @@ def test_vacuum_boundary_phi_and_cross_energy():
     w = oracle.ewald_uv(pos, q, mask, box, boundary="vacuum")
     assert w["total"] == pytest.approx(e_all - e_u - e_v, rel=1e-10, abs=1e-10)
     assert abs(w["dipole"]) > 1e-4
+
+
+def test_softcore_nf_uv_pins():
+    # soft-core near-field u-v sums: at lam = 0 (or alpha = 0) s = r; the hard
+    # sum equals sum_u q_u phi_NF(u) of the solvent charges alone from the
+    # offset-by-offset near-field oracle (this one enumerates images); the
+    # lam derivative is that of the sum itself; and for one pair in a large
+    # box the sum is the closed form
+    box = 9.0
+    pos, q = workloads.random_charges(60, box, seed=51, net=0.4)
+    mask = np.zeros(60, np.uint8); mask[[3, 17, 40]] = 1
+    for levels in (1, 2, 3):
+        d0, dsc, dl = oracle.softcore_nf_uv(pos, q, mask, box, levels, 0.0, 0.5, 2.5, 6)
+        assert dsc == pytest.approx(d0, rel=1e-13)
+        qv = np.where(mask == 1, 0.0, q)
+        phi, _ = oracle.nearfield(pos, qv, box, levels)
+        assert d0 == pytest.approx(float(np.sum(q[mask == 1] * phi[mask == 1])), rel=1e-12)
+        d0b, dscb, _ = oracle.softcore_nf_uv(pos, q, mask, box, levels, 0.7, 0.0, 2.5, 6)
+        assert dscb == pytest.approx(d0, rel=1e-13) and d0b == d0
+        lam, h = 0.35, 1e-6
+        _, _, dl = oracle.softcore_nf_uv(pos, q, mask, box, levels, lam, 0.5, 2.5, 6)
+        fp = oracle.softcore_nf_uv(pos, q, mask, box, levels, lam + h, 0.5, 2.5, 6)[1]
+        fm = oracle.softcore_nf_uv(pos, q, mask, box, levels, lam - h, 0.5, 2.5, 6)[1]
+        assert dl == pytest.approx((fp - fm) / (2 * h), rel=1e-7)
+    # one u-v pair 1.5 apart near the centre of a box of 100 on a 2-level tree
+    # (leaf 25: the pair is in one leaf and no image is within reach)
+    p2 = np.array([[50.0, 50.0, 50.0], [51.5, 50.0, 50.0]])
+    q2 = np.array([1.0, -0.8])
+    d0, dsc, dl = oracle.softcore_nf_uv(p2, q2, np.array([1, 0]), 100.0, 2, 0.6, 0.5, 2.0, 6)
+    x = 0.5 * 0.6 * 2.0 ** 6 + 1.5 ** 6
+    assert d0 == pytest.approx(-0.8 / 1.5, rel=1e-14)
+    assert dsc == pytest.approx(-0.8 * x ** (-1 / 6), rel=1e-14)
+    assert dl == pytest.approx(-0.8 * (-(0.5 * 2.0 ** 6 / 6) * x ** (-7 / 6)), rel=1e-13)
+
+
+def test_softcore_lambda_energy_derivative():
+    # dV/dlam of the soft-core V_lambda is the derivative of V_lambda itself
+    box = 8.0
+    pos, q = workloads.random_charges(24, box, seed=52, net=-0.5)
+    mask = np.zeros(24, np.uint8); mask[[2, 9]] = 1
+    sc = dict(levels=2, alpha=0.5, sigma=2.0, c=6)
+    lam, h = 0.6, 1e-5
+    v, dv = oracle.lambda_energy(pos, q, mask, box, lam, softcore=sc)
+    vp = oracle.lambda_energy(pos, q, mask, box, lam + h, softcore=sc)[0]
+    vm = oracle.lambda_energy(pos, q, mask, box, lam - h, softcore=sc)[0]
+    assert dv == pytest.approx((vp - vm) / (2 * h), rel=1e-6, abs=1e-9)
+    # the end points: lam = 0 is the plain energy, lam = 1 the decoupled one
+    e = oracle.ewald(pos, q, box)["terms"]["total"]
+    assert oracle.lambda_energy(pos, q, mask, box, 0.0, softcore=sc)[0] == pytest.approx(e, rel=1e-12)
+    assert oracle.lambda_energy(pos, q, mask, box, 1.0, softcore=sc)[0] == pytest.approx(
+        oracle.lambda_energy(pos, q, mask, box, 1.0)[0], rel=1e-12)
