@@ -188,6 +188,27 @@ fmm_status fmm_lambda_energy(fmm_plan_t plan, const uint8_t *mask, double lambda
                              double *dv_dlambda);
 
 /*
+ * fmm_plan_softcore -- soft-core near-field solute-solvent Coulomb pairs in
+ * fmm_lambda_energy and fmm_lambda_energy_batch.  The paper gives the
+ * soft-core form for the solute-solvent LJ term of its charging path
+ * (section "Calculation detail") and notes that it applies to the
+ * electrostatic near-field term as well; here every u-v pair of the near field
+ * (eq. EqNF: the +-2-leaf neighbourhood of the plan's tree) takes
+ *   q_u q_v / s,  s = (alpha lambda sigma^c + r^c)^(1/c),
+ * in place of q_u q_v / r inside the (1 - lambda)-scaled coupling, so that
+ *   V_lambda    = E - lambda e_uv + (1 - lambda)(Dsc - D0),
+ *   dV/dlambda  = -e_uv + D0 - Dsc + (1 - lambda) dDsc/dlambda,
+ * with D0 and Dsc the hard and soft sums over those pairs (the far field and
+ * the background terms keep their plain form).  alpha = 0 (the default)
+ * turns it off; sigma > 0 is a length, c an integer in [1, 12]; with it on,
+ * lambda must lie in [0, 1].  The near-field pair set depends on the tree
+ * depth, so results are comparable between plans of equal depth only.  On a
+ * batch plan it applies to every box.  fmm_solute_solvent_energy is not
+ * affected.
+ */
+fmm_status fmm_plan_softcore(fmm_plan_t plan, double alpha, double sigma, int c);
+
+/*
  * fmm_potential_parts -- near- and far-field parts separately (no charged,
  * quadrupole or dipole terms), per atom in the caller's order, for checking
  * the stages on their own.  phi_nf / phi_ff: device n FP64 (or NULL);

@@ -33,7 +33,7 @@ EXPORTED = (
     "fmm_potential_parts", "fmm_bin", "fmm_lattice_tensor", "fmm_profile", "fmm_profile_read",
     "fmm_last_error", "fmm_destroy", "fmm_version", "fmm_plan_batch", "fmm_energy_forces_batch",
     "fmm_solute_solvent_energy_batch", "fmm_autotune_batch", "fmm_batch_levels", "fmm_lambda_energy",
-    "fmm_lambda_energy_batch", "fmm_plan_options",
+    "fmm_lambda_energy_batch", "fmm_plan_options", "fmm_plan_softcore",
 )
 
 STAGES = ("sort", "gather", "p2m", "m2m", "lattice", "m2l", "m2l_leaf", "l2l", "l2p", "p2p", "final", "total")
@@ -64,6 +64,8 @@ def load():
         lib.fmm_plan_config.restype = ci
         lib.fmm_plan_options.argtypes = [vp, ci, ci]
         lib.fmm_plan_options.restype = ci
+        lib.fmm_plan_softcore.argtypes = [vp, dbl, dbl, ci]
+        lib.fmm_plan_softcore.restype = ci
         lib.fmm_energy_forces.argtypes = [vp, i64, vp, vp, ctypes.POINTER(dbl), vp, vp]
         lib.fmm_energy_forces.restype = ci
         lib.fmm_solute_solvent_energy.argtypes = [vp, vp, ctypes.POINTER(dbl)]
@@ -164,6 +166,10 @@ def fmm_plan_config(plan: Plan, precision: int = FMM_FP64, kappa: float = 0.0, s
 
 def fmm_plan_options(plan: Plan, boundary: int = FMM_BOUNDARY_CONDUCTING, uv_scheme: int = FMM_UV_SYMMETRIC):
     _check(load().fmm_plan_options(plan.handle, int(boundary), int(uv_scheme)), plan)
+
+
+def fmm_plan_softcore(plan: Plan, alpha: float, sigma: float = 1.0, c: int = 6):
+    _check(load().fmm_plan_softcore(plan.handle, float(alpha), float(sigma), int(c)), plan)
 
 
 def fmm_energy_forces(plan: Plan, pos, q, forces=True, phi=False):

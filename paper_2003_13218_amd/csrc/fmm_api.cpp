@@ -97,6 +97,12 @@ struct fmm_plan {
     DeviceBuf phi_nf, field_nf, phi_ff, field_ff, phi_u, field_u, nfuv, partials, scalars, flag;
     DeviceBuf sflag;    // sparse solute pass: one flag per cell, level 0 first, then levels 1..L
     DeviceBuf mask_sw;  // exchanged solute mask (FMM_UV_SWAP)
+    DeviceBuf mask_s;   // solute mask in sorted order
+    DeviceBuf nfsc, nfdl;  // soft-core near-field u-v sums per solute atom
+    // soft-core near-field u-v pairs of the lambda-coupled energy (alpha 0: off)
+    double sc_alpha = 0.0, sc_sigma = 1.0;
+    int sc_c = 6;
+    double uv_d0 = 0.0, uv_dsc = 0.0, uv_dl = 0.0;  // near-field sums of the last solute-solvent pass
     int boundary = FMM_BOUNDARY_CONDUCTING;
     int uv_scheme = FMM_UV_SYMMETRIC;
     double *h_scalars = nullptr;  // pinned host mirror of `scalars`
@@ -489,7 +495,7 @@ static fmm_status ensure_workspace(fmm_plan_t pl, int64_t n) {
             !pl->pstart.ensure(sizeof(int32_t) * (nleaf + 1)) ||
             !pl->scan.ensure(sizeof(int32_t) * scan_scratch_len(nleaf)) ||
             !pl->scalars.ensure(sizeof(double) * kScalars) || !pl->flag.ensure(sizeof(int) * 4) ||
-            !pl->partials.ensure(sizeof(double) * 2 * 5 * 1024) ||
+            !pl->partials.ensure(sizeof(double) * 2 * 6 * 1024) ||
             !pl->sflag.ensure(sizeof(uint32_t) * (size_t)(1 + cells)))
             return fail(pl, FMM_ERR_NOMEM, "tree workspace allocation");
         pl->tree_ready = true;
@@ -503,7 +509,8 @@ static fmm_status ensure_workspace(fmm_plan_t pl, int64_t n) {
             !pl->phi_nf.ensure(sizeof(double) * nn) || !pl->field_nf.ensure(sizeof(double) * 3 * nn) ||
             !pl->phi_ff.ensure(sizeof(double) * nn) || !pl->field_ff.ensure(sizeof(double) * 3 * nn) ||
             !pl->phi_u.ensure(sizeof(double) * nn) || !pl->field_u.ensure(sizeof(double) * 3 * nn) ||
-            !pl->nfuv.ensure(sizeof(double) * nn) || !pl->mask_sw.ensure(nn))
+            !pl->nfuv.ensure(sizeof(double) * nn) || !pl->mask_sw.ensure(nn) || !pl->mask_s.ensure(nn) ||
+            !pl->nfsc.ensure(sizeof(double) * nn) || !pl->nfdl.ensure(sizeof(double) * nn))
             return fail(pl, FMM_ERR_NOMEM, "per-atom workspace allocation");
         pl->cap_n = n;
     }
@@ -869,8 +876,9 @@ static fmm_status sparse_solute_field(fmm_plan_t pl, const uint8_t *mask) {
     return FMM_OK;
 }
 
+// lam >= 0 with a soft-core set: also the soft-core near-field sums at lam
 template <typename T>
-static fmm_status enqueue_solute_solvent(fmm_plan_t pl, const uint8_t *mask) {
+static fmm_status enqueue_solute_solvent(fmm_plan_t pl, const uint8_t *mask, double lam = -1.0) {
     hipStream_t s = pl->stream;
     const int64_t n = pl->n_state;
     fmm_status st;
@@ -890,18 +898,27 @@ static fmm_status enqueue_solute_solvent(fmm_plan_t pl, const uint8_t *mask) {
     double *sc0 = pl->scalars.as<double>();
     HIPCHK(pl, hipMemcpyAsync(sc0 + 20, pl->M0.ptr, sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
     const double h_leaf = pl->box / (double)(1 << pl->levels);
+    const bool soft = lam >= 0.0 && pl->sc_alpha > 0.0;
+    SoftCore sco{};
+    if (soft) {
+        const double sigc = std::pow(pl->sc_sigma, (double)pl->sc_c);
+        sco = SoftCore{pl->sc_alpha * lam * sigc, pl->sc_alpha * sigc / pl->sc_c, pl->sc_c, pl->nfsc.as<double>(),
+                       pl->nfdl.as<double>()};
+    }
     HIPCHK(pl, launch_p2p_uv<T>(n, pl->levels, pl->xq.ptr, pl->start.as<int32_t>(), pl->perm.as<int32_t>(), mask,
-                                h_leaf, pl->nfuv.as<double>(), s), "P2P uv");
+                                pl->mask_s.as<uint8_t>(), h_leaf, pl->nfuv.as<double>(), soft ? &sco : nullptr, s),
+           "P2P uv");
     const int nb = moments_blocks(n);
     double *sc = pl->scalars.as<double>();
     HIPCHK(pl, launch_uv_sums<T>(n, pl->perm.as<int32_t>(), pl->xs.as<double>(), mask, pl->phi_ff.as<double>(),
-                                 pl->phi_u.as<double>(), pl->nfuv.as<double>(), pl->partials.as<double>(), nb, sc + 16, s),
+                                 pl->phi_u.as<double>(), pl->nfuv.as<double>(), soft ? pl->nfsc.as<double>() : nullptr,
+                                 soft ? pl->nfdl.as<double>() : nullptr, pl->partials.as<double>(), nb, sc + 40, s),
            "uv sums");
     HIPCHK(pl, launch_moments(n, pl->xs.as<double>(), pl->perm.as<int32_t>(), mask, 1, pl->partials.as<double>(), nb,
                               sc + 24, s), "moments");
     HIPCHK(pl, launch_moments(n, pl->xs.as<double>(), pl->perm.as<int32_t>(), mask, 0, pl->partials.as<double>(), nb,
                               sc + 32, s), "moments");
-    return enqueue_readback(pl, 40);
+    return enqueue_readback(pl, 46);
 }
 
 // W_uv from the pass-2 scalars, after the plan stream has been synchronised
@@ -909,7 +926,10 @@ static fmm_status finish_solute_solvent(fmm_plan_t pl, double *e_uv) {
     fmm_status st = check_readback(pl);
     if (st != FMM_OK) return st;
     const double *h = pl->h_scalars;
-    const double A = h[16], B = h[17], C = h[18], D = h[19];
+    const double A = h[40], B = h[41], C = h[42], D = h[43];
+    pl->uv_d0 = D;
+    pl->uv_dsc = h[44];
+    pl->uv_dl = h[45];
     const double Qu = h[24], mux = h[25], muy = h[26], muz = h[27], Su = h[28];
     const double Qv = h[32], mvx = h[33], mvy = h[34], mvz = h[35], Sv = h[36];
     const double V = pl->box * pl->box * pl->box;
@@ -932,36 +952,77 @@ static fmm_status finish_solute_solvent(fmm_plan_t pl, double *e_uv) {
 }
 
 template <typename T>
-static fmm_status solute_solvent_t(fmm_plan_t pl, const uint8_t *mask, double *e_uv) {
-    fmm_status st = enqueue_solute_solvent<T>(pl, mask);
+static fmm_status solute_solvent_t(fmm_plan_t pl, const uint8_t *mask, double lam, double *e_uv) {
+    fmm_status st = enqueue_solute_solvent<T>(pl, mask, lam);
     if (st != FMM_OK) return st;
     HIPCHK(pl, hipStreamSynchronize(pl->stream), "synchronize");
     return finish_solute_solvent(pl, e_uv);
 }
 
-extern "C" fmm_status fmm_solute_solvent_energy(fmm_plan_t pl, const uint8_t *mask, double *e_uv) {
+// e_uv; with lam >= 0 and a soft-core set, also the soft-core near-field sums
+// (pl->uv_d0, uv_dsc, uv_dl) at lam
+static fmm_status solute_solvent_single(fmm_plan_t pl, const uint8_t *mask, double lam, double *e_uv) {
     if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
     if (pl->is_batch) return fail(pl, FMM_ERR_INVALID, "batch plan: use fmm_solute_solvent_energy_batch");
     if (!e_uv) return fail(pl, FMM_ERR_INVALID, "e_uv must be non-NULL");
     if (!pl->have_state) return fail(pl, FMM_ERR_STATE, "fmm_solute_solvent_energy needs a preceding fmm_energy_forces");
+    pl->uv_d0 = pl->uv_dsc = pl->uv_dl = 0.0;
     if (pl->n_state == 0) { *e_uv = 0.0; return FMM_OK; }
     if (!mask) return fail(pl, FMM_ERR_INVALID, "mask must be non-NULL");
     HIPCHK(pl, hipSetDevice(pl->device), "hipSetDevice");
     fmm_status st = ensure_m2l_ops(pl, (pl->uv_scheme & FMM_UV_SPARSE) != 0);
     if (st != FMM_OK) return st;
-    return pl->prec == FMM_FP64 ? solute_solvent_t<double>(pl, mask, e_uv) : solute_solvent_t<float>(pl, mask, e_uv);
+    return pl->prec == FMM_FP64 ? solute_solvent_t<double>(pl, mask, lam, e_uv)
+                                : solute_solvent_t<float>(pl, mask, lam, e_uv);
+}
+
+extern "C" fmm_status fmm_solute_solvent_energy(fmm_plan_t pl, const uint8_t *mask, double *e_uv) {
+    return solute_solvent_single(pl, mask, -1.0, e_uv);
+}
+
+// eq. Vswucheme: the solute-solvent coupling scaled by (1 - lambda), V = E -
+// lambda W.  With the soft-core near field the u-v NF pairs' share (1 -
+// lambda) D0 of that is replaced by (1 - lambda) Dsc(lambda).
+static void lambda_values(const struct fmm_plan *b, double e, double w, double lam, double *v, double *dv) {
+    double vv = e - lam * w, dd = -w;
+    if (b->sc_alpha > 0.0) {
+        vv += (1.0 - lam) * (b->uv_dsc - b->uv_d0);
+        dd += b->uv_d0 - b->uv_dsc + (1.0 - lam) * b->uv_dl;
+    }
+    if (v) *v = vv;
+    if (dv) *dv = dd;
+}
+
+static fmm_status check_lambda(fmm_plan_t pl, double lambda) {
+    if (!std::isfinite(lambda)) return fail(pl, FMM_ERR_INVALID, "lambda must be finite");
+    if (pl->sc_alpha > 0.0 && (lambda < 0.0 || lambda > 1.0))
+        return fail(pl, FMM_ERR_INVALID, "lambda must be in [0, 1] with a soft-core near field");
+    return FMM_OK;
 }
 
 extern "C" fmm_status fmm_lambda_energy(fmm_plan_t pl, const uint8_t *mask, double lambda, double *v_lambda,
                                         double *dv_dlambda) {
     if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
-    if (!std::isfinite(lambda)) return fail(pl, FMM_ERR_INVALID, "lambda must be finite");
-    double w = 0.0;
-    const fmm_status st = fmm_solute_solvent_energy(pl, mask, &w);
+    fmm_status st = check_lambda(pl, lambda);
     if (st != FMM_OK) return st;
-    // eq. Vswucheme: the solute-solvent coupling scaled by (1 - lambda)
-    if (v_lambda) *v_lambda = pl->last_energy - lambda * w;
-    if (dv_dlambda) *dv_dlambda = -w;
+    double w = 0.0;
+    if ((st = solute_solvent_single(pl, mask, lambda, &w)) != FMM_OK) return st;
+    lambda_values(pl, pl->last_energy, w, lambda, v_lambda, dv_dlambda);
+    return FMM_OK;
+}
+
+extern "C" fmm_status fmm_plan_softcore(fmm_plan_t pl, double alpha, double sigma, int c) {
+    if (!pl) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan_softcore: plan is NULL");
+    if (!std::isfinite(alpha) || alpha < 0.0) return fail(pl, FMM_ERR_INVALID, "fmm_plan_softcore: alpha must be >= 0");
+    if (!std::isfinite(sigma) || sigma <= 0.0) return fail(pl, FMM_ERR_INVALID, "fmm_plan_softcore: sigma must be > 0");
+    if (c < 1 || c > 12) return fail(pl, FMM_ERR_INVALID, "fmm_plan_softcore: c must be in [1, 12]");
+    auto set = [&](fmm_plan_t b) {
+        b->sc_alpha = alpha;
+        b->sc_sigma = sigma;
+        b->sc_c = c;
+    };
+    set(pl);
+    for (fmm_plan_t b : pl->sub) set(b);
     return FMM_OK;
 }
 
@@ -1065,7 +1126,7 @@ extern "C" void fmm_destroy(fmm_plan_t pl) {
                          &pl->count, &pl->cursor, &pl->start, &pl->pstart, &pl->xqp, &pl->perm, &pl->scan, &pl->xq, &pl->xq_u, &pl->xs, &pl->m2l_part,
                          &pl->Mlev, &pl->Llev, &pl->M0, &pl->L0, &pl->phi_nf, &pl->field_nf, &pl->phi_ff,
                          &pl->field_ff, &pl->phi_u, &pl->field_u, &pl->nfuv, &pl->partials, &pl->scalars, &pl->flag,
-                         &pl->sflag, &pl->mask_sw};
+                         &pl->sflag, &pl->mask_sw, &pl->mask_s, &pl->nfsc, &pl->nfdl};
     for (DeviceBuf *b : bufs) b->release();
     free_events(pl);
     if (pl->h_scalars) (void)hipHostFree(pl->h_scalars);
@@ -1284,7 +1345,9 @@ extern "C" fmm_status fmm_energy_forces_batch(fmm_plan_t pl, const int64_t *offs
     return FMM_OK;
 }
 
-extern "C" fmm_status fmm_solute_solvent_energy_batch(fmm_plan_t pl, const uint8_t *mask, double *e_uv) {
+// lams (host, nbox) or NULL: with a soft-core set, the per-box lambda of the
+// soft-core near-field sums
+static fmm_status solute_solvent_batch(fmm_plan_t pl, const uint8_t *mask, const double *lams, double *e_uv) {
     if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
     if (!pl->is_batch) return fail(pl, FMM_ERR_INVALID, "fmm_solute_solvent_energy_batch: not a batch plan");
     if (!e_uv) return fail(pl, FMM_ERR_INVALID, "e_uv is NULL");
@@ -1306,10 +1369,29 @@ extern "C" fmm_status fmm_solute_solvent_energy_batch(fmm_plan_t pl, const uint8
     key.push_back((int64_t)(uintptr_t)mask);
     key.push_back(pl->prec);
     key.push_back(pl->uv_scheme);
+    const bool soft = lams && pl->sc_alpha > 0.0;
+    if (soft) {
+        // the soft-core parameters and lambdas are kernel arguments of the graph
+        const double prm[2] = {pl->sc_alpha, pl->sc_sigma};
+        for (double x : prm) {
+            int64_t bits;
+            std::memcpy(&bits, &x, sizeof bits);
+            key.push_back(bits);
+        }
+        key.push_back(pl->sc_c);
+        for (size_t w = 0; w < nb; ++w) {
+            int64_t bits;
+            std::memcpy(&bits, &lams[w], sizeof bits);
+            key.push_back(bits);
+        }
+    }
+    key.push_back(soft ? 1 : 0);
+    for (fmm_plan_t b : pl->sub) b->uv_d0 = b->uv_dsc = b->uv_dl = 0.0;
     fmm_status st = batch_run(pl, pl->g_uv, key, off, [&](size_t w) -> fmm_status {
         fmm_plan_t b = pl->sub[w];
-        return b->prec == FMM_FP64 ? enqueue_solute_solvent<double>(b, mask + off[w])
-                                   : enqueue_solute_solvent<float>(b, mask + off[w]);
+        const double lam = soft ? lams[w] : -1.0;
+        return b->prec == FMM_FP64 ? enqueue_solute_solvent<double>(b, mask + off[w], lam)
+                                   : enqueue_solute_solvent<float>(b, mask + off[w], lam);
     });
     if (st != FMM_OK) return st;
     HIPCHK(pl, hipStreamSynchronize(pl->stream), "synchronize");
@@ -1324,21 +1406,25 @@ extern "C" fmm_status fmm_solute_solvent_energy_batch(fmm_plan_t pl, const uint8
     return FMM_OK;
 }
 
+extern "C" fmm_status fmm_solute_solvent_energy_batch(fmm_plan_t pl, const uint8_t *mask, double *e_uv) {
+    return solute_solvent_batch(pl, mask, nullptr, e_uv);
+}
+
 extern "C" fmm_status fmm_lambda_energy_batch(fmm_plan_t pl, const uint8_t *mask, const double *lambdas,
                                               double *v_lambda, double *dv_dlambda) {
     if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
     if (!pl->is_batch) return fail(pl, FMM_ERR_INVALID, "fmm_lambda_energy_batch: not a batch plan");
     if (!lambdas) return fail(pl, FMM_ERR_INVALID, "lambdas is NULL");
     const size_t nb = pl->sub.size();
+    fmm_status st;
     for (size_t w = 0; w < nb; ++w)
-        if (!std::isfinite(lambdas[w])) return fail(pl, FMM_ERR_INVALID, "lambdas must be finite");
+        if ((st = check_lambda(pl, lambdas[w])) != FMM_OK) return st;
     std::vector<double> e_uv(nb);
-    const fmm_status st = fmm_solute_solvent_energy_batch(pl, mask, e_uv.data());
-    if (st != FMM_OK) return st;
+    if ((st = solute_solvent_batch(pl, mask, lambdas, e_uv.data())) != FMM_OK) return st;
     for (size_t w = 0; w < nb; ++w) {
         const double e = (pl->batch_off[w + 1] > pl->batch_off[w]) ? pl->sub[w]->last_energy : 0.0;
-        if (v_lambda) v_lambda[w] = e - lambdas[w] * e_uv[w];
-        if (dv_dlambda) dv_dlambda[w] = -e_uv[w];
+        lambda_values(pl->sub[w], e, e_uv[w], lambdas[w], v_lambda ? &v_lambda[w] : nullptr,
+                      dv_dlambda ? &dv_dlambda[w] : nullptr);
     }
     return FMM_OK;
 }

@@ -174,10 +174,21 @@ hipError_t launch_l2l_mfma(int64_t nparent, const Tin *Lparent, Tout *Lchild, co
 template <typename T>
 hipError_t launch_p2p(int64_t nleaf, int levels, const void *xqp, const int32_t *pstart, const int32_t *start,
                       double h, double *phi, T *field, int groups, int nsplit, int max_wg, hipStream_t s);
+// Soft-core near-field u-v pairs (lambda-coupled energy): 1/r -> 1/s,
+// s = (asc + r^c)^(1/c), asc = alpha lambda sigma^c, kd = alpha sigma^c / c;
+// per solute atom q_s sum q_j / s into out_sc and q_s sum q_j d(1/s)/dlambda
+// into out_dl
+struct SoftCore {
+    double asc, kd;
+    int c;
+    double *out_sc, *out_dl;
+};
+// ms: n bytes of scratch (the mask in sorted order); out_per_atom is written
+// at the solute atoms only; sc may be NULL (no soft-core sums)
 template <typename T>
 hipError_t launch_p2p_uv(int64_t n, int levels, const void *xq, const int32_t *start,
-                         const int32_t *perm, const uint8_t *mask, double h, double *out_per_atom,
-                         hipStream_t s);
+                         const int32_t *perm, const uint8_t *mask, uint8_t *ms, double h, double *out_per_atom,
+                         const SoftCore *sc, hipStream_t s);
 
 // k_reduce.hip
 struct Moments {  // device-side FP64 results of the moment reduction
@@ -196,9 +207,11 @@ hipError_t launch_finalize(int64_t n, const int32_t *perm, const double *xs, dou
 template <typename T>
 hipError_t launch_parts_out(int64_t n, const int32_t *perm, const double *phi_s, const T *field_s,
                             const double *m0, double cq, double *phi, double *field, hipStream_t s);
+// out6: sum_u q phi_uv, sum_u q phi_u, sum_v q phi_u, sum_u nf_uv, and the
+// sums over u of nf_sc and nf_dl (0 when those are NULL)
 template <typename T>
 hipError_t launch_uv_sums(int64_t n, const int32_t *perm, const double *xs, const uint8_t *mask,
-                          const double *phi_uv, const double *phi_u, const double *nf_uv, double *partials,
-                          int nblocks, double *out4, hipStream_t s);
+                          const double *phi_uv, const double *phi_u, const double *nf_uv, const double *nf_sc,
+                          const double *nf_dl, double *partials, int nblocks, double *out6, hipStream_t s);
 
 }  // namespace fmm

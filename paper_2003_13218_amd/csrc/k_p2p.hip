@@ -142,66 +142,143 @@ template hipError_t launch_p2p<double>(int64_t, int, const void *, const int32_t
                                        double *, double *, int, int, int, hipStream_t);
 
 // Near-field solute-solvent pairs: out[s] = q_s sum_{j in NF(s), solvent} q_j / r
-// for solute atoms s (0 for solvent).  One wavefront per leaf: the lanes flag
-// the leaf's solute atoms; for each of them (wave-uniform loop) the lanes
-// split the solvent sources of the 125 neighbour leaves, each lane summing its
-// terms in FP64, then a fixed shuffle tree adds the lane sums.  Leaves without
-// solute atoms only write zeros.
+// for the solute atoms s (entries of solvent atoms are not written).  With
+// out_sc set, also the soft-core sums of the lambda-coupled energy, in FP64:
+// out_sc[s] = q_s sum q_j / s_ij and out_dl[s] = q_s sum q_j d(1/s_ij)/dlambda,
+// s = (asc + r^c)^(1/c) with asc = alpha lambda sigma^c, and
+// d(1/s)/dlambda = -kd s^(-c-1), kd = alpha sigma^c / c.
+// One workgroup per leaf.  The leaf's solute atoms are compacted (in order)
+// into LDS; for each of them the 256 threads split the 125 neighbour leaves,
+// two threads per leaf taking one half of its atoms each, sum their terms in
+// FP64, and a fixed LDS tree adds the 256 partial sums.  Leaves without solute
+// atoms read their mask bytes and return.
+constexpr int kUvBlock = 256;
+
+__global__ void k_sorted_mask(int64_t n, const int32_t *__restrict__ perm, const uint8_t *__restrict__ mask,
+                              uint8_t *__restrict__ ms) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+         s += (int64_t)gridDim.x * blockDim.x)
+        ms[s] = mask[perm[s]] ? 1 : 0;
+}
+
+// r^c for a small positive integer c (r2 = r^2)
+__device__ inline double pow_int_r(double r2, int c) {
+    double x = (c & 1) ? sqrt(r2) : 1.0;
+    for (int k = 0; k < c / 2; ++k) x *= r2;
+    return x;
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_p2p_uv(int64_t nleaf, int levels, const T *__restrict__ xq,
-                                                const int32_t *__restrict__ start,
-                                                const int32_t *__restrict__ perm, const uint8_t *__restrict__ mask,
-                                                T h, double *__restrict__ out) {
-    const int lane = threadIdx.x & 63;
-    const int64_t leaf = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
-    if (leaf >= nleaf) return;  // whole wavefront; no block barriers below
-    uint32_t cx, cy, cz;
-    demorton3((uint32_t)leaf, cx, cy, cz);
-    const uint32_t nmask = (1u << levels) - 1u;
+__global__ __launch_bounds__(kUvBlock) void k_p2p_uv(int levels, const T *__restrict__ xq,
+                                                     const int32_t *__restrict__ start,
+                                                     const uint8_t *__restrict__ ms, T h,
+                                                     double *__restrict__ out, double asc, double kd, int c,
+                                                     double *__restrict__ out_sc, double *__restrict__ out_dl) {
+    __shared__ int32_t list[kUvBlock];
+    __shared__ int wave_cnt[kUvBlock / 64];
+    __shared__ double red[3][kUvBlock];
+    const bool soft = out_sc != nullptr;
+    const double inv_c = 1.0 / (double)c;
+    const uint32_t leaf = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int32_t s0 = start[leaf], s1 = start[leaf + 1];
-    for (int32_t base = s0; base < s1; base += 64) {
-        const int32_t i = base + lane;
-        const bool is_u = i < s1 && mask[perm[i]] != 0;
-        if (i < s1 && !is_u) out[i] = 0.0;
-        uint64_t todo = __ballot(is_u);
-        while (todo) {
-            const int k = __builtin_ctzll(todo);
-            todo &= todo - 1;
-            const int32_t a = base + k;  // wave-uniform solute atom
-            const T xi = xq[4 * (int64_t)a], yi = xq[4 * (int64_t)a + 1], zi = xq[4 * (int64_t)a + 2];
-            double acc = 0.0;
-            for (int dx = -kWS; dx <= kWS; ++dx)
-                for (int dy = -kWS; dy <= kWS; ++dy)
-                    for (int dz = -kWS; dz <= kWS; ++dz) {
-                        const uint32_t sc = morton3((cx + dx) & nmask, (cy + dy) & nmask, (cz + dz) & nmask);
-                        const T ox = xi - (T)dx * h, oy = yi - (T)dy * h, oz = zi - (T)dz * h;
-                        for (int32_t j = start[sc] + lane; j < start[sc + 1]; j += 64) {
-                            if (mask[perm[j]]) continue;
-                            const T *bj = xq + 4 * (int64_t)j;
-                            const T ddx = ox - bj[0], ddy = oy - bj[1], ddz = oz - bj[2];
-                            const T r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-                            acc += (double)(bj[3] * rsqrt_t<T>(r2));
-                        }
-                    }
-#pragma unroll
-            for (int m = 1; m < 64; m <<= 1) acc += __shfl_xor(acc, m);
-            if (lane == 0) out[a] = (double)xq[4 * (int64_t)a + 3] * acc;
+    bool ready = false;  // neighbour range of this thread set up
+    int32_t j0 = 0, j1 = 0;
+    T ox0 = 0, oy0 = 0, oz0 = 0;  // -(unwrapped offset) x h of this thread's neighbour leaf
+    for (int32_t base = s0; base < s1; base += kUvBlock) {
+        const int32_t i = base + tid;
+        const bool is_u = i < s1 && ms[i] != 0;
+        const uint64_t b = __ballot(is_u);
+        if (lane == 0) wave_cnt[wv] = __popcll(b);
+        __syncthreads();
+        int off = 0, nu = 0;
+        for (int w = 0; w < kUvBlock / 64; ++w) {
+            if (w < wv) off += wave_cnt[w];
+            nu += wave_cnt[w];
+        }
+        if (is_u) list[off + __popcll(b & ((1ull << lane) - 1ull))] = i;
+        __syncthreads();
+        if (nu > 0 && !ready) {
+            ready = true;
+            const int c = tid >> 1;
+            if (c < 125) {
+                uint32_t cx, cy, cz;
+                demorton3(leaf, cx, cy, cz);
+                const uint32_t nmask = (1u << levels) - 1u;
+                const int dx = c / 25 - kWS, dy = (c / 5) % 5 - kWS, dz = c % 5 - kWS;
+                const uint32_t sc = morton3((cx + dx) & nmask, (cy + dy) & nmask, (cz + dz) & nmask);
+                const int32_t a0 = start[sc], a1 = start[sc + 1];
+                const int32_t mid = a0 + (a1 - a0 + 1) / 2;
+                j0 = (tid & 1) ? mid : a0;
+                j1 = (tid & 1) ? a1 : mid;
+                ox0 = -(T)dx * h;
+                oy0 = -(T)dy * h;
+                oz0 = -(T)dz * h;
+            }
+        }
+        for (int k = 0; k < nu; ++k) {
+            const int32_t a = list[k];
+            const T xi = xq[4 * (int64_t)a] + ox0, yi = xq[4 * (int64_t)a + 1] + oy0,
+                    zi = xq[4 * (int64_t)a + 2] + oz0;
+            double acc = 0.0, asc_sum = 0.0, adl = 0.0;
+            for (int32_t j = j0; j < j1; ++j) {
+                if (ms[j]) continue;
+                const T *bj = xq + 4 * (int64_t)j;
+                const T ddx = xi - bj[0], ddy = yi - bj[1], ddz = zi - bj[2];
+                const T r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                acc += (double)(bj[3] * rsqrt_t<T>(r2));
+                if (soft) {
+                    const double dx = (double)ddx, dy = (double)ddy, dz = (double)ddz;
+                    const double x = asc + pow_int_r(dx * dx + dy * dy + dz * dz, c);
+                    const double inv_s = pow(x, -inv_c);
+                    asc_sum += (double)bj[3] * inv_s;
+                    adl -= (double)bj[3] * kd * inv_s / x;
+                }
+            }
+            red[0][tid] = acc;
+            red[1][tid] = asc_sum;
+            red[2][tid] = adl;
+            __syncthreads();
+            for (int st = kUvBlock / 2; st > 0; st >>= 1) {
+                if (tid < st) {
+                    red[0][tid] += red[0][tid + st];
+                    red[1][tid] += red[1][tid + st];
+                    red[2][tid] += red[2][tid + st];
+                }
+                __syncthreads();
+            }
+            if (tid == 0) {
+                const double qa = (double)xq[4 * (int64_t)a + 3];
+                out[a] = qa * red[0][0];
+                if (soft) {
+                    out_sc[a] = qa * red[1][0];
+                    out_dl[a] = qa * red[2][0];
+                }
+            }
+            __syncthreads();
         }
     }
 }
 
 template <typename T>
 hipError_t launch_p2p_uv(int64_t n, int levels, const void *xq, const int32_t *start, const int32_t *perm,
-                         const uint8_t *mask, double h, double *out, hipStream_t s) {
+                         const uint8_t *mask, uint8_t *ms, double h, double *out, const SoftCore *sc, hipStream_t s) {
+    if (sc && (sc->c < 1 || sc->c > 12)) return hipErrorInvalidValue;
     if (n <= 0) return hipSuccess;
+    int64_t g = (n + 255) / 256;
+    if (g > 65535) g = 65535;
+    hipLaunchKernelGGL(k_sorted_mask, dim3((unsigned)g), dim3(256), 0, s, n, perm, mask, ms);
     const int64_t nleaf = (int64_t)1 << (3 * levels);
-    hipLaunchKernelGGL(k_p2p_uv<T>, dim3((unsigned)((nleaf + 3) / 4)), dim3(256), 0, s, nleaf, levels,
-                       (const T *)xq, start, perm, mask, (T)h, out);
+    hipLaunchKernelGGL(k_p2p_uv<T>, dim3((unsigned)nleaf), dim3(kUvBlock), 0, s, levels, (const T *)xq, start, ms,
+                       (T)h, out, sc ? sc->asc : 0.0, sc ? sc->kd : 0.0, sc ? sc->c : 1, sc ? sc->out_sc : nullptr,
+                       sc ? sc->out_dl : nullptr);
     return hipGetLastError();
 }
 template hipError_t launch_p2p_uv<float>(int64_t, int, const void *, const int32_t *, const int32_t *,
-                                         const uint8_t *, double, double *, hipStream_t);
+                                         const uint8_t *, uint8_t *, double, double *, const SoftCore *,
+                                         hipStream_t);
 template hipError_t launch_p2p_uv<double>(int64_t, int, const void *, const int32_t *, const int32_t *,
-                                          const uint8_t *, double, double *, hipStream_t);
+                                          const uint8_t *, uint8_t *, double, double *, const SoftCore *,
+                                          hipStream_t);
 
 }  // namespace fmm

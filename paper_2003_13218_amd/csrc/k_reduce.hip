@@ -236,8 +236,10 @@ __global__ __launch_bounds__(kRedBlock) void k_uv_sums(int64_t n, const int32_t 
                                                         const double *__restrict__ phi_uv,
                                                         const double *__restrict__ phi_u,
                                                         const double *__restrict__ nf_uv,
+                                                        const double *__restrict__ nf_sc,
+                                                        const double *__restrict__ nf_dl,
                                                         double *__restrict__ partials) {
-    NSum v[4];
+    NSum v[6];
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
          s += (int64_t)gridDim.x * blockDim.x) {
         const double qi = xs[4 * s + 3];
@@ -245,32 +247,36 @@ __global__ __launch_bounds__(kRedBlock) void k_uv_sums(int64_t n, const int32_t 
             v[0].add(qi * phi_uv[s]);
             v[1].add(qi * phi_u[s]);
             v[3].add(nf_uv[s]);
+            if (nf_sc) {
+                v[4].add(nf_sc[s]);
+                v[5].add(nf_dl[s]);
+            }
         } else {
             v[2].add(qi * phi_u[s]);
         }
     }
-    block_reduce<4>(v);
+    block_reduce<6>(v);
     if (threadIdx.x == 0)
-        for (int k = 0; k < 4; ++k) {
-            partials[(blockIdx.x * 4 + k) * 2] = v[k].s;
-            partials[(blockIdx.x * 4 + k) * 2 + 1] = v[k].c;
+        for (int k = 0; k < 6; ++k) {
+            partials[(blockIdx.x * 6 + k) * 2] = v[k].s;
+            partials[(blockIdx.x * 6 + k) * 2 + 1] = v[k].c;
         }
 }
 
 template <typename T>
 hipError_t launch_uv_sums(int64_t n, const int32_t *perm, const double *xs, const uint8_t *mask,
-                          const double *phi_uv, const double *phi_u, const double *nf_uv, double *partials, int nblocks, double *out4,
-                          hipStream_t s) {
+                          const double *phi_uv, const double *phi_u, const double *nf_uv, const double *nf_sc,
+                          const double *nf_dl, double *partials, int nblocks, double *out6, hipStream_t s) {
     hipLaunchKernelGGL(k_uv_sums<T>, dim3(nblocks), dim3(kRedBlock), 0, s, n, perm, xs, mask, phi_uv, phi_u,
-                       nf_uv, partials);
-    hipLaunchKernelGGL(k_final_sum<4>, dim3(1), dim3(kRedBlock), 0, s, partials, nblocks, out4);
+                       nf_uv, nf_sc, nf_dl, partials);
+    hipLaunchKernelGGL(k_final_sum<6>, dim3(1), dim3(kRedBlock), 0, s, partials, nblocks, out6);
     return hipGetLastError();
 }
 template hipError_t launch_uv_sums<float>(int64_t, const int32_t *, const double *, const uint8_t *,
-                                          const double *, const double *, const double *, double *, int, double *,
-                                          hipStream_t);
+                                          const double *, const double *, const double *, const double *,
+                                          const double *, double *, int, double *, hipStream_t);
 template hipError_t launch_uv_sums<double>(int64_t, const int32_t *, const double *, const uint8_t *,
-                                           const double *, const double *, const double *, double *, int,
-                                           double *, hipStream_t);
+                                           const double *, const double *, const double *, const double *,
+                                           const double *, double *, int, double *, hipStream_t);
 
 }  // namespace fmm

@@ -59,16 +59,21 @@ __device__ inline size_t swz(int oid, int row, int col, int NB) {
     return ((((size_t)oid * NB + kc) * NB + rb) * 64 + lane) * 4 + (col & 3);
 }
 
-// acc += O_oid[row][:] . v[:] for the K columns (v: K doubles, uniform)
+// acc + O_oid[row][:] . v[:] over the K columns (v: K doubles, uniform).
+// Two accumulators and an unrolled loop keep several loads in flight.
 __device__ inline double swz_dot(const double *__restrict__ ops, int oid, int row, int NB, int K,
                                  const double *__restrict__ v, double acc) {
-    const int kfull = K & ~3;
-    for (int col = 0; col < kfull; col += 4) {
-        const double *o = ops + swz(oid, row, col, NB);  // 4 contiguous columns
+    const int k8 = K & ~7;
+    double a1 = 0.0;
+#pragma unroll 2
+    for (int col = 0; col < k8; col += 8) {
+        const double *o = ops + swz(oid, row, col, NB);      // columns col .. col+3
+        const double *o2 = ops + swz(oid, row, col + 4, NB); // columns col+4 .. col+7
         acc += o[0] * v[col] + o[1] * v[col + 1] + o[2] * v[col + 2] + o[3] * v[col + 3];
+        a1 += o2[0] * v[col + 4] + o2[1] * v[col + 5] + o2[2] * v[col + 6] + o2[3] * v[col + 7];
     }
-    for (int col = kfull; col < K; ++col) acc += ops[swz(oid, row, col, NB)] * v[col];
-    return acc;
+    for (int col = k8; col < K; ++col) acc += ops[swz(oid, row, col, NB)] * v[col];
+    return acc + a1;
 }
 
 // M~(P) = sum over flagged children 8P + o of A_o M~(8P + o) with the swizzled
