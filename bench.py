@@ -32,6 +32,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 M2L_IL = 875  # interaction-list size per cell
+# list entries per cell of the FP32/FP64 kernel: the 875 offsets form 302
+# (t, -t) pairs, each one operator product (O_-t = D O_t D), and 271 singles
+M2L_ENTRIES = 573
 PEAK_TFLOPS = {"mixed": 157.3, "bf16": 2500.0, "fp64": 78.6}  # dense MFMA peaks of MI355X (FP32, BF16, FP64)
 PREC_NAMES = {"fp64": 0, "mixed": 1, "bf16": 2}
 def leaf_kernel(prec_name, p):
@@ -42,10 +45,12 @@ def leaf_kernel(prec_name, p):
     return f"k_m2l_lds<{'double' if prec_name == 'fp64' else 'float'}, false, {min(11, nb)}>"
 
 
-def m2l_flops(p, level):
-    """Algorithmic M2L flops of one level: 2 K^2 per (target, source) pair."""
+def m2l_flops(p, level, prec_name="mixed"):
+    """Algorithmic M2L flops of one level: 2 K^2 per (target, list entry); the
+    FP32/FP64 kernels take a (t, -t) pair as one entry, the BF16 kernel every
+    offset."""
     K = (p + 1) ** 2
-    return 2.0 * K * K * M2L_IL * 8 ** level
+    return 2.0 * K * K * (M2L_IL if prec_name == "bf16" else M2L_ENTRIES) * 8 ** level
 
 
 def recorded_traffic(kernel, workload):
@@ -141,7 +146,7 @@ def run_single(args, w, p, prec_name, steps, warmup, fp64_leg, cpu_leg):
 
     # dominant kernel: M2L at the finest level; algorithmic flops per launch
     # divided by its event-timed average duration on the plan's stream
-    flops_leaf = m2l_flops(p, w.levels)
+    flops_leaf = m2l_flops(p, w.levels, prec_name)
     m2l_ms = st["m2l_leaf"]
     achieved = flops_leaf / (m2l_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec_name]

@@ -46,13 +46,17 @@ struct OpSet {
     int p = 0;
     Offsets offs;
     DeviceBuf ops32, ops64, opsbf, il, offv;  // M2L (FP32 / FP64 / bfloat16), interaction lists
+    // paired (t, -t) list entries of the FP32/FP64 M2L, the row order of its
+    // operators (row -> storage row) and its inverse (storage row -> row)
+    DeviceBuf pairs, rowmap, rowpos;
     DeviceBuf tree32, tree64;                 // swizzled M2M (8) then L2L (8) octant operators
     // levels 1 and 2 (grids of 2 and 4 cells per axis): FP64 operators summed
     // over the offsets that reach the same source cell (alias_ops), their
     // lists (8 x n^3 ids) and offsets (the residues of t modulo n)
     DeviceBuf alias_ops[2], alias_il[2], alias_off[2];
     ~OpSet() {
-        DeviceBuf *b[] = {&ops32, &ops64, &opsbf, &il, &offv, &tree32, &tree64, &alias_ops[0], &alias_ops[1],
+        DeviceBuf *b[] = {&ops32, &ops64, &opsbf, &il, &offv, &pairs, &rowmap, &rowpos, &tree32, &tree64,
+                          &alias_ops[0], &alias_ops[1],
                           &alias_il[0], &alias_il[1], &alias_off[0], &alias_off[1]};
         for (DeviceBuf *x : b) x->release();
     }
@@ -242,8 +246,21 @@ static fmm_status make_opset(int p, std::shared_ptr<OpSet> &out, std::string &ms
     std::vector<double> s64(ne);
     swizzle_ops<float>(p, 16, rm.data(), s32.data());
     swizzle_ops<double>(p, 16, rm.data(), s64.data());
+    std::vector<int32_t> pairs((size_t)8 * 2 * kM2LEntries);
+    build_m2l_pairs(op->offs.vec.data(), op->offs.il.data(), pairs.data());
+    if (pairs[0] < 0) {
+        msg = "fmm_plan: interaction list does not pair up";
+        return FMM_ERR_INVALID;
+    }
+    const int nrow = 16 * m2l_row_blocks(p);
+    std::vector<int32_t> rowmap(nrow), rowpos(Kp, -1);
+    m2l_row_map(p, rowmap.data());
+    for (int i = 0; i < nrow; ++i)
+        if (rowmap[i] >= 0) rowpos[rowmap[i]] = i;
     if (!op->tree32.ensure(ne * sizeof(float)) || !op->tree64.ensure(ne * sizeof(double)) ||
-        !op->il.ensure(sizeof(int32_t) * 8 * kILSize) || !op->offv.ensure(sizeof(int32_t) * 3 * kNumOffsets)) {
+        !op->il.ensure(sizeof(int32_t) * 8 * kILSize) || !op->offv.ensure(sizeof(int32_t) * 3 * kNumOffsets) ||
+        !op->pairs.ensure(sizeof(int32_t) * pairs.size()) || !op->rowmap.ensure(sizeof(int32_t) * nrow) ||
+        !op->rowpos.ensure(sizeof(int32_t) * Kp)) {
         msg = "fmm_plan: device allocation";
         return FMM_ERR_NOMEM;
     }
@@ -251,7 +268,10 @@ static fmm_status make_opset(int p, std::shared_ptr<OpSet> &out, std::string &ms
         hipMemcpy(op->tree64.ptr, s64.data(), ne * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(op->il.ptr, op->offs.il.data(), sizeof(int32_t) * 8 * kILSize, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(op->offv.ptr, op->offs.vec.data(), sizeof(int32_t) * 3 * kNumOffsets, hipMemcpyHostToDevice) !=
-            hipSuccess) {
+            hipSuccess ||
+        hipMemcpy(op->pairs.ptr, pairs.data(), sizeof(int32_t) * pairs.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(op->rowmap.ptr, rowmap.data(), sizeof(int32_t) * nrow, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(op->rowpos.ptr, rowpos.data(), sizeof(int32_t) * Kp, hipMemcpyHostToDevice) != hipSuccess) {
         msg = "fmm_plan: upload failed";
         return FMM_ERR_DEVICE;
     }
@@ -387,7 +407,6 @@ static fmm_status plan_create(double box, int levels, int p, const std::shared_p
         fmm_destroy(pl);
         return s;
     };
-    if (const char *v = std::getenv("FMM_M2L_VARIANT")) set_m2l_variant(std::atoi(v));
     if (const char *v = std::getenv("FMM_TOP_FP64")) pl->top_fp64 = std::max(0, std::atoi(v));
     if (pl->device < 64 && !rec_uploaded[pl->device]) {
         RecTables t;
@@ -581,21 +600,22 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
     for (int l = 1; l <= L; ++l) {
         if (l == L) stage_begin(pl, FMM_STAGE_M2L_LEAF);
         hipError_t e;
+        const OpSet &o = *pl->op;
         if (l <= top && l <= 2)
-            e = launch_m2l<double>(l, pl->op->alias_ops[l - 1].as<double>(), pl->op->alias_il[l - 1].as<int32_t>(),
-                                   pl->op->alias_off[l - 1].as<int32_t>(), MD(l), LD(l), pl->m2l_part.as<double>(), p,
-                                   Kp, s, 1 << (3 * l));
+            e = launch_m2l<double>(l, o.alias_ops[l - 1].as<double>(), o.alias_il[l - 1].as<int32_t>(),
+                                   o.alias_off[l - 1].as<int32_t>(), nullptr, MD(l), LD(l), pl->m2l_part.as<double>(),
+                                   p, Kp, s, 1 << (3 * l));
         else if (l <= top)
-            e = launch_m2l<double>(l, pl->op->ops64.as<double>(), pl->op->il.as<int32_t>(), pl->op->offv.as<int32_t>(), MD(l),
-                                   LD(l), pl->m2l_part.as<double>(), p, Kp, s);
+            e = launch_m2l<double>(l, o.ops64.as<double>(), o.pairs.as<int32_t>(), o.offv.as<int32_t>(),
+                                   o.rowmap.as<int32_t>(), MD(l), LD(l), pl->m2l_part.as<double>(), p, Kp, s);
         else if (!TD && pl->prec == FMM_MIXED_BF16_M2L)
             e = launch_m2l_bf16(l, pl->op->opsbf.ptr, pl->op->il.as<int32_t>(), pl->op->offv.as<int32_t>(),
                                 reinterpret_cast<const float *>(MT(l)), reinterpret_cast<float *>(LT(l)),
                                 pl->m2l_part.as<float>(), p, Kp, s);
         else
-            e = launch_m2l<T>(l, sizeof(T) == 8 ? (const T *)pl->op->ops64.ptr : (const T *)pl->op->ops32.ptr,
-                              pl->op->il.as<int32_t>(), pl->op->offv.as<int32_t>(), MT(l), LT(l), pl->m2l_part.as<T>(), p,
-                              Kp, s);
+            e = launch_m2l<T>(l, sizeof(T) == 8 ? (const T *)o.ops64.ptr : (const T *)o.ops32.ptr,
+                              o.pairs.as<int32_t>(), o.offv.as<int32_t>(), o.rowmap.as<int32_t>(), MT(l), LT(l),
+                              pl->m2l_part.as<T>(), p, Kp, s);
         HIPCHK(pl, e, "M2L");
         if (l == L) stage_end(pl, FMM_STAGE_M2L_LEAF);
     }
@@ -865,8 +885,9 @@ static fmm_status sparse_solute_field(fmm_plan_t pl, const uint8_t *mask) {
         const bool alias = l <= 2;
         HIPCHK(pl, launch_m2l_sparse(l, fl[l], alias ? o.alias_il[l - 1].as<int32_t>() : o.il.as<int32_t>(),
                                      alias ? o.alias_off[l - 1].as<int32_t>() : o.offv.as<int32_t>(),
-                                     alias ? o.alias_ops[l - 1].as<double>() : o.ops64.as<double>(), MD(l), LD(l), K,
-                                     Kp, alias ? 1 << (3 * l) : kILSize, s), "M2L");
+                                     alias ? o.alias_ops[l - 1].as<double>() : o.ops64.as<double>(),
+                                     alias ? nullptr : o.rowpos.as<int32_t>(), m2l_row_blocks(p), MD(l), LD(l), K, Kp,
+                                     alias ? 1 << (3 * l) : kILSize, s), "M2L");
     }
     for (int l = 1; l <= L; ++l)
         HIPCHK(pl, launch_l2l_sparse(level_cells(l), fl[l], l == 1 ? pl->L0.as<double>() : LD(l - 1), LD(l), tree, K,

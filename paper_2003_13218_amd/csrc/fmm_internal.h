@@ -14,6 +14,7 @@ namespace fmm {
 constexpr int kWS = 2;            // near field / well-separatedness: +-2 cells
 constexpr int kNumOffsets = 1206; // distinct M2L offsets: [-5,5]^3 minus [-2,2]^3
 constexpr int kILSize = 875;      // interaction list size per parity class
+constexpr int kM2LEntries = 573;  // paired list entries per class: 302 (t, -t) pairs + 271 single offsets
 constexpr int kMaxP = 20;
 constexpr int kMaxP2PGroups = 16;  // largest source-group count of the P2P kernel
 constexpr int kMaxLevels = 10;
@@ -127,28 +128,44 @@ hipError_t launch_l2p_sparse(int64_t n, const double *xs, const uint32_t *key, c
                              const uint8_t *mask, double box, int levels, int p, int Kp, const double *L, double *phi,
                              hipStream_t s);
 // k_sparse.hip: ops = the 16 swizzled FP64 octant operators (M2M then L2L)
-// for M2M / L2L; for M2L the swizzled FP64 operators with their lists (nil
-// entries per parity class, as launch_m2l)
+// for M2M / L2L; for M2L the FP64 operators with their plain lists (nil
+// entries per parity class): the row-ordered full-list operators with rowpos
+// (storage row -> operator row) and nbr = m2l_row_blocks, or the aliased
+// operators in storage order with rowpos NULL
 hipError_t launch_m2m_sparse(int64_t nparent, const uint32_t *fparent, const uint32_t *fchild, const double *Mc,
                              double *Mp, const void *ops, int K, int Kp, bool all, hipStream_t s);
 hipError_t launch_m2l_sparse(int level, const uint32_t *flag, const int32_t *il, const int32_t *offs,
-                             const double *ops, const double *M, double *L, int K, int Kp, int nil, hipStream_t s);
+                             const double *ops, const int32_t *rowpos, int nbr, const double *M, double *L, int K,
+                             int Kp, int nil, hipStream_t s);
 hipError_t launch_l2l_sparse(int64_t nchild, const uint32_t *flag, const double *Lp, double *Lc, const void *ops,
                              int K, int Kp, hipStream_t s);
 
 // k_m2l.hip
 // Levels with few target cells split the interaction list into slices
 // (split-K) whose partial sums go to `partial` and are added in a fixed order.
-// il: 8 parity classes x nil operator ids; offs: 3 ints per operator id (the
-// source cell is the target cell + offset, wrapped on the level's grid).
-// nil = 875 for the interaction list itself, fewer for the aliased levels.
+// offs: 3 ints per operator id (the source cell is the target cell + offset,
+// wrapped on the level's grid).
+//   nil == 875: the full interaction list, as the paired entries `list`
+//     (8 x kM2LEntries x 2 operator ids, second -1 for a single offset; see
+//     build_m2l_pairs) with the row-ordered operators of swizzle_m2l_ops and
+//     `rowmap` (m2l_row_map) to put the result rows back in storage order;
+//   nil < 875 (the aliased levels 1 and 2): `list` holds 8 x nil operator ids
+//     of operators in the plain swizzle_ops layout, rowmap unused.
 int m2l_slices(int level);
-void set_m2l_variant(int v);  // tuning: 0 default, 1 offset-split, 2 LDS-shared
 template <typename T>
-hipError_t launch_m2l(int level, const T *ops, const int32_t *il, const int32_t *offs, const T *M,
-                      T *L, T *partial, int p, int Kp, hipStream_t s, int nil = kILSize);
+hipError_t launch_m2l(int level, const T *ops, const int32_t *list, const int32_t *offs, const int32_t *rowmap,
+                      const T *M, T *L, T *partial, int p, int Kp, hipStream_t s, int nil = kILSize);
+// Row order of the full-list operators: even-degree rows, then odd-degree
+// rows, each padded to 16-row blocks (m2l_row_blocks blocks in all, the first
+// m2l_even_blocks even); map[16 * m2l_row_blocks] = storage row (every row
+// of 0 .. Kp-1 once, the padding rows K .. Kp-1 on zero operator rows) or -1
+int m2l_row_blocks(int p);
+int m2l_even_blocks(int p);
+void m2l_row_map(int p, int32_t *map);
+void build_m2l_pairs(const int32_t *vec /*1206 x 3*/, const int32_t *il /*8 x 875*/,
+                     int32_t *pairs /*8 x kM2LEntries x 2*/);
 template <typename T>
-size_t m2l_ops_elems(int p);  // element count of the swizzled operator array
+size_t m2l_ops_elems(int p);  // element count of the swizzled, row-ordered operator array
 template <typename T>
 void swizzle_m2l_ops(int p, const double *ops_rowmajor /*1206 x K x K*/, T *out);
 // M2L operators as bfloat16 (round to nearest even) in the lane order of

@@ -22,8 +22,10 @@
 //     dispatch of workgroups to the 8 XCDs every XCD streams one class's 875
 //     operators through its own L2.
 #include <algorithm>
-#include <type_traits>
+#include <cstdlib>
 #include <cstring>
+#include <type_traits>
+#include <vector>
 
 #include "fmm_internal.h"
 #include "mfma.h"
@@ -33,10 +35,80 @@ namespace fmm {
 
 constexpr int kRowBlocksPerWave = 11;  // 176 rows: K <= 169 (p <= 12) in one row group
 
+// ---------------------------------------------------------------------------
+// Row order of the M2L operators.  O_{-t} = D O_t D with D = diag((-1)^n) over
+// the degree n of each coefficient (the irregular harmonics are odd or even in
+// t with their degree), so for a target whose list holds both t and -t
+//   O_t M_a + O_{-t} M_b = [rows of even n]  O_t (M_a + D M_b)
+//                        + [rows of odd n]   O_t (M_a - D M_b):
+// one operator product for the pair instead of two.  The operators are
+// stored with the even-degree rows first and the odd-degree rows after, each
+// group padded to whole 16-row blocks, so that every matrix-core row block
+// belongs to one group; columns keep the storage order of the expansions.
+// ---------------------------------------------------------------------------
+static int even_degree_rows(int p) {
+    int e = 0;
+    for (int n = 0; n <= p; n += 2) e += 2 * n + 1;
+    return e;
+}
+int m2l_even_blocks(int p) { return (even_degree_rows(p) + 15) / 16; }
+int m2l_row_blocks(int p) {
+    const int e = even_degree_rows(p), o = num_coeffs(p) - e;
+    return (e + 15) / 16 + (o + 15) / 16;
+}
+// The padding rows K .. Kp-1 of the storage order take the first unused
+// slots (their operator rows are zero), so the kernel writes every stored row.
+void m2l_row_map(int p, int32_t *map) {
+    const int nr = 16 * m2l_row_blocks(p), eb = 16 * m2l_even_blocks(p);
+    for (int i = 0; i < nr; ++i) map[i] = -1;
+    int ie = 0, io = eb;
+    for (int n = 0; n <= p; ++n)
+        for (int k = n * n; k < (n + 1) * (n + 1); ++k) map[(n & 1) ? io++ : ie++] = k;
+    int pad = num_coeffs(p);
+    for (int i = 0; i < nr && pad < padded_coeffs(p); ++i)
+        if (map[i] < 0) map[i] = pad++;
+}
+
+// Interaction-list entries of the paired kernel: per parity class, every
+// offset t whose negation is in the same list is paired with it (the entry
+// (t, -t) appears once, at the first of the two in list order), the others
+// stand alone (second id -1).  Within [-5, 4] or [-4, 5] per axis the pairs
+// are the offsets inside [-4, 4]^3: 302 pairs and 271 single offsets.
+void build_m2l_pairs(const int32_t *vec, const int32_t *il, int32_t *pairs) {
+    for (int par = 0; par < 8; ++par) {
+        const int32_t *l = il + par * kILSize;
+        int32_t *out = pairs + (size_t)par * 2 * kM2LEntries;
+        bool used[kNumOffsets] = {};
+        int ne = 0;
+        for (int i = 0; i < kILSize; ++i) {
+            const int a = l[i];
+            if (used[a]) continue;
+            used[a] = true;
+            int b = -1;
+            for (int j = 0; j < kILSize; ++j) {
+                const int c = l[j];
+                if (vec[3 * c] == -vec[3 * a] && vec[3 * c + 1] == -vec[3 * a + 1] && vec[3 * c + 2] == -vec[3 * a + 2]) {
+                    b = c;
+                    break;
+                }
+            }
+            if (b >= 0) used[b] = true;
+            if (ne < kM2LEntries) {
+                out[2 * ne] = a;
+                out[2 * ne + 1] = b;
+            }
+            ++ne;
+        }
+        if (ne != kM2LEntries) {  // the list geometry guarantees 573
+            for (int e = 0; e < 2 * kM2LEntries; ++e) out[e] = -1;
+        }
+    }
+}
+
 template <typename T>
 size_t m2l_ops_elems(int p) {
     const size_t Kp = (size_t)padded_coeffs(p);
-    return (size_t)kNumOffsets * Kp * Kp;
+    return (size_t)kNumOffsets * (Kp / 16) * m2l_row_blocks(p) * 256;
 }
 template size_t m2l_ops_elems<float>(int);
 template size_t m2l_ops_elems<double>(int);
@@ -63,9 +135,26 @@ void swizzle_ops(int p, int nops, const double *ops, T *out) {
 template void swizzle_ops<float>(int, int, const double *, float *);
 template void swizzle_ops<double>(int, int, const double *, double *);
 
+// The M2L operators with their rows in the order of m2l_row_map:
+// out[(((oid * NKC + kc) * NBR + rb) * 64 + lane) * 4 + j] =
+//     O_oid[map[16 rb + lane % 16]][16 kc + 4 (lane / 16) + j]
 template <typename T>
 void swizzle_m2l_ops(int p, const double *ops, T *out) {
-    swizzle_ops<T>(p, kNumOffsets, ops, out);
+    const int K = num_coeffs(p), NKC = padded_coeffs(p) / 16, NBR = m2l_row_blocks(p);
+    std::vector<int32_t> map((size_t)16 * NBR);
+    m2l_row_map(p, map.data());
+    for (int oid = 0; oid < kNumOffsets; ++oid) {
+        const double *A = ops + (size_t)oid * K * K;
+        for (int kc = 0; kc < NKC; ++kc)
+            for (int rb = 0; rb < NBR; ++rb)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int j = 0; j < 4; ++j) {
+                        const int row = map[16 * rb + (lane & 15)];
+                        const int col = 16 * kc + 4 * (lane >> 4) + j;
+                        const double v = (row >= 0 && row < K && col < K) ? A[(size_t)row * K + col] : 0.0;
+                        out[((((size_t)oid * NKC + kc) * NBR + rb) * 64 + lane) * 4 + j] = (T)v;
+                    }
+    }
 }
 template void swizzle_m2l_ops<float>(int, const double *, float *);
 template void swizzle_m2l_ops<double>(int, const double *, double *);
@@ -221,6 +310,7 @@ template <typename T> struct PolMfma {  // FP32 or FP64 operands, v_mfma_*_16x16
     using R = B;                          // multipole fragment as loaded
     static constexpr int KW = 16;
     static constexpr bool kFlush64 = sizeof(T) == 4;
+    static constexpr bool kPaired = true;  // list of (t, -t) entries, row-ordered operators
     __device__ static R load_b(const S *p, bool in) {
         return in ? *reinterpret_cast<const R *>(p) : R{0, 0, 0, 0};
     }
@@ -239,6 +329,7 @@ struct PolBf16 {  // BF16 operands, FP32 storage and accumulation, v_mfma_f32_16
     typedef float R __attribute__((ext_vector_type(8)));  // loaded as FP32, rounded at use
     static constexpr int KW = 32;
     static constexpr bool kFlush64 = false;
+    static constexpr bool kPaired = false;  // plain list, storage-ordered operators
     __device__ static R load_b(const S *p, bool in) {
         return in ? *reinterpret_cast<const R *>(p) : R{0, 0, 0, 0, 0, 0, 0, 0};
     }
@@ -252,6 +343,22 @@ struct PolBf16 {  // BF16 operands, FP32 storage and accumulation, v_mfma_f32_16
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
     }
 };
+
+// Bit-level helpers of the paired kernel: x with its sign flipped when bit is
+// 1, and a per-element choice between two fragments by an all-ones / zero mask
+// (bit operations, so a run-time choice never becomes a branch).
+__device__ inline float neg_if(float x, uint32_t bit) { return __uint_as_float(__float_as_uint(x) ^ (bit << 31)); }
+__device__ inline double neg_if(double x, uint32_t bit) {
+    return __longlong_as_double(__double_as_longlong(x) ^ ((long long)bit << 63));
+}
+__device__ inline float pick(float a, float b, uint32_t m) {
+    return __uint_as_float((__float_as_uint(a) & m) | (__float_as_uint(b) & ~m));
+}
+__device__ inline double pick(double a, double b, uint32_t m) {
+    const unsigned long long mm = ((unsigned long long)m << 32) | m;
+    return __longlong_as_double((long long)(((unsigned long long)__double_as_longlong(a) & mm) |
+                                            ((unsigned long long)__double_as_longlong(b) & ~mm)));
+}
 
 // Chunks per LDS stage: enough matrix-core work per barrier (about 40 FP32
 // MFMA-equivalents) within 48 KB of double-buffered LDS and a few registers.
@@ -284,17 +391,24 @@ template <typename P, int NRB> constexpr int stage_chunks() {
 // SPLIT: split-K over offset slices (partials to a buffer, added in a fixed
 // order by k_m2l_reduce), compiled separately so profiles tell levels apart.
 // ---------------------------------------------------------------------------
-template <typename P, bool SPLIT, int NRB, int U>
+// NE >= 0: the number of even-degree row blocks of this row group, fixed at
+// compile time (the single row group of every p <= 12); NE < 0: taken from
+// ne_blocks at run time, with a bit mask per row block.
+template <typename P, bool SPLIT, int NRB, int U, int NE>
 __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict__ ops,
                                                  const int32_t *__restrict__ il, const int32_t *__restrict__ offs,
+                                                 const int32_t *__restrict__ rowmap,
                                                  const typename P::S *__restrict__ M, typename P::S *__restrict__ L,
-                                                 int nh_bits, int NB, int NKC, int Kp, int rb0, int nslices_arg) {
+                                                 int nh_bits, int NB, int NKC, int Kp, int rb0, int nslices_arg,
+                                                 int ne_blocks) {
     using S = typename P::S;
     using A = typename P::A;
     using B = typename P::B;
     using Acc = typename P::Acc;
     using R = typename P::R;
     constexpr bool F64 = P::kFlush64;
+    constexpr bool PAIR = P::kPaired;
+    constexpr int NENT = PAIR ? kM2LEntries : kILSize;  // list entries per parity class
     constexpr int CHUNK = NRB * 64;             // fragments per chunk
     constexpr int PC = (CHUNK + 255) / 256;     // fragment loads per thread per chunk
     __shared__ A lds[2][U * CHUNK];
@@ -319,29 +433,70 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
     tz = 2 * tz + (parity & 1);
     const uint32_t tcell = 8 * Pt + (uint32_t)parity;
 
-    const int t0 = slice * kILSize / nslices, t1 = (slice + 1) * kILSize / nslices;
+    const int t0 = slice * NENT / nslices, t1 = (slice + 1) * NENT / nslices;
     const int nchunk = (t1 - t0) * NKC;
     const int nstage = (nchunk + U - 1) / U;
     const size_t op_stride = (size_t)NKC * NB * 64;  // fragments per offset
-    const int32_t *ilp = il + parity * kILSize;
+    const int32_t *ilp = il + parity * NENT * (PAIR ? 2 : 1);
     const int kq = (P::KW / 4) * (lane >> 4);        // this lane's k offset inside a chunk
 
-    // chunk cursor (t, kc); the operator id and the multipole row of this
-    // lane's source cell change only with t
+    // paired list: odd-degree columns of this lane (bit 4 kc + j: column
+    // 16 kc + kq + j, kc < 16 in sg0, kc >= 16 in sg1), and per row block of
+    // this group whether it holds even-degree rows (all-ones) or odd (zero)
+    uint64_t sg0 = 0, sg1 = 0;
+    uint32_t even_rb[NRB];
+    if constexpr (PAIR) {
+        for (int c2 = 0; c2 < NKC; ++c2)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int col = 16 * c2 + kq + j;
+                int n = (int)sqrtf((float)col);
+                if (n * n > col) --n;
+                if ((n + 1) * (n + 1) <= col) ++n;
+                if (n & 1) {
+                    const uint64_t bit = 1ull << (4 * (c2 & 15) + j);
+                    if (c2 < 16) sg0 |= bit;
+                    else sg1 |= bit;
+                }
+            }
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb) even_rb[rb] = (rb0 + rb < ne_blocks) ? 0xffffffffu : 0u;
+    }
+
+    // chunk cursor (t, kc); the operator id and the multipole rows of this
+    // lane's source cells change only with t.  Paired entries have a second
+    // source cell (offset -t); for single offsets src2 repeats src and m2 = 0
+    // zeroes its fragment.
     struct Cursor {
         int t, kc;
-        size_t base;   // first fragment of the chunk
-        const S *src;  // this lane's coefficients of the source multipole
+        size_t base;    // first fragment of the chunk
+        const S *src;   // this lane's coefficients of the source multipole
+        const S *src2;  // ... of the paired source (offset -t)
+        uint32_t m2;    // all-ones if the entry is a pair, else 0
+    };
+    auto source = [&](int oid) {
+        const uint32_t sx = (tx + (uint32_t)offs[3 * oid]) & nmask;
+        const uint32_t sy = (ty + (uint32_t)offs[3 * oid + 1]) & nmask;
+        const uint32_t sz = (tz + (uint32_t)offs[3 * oid + 2]) & nmask;
+        return M + (size_t)morton3(sx, sy, sz) * Kp + kq;
     };
     auto set_t = [&](Cursor &c, int t) {
         c.t = t;
         c.kc = 0;
-        const int oid = ilp[min(t, t1 - 1)];  // past the end: stay on a valid chunk
-        const uint32_t sx = (tx + (uint32_t)offs[3 * oid]) & nmask;
-        const uint32_t sy = (ty + (uint32_t)offs[3 * oid + 1]) & nmask;
-        const uint32_t sz = (tz + (uint32_t)offs[3 * oid + 2]) & nmask;
-        c.src = M + (size_t)morton3(sx, sy, sz) * Kp + kq;
-        c.base = (size_t)oid * op_stride + (size_t)rb0 * 64;
+        const int e = min(t, t1 - 1);  // past the end: stay on a valid chunk
+        if constexpr (PAIR) {
+            const int oid = ilp[2 * e], oid2 = ilp[2 * e + 1];
+            c.src = source(oid);
+            c.src2 = oid2 >= 0 ? source(oid2) : c.src;
+            c.m2 = oid2 >= 0 ? 0xffffffffu : 0u;
+            c.base = (size_t)oid * op_stride + (size_t)rb0 * 64;
+        } else {
+            const int oid = ilp[e];
+            c.src = source(oid);
+            c.src2 = c.src;
+            c.m2 = 0u;
+            c.base = (size_t)oid * op_stride + (size_t)rb0 * 64;
+        }
     };
     auto advance = [&](Cursor &c) {
         if (++c.kc == NKC) set_t(c, c.t + 1);
@@ -350,11 +505,11 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
     // the multipole fragment of the cursor's chunk: zero past the list (only
     // reachable inside a stage when U > 1) and past Kp (only for 32-wide
     // chunks, whose last one may stick out of the padded row)
-    auto frag_b = [&](const Cursor &c) -> R {
+    auto frag_b = [&](const Cursor &c, const S *src) -> R {
         bool in = true;
         if constexpr (U > 1) in = c.t < t1;
         if constexpr (P::KW > 16) in = in && P::KW * c.kc + kq < Kp;
-        return P::load_b(c.src + P::KW * c.kc, in);
+        return P::load_b(src + P::KW * c.kc, in);
     };
 
     Acc acc[NRB];
@@ -374,14 +529,19 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
     const bool last_in = tid + 256 * (PC - 1) < CHUNK;
 
     // prologue: stage 0 into LDS buffer 0
-    R bcur[U];
+    R bcur[U], bcur2[PAIR ? U : 1];
+    uint32_t mcur[PAIR ? U : 1];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
         for (int v = 0; v < PC - 1; ++v) lds[0][u * CHUNK + tid + 256 * v] = ops[pc.base + tid + 256 * v];
         const A x = ops[pc.base + e_last];
         if (last_in) lds[0][u * CHUNK + e_last] = x;
-        bcur[u] = frag_b(pc);
+        bcur[u] = frag_b(pc, pc.src);
+        if constexpr (PAIR) {
+            bcur2[u] = frag_b(pc, pc.src2);
+            mcur[u] = pc.m2;
+        }
         advance(pc);
     }
     // drain every prologue load: otherwise the compiler's wait bookkeeping
@@ -393,13 +553,18 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
         const int cur = st & 1;
         // prefetch the next stage (past the end: harmless re-reads)
         A pre[U][PC];
-        R bnext[U];
+        R bnext[U], bnext2[PAIR ? U : 1];
+        uint32_t mnext[PAIR ? U : 1];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll
             for (int v = 0; v < PC - 1; ++v) pre[u][v] = ops[pc.base + tid + 256 * v];
             pre[u][PC - 1] = ops[pc.base + e_last];
-            bnext[u] = frag_b(pc);
+            bnext[u] = frag_b(pc, pc.src);
+            if constexpr (PAIR) {
+                bnext2[u] = frag_b(pc, pc.src2);
+                mnext[u] = pc.m2;
+            }
             // compiler-only barrier: keeps the loads above the cursor update
             // (otherwise they are sunk below its branch, towards their use)
             asm volatile("" ::: "memory");
@@ -418,9 +583,34 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
             // fragments are twice as large: there the compiler's interleaving
             // of reads and MFMAs is kept, measured faster)
             if constexpr (sizeof(A) == 16) __builtin_amdgcn_sched_barrier(0);
-            const B b = P::to_b(bcur[u]);
+            if constexpr (PAIR) {
+                // v1 = b + D b2 feeds the even-degree rows, v2 = b - D b2 the odd
+                const uint64_t w = kc < 16 ? sg0 : sg1;
+                const uint32_t sb = (uint32_t)(w >> (4 * (kc & 15))) & 15u;
+                B v1, v2;
 #pragma unroll
-            for (int rb = 0; rb < NRB; ++rb) acc[rb] = P::mma(a[rb], b, acc[rb]);
+                for (int j = 0; j < 4; ++j) {
+                    const S m = neg_if(pick((S)bcur2[u][j], (S)0, mcur[u]), (sb >> j) & 1u);
+                    v1[j] = bcur[u][j] + m;
+                    v2[j] = bcur[u][j] - m;
+                }
+                if constexpr (NE >= 0) {
+#pragma unroll
+                    for (int rb = 0; rb < NRB; ++rb) acc[rb] = P::mma(a[rb], rb < NE ? v1 : v2, acc[rb]);
+                } else {
+#pragma unroll
+                    for (int rb = 0; rb < NRB; ++rb) {
+                        B b;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) b[j] = pick(v1[j], v2[j], even_rb[rb]);
+                        acc[rb] = P::mma(a[rb], b, acc[rb]);
+                    }
+                }
+            } else {
+                const B b = P::to_b(bcur[u]);
+#pragma unroll
+                for (int rb = 0; rb < NRB; ++rb) acc[rb] = P::mma(a[rb], b, acc[rb]);
+            }
             if (++kc == NKC) {
                 kc = 0;
                 if constexpr (F64) {
@@ -444,6 +634,10 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
             for (int v = 0; v < PC - 1; ++v) lds[cur ^ 1][u * CHUNK + tid + 256 * v] = pre[u][v];
             if (last_in) lds[cur ^ 1][u * CHUNK + e_last] = pre[u][PC - 1];
             bcur[u] = bnext[u];
+            if constexpr (PAIR) {
+                bcur2[u] = bnext2[u];
+                mcur[u] = mnext[u];
+            }
         }
         __syncthreads();
     }
@@ -454,36 +648,56 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
     for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int row = 16 * (rb0 + rb) + Mfma<S>::row(lane, r);
-            out[(size_t)tcell * Kp + row] = F64 ? (S)(hi[rb][r] + (double)acc[rb][r]) : (S)acc[rb][r];
+            const int prow = 16 * (rb0 + rb) + Mfma<S>::row(lane, r);
+            const int row = PAIR ? rowmap[prow] : prow;
+            if (row >= 0)
+                out[(size_t)tcell * Kp + row] = F64 ? (S)(hi[rb][r] + (double)acc[rb][r]) : (S)acc[rb][r];
         }
+}
+
+// Even-degree row blocks of the single row group of order p <= 12 with NRB
+// row blocks (NRB = m2l_row_blocks(p) determines it for those p; -1: none).
+constexpr int single_group_even_blocks(int nrb) {
+    constexpr int table[12] = {-1, 1, 1, 1, 2, 2, 3, 3, -1, 5, 5, 6};
+    return nrb >= 0 && nrb < 12 ? table[nrb] : -1;
 }
 
 // Launches the LDS-shared kernel for every group of up to kRowBlocksPerWave
 // row blocks (one launch per group, NRB and U fixed at compile time).
 template <typename P>
-static hipError_t launch_lds(const void *ops, const int32_t *il, const int32_t *offs, const typename P::S *M,
-                             typename P::S *out, int nh_bits, int NB, int NKC, int Kp, int nslices, hipStream_t s) {
+static hipError_t launch_lds(const void *ops, const int32_t *il, const int32_t *offs, const int32_t *rowmap,
+                             const typename P::S *M, typename P::S *out, int nh_bits, int NB, int NKC, int Kp,
+                             int nslices, int ne_blocks, hipStream_t s) {
+    if (P::kPaired && NKC > 32) return hipErrorInvalidValue;  // column parity bits: two 64-bit words
     using A = typename P::A;
     const int64_t ntile = (((int64_t)1 << (3 * nh_bits)) + 63) / 64;
     const int64_t grid = 8 * ntile * nslices;
     const A *o = reinterpret_cast<const A *>(ops);
     for (int rb0 = 0; rb0 < NB; rb0 += kRowBlocksPerWave) {
         const int nrb = std::min(kRowBlocksPerWave, NB - rb0);
+        const int ne_local = std::max(0, std::min(nrb, ne_blocks - rb0));
+        const bool fixed = P::kPaired && ne_local == single_group_even_blocks(nrb);
         switch (nrb) {
+#define FMM_M2L_LDS_LAUNCH(N, NE)                                                                              \
+    if (nslices > 1)                                                                                           \
+        hipLaunchKernelGGL((k_m2l_lds<P, true, N, stage_chunks<P, N>(), NE>), dim3((unsigned)grid), dim3(256), \
+                           0, s, o, il, offs, rowmap, M, out, nh_bits, NB, NKC, Kp, rb0, nslices, ne_blocks); \
+    else                                                                                                       \
+        hipLaunchKernelGGL((k_m2l_lds<P, false, N, stage_chunks<P, N>(), NE>), dim3((unsigned)grid),          \
+                           dim3(256), 0, s, o, il, offs, rowmap, M, out, nh_bits, NB, NKC, Kp, rb0, 1, ne_blocks);
 #define FMM_M2L_LDS_CASE(N)                                                                                    \
     case N:                                                                                                    \
-        if (nslices > 1)                                                                                       \
-            hipLaunchKernelGGL((k_m2l_lds<P, true, N, stage_chunks<P, N>()>), dim3((unsigned)grid), dim3(256), \
-                               0, s, o, il, offs, M, out, nh_bits, NB, NKC, Kp, rb0, nslices);                \
-        else                                                                                                   \
-            hipLaunchKernelGGL((k_m2l_lds<P, false, N, stage_chunks<P, N>()>), dim3((unsigned)grid),          \
-                               dim3(256), 0, s, o, il, offs, M, out, nh_bits, NB, NKC, Kp, rb0, 1);           \
+        if (fixed) {                                                                                           \
+            FMM_M2L_LDS_LAUNCH(N, single_group_even_blocks(N))                                                 \
+        } else {                                                                                               \
+            FMM_M2L_LDS_LAUNCH(N, -1)                                                                          \
+        }                                                                                                      \
         break;
             FMM_M2L_LDS_CASE(1) FMM_M2L_LDS_CASE(2) FMM_M2L_LDS_CASE(3) FMM_M2L_LDS_CASE(4)
             FMM_M2L_LDS_CASE(5) FMM_M2L_LDS_CASE(6) FMM_M2L_LDS_CASE(7) FMM_M2L_LDS_CASE(8)
             FMM_M2L_LDS_CASE(9) FMM_M2L_LDS_CASE(10) FMM_M2L_LDS_CASE(11)
 #undef FMM_M2L_LDS_CASE
+#undef FMM_M2L_LDS_LAUNCH
             default: return hipErrorInvalidValue;
         }
         hipError_t e = hipGetLastError();
@@ -506,27 +720,20 @@ __global__ void k_m2l_reduce(const T *__restrict__ partial, T *__restrict__ L, i
 // Slices per level: enough workgroups (>= ~512) to fill 256 CUs at two
 // resident workgroups each; levels >= 5 have enough targets on their own.
 int m2l_slices(int level) {
+    static const int leaf = [] {
+        const char *v = std::getenv("FMM_M2L_FINE_SLICES");
+        const int k = v ? std::atoi(v) : 0;
+        return (k == 1 || k == 2 || k == 4 || k == 8) ? k : 1;
+    }();
     switch (level) {
         case 1: return 64;
         case 2: return 64;
         case 3: return 64;
         case 4: return 32;
-        default: return 1;
+        default: return leaf;
     }
 }
 
-// Levels from this one on use the LDS-shared kernel (measured on the 1M-atom
-// box: level 3 in FP64 with 64 slices 0.4 ms faster than the offset-split
-// kernel); the two coarsest levels (aliased lists of 8 and 64 entries) use the
-// offset-split kernel.  m2l_variant 1 forces the offset-split kernel everywhere
-// (tuning and cross-checks).
-constexpr int kLdsLevel = 3;
-static int g_m2l_variant = 0;
-void set_m2l_variant(int v) { g_m2l_variant = v; }
-template <typename T> static bool use_lds_kernel(int level) {
-    if (level < kLdsLevel) return false;
-    return g_m2l_variant != 1;
-}
 
 // ---------------------------------------------------------------------------
 // M2L with BF16 operands (precision mode FMM_MIXED_BF16_M2L): the same
@@ -576,8 +783,8 @@ hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const 
     const int NB = Kp / 16;
     const int nh_bits = level - 1;
     const int nslices = partial ? m2l_slices(level) : 1;
-    hipError_t e = launch_lds<PolBf16>(ops, il, offs, M, nslices > 1 ? partial : L, nh_bits, NB, bf16_chunks(p), Kp,
-                                       nslices, s);
+    hipError_t e = launch_lds<PolBf16>(ops, il, offs, nullptr, M, nslices > 1 ? partial : L, nh_bits, NB,
+                                       bf16_chunks(p), Kp, nslices, 0, s);
     if (e != hipSuccess || nslices == 1) return e;
     const int64_t elems = ((int64_t)8 << (3 * nh_bits)) * Kp;
     int64_t g = (elems + 255) / 256;
@@ -586,27 +793,30 @@ hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const 
     return hipGetLastError();
 }
 
+// The full interaction list (nil == 875) runs on the LDS-shared kernel with
+// the paired entries; the aliased lists of levels 1 and 2 (nil = 8 or 64
+// pre-summed operators) on the offset-split kernel.
 template <typename T>
-hipError_t launch_m2l(int level, const T *ops, const int32_t *il, const int32_t *offs, const T *M, T *L,
-                      T *partial, int p, int Kp, hipStream_t s, int nil) {
+hipError_t launch_m2l(int level, const T *ops, const int32_t *list, const int32_t *offs, const int32_t *rowmap,
+                      const T *M, T *L, T *partial, int p, int Kp, hipStream_t s, int nil) {
     constexpr int CB = Mfma<T>::CB;
     const int NB = Kp / 16;
-    int R = 1;
-    if (NB > kRowBlocksPerWave) R = 2;
-    if (NB > 2 * kRowBlocksPerWave) R = 4;
-    if (NB > 4 * kRowBlocksPerWave) return hipErrorInvalidValue;
     const int nh_bits = level - 1;
     const int64_t ntarget = (int64_t)1 << (3 * nh_bits);
     const int nslices = partial ? std::min(m2l_slices(level), nil) : 1;
-    if (use_lds_kernel<T>(level)) {
-        if (nil != kILSize) return hipErrorInvalidValue;  // the LDS kernel walks the full list
-        const hipError_t e = launch_lds<PolMfma<T>>(ops, il, offs, M, nslices > 1 ? partial : L, nh_bits, NB, NB,
-                                                     Kp, nslices, s);
+    if (nil == kILSize) {
+        if (!rowmap) return hipErrorInvalidValue;
+        const hipError_t e = launch_lds<PolMfma<T>>(ops, list, offs, rowmap, M, nslices > 1 ? partial : L, nh_bits,
+                                                     m2l_row_blocks(p), NB, Kp, nslices, m2l_even_blocks(p), s);
         if (e != hipSuccess) return e;
     } else {
+        int R = 1;
+        if (NB > kRowBlocksPerWave) R = 2;
+        if (NB > 2 * kRowBlocksPerWave) R = 4;
+        if (NB > 4 * kRowBlocksPerWave) return hipErrorInvalidValue;
         const int64_t ntile = (ntarget + 16 * CB - 1) / (16 * CB);
         const int64_t grid = 8 * ntile * nslices;
-        hipLaunchKernelGGL(k_m2l<T>, dim3((unsigned)grid), dim3(256), 0, s, ops, il, offs, M,
+        hipLaunchKernelGGL(k_m2l<T>, dim3((unsigned)grid), dim3(256), 0, s, ops, list, offs, M,
                            nslices > 1 ? partial : L, nh_bits, NB, Kp, R, nslices, nil);
     }
     hipError_t e = hipGetLastError();
@@ -617,9 +827,9 @@ hipError_t launch_m2l(int level, const T *ops, const int32_t *il, const int32_t 
     hipLaunchKernelGGL(k_m2l_reduce<T>, dim3((unsigned)g), dim3(256), 0, s, partial, L, nslices, elems);
     return hipGetLastError();
 }
-template hipError_t launch_m2l<float>(int, const float *, const int32_t *, const int32_t *, const float *,
-                                      float *, float *, int, int, hipStream_t, int);
-template hipError_t launch_m2l<double>(int, const double *, const int32_t *, const int32_t *, const double *,
-                                       double *, double *, int, int, hipStream_t, int);
+template hipError_t launch_m2l<float>(int, const float *, const int32_t *, const int32_t *, const int32_t *,
+                                      const float *, float *, float *, int, int, hipStream_t, int);
+template hipError_t launch_m2l<double>(int, const double *, const int32_t *, const int32_t *, const int32_t *,
+                                       const double *, double *, double *, int, int, hipStream_t, int);
 
 }  // namespace fmm

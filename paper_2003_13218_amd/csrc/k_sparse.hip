@@ -49,30 +49,32 @@ hipError_t launch_flags(int64_t n, const uint8_t *mask, const uint32_t *key, int
 }
 
 // Element (row, col) of operator oid in the matrix-core swizzle
-// [oid][col block][row block][lane][4] written by swizzle_ops: lanes hold
-// rows 16 rb + lane % 16 and columns 16 kc + 4 (lane / 16) + j.  A thread
-// per row walks the columns; for consecutive rows the elements sit 4 apart,
-// so the four consecutive j of a column block share the lines it fetched.
-__device__ inline size_t swz(int oid, int row, int col, int NB) {
+// [oid][col block (NKC)][row block (NBR)][lane][4] written by swizzle_ops and
+// swizzle_m2l_ops: lanes hold rows 16 rb + lane % 16 and columns 16 kc +
+// 4 (lane / 16) + j.  A thread per row walks the columns; for consecutive rows
+// the elements sit 4 apart, so the four consecutive j of a column block share
+// the lines it fetched.
+__device__ inline size_t swz(int oid, int row, int col, int NKC, int NBR) {
     const int rb = row >> 4, kc = col >> 4;
     const int lane = (row & 15) + 16 * ((col & 15) >> 2);
-    return ((((size_t)oid * NB + kc) * NB + rb) * 64 + lane) * 4 + (col & 3);
+    return ((((size_t)oid * NKC + kc) * NBR + rb) * 64 + lane) * 4 + (col & 3);
 }
 
-// acc + O_oid[row][:] . v[:] over the K columns (v: K doubles, uniform).
-// Two accumulators and an unrolled loop keep several loads in flight.
-__device__ inline double swz_dot(const double *__restrict__ ops, int oid, int row, int NB, int K,
+// acc + O_oid[row][:] . v[:] over the K columns (v: K doubles, uniform), row
+// in the operator's own row order.  Two accumulators and an unrolled loop keep
+// several loads in flight.
+__device__ inline double swz_dot(const double *__restrict__ ops, int oid, int row, int NKC, int NBR, int K,
                                  const double *__restrict__ v, double acc) {
     const int k8 = K & ~7;
     double a1 = 0.0;
 #pragma unroll 2
     for (int col = 0; col < k8; col += 8) {
-        const double *o = ops + swz(oid, row, col, NB);      // columns col .. col+3
-        const double *o2 = ops + swz(oid, row, col + 4, NB); // columns col+4 .. col+7
+        const double *o = ops + swz(oid, row, col, NKC, NBR);      // columns col .. col+3
+        const double *o2 = ops + swz(oid, row, col + 4, NKC, NBR); // columns col+4 .. col+7
         acc += o[0] * v[col] + o[1] * v[col + 1] + o[2] * v[col + 2] + o[3] * v[col + 3];
         a1 += o2[0] * v[col + 4] + o2[1] * v[col + 5] + o2[2] * v[col + 6] + o2[3] * v[col + 7];
     }
-    for (int col = k8; col < K; ++col) acc += ops[swz(oid, row, col, NB)] * v[col];
+    for (int col = k8; col < K; ++col) acc += ops[swz(oid, row, col, NKC, NBR)] * v[col];
     return acc + a1;
 }
 
@@ -91,7 +93,7 @@ __global__ __launch_bounds__(256) void k_m2m_sparse(const uint32_t *__restrict__
         double acc = 0.0;
         if (row < K)
             for (int o = 0; o < 8; ++o)
-                if (fchild[8 * P + o]) acc = swz_dot(ops, o, row, NB, K, Mc + (8 * P + o) * Kp, acc);
+                if (fchild[8 * P + o]) acc = swz_dot(ops, o, row, NB, NB, K, Mc + (8 * P + o) * Kp, acc);
         Mp[P * Kp + row] = acc;
     }
 }
@@ -109,11 +111,14 @@ constexpr int kSparseBlock = 256;
 // flagged of O_t M~(c + t), for the flagged targets c of a level with 2^l
 // cells per axis.  The block first compacts the flagged entries of its list
 // (in list order, so the sum order is fixed), then a thread per row sums
-// their products.
+// their products.  rowpos: storage row -> operator row of the row-ordered
+// full-list operators (NBR row blocks), or NULL for operators in storage
+// order (the aliased levels).
 __global__ __launch_bounds__(kSparseBlock) void k_m2l_sparse(int level, const uint32_t *__restrict__ flag,
                                                              const int32_t *__restrict__ il,
                                                              const int32_t *__restrict__ offs,
                                                              const double *__restrict__ ops,
+                                                             const int32_t *__restrict__ rowpos, int NBR,
                                                              const double *__restrict__ M, double *__restrict__ L,
                                                              int K, int Kp, int nil) {
     __shared__ int32_t hit_oid[kILSize], hit_src[kILSize];
@@ -151,21 +156,25 @@ __global__ __launch_bounds__(kSparseBlock) void k_m2l_sparse(int level, const ui
         for (int w = 0; w < kSparseBlock / 64; ++w) nhit += wave_cnt[w];
         __syncthreads();
     }
+    const int nbr = rowpos ? NBR : NB;
     for (int row = tid; row < Kp; row += kSparseBlock) {
         double acc = 0.0;
-        if (row < K)
+        if (row < K) {
+            const int orow = rowpos ? rowpos[row] : row;
             for (int h = 0; h < nhit; ++h)
-                acc = swz_dot(ops, hit_oid[h], row, NB, K, M + (size_t)hit_src[h] * Kp, acc);
+                acc = swz_dot(ops, hit_oid[h], orow, NB, nbr, K, M + (size_t)hit_src[h] * Kp, acc);
+        }
         L[(size_t)c * Kp + row] = acc;
     }
 }
 
 hipError_t launch_m2l_sparse(int level, const uint32_t *flag, const int32_t *il, const int32_t *offs,
-                             const double *ops, const double *M, double *L, int K, int Kp, int nil, hipStream_t s) {
+                             const double *ops, const int32_t *rowpos, int nbr, const double *M, double *L, int K,
+                             int Kp, int nil, hipStream_t s) {
     if (nil < 1 || nil > kILSize) return hipErrorInvalidValue;
     const int64_t nc = (int64_t)1 << (3 * level);
-    hipLaunchKernelGGL(k_m2l_sparse, dim3((unsigned)nc), dim3(kSparseBlock), 0, s, level, flag, il, offs, ops, M, L,
-                       K, Kp, nil);
+    hipLaunchKernelGGL(k_m2l_sparse, dim3((unsigned)nc), dim3(kSparseBlock), 0, s, level, flag, il, offs, ops, rowpos,
+                       nbr, M, L, K, Kp, nil);
     return hipGetLastError();
 }
 
@@ -180,7 +189,7 @@ __global__ __launch_bounds__(256) void k_l2l_sparse(const uint32_t *__restrict__
     const int o = (int)(c & 7);
     const double *lp = Lp + (c >> 3) * Kp;
     for (int row = threadIdx.x; row < K; row += blockDim.x)
-        Lc[c * Kp + row] += swz_dot(ops, 8 + o, row, NB, K, lp, 0.0);
+        Lc[c * Kp + row] += swz_dot(ops, 8 + o, row, NB, NB, K, lp, 0.0);
 }
 
 hipError_t launch_l2l_sparse(int64_t nchild, const uint32_t *flag, const double *Lp, double *Lc, const void *ops,
