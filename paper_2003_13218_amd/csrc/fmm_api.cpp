@@ -98,6 +98,7 @@ struct fmm_plan {
     // per-call workspace
     DeviceBuf key, count, cursor, start, perm, scan, xq, xq_u, xs, Mlev, Llev, M0, L0, m2l_part;
     DeviceBuf pstart, xqp;  // near-field copy of xq, leaves padded to the P2P group count
+    DeviceBuf mneg;         // sign-flipped multipoles of the level in M2L (paired list)
     DeviceBuf phi_nf, field_nf, phi_ff, field_ff, phi_u, field_u, nfuv, partials, scalars, flag;
     DeviceBuf sflag;    // sparse solute pass: one flag per cell, level 0 first, then levels 1..L
     DeviceBuf mask_sw;  // exchanged solute mask (FMM_UV_SWAP)
@@ -508,6 +509,7 @@ static fmm_status ensure_workspace(fmm_plan_t pl, int64_t n) {
         for (int l = 1; l <= pl->levels; ++l)
             if (m2l_slices(l) > 1) part = std::max(part, (int64_t)m2l_slices(l) * level_cells(l));
         if (!pl->Mlev.ensure(tb) || !pl->Llev.ensure(tb) || !pl->M0.ensure(sizeof(double) * pl->Kp) ||
+            !pl->mneg.ensure(sizeof(double) * (size_t)nleaf * pl->Kp) ||
             !pl->m2l_part.ensure(sizeof(double) * (size_t)std::max<int64_t>(part, 1) * pl->Kp) ||
             !pl->L0.ensure(sizeof(double) * pl->Kp) || !pl->count.ensure(sizeof(uint32_t) * nleaf) ||
             !pl->cursor.ensure(sizeof(uint32_t) * nleaf) || !pl->start.ensure(sizeof(int32_t) * (nleaf + 1)) ||
@@ -603,19 +605,20 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
         const OpSet &o = *pl->op;
         if (l <= top && l <= 2)
             e = launch_m2l<double>(l, o.alias_ops[l - 1].as<double>(), o.alias_il[l - 1].as<int32_t>(),
-                                   o.alias_off[l - 1].as<int32_t>(), nullptr, MD(l), LD(l), pl->m2l_part.as<double>(),
-                                   p, Kp, s, 1 << (3 * l));
+                                   o.alias_off[l - 1].as<int32_t>(), nullptr, MD(l), nullptr, LD(l),
+                                   pl->m2l_part.as<double>(), p, Kp, s, 1 << (3 * l));
         else if (l <= top)
             e = launch_m2l<double>(l, o.ops64.as<double>(), o.pairs.as<int32_t>(), o.offv.as<int32_t>(),
-                                   o.rowmap.as<int32_t>(), MD(l), LD(l), pl->m2l_part.as<double>(), p, Kp, s);
+                                   o.rowmap.as<int32_t>(), MD(l), pl->mneg.as<double>(), LD(l),
+                                   pl->m2l_part.as<double>(), p, Kp, s);
         else if (!TD && pl->prec == FMM_MIXED_BF16_M2L)
             e = launch_m2l_bf16(l, pl->op->opsbf.ptr, pl->op->il.as<int32_t>(), pl->op->offv.as<int32_t>(),
                                 reinterpret_cast<const float *>(MT(l)), reinterpret_cast<float *>(LT(l)),
                                 pl->m2l_part.as<float>(), p, Kp, s);
         else
             e = launch_m2l<T>(l, sizeof(T) == 8 ? (const T *)o.ops64.ptr : (const T *)o.ops32.ptr,
-                              o.pairs.as<int32_t>(), o.offv.as<int32_t>(), o.rowmap.as<int32_t>(), MT(l), LT(l),
-                              pl->m2l_part.as<T>(), p, Kp, s);
+                              o.pairs.as<int32_t>(), o.offv.as<int32_t>(), o.rowmap.as<int32_t>(), MT(l),
+                              pl->mneg.as<T>(), LT(l), pl->m2l_part.as<T>(), p, Kp, s);
         HIPCHK(pl, e, "M2L");
         if (l == L) stage_end(pl, FMM_STAGE_M2L_LEAF);
     }
@@ -1145,7 +1148,7 @@ extern "C" void fmm_destroy(fmm_plan_t pl) {
     }
     DeviceBuf *bufs[] = {&pl->lat, &pl->key,
                          &pl->count, &pl->cursor, &pl->start, &pl->pstart, &pl->xqp, &pl->perm, &pl->scan, &pl->xq, &pl->xq_u, &pl->xs, &pl->m2l_part,
-                         &pl->Mlev, &pl->Llev, &pl->M0, &pl->L0, &pl->phi_nf, &pl->field_nf, &pl->phi_ff,
+                         &pl->Mlev, &pl->Llev, &pl->mneg, &pl->M0, &pl->L0, &pl->phi_nf, &pl->field_nf, &pl->phi_ff,
                          &pl->field_ff, &pl->phi_u, &pl->field_u, &pl->nfuv, &pl->partials, &pl->scalars, &pl->flag,
                          &pl->sflag, &pl->mask_sw, &pl->mask_s, &pl->nfsc, &pl->nfdl};
     for (DeviceBuf *b : bufs) b->release();

@@ -152,9 +152,10 @@ hipError_t launch_l2l_sparse(int64_t nchild, const uint32_t *flag, const double 
 //   nil < 875 (the aliased levels 1 and 2): `list` holds 8 x nil operator ids
 //     of operators in the plain swizzle_ops layout, rowmap unused.
 int m2l_slices(int level);
+// Mneg: scratch of the level's cells x Kp elements (full list only)
 template <typename T>
 hipError_t launch_m2l(int level, const T *ops, const int32_t *list, const int32_t *offs, const int32_t *rowmap,
-                      const T *M, T *L, T *partial, int p, int Kp, hipStream_t s, int nil = kILSize);
+                      const T *M, T *Mneg, T *L, T *partial, int p, int Kp, hipStream_t s, int nil = kILSize);
 // Row order of the full-list operators: even-degree rows, then odd-degree
 // rows, each padded to 16-row blocks (m2l_row_blocks blocks in all, the first
 // m2l_even_blocks even); map[16 * m2l_row_blocks] = storage row (every row

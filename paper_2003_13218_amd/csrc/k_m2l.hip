@@ -344,13 +344,8 @@ struct PolBf16 {  // BF16 operands, FP32 storage and accumulation, v_mfma_f32_16
     }
 };
 
-// Bit-level helpers of the paired kernel: x with its sign flipped when bit is
-// 1, and a per-element choice between two fragments by an all-ones / zero mask
-// (bit operations, so a run-time choice never becomes a branch).
-__device__ inline float neg_if(float x, uint32_t bit) { return __uint_as_float(__float_as_uint(x) ^ (bit << 31)); }
-__device__ inline double neg_if(double x, uint32_t bit) {
-    return __longlong_as_double(__double_as_longlong(x) ^ ((long long)bit << 63));
-}
+// Per-element choice between two fragments by an all-ones / zero mask (bit
+// operations, so a run-time choice never becomes a branch).
 __device__ inline float pick(float a, float b, uint32_t m) {
     return __uint_as_float((__float_as_uint(a) & m) | (__float_as_uint(b) & ~m));
 }
@@ -391,16 +386,18 @@ template <typename P, int NRB> constexpr int stage_chunks() {
 // SPLIT: split-K over offset slices (partials to a buffer, added in a fixed
 // order by k_m2l_reduce), compiled separately so profiles tell levels apart.
 // ---------------------------------------------------------------------------
-// NE >= 0: the number of even-degree row blocks of this row group, fixed at
-// compile time (the single row group of every p <= 12); NE < 0: taken from
-// ne_blocks at run time, with a bit mask per row block.
+// NE: the number of even-degree row blocks of this row group (the first NE
+// blocks), fixed at compile time: the single group of p <= 12 holds both
+// kinds, larger orders split their rows into groups of one kind (NE = NRB or
+// 0).  Unused by the unpaired (BF16) policy.
 template <typename P, bool SPLIT, int NRB, int U, int NE>
 __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict__ ops,
                                                  const int32_t *__restrict__ il, const int32_t *__restrict__ offs,
                                                  const int32_t *__restrict__ rowmap,
-                                                 const typename P::S *__restrict__ M, typename P::S *__restrict__ L,
-                                                 int nh_bits, int NB, int NKC, int Kp, int rb0, int nslices_arg,
-                                                 int ne_blocks) {
+                                                 const typename P::S *__restrict__ M,
+                                                 const typename P::S *__restrict__ Mneg,
+                                                 typename P::S *__restrict__ L,
+                                                 int nh_bits, int NB, int NKC, int Kp, int rb0, int nslices_arg) {
     using S = typename P::S;
     using A = typename P::A;
     using B = typename P::B;
@@ -440,45 +437,22 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
     const int32_t *ilp = il + parity * NENT * (PAIR ? 2 : 1);
     const int kq = (P::KW / 4) * (lane >> 4);        // this lane's k offset inside a chunk
 
-    // paired list: odd-degree columns of this lane (bit 4 kc + j: column
-    // 16 kc + kq + j, kc < 16 in sg0, kc >= 16 in sg1), and per row block of
-    // this group whether it holds even-degree rows (all-ones) or odd (zero)
-    uint64_t sg0 = 0, sg1 = 0;
-    uint32_t even_rb[NRB];
-    if constexpr (PAIR) {
-        for (int c2 = 0; c2 < NKC; ++c2)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int col = 16 * c2 + kq + j;
-                int n = (int)sqrtf((float)col);
-                if (n * n > col) --n;
-                if ((n + 1) * (n + 1) <= col) ++n;
-                if (n & 1) {
-                    const uint64_t bit = 1ull << (4 * (c2 & 15) + j);
-                    if (c2 < 16) sg0 |= bit;
-                    else sg1 |= bit;
-                }
-            }
-#pragma unroll
-        for (int rb = 0; rb < NRB; ++rb) even_rb[rb] = (rb0 + rb < ne_blocks) ? 0xffffffffu : 0u;
-    }
-
     // chunk cursor (t, kc); the operator id and the multipole rows of this
     // lane's source cells change only with t.  Paired entries have a second
-    // source cell (offset -t); for single offsets src2 repeats src and m2 = 0
-    // zeroes its fragment.
+    // source cell (offset -t), read from Mneg = D M (odd degrees negated); for
+    // single offsets src2 repeats src and m2 = 0 zeroes its fragment.
     struct Cursor {
         int t, kc;
         size_t base;    // first fragment of the chunk
         const S *src;   // this lane's coefficients of the source multipole
-        const S *src2;  // ... of the paired source (offset -t)
+        const S *src2;  // ... of the paired source (offset -t), sign-flipped
         uint32_t m2;    // all-ones if the entry is a pair, else 0
     };
-    auto source = [&](int oid) {
+    auto source = [&](const S *base, int oid) {
         const uint32_t sx = (tx + (uint32_t)offs[3 * oid]) & nmask;
         const uint32_t sy = (ty + (uint32_t)offs[3 * oid + 1]) & nmask;
         const uint32_t sz = (tz + (uint32_t)offs[3 * oid + 2]) & nmask;
-        return M + (size_t)morton3(sx, sy, sz) * Kp + kq;
+        return base + (size_t)morton3(sx, sy, sz) * Kp + kq;
     };
     auto set_t = [&](Cursor &c, int t) {
         c.t = t;
@@ -486,13 +460,13 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
         const int e = min(t, t1 - 1);  // past the end: stay on a valid chunk
         if constexpr (PAIR) {
             const int oid = ilp[2 * e], oid2 = ilp[2 * e + 1];
-            c.src = source(oid);
-            c.src2 = oid2 >= 0 ? source(oid2) : c.src;
+            c.src = source(M, oid);
+            c.src2 = oid2 >= 0 ? source(Mneg, oid2) : c.src;
             c.m2 = oid2 >= 0 ? 0xffffffffu : 0u;
             c.base = (size_t)oid * op_stride + (size_t)rb0 * 64;
         } else {
             const int oid = ilp[e];
-            c.src = source(oid);
+            c.src = source(M, oid);
             c.src2 = c.src;
             c.m2 = 0u;
             c.base = (size_t)oid * op_stride + (size_t)rb0 * 64;
@@ -585,27 +559,15 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
             if constexpr (sizeof(A) == 16) __builtin_amdgcn_sched_barrier(0);
             if constexpr (PAIR) {
                 // v1 = b + D b2 feeds the even-degree rows, v2 = b - D b2 the odd
-                const uint64_t w = kc < 16 ? sg0 : sg1;
-                const uint32_t sb = (uint32_t)(w >> (4 * (kc & 15))) & 15u;
                 B v1, v2;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const S m = neg_if(pick((S)bcur2[u][j], (S)0, mcur[u]), (sb >> j) & 1u);
+                    const S m = pick((S)bcur2[u][j], (S)0, mcur[u]);
                     v1[j] = bcur[u][j] + m;
                     v2[j] = bcur[u][j] - m;
                 }
-                if constexpr (NE >= 0) {
 #pragma unroll
-                    for (int rb = 0; rb < NRB; ++rb) acc[rb] = P::mma(a[rb], rb < NE ? v1 : v2, acc[rb]);
-                } else {
-#pragma unroll
-                    for (int rb = 0; rb < NRB; ++rb) {
-                        B b;
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) b[j] = pick(v1[j], v2[j], even_rb[rb]);
-                        acc[rb] = P::mma(a[rb], b, acc[rb]);
-                    }
-                }
+                for (int rb = 0; rb < NRB; ++rb) acc[rb] = P::mma(a[rb], rb < NE ? v1 : v2, acc[rb]);
             } else {
                 const B b = P::to_b(bcur[u]);
 #pragma unroll
@@ -656,41 +618,68 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
 }
 
 // Even-degree row blocks of the single row group of order p <= 12 with NRB
-// row blocks (NRB = m2l_row_blocks(p) determines it for those p; -1: none).
+// row blocks (NRB = m2l_row_blocks(p) determines it for those p; 0: none).
 constexpr int single_group_even_blocks(int nrb) {
-    constexpr int table[12] = {-1, 1, 1, 1, 2, 2, 3, 3, -1, 5, 5, 6};
-    return nrb >= 0 && nrb < 12 ? table[nrb] : -1;
+    constexpr int table[12] = {0, 1, 1, 1, 2, 2, 3, 3, 0, 5, 5, 6};
+    return nrb >= 0 && nrb < 12 ? table[nrb] : 0;
 }
 
-// Launches the LDS-shared kernel for every group of up to kRowBlocksPerWave
-// row blocks (one launch per group, NRB and U fixed at compile time).
+// Launches the LDS-shared kernel for every row group (NRB, U and the group's
+// even-degree block count fixed at compile time).  Row groups hold up to
+// kRowBlocksPerWave blocks; with the paired list an order whose rows do not
+// fit one group gets groups of even-degree blocks and groups of odd-degree
+// blocks, so that no group mixes them at a position other than the one of
+// single_group_even_blocks.
 template <typename P>
 static hipError_t launch_lds(const void *ops, const int32_t *il, const int32_t *offs, const int32_t *rowmap,
-                             const typename P::S *M, typename P::S *out, int nh_bits, int NB, int NKC, int Kp,
-                             int nslices, int ne_blocks, hipStream_t s) {
-    if (P::kPaired && NKC > 32) return hipErrorInvalidValue;  // column parity bits: two 64-bit words
+                             const typename P::S *M, const typename P::S *Mneg, typename P::S *out, int nh_bits,
+                             int NB, int NKC, int Kp, int nslices, int ne_blocks, hipStream_t s) {
     using A = typename P::A;
+    if (P::kPaired && NKC > 32) return hipErrorInvalidValue;  // column parity bits: two 64-bit words
+    struct Group {
+        int rb0, nrb, ne;
+    };
+    Group groups[16];
+    int ng = 0;
+    auto add = [&](int from, int to, bool even) {
+        for (int r = from; r < to; r += kRowBlocksPerWave) {
+            if (ng == 16) return false;
+            const int n = std::min(kRowBlocksPerWave, to - r);
+            groups[ng++] = Group{r, n, even ? n : 0};
+        }
+        return true;
+    };
+    if (!P::kPaired) {
+        if (!add(0, NB, false)) return hipErrorInvalidValue;
+    } else if (NB <= kRowBlocksPerWave) {
+        if (ne_blocks != single_group_even_blocks(NB)) return hipErrorInvalidValue;
+        groups[ng++] = Group{0, NB, ne_blocks};
+    } else if (!add(0, ne_blocks, true) || !add(ne_blocks, NB, false)) {
+        return hipErrorInvalidValue;
+    }
     const int64_t ntile = (((int64_t)1 << (3 * nh_bits)) + 63) / 64;
     const int64_t grid = 8 * ntile * nslices;
     const A *o = reinterpret_cast<const A *>(ops);
-    for (int rb0 = 0; rb0 < NB; rb0 += kRowBlocksPerWave) {
-        const int nrb = std::min(kRowBlocksPerWave, NB - rb0);
-        const int ne_local = std::max(0, std::min(nrb, ne_blocks - rb0));
-        const bool fixed = P::kPaired && ne_local == single_group_even_blocks(nrb);
+    for (int gi = 0; gi < ng; ++gi) {
+        const int rb0 = groups[gi].rb0, nrb = groups[gi].nrb, ne = groups[gi].ne;
         switch (nrb) {
 #define FMM_M2L_LDS_LAUNCH(N, NE)                                                                              \
     if (nslices > 1)                                                                                           \
         hipLaunchKernelGGL((k_m2l_lds<P, true, N, stage_chunks<P, N>(), NE>), dim3((unsigned)grid), dim3(256), \
-                           0, s, o, il, offs, rowmap, M, out, nh_bits, NB, NKC, Kp, rb0, nslices, ne_blocks); \
+                           0, s, o, il, offs, rowmap, M, Mneg, out, nh_bits, NB, NKC, Kp, rb0, nslices);            \
     else                                                                                                       \
         hipLaunchKernelGGL((k_m2l_lds<P, false, N, stage_chunks<P, N>(), NE>), dim3((unsigned)grid),          \
-                           dim3(256), 0, s, o, il, offs, rowmap, M, out, nh_bits, NB, NKC, Kp, rb0, 1, ne_blocks);
+                           dim3(256), 0, s, o, il, offs, rowmap, M, Mneg, out, nh_bits, NB, NKC, Kp, rb0, 1);
 #define FMM_M2L_LDS_CASE(N)                                                                                    \
     case N:                                                                                                    \
-        if (fixed) {                                                                                           \
+        if (!P::kPaired || ne == 0) {                                                                          \
+            FMM_M2L_LDS_LAUNCH(N, 0)                                                                           \
+        } else if (ne == N) {                                                                                  \
+            FMM_M2L_LDS_LAUNCH(N, N)                                                                           \
+        } else if (ne == single_group_even_blocks(N)) {                                                        \
             FMM_M2L_LDS_LAUNCH(N, single_group_even_blocks(N))                                                 \
         } else {                                                                                               \
-            FMM_M2L_LDS_LAUNCH(N, -1)                                                                          \
+            return hipErrorInvalidValue;                                                                       \
         }                                                                                                      \
         break;
             FMM_M2L_LDS_CASE(1) FMM_M2L_LDS_CASE(2) FMM_M2L_LDS_CASE(3) FMM_M2L_LDS_CASE(4)
@@ -783,7 +772,7 @@ hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const 
     const int NB = Kp / 16;
     const int nh_bits = level - 1;
     const int nslices = partial ? m2l_slices(level) : 1;
-    hipError_t e = launch_lds<PolBf16>(ops, il, offs, nullptr, M, nslices > 1 ? partial : L, nh_bits, NB,
+    hipError_t e = launch_lds<PolBf16>(ops, il, offs, nullptr, M, M, nslices > 1 ? partial : L, nh_bits, NB,
                                        bf16_chunks(p), Kp, nslices, 0, s);
     if (e != hipSuccess || nslices == 1) return e;
     const int64_t elems = ((int64_t)8 << (3 * nh_bits)) * Kp;
@@ -793,21 +782,40 @@ hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const 
     return hipGetLastError();
 }
 
+// Mneg[c][k] = (-1)^n(k) M[c][k] (n(k) the degree of coefficient k): the
+// multipoles as the paired kernel reads them for the offset -t of a pair.
+template <typename T>
+__global__ void k_m2l_flip(const T *__restrict__ M, T *__restrict__ Mneg, int64_t n, int Kp) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(i % Kp);
+        int d = (int)sqrtf((float)k);
+        if (d * d > k) --d;
+        if ((d + 1) * (d + 1) <= k) ++d;
+        Mneg[i] = (d & 1) ? -M[i] : M[i];
+    }
+}
+
 // The full interaction list (nil == 875) runs on the LDS-shared kernel with
-// the paired entries; the aliased lists of levels 1 and 2 (nil = 8 or 64
-// pre-summed operators) on the offset-split kernel.
+// the paired entries (Mneg: scratch for the level's sign-flipped multipoles,
+// cells x Kp); the aliased lists of levels 1 and 2 (nil = 8 or 64 pre-summed
+// operators) on the offset-split kernel.
 template <typename T>
 hipError_t launch_m2l(int level, const T *ops, const int32_t *list, const int32_t *offs, const int32_t *rowmap,
-                      const T *M, T *L, T *partial, int p, int Kp, hipStream_t s, int nil) {
+                      const T *M, T *Mneg, T *L, T *partial, int p, int Kp, hipStream_t s, int nil) {
     constexpr int CB = Mfma<T>::CB;
     const int NB = Kp / 16;
     const int nh_bits = level - 1;
     const int64_t ntarget = (int64_t)1 << (3 * nh_bits);
     const int nslices = partial ? std::min(m2l_slices(level), nil) : 1;
     if (nil == kILSize) {
-        if (!rowmap) return hipErrorInvalidValue;
-        const hipError_t e = launch_lds<PolMfma<T>>(ops, list, offs, rowmap, M, nslices > 1 ? partial : L, nh_bits,
-                                                     m2l_row_blocks(p), NB, Kp, nslices, m2l_even_blocks(p), s);
+        if (!rowmap || !Mneg) return hipErrorInvalidValue;
+        const int64_t n = ((int64_t)8 << (3 * nh_bits)) * Kp;
+        int64_t g = (n + 255) / 256;
+        if (g > 65535) g = 65535;
+        hipLaunchKernelGGL(k_m2l_flip<T>, dim3((unsigned)g), dim3(256), 0, s, M, Mneg, n, Kp);
+        const hipError_t e = launch_lds<PolMfma<T>>(ops, list, offs, rowmap, M, Mneg, nslices > 1 ? partial : L,
+                                                     nh_bits, m2l_row_blocks(p), NB, Kp, nslices, m2l_even_blocks(p),
+                                                     s);
         if (e != hipSuccess) return e;
     } else {
         int R = 1;
@@ -828,8 +836,8 @@ hipError_t launch_m2l(int level, const T *ops, const int32_t *list, const int32_
     return hipGetLastError();
 }
 template hipError_t launch_m2l<float>(int, const float *, const int32_t *, const int32_t *, const int32_t *,
-                                      const float *, float *, float *, int, int, hipStream_t, int);
+                                      const float *, float *, float *, float *, int, int, hipStream_t, int);
 template hipError_t launch_m2l<double>(int, const double *, const int32_t *, const int32_t *, const int32_t *,
-                                       const double *, double *, double *, int, int, hipStream_t, int);
+                                       const double *, double *, double *, double *, int, int, hipStream_t, int);
 
 }  // namespace fmm

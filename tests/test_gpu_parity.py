@@ -111,6 +111,19 @@ def test_c1_fp64_forces_at_higher_order(fmm):
     assert rms_rel(ph.cpu().numpy(), o["phi"]) < 1e-6
 
 
+@pytest.mark.parametrize("p,prec", [(13, 0), (14, 1), (20, 0)])
+def test_c1_orders_with_several_row_groups(fmm, p, prec):
+    # the M2L rows of these orders (196, 225 and 441 coefficients) do not fit
+    # one row group: even- and odd-degree rows run in groups of their own
+    w, o = ewald_full("C1")
+    plan = _plan(fmm, w.box, w.levels, p, prec)
+    e, f, ph = fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q), forces=True, phi=True)
+    tol = 1e-6 if prec == 0 else 1e-5
+    assert abs(e - o["terms"]["total"]) / abs(o["terms"]["total"]) < (1e-8 if prec == 0 else 1e-6)
+    assert rms_rel(f.cpu().numpy(), o["force"]) < tol
+    assert rms_rel(ph.cpu().numpy(), o["phi"]) < tol
+
+
 @pytest.mark.parametrize("prec,tol", [(0, 1e-6), (1, 1e-5)])
 def test_c2_energy_forces(fmm, prec, tol):
     w, o = ewald_full("C2")
