@@ -111,6 +111,19 @@ def test_c1_fp64_forces_at_higher_order(fmm):
     assert rms_rel(ph.cpu().numpy(), o["phi"]) < 1e-6
 
 
+@pytest.mark.parametrize("levels", [1, 2])
+def test_c1_mixed_shallow_trees(fmm, levels):
+    # mixed mode on trees of 1 and 2 levels: the finest level is FP32 and takes
+    # the full (paired) interaction list on a grid of 2 or 4 cells per axis,
+    # where every source cell is reached under several image shifts
+    w, o = ewald_full("C1")
+    plan = _plan(fmm, w.box, levels, 12, fmm.FMM_MIXED)
+    e, f, ph = fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q), forces=True, phi=True)
+    assert abs(e - o["terms"]["total"]) / abs(o["terms"]["total"]) < 1e-6
+    assert rms_rel(f.cpu().numpy(), o["force"]) < 1e-5
+    assert rms_rel(ph.cpu().numpy(), o["phi"]) < 1e-5
+
+
 @pytest.mark.parametrize("p,prec", [(13, 0), (14, 1), (20, 0)])
 def test_c1_orders_with_several_row_groups(fmm, p, prec):
     # the M2L rows of these orders (196, 225 and 441 coefficients) do not fit
