@@ -23,6 +23,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -32,25 +33,53 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 M2L_IL = 875  # interaction-list size per cell
-# list entries per cell of the FP32/FP64 kernel: the 875 offsets form 302
-# (t, -t) pairs, each one operator product (O_-t = D O_t D), and 271 singles
-M2L_ENTRIES = 573
-PEAK_TFLOPS = {"mixed": 157.3, "bf16": 2500.0, "fp64": 78.6}  # dense MFMA peaks of MI355X (FP32, BF16, FP64)
-PREC_NAMES = {"fp64": 0, "mixed": 1, "bf16": 2}
+# list entries per cell of the FP32/FP64 kernel under the two symmetry schemes
+# of the library (operators of reflected offsets differ by signs only):
+# scheme 1 folds the (t, -t) pairs (302 pairs + 271 singles), scheme 2 the
+# orbits of the two-axis flips (305 orbits of 1 to 4 offsets)
+M2L_ENTRIES = {1: 573, 2: 305}
+
+
+def _row_class(scheme, k):
+    n = int(math.isqrt(k))
+    r = k - n * n
+    m, im = (r + 1) // 2, r > 0 and r % 2 == 0
+    return n & 1 if scheme == 1 else 2 * (m & 1) + ((n & 1) ^ int(im))
+
+
+def _class_blocks(p, scheme):
+    K = (p + 1) ** 2
+    counts = [0] * (2 if scheme == 1 else 4)
+    for k in range(K):
+        counts[_row_class(scheme, k)] += 1
+    return [(c + 15) // 16 for c in counts]
+
+
+def m2l_scheme(p):
+    """The scheme the library picks for order p: the one with fewer entries x
+    padded row blocks (its rule in m2l_scheme, k_m2l.hip)."""
+    return 2 if M2L_ENTRIES[2] * sum(_class_blocks(p, 2)) < M2L_ENTRIES[1] * sum(_class_blocks(p, 1)) else 1
+
+
 def leaf_kernel(prec_name, p):
     """Name of the finest-level M2L kernel (first row group) for this order."""
     if prec_name == "bf16":
         return "k_m2l_bf16<false>"
-    nb = ((p + 1) ** 2 + 15) // 16
-    return f"k_m2l_lds<{'double' if prec_name == 'fp64' else 'float'}, false, {min(11, nb)}>"
+    t = "double" if prec_name == "fp64" else "float"
+    if m2l_scheme(p) == 2:
+        b = _class_blocks(p, 2)
+        nrb = min(11, b[0] + b[1])
+        return f"k_m2l_lds<{t}, false, {nrb}> x2 (row-class halves)"
+    return f"k_m2l_lds<{t}, false, {min(11, sum(_class_blocks(p, 1)))}>"
 
 
 def m2l_flops(p, level, prec_name="mixed"):
     """Algorithmic M2L flops of one level: 2 K^2 per (target, list entry); the
-    FP32/FP64 kernels take a (t, -t) pair as one entry, the BF16 kernel every
-    offset."""
+    FP32/FP64 kernels take one symmetry-folded entry as one operator product,
+    the BF16 kernel every offset."""
     K = (p + 1) ** 2
-    return 2.0 * K * K * (M2L_IL if prec_name == "bf16" else M2L_ENTRIES) * 8 ** level
+    entries = M2L_IL if prec_name == "bf16" else M2L_ENTRIES[m2l_scheme(p)]
+    return 2.0 * K * K * entries * 8 ** level
 
 
 def recorded_traffic(kernel, workload):
@@ -155,7 +184,8 @@ def run_single(args, w, p, prec_name, steps, warmup, fp64_leg, cpu_leg):
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": recorded_traffic(kernel, workload),
                 "kernel": f"{kernel} (M2L, level {w.levels})", "avg_ms": round(m2l_ms, 4),
-                "flops_per_launch": flops_leaf}
+                "flops_per_launch": flops_leaf,
+                "list_entries_per_cell": M2L_IL if prec_name == "bf16" else M2L_ENTRIES[m2l_scheme(p)]}
     desc = {"C3": "333,333 waters + one -1 ion", "C5": "1,000,000 waters + 8 ions (net +3)"}.get(w.name, w.name)
     metric = ("atom-evals/s (energy+forces) at 1M atoms, mixed vs FP64 FMM, rel err <=1e-5" if w.name == "C3"
               else f"atom-evals/s (energy+forces) on {w.name} ({w.n} atoms)")

@@ -46,16 +46,17 @@ struct OpSet {
     int p = 0;
     Offsets offs;
     DeviceBuf ops32, ops64, opsbf, il, offv;  // M2L (FP32 / FP64 / bfloat16), interaction lists
-    // paired (t, -t) list entries of the FP32/FP64 M2L, the row order of its
-    // operators (row -> storage row) and its inverse (storage row -> row)
-    DeviceBuf pairs, rowmap, rowpos;
+    // symmetry-folded list entries of the FP32/FP64 M2L (m2l_scheme), the row
+    // order of its operators (row -> storage row) and its inverse (storage
+    // row -> row), and Kp zeros (the source of an absent image)
+    DeviceBuf pairs, rowmap, rowpos, zeros;
     DeviceBuf tree32, tree64;                 // swizzled M2M (8) then L2L (8) octant operators
     // levels 1 and 2 (grids of 2 and 4 cells per axis): FP64 operators summed
     // over the offsets that reach the same source cell (alias_ops), their
     // lists (8 x n^3 ids) and offsets (the residues of t modulo n)
     DeviceBuf alias_ops[2], alias_il[2], alias_off[2];
     ~OpSet() {
-        DeviceBuf *b[] = {&ops32, &ops64, &opsbf, &il, &offv, &pairs, &rowmap, &rowpos, &tree32, &tree64,
+        DeviceBuf *b[] = {&ops32, &ops64, &opsbf, &il, &offv, &pairs, &rowmap, &rowpos, &zeros, &tree32, &tree64,
                           &alias_ops[0], &alias_ops[1],
                           &alias_il[0], &alias_il[1], &alias_off[0], &alias_off[1]};
         for (DeviceBuf *x : b) x->release();
@@ -98,7 +99,7 @@ struct fmm_plan {
     // per-call workspace
     DeviceBuf key, count, cursor, start, perm, scan, xq, xq_u, xs, Mlev, Llev, M0, L0, m2l_part;
     DeviceBuf pstart, xqp;  // near-field copy of xq, leaves padded to the P2P group count
-    DeviceBuf mneg;         // sign-flipped multipoles of the level in M2L (paired list)
+    DeviceBuf mflip;        // sign-flipped multipoles of the level in M2L (symmetry-folded list)
     DeviceBuf phi_nf, field_nf, phi_ff, field_ff, phi_u, field_u, nfuv, partials, scalars, flag;
     DeviceBuf sflag;    // sparse solute pass: one flag per cell, level 0 first, then levels 1..L
     DeviceBuf mask_sw;  // exchanged solute mask (FMM_UV_SWAP)
@@ -247,12 +248,12 @@ static fmm_status make_opset(int p, std::shared_ptr<OpSet> &out, std::string &ms
     std::vector<double> s64(ne);
     swizzle_ops<float>(p, 16, rm.data(), s32.data());
     swizzle_ops<double>(p, 16, rm.data(), s64.data());
-    std::vector<int32_t> pairs((size_t)8 * 2 * kM2LEntries);
-    build_m2l_pairs(op->offs.vec.data(), op->offs.il.data(), pairs.data());
-    if (pairs[0] < 0) {
-        msg = "fmm_plan: interaction list does not pair up";
+    std::vector<int32_t> pairs((size_t)8 * m2l_list_entries(p) * m2l_list_width(p));
+    if (!build_m2l_list(p, op->offs.vec.data(), op->offs.il.data(), pairs.data())) {
+        msg = "fmm_plan: interaction list does not fold into the expected entries";
         return FMM_ERR_INVALID;
     }
+    const std::vector<double> zeros((size_t)Kp, 0.0);
     const int nrow = 16 * m2l_row_blocks(p);
     std::vector<int32_t> rowmap(nrow), rowpos(Kp, -1);
     m2l_row_map(p, rowmap.data());
@@ -261,7 +262,7 @@ static fmm_status make_opset(int p, std::shared_ptr<OpSet> &out, std::string &ms
     if (!op->tree32.ensure(ne * sizeof(float)) || !op->tree64.ensure(ne * sizeof(double)) ||
         !op->il.ensure(sizeof(int32_t) * 8 * kILSize) || !op->offv.ensure(sizeof(int32_t) * 3 * kNumOffsets) ||
         !op->pairs.ensure(sizeof(int32_t) * pairs.size()) || !op->rowmap.ensure(sizeof(int32_t) * nrow) ||
-        !op->rowpos.ensure(sizeof(int32_t) * Kp)) {
+        !op->rowpos.ensure(sizeof(int32_t) * Kp) || !op->zeros.ensure(sizeof(double) * Kp)) {
         msg = "fmm_plan: device allocation";
         return FMM_ERR_NOMEM;
     }
@@ -272,7 +273,8 @@ static fmm_status make_opset(int p, std::shared_ptr<OpSet> &out, std::string &ms
             hipSuccess ||
         hipMemcpy(op->pairs.ptr, pairs.data(), sizeof(int32_t) * pairs.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(op->rowmap.ptr, rowmap.data(), sizeof(int32_t) * nrow, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(op->rowpos.ptr, rowpos.data(), sizeof(int32_t) * Kp, hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(op->rowpos.ptr, rowpos.data(), sizeof(int32_t) * Kp, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(op->zeros.ptr, zeros.data(), sizeof(double) * Kp, hipMemcpyHostToDevice) != hipSuccess) {
         msg = "fmm_plan: upload failed";
         return FMM_ERR_DEVICE;
     }
@@ -509,7 +511,7 @@ static fmm_status ensure_workspace(fmm_plan_t pl, int64_t n) {
         for (int l = 1; l <= pl->levels; ++l)
             if (m2l_slices(l) > 1) part = std::max(part, (int64_t)m2l_slices(l) * level_cells(l));
         if (!pl->Mlev.ensure(tb) || !pl->Llev.ensure(tb) || !pl->M0.ensure(sizeof(double) * pl->Kp) ||
-            !pl->mneg.ensure(sizeof(double) * (size_t)nleaf * pl->Kp) ||
+            !pl->mflip.ensure(sizeof(double) * (size_t)m2l_flip_copies(pl->p) * nleaf * pl->Kp) ||
             !pl->m2l_part.ensure(sizeof(double) * (size_t)std::max<int64_t>(part, 1) * pl->Kp) ||
             !pl->L0.ensure(sizeof(double) * pl->Kp) || !pl->count.ensure(sizeof(uint32_t) * nleaf) ||
             !pl->cursor.ensure(sizeof(uint32_t) * nleaf) || !pl->start.ensure(sizeof(int32_t) * (nleaf + 1)) ||
@@ -605,12 +607,12 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
         const OpSet &o = *pl->op;
         if (l <= top && l <= 2)
             e = launch_m2l<double>(l, o.alias_ops[l - 1].as<double>(), o.alias_il[l - 1].as<int32_t>(),
-                                   o.alias_off[l - 1].as<int32_t>(), nullptr, MD(l), nullptr, LD(l),
+                                   o.alias_off[l - 1].as<int32_t>(), nullptr, MD(l), nullptr, nullptr, LD(l),
                                    pl->m2l_part.as<double>(), p, Kp, s, 1 << (3 * l));
         else if (l <= top)
             e = launch_m2l<double>(l, o.ops64.as<double>(), o.pairs.as<int32_t>(), o.offv.as<int32_t>(),
-                                   o.rowmap.as<int32_t>(), MD(l), pl->mneg.as<double>(), LD(l),
-                                   pl->m2l_part.as<double>(), p, Kp, s);
+                                   o.rowmap.as<int32_t>(), MD(l), pl->mflip.as<double>(), o.zeros.as<double>(),
+                                   LD(l), pl->m2l_part.as<double>(), p, Kp, s);
         else if (!TD && pl->prec == FMM_MIXED_BF16_M2L)
             e = launch_m2l_bf16(l, pl->op->opsbf.ptr, pl->op->il.as<int32_t>(), pl->op->offv.as<int32_t>(),
                                 reinterpret_cast<const float *>(MT(l)), reinterpret_cast<float *>(LT(l)),
@@ -618,7 +620,7 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
         else
             e = launch_m2l<T>(l, sizeof(T) == 8 ? (const T *)o.ops64.ptr : (const T *)o.ops32.ptr,
                               o.pairs.as<int32_t>(), o.offv.as<int32_t>(), o.rowmap.as<int32_t>(), MT(l),
-                              pl->mneg.as<T>(), LT(l), pl->m2l_part.as<T>(), p, Kp, s);
+                              pl->mflip.as<T>(), o.zeros.as<T>(), LT(l), pl->m2l_part.as<T>(), p, Kp, s);
         HIPCHK(pl, e, "M2L");
         if (l == L) stage_end(pl, FMM_STAGE_M2L_LEAF);
     }
@@ -1148,7 +1150,7 @@ extern "C" void fmm_destroy(fmm_plan_t pl) {
     }
     DeviceBuf *bufs[] = {&pl->lat, &pl->key,
                          &pl->count, &pl->cursor, &pl->start, &pl->pstart, &pl->xqp, &pl->perm, &pl->scan, &pl->xq, &pl->xq_u, &pl->xs, &pl->m2l_part,
-                         &pl->Mlev, &pl->Llev, &pl->mneg, &pl->M0, &pl->L0, &pl->phi_nf, &pl->field_nf, &pl->phi_ff,
+                         &pl->Mlev, &pl->Llev, &pl->mflip, &pl->M0, &pl->L0, &pl->phi_nf, &pl->field_nf, &pl->phi_ff,
                          &pl->field_ff, &pl->phi_u, &pl->field_u, &pl->nfuv, &pl->partials, &pl->scalars, &pl->flag,
                          &pl->sflag, &pl->mask_sw, &pl->mask_s, &pl->nfsc, &pl->nfdl};
     for (DeviceBuf *b : bufs) b->release();

@@ -14,7 +14,8 @@ namespace fmm {
 constexpr int kWS = 2;            // near field / well-separatedness: +-2 cells
 constexpr int kNumOffsets = 1206; // distinct M2L offsets: [-5,5]^3 minus [-2,2]^3
 constexpr int kILSize = 875;      // interaction list size per parity class
-constexpr int kM2LEntries = 573;  // paired list entries per class: 302 (t, -t) pairs + 271 single offsets
+constexpr int kM2LPairEntries = 573;   // list entries per class, scheme 1: 302 (t, -t) pairs + 271 singles
+constexpr int kM2LOrbitEntries = 305;  // list entries per class, scheme 2: orbits of the two-axis flips
 constexpr int kMaxP = 20;
 constexpr int kMaxP2PGroups = 16;  // largest source-group count of the P2P kernel
 constexpr int kMaxLevels = 10;
@@ -145,26 +146,34 @@ hipError_t launch_l2l_sparse(int64_t nchild, const uint32_t *flag, const double 
 // (split-K) whose partial sums go to `partial` and are added in a fixed order.
 // offs: 3 ints per operator id (the source cell is the target cell + offset,
 // wrapped on the level's grid).
-//   nil == 875: the full interaction list, as the paired entries `list`
-//     (8 x kM2LEntries x 2 operator ids, second -1 for a single offset; see
-//     build_m2l_pairs) with the row-ordered operators of swizzle_m2l_ops and
-//     `rowmap` (m2l_row_map) to put the result rows back in storage order;
+//   nil == 875: the full interaction list, as the symmetry-folded entries
+//     `list` (8 x m2l_list_entries x m2l_list_width operator ids, -1 for an
+//     absent source; see build_m2l_list) with the class-ordered operators of
+//     swizzle_m2l_ops and `rowmap` (m2l_row_map) to put the result rows back
+//     in storage order; Mflip: scratch for the level's sign-flipped
+//     multipoles (m2l_flip_copies(p) x cells x Kp elements); zeros: Kp zero
+//     elements (the source of an absent image);
 //   nil < 875 (the aliased levels 1 and 2): `list` holds 8 x nil operator ids
-//     of operators in the plain swizzle_ops layout, rowmap unused.
+//     of operators in the plain swizzle_ops layout; rowmap, Mflip, zeros unused.
 int m2l_slices(int level);
-// Mneg: scratch of the level's cells x Kp elements (full list only)
 template <typename T>
 hipError_t launch_m2l(int level, const T *ops, const int32_t *list, const int32_t *offs, const int32_t *rowmap,
-                      const T *M, T *Mneg, T *L, T *partial, int p, int Kp, hipStream_t s, int nil = kILSize);
-// Row order of the full-list operators: even-degree rows, then odd-degree
-// rows, each padded to 16-row blocks (m2l_row_blocks blocks in all, the first
-// m2l_even_blocks even); map[16 * m2l_row_blocks] = storage row (every row
-// of 0 .. Kp-1 once, the padding rows K .. Kp-1 on zero operator rows) or -1
+                      const T *M, T *Mflip, const T *zeros, T *L, T *partial, int p, int Kp, hipStream_t s,
+                      int nil = kILSize);
+// Symmetry scheme of the full-list operators for order p (1: (t, -t) pairs,
+// 2: orbits of the two-axis flips), their row blocks (rows grouped by class,
+// each class padded to 16), the blocks per class (returns the class count),
+// list entries per parity class and ints per entry, flipped copies needed
+int m2l_scheme(int p);
 int m2l_row_blocks(int p);
-int m2l_even_blocks(int p);
+int m2l_class_blocks(int p, int *blocks /*4*/);
+int m2l_list_entries(int p);
+int m2l_list_width(int p);
+inline int m2l_flip_copies(int p) { return m2l_scheme(p) == 1 ? 1 : 3; }
+// map[16 * m2l_row_blocks] = storage row of each operator row (every row of
+// 0 .. Kp-1 once, the padding rows K .. Kp-1 on zero operator rows) or -1
 void m2l_row_map(int p, int32_t *map);
-void build_m2l_pairs(const int32_t *vec /*1206 x 3*/, const int32_t *il /*8 x 875*/,
-                     int32_t *pairs /*8 x kM2LEntries x 2*/);
+bool build_m2l_list(int p, const int32_t *vec /*1206 x 3*/, const int32_t *il /*8 x 875*/, int32_t *out);
 template <typename T>
 size_t m2l_ops_elems(int p);  // element count of the swizzled, row-ordered operator array
 template <typename T>

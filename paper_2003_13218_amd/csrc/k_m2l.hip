@@ -34,75 +34,125 @@
 namespace fmm {
 
 constexpr int kRowBlocksPerWave = 11;  // 176 rows: K <= 169 (p <= 12) in one row group
+constexpr int kMaxRowGroups = 16;
 
 // ---------------------------------------------------------------------------
-// Row order of the M2L operators.  O_{-t} = D O_t D with D = diag((-1)^n) over
-// the degree n of each coefficient (the irregular harmonics are odd or even in
-// t with their degree), so for a target whose list holds both t and -t
-//   O_t M_a + O_{-t} M_b = [rows of even n]  O_t (M_a + D M_b)
-//                        + [rows of odd n]   O_t (M_a - D M_b):
-// one operator product for the pair instead of two.  The operators are
-// stored with the even-degree rows first and the odd-degree rows after, each
-// group padded to whole 16-row blocks, so that every matrix-core row block
-// belongs to one group; columns keep the storage order of the expansions.
+// Symmetries of the M2L operators.  Reflecting the translation in any set of
+// axes changes an operator by signs only: for s in {+-1}^3
+//   O_{s t} = D_s O_t D_s,   D_s = diag(sigma_s(k)),
+// where for a coefficient of degree n, order m and real or imaginary part
+//   x -> -x multiplies it by (-1)^m, and by -1 more for an imaginary part,
+//   y -> -y by -1 for an imaginary part,   z -> -z by (-1)^(n+m).
+// (the irregular harmonics I_n^m(s t) are +-I_n^m(t) or their conjugates).
+// For a group H of reflections and a target whose list holds the images s t,
+//   sum_{s in H} O_{s t} M_s = sum_{s} D_s O_t D_s M_s,
+// and the rows of a character class chi of H (rows k with sigma_s(k) = chi(s)
+// for all s in H) receive  O_t (sum_s chi(s) D_s M_s):  one operator product
+// per orbit, class by class.  Two groups are used:
+//   scheme 1, H = {identity, -1}: classes even / odd degree; per parity class
+//     the 875 offsets form 302 pairs (t, -t) and 271 single offsets: 573
+//     entries, sources (t, -t);
+//   scheme 2, H = {identity, (-,-,+), (-,+,-), (+,-,-)} (two-axis flips):
+//     four classes; 305 orbits of 1 to 4 offsets, sources in the order of H.
+// Operators are stored with their rows grouped by class, each class padded to
+// whole 16-row blocks (so a matrix-core row block holds one class), columns in
+// storage order.  Scheme 2 needs four padded classes; it is taken where its
+// matrix-core work (entries x row blocks) is smaller, i.e. for p >= 5.
 // ---------------------------------------------------------------------------
-static int even_degree_rows(int p) {
-    int e = 0;
-    for (int n = 0; n <= p; n += 2) e += 2 * n + 1;
-    return e;
+struct Coef {
+    int n, m;
+    bool im;
+};
+static Coef coef(int k) {
+    int n = 0;
+    while ((n + 1) * (n + 1) <= k) ++n;
+    const int r = k - n * n;
+    return Coef{n, (r + 1) / 2, r > 0 && (r % 2 == 0)};
 }
-int m2l_even_blocks(int p) { return (even_degree_rows(p) + 15) / 16; }
-int m2l_row_blocks(int p) {
-    const int e = even_degree_rows(p), o = num_coeffs(p) - e;
-    return (e + 15) / 16 + (o + 15) / 16;
+static int row_class(int scheme, int k) {
+    const Coef c = coef(k);
+    if (scheme == 1) return c.n & 1;
+    return 2 * (c.m & 1) + ((c.n & 1) ^ (c.im ? 1 : 0));
 }
+static int class_rows(int p, int scheme, int cls) {
+    int r = 0;
+    for (int k = 0; k < num_coeffs(p); ++k) r += row_class(scheme, k) == cls;
+    return r;
+}
+static int scheme_blocks(int p, int scheme) {
+    int b = 0;
+    for (int c = 0; c < (scheme == 1 ? 2 : 4); ++c) b += (class_rows(p, scheme, c) + 15) / 16;
+    return b;
+}
+int m2l_scheme(int p) {
+    static const int forced = [] {
+        const char *v = std::getenv("FMM_M2L_SCHEME");
+        return v ? std::atoi(v) : 0;
+    }();
+    if (forced == 1 || forced == 2) return forced;
+    return (int64_t)kM2LOrbitEntries * scheme_blocks(p, 2) < (int64_t)kM2LPairEntries * scheme_blocks(p, 1) ? 2 : 1;
+}
+int m2l_row_blocks(int p) { return scheme_blocks(p, m2l_scheme(p)); }
+int m2l_class_blocks(int p, int *blocks) {
+    const int sch = m2l_scheme(p), nc = sch == 1 ? 2 : 4;
+    for (int c = 0; c < nc; ++c) blocks[c] = (class_rows(p, sch, c) + 15) / 16;
+    return nc;
+}
+int m2l_list_entries(int p) { return m2l_scheme(p) == 1 ? kM2LPairEntries : kM2LOrbitEntries; }
+int m2l_list_width(int p) { return m2l_scheme(p) == 1 ? 2 : 4; }
+
 // The padding rows K .. Kp-1 of the storage order take the first unused
 // slots (their operator rows are zero), so the kernel writes every stored row.
 void m2l_row_map(int p, int32_t *map) {
-    const int nr = 16 * m2l_row_blocks(p), eb = 16 * m2l_even_blocks(p);
+    const int sch = m2l_scheme(p);
+    int blocks[4], start[4];
+    const int nc = m2l_class_blocks(p, blocks);
+    const int nr = 16 * m2l_row_blocks(p);
     for (int i = 0; i < nr; ++i) map[i] = -1;
-    int ie = 0, io = eb;
-    for (int n = 0; n <= p; ++n)
-        for (int k = n * n; k < (n + 1) * (n + 1); ++k) map[(n & 1) ? io++ : ie++] = k;
+    for (int c = 0, at = 0; c < nc; ++c) {
+        start[c] = at;
+        at += 16 * blocks[c];
+    }
+    for (int k = 0; k < num_coeffs(p); ++k) map[start[row_class(sch, k)]++] = k;
     int pad = num_coeffs(p);
     for (int i = 0; i < nr && pad < padded_coeffs(p); ++i)
         if (map[i] < 0) map[i] = pad++;
 }
 
-// Interaction-list entries of the paired kernel: per parity class, every
-// offset t whose negation is in the same list is paired with it (the entry
-// (t, -t) appears once, at the first of the two in list order), the others
-// stand alone (second id -1).  Within [-5, 4] or [-4, 5] per axis the pairs
-// are the offsets inside [-4, 4]^3: 302 pairs and 271 single offsets.
-void build_m2l_pairs(const int32_t *vec, const int32_t *il, int32_t *pairs) {
+// List entries per parity class (m2l_list_width ints each, -1 for an absent
+// source): the orbits of the scheme's group within the class's list, each
+// orbit at the position of its first offset in list order, each offset in
+// exactly one entry.  False if the counts differ from the constants.
+bool build_m2l_list(int p, const int32_t *vec, const int32_t *il, int32_t *out) {
+    const int sch = m2l_scheme(p), W = m2l_list_width(p), NE = m2l_list_entries(p);
+    static const int H1[2][3] = {{1, 1, 1}, {-1, -1, -1}};
+    static const int H2[4][3] = {{1, 1, 1}, {-1, -1, 1}, {-1, 1, -1}, {1, -1, -1}};
     for (int par = 0; par < 8; ++par) {
         const int32_t *l = il + par * kILSize;
-        int32_t *out = pairs + (size_t)par * 2 * kM2LEntries;
+        int32_t *o = out + (size_t)par * W * NE;
         bool used[kNumOffsets] = {};
         int ne = 0;
         for (int i = 0; i < kILSize; ++i) {
             const int a = l[i];
             if (used[a]) continue;
-            used[a] = true;
-            int b = -1;
-            for (int j = 0; j < kILSize; ++j) {
-                const int c = l[j];
-                if (vec[3 * c] == -vec[3 * a] && vec[3 * c + 1] == -vec[3 * a + 1] && vec[3 * c + 2] == -vec[3 * a + 2]) {
-                    b = c;
-                    break;
+            if (ne == NE) return false;
+            for (int w = 0; w < W; ++w) {
+                const int *sg = sch == 1 ? H1[w] : H2[w];
+                int found = -1;
+                for (int jj = 0; jj < kILSize && found < 0; ++jj) {
+                    const int c = l[jj];
+                    if (!used[c] && vec[3 * c] == sg[0] * vec[3 * a] && vec[3 * c + 1] == sg[1] * vec[3 * a + 1] &&
+                        vec[3 * c + 2] == sg[2] * vec[3 * a + 2])
+                        found = c;
                 }
-            }
-            if (b >= 0) used[b] = true;
-            if (ne < kM2LEntries) {
-                out[2 * ne] = a;
-                out[2 * ne + 1] = b;
+                if (found >= 0) used[found] = true;
+                o[W * ne + w] = found;
             }
             ++ne;
         }
-        if (ne != kM2LEntries) {  // the list geometry guarantees 573
-            for (int e = 0; e < 2 * kM2LEntries; ++e) out[e] = -1;
-        }
+        if (ne != NE) return false;
     }
+    return true;
 }
 
 template <typename T>
@@ -386,26 +436,29 @@ template <typename P, int NRB> constexpr int stage_chunks() {
 // SPLIT: split-K over offset slices (partials to a buffer, added in a fixed
 // order by k_m2l_reduce), compiled separately so profiles tell levels apart.
 // ---------------------------------------------------------------------------
-// NE: the number of even-degree row blocks of this row group (the first NE
-// blocks), fixed at compile time: the single group of p <= 12 holds both
-// kinds, larger orders split their rows into groups of one kind (NE = NRB or
-// 0).  Unused by the unpaired (BF16) policy.
-template <typename P, bool SPLIT, int NRB, int U, int NE>
+// SYM: 0 plain list (one source per entry); 1 pairs (t, -t); 2 / 3 orbits of
+// the two-axis flips, first / second half of the row classes.  The first NE
+// row blocks of the group take the first combination of the entry's sources,
+// the others the second (compile-time constants).  Sources: M for the entry's
+// first offset, the sign-flipped copies Mflip + f * fstride (D_s M of the
+// group element s of slot f + 1) for the others, zeros for an absent image.
+template <typename P, bool SPLIT, int NRB, int U, int NE, int SYM>
 __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict__ ops,
                                                  const int32_t *__restrict__ il, const int32_t *__restrict__ offs,
                                                  const int32_t *__restrict__ rowmap,
                                                  const typename P::S *__restrict__ M,
-                                                 const typename P::S *__restrict__ Mneg,
-                                                 typename P::S *__restrict__ L,
-                                                 int nh_bits, int NB, int NKC, int Kp, int rb0, int nslices_arg) {
+                                                 const typename P::S *__restrict__ Mflip,
+                                                 const typename P::S *__restrict__ zeros, int64_t fstride,
+                                                 typename P::S *__restrict__ L, int nh_bits, int NB, int NKC, int Kp,
+                                                 int rb0, int nslices_arg) {
     using S = typename P::S;
     using A = typename P::A;
     using B = typename P::B;
     using Acc = typename P::Acc;
     using R = typename P::R;
     constexpr bool F64 = P::kFlush64;
-    constexpr bool PAIR = P::kPaired;
-    constexpr int NENT = PAIR ? kM2LEntries : kILSize;  // list entries per parity class
+    constexpr int NSRC = SYM == 0 ? 1 : (SYM == 1 ? 2 : 4);       // sources per list entry
+    constexpr int NENT = SYM == 0 ? kILSize : (SYM == 1 ? kM2LPairEntries : kM2LOrbitEntries);
     constexpr int CHUNK = NRB * 64;             // fragments per chunk
     constexpr int PC = (CHUNK + 255) / 256;     // fragment loads per thread per chunk
     __shared__ A lds[2][U * CHUNK];
@@ -434,19 +487,15 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
     const int nchunk = (t1 - t0) * NKC;
     const int nstage = (nchunk + U - 1) / U;
     const size_t op_stride = (size_t)NKC * NB * 64;  // fragments per offset
-    const int32_t *ilp = il + parity * NENT * (PAIR ? 2 : 1);
+    const int32_t *ilp = il + parity * NENT * NSRC;
     const int kq = (P::KW / 4) * (lane >> 4);        // this lane's k offset inside a chunk
 
     // chunk cursor (t, kc); the operator id and the multipole rows of this
-    // lane's source cells change only with t.  Paired entries have a second
-    // source cell (offset -t), read from Mneg = D M (odd degrees negated); for
-    // single offsets src2 repeats src and m2 = 0 zeroes its fragment.
+    // lane's source cells change only with t
     struct Cursor {
         int t, kc;
-        size_t base;    // first fragment of the chunk
-        const S *src;   // this lane's coefficients of the source multipole
-        const S *src2;  // ... of the paired source (offset -t), sign-flipped
-        uint32_t m2;    // all-ones if the entry is a pair, else 0
+        size_t base;         // first fragment of the chunk
+        const S *src[NSRC];  // this lane's coefficients of each source multipole
     };
     auto source = [&](const S *base, int oid) {
         const uint32_t sx = (tx + (uint32_t)offs[3 * oid]) & nmask;
@@ -458,19 +507,14 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
         c.t = t;
         c.kc = 0;
         const int e = min(t, t1 - 1);  // past the end: stay on a valid chunk
-        if constexpr (PAIR) {
-            const int oid = ilp[2 * e], oid2 = ilp[2 * e + 1];
-            c.src = source(M, oid);
-            c.src2 = oid2 >= 0 ? source(Mneg, oid2) : c.src;
-            c.m2 = oid2 >= 0 ? 0xffffffffu : 0u;
-            c.base = (size_t)oid * op_stride + (size_t)rb0 * 64;
-        } else {
-            const int oid = ilp[e];
-            c.src = source(M, oid);
-            c.src2 = c.src;
-            c.m2 = 0u;
-            c.base = (size_t)oid * op_stride + (size_t)rb0 * 64;
+        const int oid = ilp[NSRC * e];
+        c.src[0] = source(M, oid);
+#pragma unroll
+        for (int f = 1; f < NSRC; ++f) {
+            const int o2 = ilp[NSRC * e + f];
+            c.src[f] = o2 >= 0 ? source(Mflip + (f - 1) * fstride, o2) : zeros + kq;
         }
+        c.base = (size_t)oid * op_stride + (size_t)rb0 * 64;
     };
     auto advance = [&](Cursor &c) {
         if (++c.kc == NKC) set_t(c, c.t + 1);
@@ -503,19 +547,15 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
     const bool last_in = tid + 256 * (PC - 1) < CHUNK;
 
     // prologue: stage 0 into LDS buffer 0
-    R bcur[U], bcur2[PAIR ? U : 1];
-    uint32_t mcur[PAIR ? U : 1];
+    R bcur[U][NSRC];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
         for (int v = 0; v < PC - 1; ++v) lds[0][u * CHUNK + tid + 256 * v] = ops[pc.base + tid + 256 * v];
         const A x = ops[pc.base + e_last];
         if (last_in) lds[0][u * CHUNK + e_last] = x;
-        bcur[u] = frag_b(pc, pc.src);
-        if constexpr (PAIR) {
-            bcur2[u] = frag_b(pc, pc.src2);
-            mcur[u] = pc.m2;
-        }
+#pragma unroll
+        for (int f = 0; f < NSRC; ++f) bcur[u][f] = frag_b(pc, pc.src[f]);
         advance(pc);
     }
     // drain every prologue load: otherwise the compiler's wait bookkeeping
@@ -527,18 +567,14 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
         const int cur = st & 1;
         // prefetch the next stage (past the end: harmless re-reads)
         A pre[U][PC];
-        R bnext[U], bnext2[PAIR ? U : 1];
-        uint32_t mnext[PAIR ? U : 1];
+        R bnext[U][NSRC];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll
             for (int v = 0; v < PC - 1; ++v) pre[u][v] = ops[pc.base + tid + 256 * v];
             pre[u][PC - 1] = ops[pc.base + e_last];
-            bnext[u] = frag_b(pc, pc.src);
-            if constexpr (PAIR) {
-                bnext2[u] = frag_b(pc, pc.src2);
-                mnext[u] = pc.m2;
-            }
+#pragma unroll
+            for (int f = 0; f < NSRC; ++f) bnext[u][f] = frag_b(pc, pc.src[f]);
             // compiler-only barrier: keeps the loads above the cursor update
             // (otherwise they are sunk below its branch, towards their use)
             asm volatile("" ::: "memory");
@@ -557,21 +593,29 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
             // fragments are twice as large: there the compiler's interleaving
             // of reads and MFMAs is kept, measured faster)
             if constexpr (sizeof(A) == 16) __builtin_amdgcn_sched_barrier(0);
-            if constexpr (PAIR) {
-                // v1 = b + D b2 feeds the even-degree rows, v2 = b - D b2 the odd
+            if constexpr (SYM == 0) {
+                const B b = P::to_b(bcur[u][0]);
+#pragma unroll
+                for (int rb = 0; rb < NRB; ++rb) acc[rb] = P::mma(a[rb], b, acc[rb]);
+            } else {
+                // the class combinations sum_s chi(s) D_s M_s of the entry:
+                // pairs: w0 +- w1; orbits: (w0 +- w1) + (w2 +- w3) for the
+                // first class of the half, (w0 +- w1) - (w2 +- w3) for the second
                 B v1, v2;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const S m = pick((S)bcur2[u][j], (S)0, mcur[u]);
-                    v1[j] = bcur[u][j] + m;
-                    v2[j] = bcur[u][j] - m;
+                    if constexpr (SYM == 1) {
+                        v1[j] = bcur[u][0][j] + bcur[u][1][j];
+                        v2[j] = bcur[u][0][j] - bcur[u][1][j];
+                    } else {
+                        const S x = SYM == 2 ? bcur[u][0][j] + bcur[u][1][j] : bcur[u][0][j] - bcur[u][1][j];
+                        const S y = SYM == 2 ? bcur[u][2][j] + bcur[u][3][j] : bcur[u][2][j] - bcur[u][3][j];
+                        v1[j] = x + y;
+                        v2[j] = x - y;
+                    }
                 }
 #pragma unroll
                 for (int rb = 0; rb < NRB; ++rb) acc[rb] = P::mma(a[rb], rb < NE ? v1 : v2, acc[rb]);
-            } else {
-                const B b = P::to_b(bcur[u]);
-#pragma unroll
-                for (int rb = 0; rb < NRB; ++rb) acc[rb] = P::mma(a[rb], b, acc[rb]);
             }
             if (++kc == NKC) {
                 kc = 0;
@@ -595,11 +639,8 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
 #pragma unroll
             for (int v = 0; v < PC - 1; ++v) lds[cur ^ 1][u * CHUNK + tid + 256 * v] = pre[u][v];
             if (last_in) lds[cur ^ 1][u * CHUNK + e_last] = pre[u][PC - 1];
-            bcur[u] = bnext[u];
-            if constexpr (PAIR) {
-                bcur2[u] = bnext2[u];
-                mcur[u] = mnext[u];
-            }
+#pragma unroll
+            for (int f = 0; f < NSRC; ++f) bcur[u][f] = bnext[u][f];
         }
         __syncthreads();
     }
@@ -611,84 +652,130 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int prow = 16 * (rb0 + rb) + Mfma<S>::row(lane, r);
-            const int row = PAIR ? rowmap[prow] : prow;
+            const int row = SYM != 0 ? rowmap[prow] : prow;
             if (row >= 0)
                 out[(size_t)tcell * Kp + row] = F64 ? (S)(hi[rb][r] + (double)acc[rb][r]) : (S)acc[rb][r];
         }
 }
 
-// Even-degree row blocks of the single row group of order p <= 12 with NRB
-// row blocks (NRB = m2l_row_blocks(p) determines it for those p; 0: none).
-constexpr int single_group_even_blocks(int nrb) {
-    constexpr int table[12] = {0, 1, 1, 1, 2, 2, 3, 3, 0, 5, 5, 6};
-    return nrb >= 0 && nrb < 12 ? table[nrb] : 0;
+// One launch of the LDS-shared kernel: operator rows [rb0, rb0 + nrb) in
+// blocks, the first ne blocks on the first source combination, kernel
+// variant sym (see k_m2l_lds).
+struct RowGroup {
+    int rb0, nrb, ne, sym;
+};
+
+// Row groups of the class-ordered operators of order p (scheme 1 or 2), or of
+// plain storage-ordered operators with NB row blocks (scheme 0).  A group
+// holds at most kRowBlocksPerWave blocks and one or two classes of the same
+// half (the two classes that share the partial sums w0 +- w1 and w2 +- w3).
+static int row_groups(int scheme, int p, int NB, RowGroup *g) {
+    int ng = 0;
+    auto chunks = [&](int from, int n, bool first, int sym) {
+        for (int r = 0; r < n; r += kRowBlocksPerWave) {
+            const int k = std::min(kRowBlocksPerWave, n - r);
+            g[ng++] = RowGroup{from + r, k, first ? k : 0, sym};
+        }
+    };
+    if (scheme == 0) {
+        chunks(0, NB, false, 0);
+        return ng;
+    }
+    int b[4];
+    const int nc = m2l_class_blocks(p, b);
+    int at = 0;
+    for (int h = 0; h < nc / 2; ++h) {
+        const int c0 = b[2 * h], c1 = b[2 * h + 1], sym = scheme == 1 ? 1 : 2 + h;
+        if (c0 + c1 == 0) continue;
+        if (c0 + c1 <= kRowBlocksPerWave) {
+            g[ng++] = RowGroup{at, c0 + c1, c0, sym};
+        } else {
+            chunks(at, c0, true, sym);
+            chunks(at + c0, c1, false, sym);
+        }
+        at += c0 + c1;
+    }
+    return ng;
 }
 
-// Launches the LDS-shared kernel for every row group (NRB, U and the group's
-// even-degree block count fixed at compile time).  Row groups hold up to
-// kRowBlocksPerWave blocks; with the paired list an order whose rows do not
-// fit one group gets groups of even-degree blocks and groups of odd-degree
-// blocks, so that no group mixes them at a position other than the one of
-// single_group_even_blocks.
+// Launches the LDS-shared kernel for every row group (NRB, U, NE and the
+// variant fixed at compile time; combinations outside the instantiated set --
+// all orders 0..20 of both schemes are covered -- give hipErrorInvalidValue).
 template <typename P>
 static hipError_t launch_lds(const void *ops, const int32_t *il, const int32_t *offs, const int32_t *rowmap,
-                             const typename P::S *M, const typename P::S *Mneg, typename P::S *out, int nh_bits,
-                             int NB, int NKC, int Kp, int nslices, int ne_blocks, hipStream_t s) {
+                             const typename P::S *M, const typename P::S *Mflip, const typename P::S *zeros,
+                             int64_t fstride, typename P::S *out, int nh_bits, int NB, int NKC, int Kp, int nslices,
+                             const RowGroup *groups, int ng, hipStream_t s) {
     using A = typename P::A;
-    if (P::kPaired && NKC > 32) return hipErrorInvalidValue;  // column parity bits: two 64-bit words
-    struct Group {
-        int rb0, nrb, ne;
-    };
-    Group groups[16];
-    int ng = 0;
-    auto add = [&](int from, int to, bool even) {
-        for (int r = from; r < to; r += kRowBlocksPerWave) {
-            if (ng == 16) return false;
-            const int n = std::min(kRowBlocksPerWave, to - r);
-            groups[ng++] = Group{r, n, even ? n : 0};
-        }
-        return true;
-    };
-    if (!P::kPaired) {
-        if (!add(0, NB, false)) return hipErrorInvalidValue;
-    } else if (NB <= kRowBlocksPerWave) {
-        if (ne_blocks != single_group_even_blocks(NB)) return hipErrorInvalidValue;
-        groups[ng++] = Group{0, NB, ne_blocks};
-    } else if (!add(0, ne_blocks, true) || !add(ne_blocks, NB, false)) {
-        return hipErrorInvalidValue;
-    }
     const int64_t ntile = (((int64_t)1 << (3 * nh_bits)) + 63) / 64;
     const int64_t grid = 8 * ntile * nslices;
     const A *o = reinterpret_cast<const A *>(ops);
     for (int gi = 0; gi < ng; ++gi) {
-        const int rb0 = groups[gi].rb0, nrb = groups[gi].nrb, ne = groups[gi].ne;
-        switch (nrb) {
-#define FMM_M2L_LDS_LAUNCH(N, NE)                                                                              \
-    if (nslices > 1)                                                                                           \
-        hipLaunchKernelGGL((k_m2l_lds<P, true, N, stage_chunks<P, N>(), NE>), dim3((unsigned)grid), dim3(256), \
-                           0, s, o, il, offs, rowmap, M, Mneg, out, nh_bits, NB, NKC, Kp, rb0, nslices);            \
-    else                                                                                                       \
-        hipLaunchKernelGGL((k_m2l_lds<P, false, N, stage_chunks<P, N>(), NE>), dim3((unsigned)grid),          \
-                           dim3(256), 0, s, o, il, offs, rowmap, M, Mneg, out, nh_bits, NB, NKC, Kp, rb0, 1);
-#define FMM_M2L_LDS_CASE(N)                                                                                    \
-    case N:                                                                                                    \
-        if (!P::kPaired || ne == 0) {                                                                          \
-            FMM_M2L_LDS_LAUNCH(N, 0)                                                                           \
-        } else if (ne == N) {                                                                                  \
-            FMM_M2L_LDS_LAUNCH(N, N)                                                                           \
-        } else if (ne == single_group_even_blocks(N)) {                                                        \
-            FMM_M2L_LDS_LAUNCH(N, single_group_even_blocks(N))                                                 \
-        } else {                                                                                               \
-            return hipErrorInvalidValue;                                                                       \
-        }                                                                                                      \
-        break;
-            FMM_M2L_LDS_CASE(1) FMM_M2L_LDS_CASE(2) FMM_M2L_LDS_CASE(3) FMM_M2L_LDS_CASE(4)
-            FMM_M2L_LDS_CASE(5) FMM_M2L_LDS_CASE(6) FMM_M2L_LDS_CASE(7) FMM_M2L_LDS_CASE(8)
-            FMM_M2L_LDS_CASE(9) FMM_M2L_LDS_CASE(10) FMM_M2L_LDS_CASE(11)
+        const int rb0 = groups[gi].rb0, nrb = groups[gi].nrb, ne = groups[gi].ne, sym = groups[gi].sym;
+        if ((sym == 0) != !P::kPaired) return hipErrorInvalidValue;
+        bool launched = false;
+#define FMM_M2L_LDS_LAUNCH(SYM, N, NE)                                                                          \
+    if (nslices > 1)                                                                                            \
+        hipLaunchKernelGGL((k_m2l_lds<P, true, N, stage_chunks<P, N>(), NE, SYM>), dim3((unsigned)grid),       \
+                           dim3(256), 0, s, o, il, offs, rowmap, M, Mflip, zeros, fstride, out, nh_bits, NB, NKC, \
+                           Kp, rb0, nslices);                                                                   \
+    else                                                                                                        \
+        hipLaunchKernelGGL((k_m2l_lds<P, false, N, stage_chunks<P, N>(), NE, SYM>), dim3((unsigned)grid),      \
+                           dim3(256), 0, s, o, il, offs, rowmap, M, Mflip, zeros, fstride, out, nh_bits, NB, NKC, \
+                           Kp, rb0, 1);
+#define FMM_M2L_LDS_CASE(SYM, N, NE)                                                                            \
+    if (!launched && sym == SYM && nrb == N && ne == NE && (SYM == 0) == !P::kPaired) {                        \
+        if constexpr ((SYM == 0) == !P::kPaired) {                                                              \
+            FMM_M2L_LDS_LAUNCH(SYM, N, NE)                                                                      \
+        }                                                                                                       \
+        launched = true;                                                                                        \
+    }
+        FMM_M2L_LDS_CASE(0, 1, 0)
+        FMM_M2L_LDS_CASE(0, 2, 0)
+        FMM_M2L_LDS_CASE(0, 3, 0)
+        FMM_M2L_LDS_CASE(0, 4, 0)
+        FMM_M2L_LDS_CASE(0, 5, 0)
+        FMM_M2L_LDS_CASE(0, 6, 0)
+        FMM_M2L_LDS_CASE(0, 7, 0)
+        FMM_M2L_LDS_CASE(0, 8, 0)
+        FMM_M2L_LDS_CASE(0, 9, 0)
+        FMM_M2L_LDS_CASE(0, 10, 0)
+        FMM_M2L_LDS_CASE(0, 11, 0)
+        FMM_M2L_LDS_CASE(1, 1, 1)
+        FMM_M2L_LDS_CASE(1, 2, 1)
+        FMM_M2L_LDS_CASE(1, 3, 1)
+        FMM_M2L_LDS_CASE(1, 4, 2)
+        FMM_M2L_LDS_CASE(1, 5, 2)
+        FMM_M2L_LDS_CASE(1, 6, 3)
+        FMM_M2L_LDS_CASE(1, 7, 3)
+        FMM_M2L_LDS_CASE(1, 9, 5)
+        FMM_M2L_LDS_CASE(1, 10, 5)
+        FMM_M2L_LDS_CASE(1, 11, 6)
+        FMM_M2L_LDS_CASE(2, 2, 1)
+        FMM_M2L_LDS_CASE(2, 4, 2)
+        FMM_M2L_LDS_CASE(2, 6, 3)
+        FMM_M2L_LDS_CASE(2, 8, 4)
+        FMM_M2L_LDS_CASE(2, 10, 5)
+        FMM_M2L_LDS_CASE(2, 1, 1)
+        FMM_M2L_LDS_CASE(2, 1, 0)
+        FMM_M2L_LDS_CASE(2, 6, 6)
+        FMM_M2L_LDS_CASE(2, 6, 0)
+        FMM_M2L_LDS_CASE(2, 7, 7)
+        FMM_M2L_LDS_CASE(2, 7, 0)
+        FMM_M2L_LDS_CASE(3, 2, 1)
+        FMM_M2L_LDS_CASE(3, 4, 2)
+        FMM_M2L_LDS_CASE(3, 6, 3)
+        FMM_M2L_LDS_CASE(3, 8, 4)
+        FMM_M2L_LDS_CASE(3, 10, 5)
+        FMM_M2L_LDS_CASE(3, 1, 1)
+        FMM_M2L_LDS_CASE(3, 1, 0)
+        FMM_M2L_LDS_CASE(3, 6, 6)
+        FMM_M2L_LDS_CASE(3, 6, 0)
+        FMM_M2L_LDS_CASE(3, 7, 7)
+        FMM_M2L_LDS_CASE(3, 7, 0)
 #undef FMM_M2L_LDS_CASE
 #undef FMM_M2L_LDS_LAUNCH
-            default: return hipErrorInvalidValue;
-        }
+        if (!launched) return hipErrorInvalidValue;
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -772,8 +859,10 @@ hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const 
     const int NB = Kp / 16;
     const int nh_bits = level - 1;
     const int nslices = partial ? m2l_slices(level) : 1;
-    hipError_t e = launch_lds<PolBf16>(ops, il, offs, nullptr, M, M, nslices > 1 ? partial : L, nh_bits, NB,
-                                       bf16_chunks(p), Kp, nslices, 0, s);
+    RowGroup grp[kMaxRowGroups];
+    const int ng = row_groups(0, p, NB, grp);
+    hipError_t e = launch_lds<PolBf16>(ops, il, offs, nullptr, M, M, M, 0, nslices > 1 ? partial : L, nh_bits, NB,
+                                       bf16_chunks(p), Kp, nslices, grp, ng, s);
     if (e != hipSuccess || nslices == 1) return e;
     const int64_t elems = ((int64_t)8 << (3 * nh_bits)) * Kp;
     int64_t g = (elems + 255) / 256;
@@ -782,40 +871,57 @@ hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const 
     return hipGetLastError();
 }
 
-// Mneg[c][k] = (-1)^n(k) M[c][k] (n(k) the degree of coefficient k): the
-// multipoles as the paired kernel reads them for the offset -t of a pair.
+// Sign-flipped copies of the level's multipoles, Mflip[f][c][k] =
+// sigma(k) M[c][k] for the group elements of the scheme's list entries:
+// scheme 1 one copy, (-1)^n (t -> -t); scheme 2 three copies, for the flips
+// (-,-,+): (-1)^m, (-,+,-): (-1)^n (-1 for an imaginary part),
+// (+,-,-): (-1)^(n+m) (-1 for an imaginary part).
+__device__ inline int flip_sign(int scheme, int f, int k) {
+    int n = (int)sqrtf((float)k);
+    if (n * n > k) --n;
+    if ((n + 1) * (n + 1) <= k) ++n;
+    const int r = k - n * n, m = (r + 1) >> 1;
+    const int im = (r > 0 && (r & 1) == 0) ? 1 : 0;
+    if (scheme == 1) return (n & 1) ? -1 : 1;
+    const int odd = f == 0 ? (m & 1) : (f == 1 ? ((n & 1) ^ im) : (((n + m) & 1) ^ im));
+    return odd ? -1 : 1;
+}
+
 template <typename T>
-__global__ void k_m2l_flip(const T *__restrict__ M, T *__restrict__ Mneg, int64_t n, int Kp) {
+__global__ void k_m2l_flip(const T *__restrict__ M, T *__restrict__ Mflip, int64_t n, int Kp, int scheme,
+                           int ncopy) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int k = (int)(i % Kp);
-        int d = (int)sqrtf((float)k);
-        if (d * d > k) --d;
-        if ((d + 1) * (d + 1) <= k) ++d;
-        Mneg[i] = (d & 1) ? -M[i] : M[i];
+        const T v = M[i];
+        for (int f = 0; f < ncopy; ++f) Mflip[(size_t)f * n + i] = flip_sign(scheme, f, k) < 0 ? -v : v;
     }
 }
 
 // The full interaction list (nil == 875) runs on the LDS-shared kernel with
-// the paired entries (Mneg: scratch for the level's sign-flipped multipoles,
-// cells x Kp); the aliased lists of levels 1 and 2 (nil = 8 or 64 pre-summed
-// operators) on the offset-split kernel.
+// the symmetry-folded entries of m2l_scheme(p); the aliased lists of levels 1
+// and 2 (nil = 8 or 64 pre-summed operators) on the offset-split kernel.
 template <typename T>
 hipError_t launch_m2l(int level, const T *ops, const int32_t *list, const int32_t *offs, const int32_t *rowmap,
-                      const T *M, T *Mneg, T *L, T *partial, int p, int Kp, hipStream_t s, int nil) {
+                      const T *M, T *Mflip, const T *zeros, T *L, T *partial, int p, int Kp, hipStream_t s, int nil) {
     constexpr int CB = Mfma<T>::CB;
     const int NB = Kp / 16;
     const int nh_bits = level - 1;
     const int64_t ntarget = (int64_t)1 << (3 * nh_bits);
     const int nslices = partial ? std::min(m2l_slices(level), nil) : 1;
     if (nil == kILSize) {
-        if (!rowmap || !Mneg) return hipErrorInvalidValue;
+        if (!rowmap || !Mflip || !zeros) return hipErrorInvalidValue;
+        const int scheme = m2l_scheme(p);
+        if (scheme == 1 && m2l_row_blocks(p) > kRowBlocksPerWave) return hipErrorInvalidValue;
         const int64_t n = ((int64_t)8 << (3 * nh_bits)) * Kp;
         int64_t g = (n + 255) / 256;
         if (g > 65535) g = 65535;
-        hipLaunchKernelGGL(k_m2l_flip<T>, dim3((unsigned)g), dim3(256), 0, s, M, Mneg, n, Kp);
-        const hipError_t e = launch_lds<PolMfma<T>>(ops, list, offs, rowmap, M, Mneg, nslices > 1 ? partial : L,
-                                                     nh_bits, m2l_row_blocks(p), NB, Kp, nslices, m2l_even_blocks(p),
-                                                     s);
+        hipLaunchKernelGGL(k_m2l_flip<T>, dim3((unsigned)g), dim3(256), 0, s, M, Mflip, n, Kp, scheme,
+                           m2l_flip_copies(p));
+        RowGroup grp[kMaxRowGroups];
+        const int ng = row_groups(scheme, p, m2l_row_blocks(p), grp);
+        const hipError_t e = launch_lds<PolMfma<T>>(ops, list, offs, rowmap, M, Mflip, zeros, n,
+                                                     nslices > 1 ? partial : L, nh_bits, m2l_row_blocks(p), NB, Kp,
+                                                     nslices, grp, ng, s);
         if (e != hipSuccess) return e;
     } else {
         int R = 1;
@@ -836,8 +942,10 @@ hipError_t launch_m2l(int level, const T *ops, const int32_t *list, const int32_
     return hipGetLastError();
 }
 template hipError_t launch_m2l<float>(int, const float *, const int32_t *, const int32_t *, const int32_t *,
-                                      const float *, float *, float *, float *, int, int, hipStream_t, int);
+                                      const float *, float *, const float *, float *, float *, int, int, hipStream_t,
+                                      int);
 template hipError_t launch_m2l<double>(int, const double *, const int32_t *, const int32_t *, const int32_t *,
-                                       const double *, double *, double *, double *, int, int, hipStream_t, int);
+                                       const double *, double *, const double *, double *, double *, int, int,
+                                       hipStream_t, int);
 
 }  // namespace fmm
