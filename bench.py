@@ -38,6 +38,8 @@ M2L_IL = 875  # interaction-list size per cell
 # scheme 1 folds the (t, -t) pairs (302 pairs + 271 singles), scheme 2 the
 # orbits of the two-axis flips (305 orbits of 1 to 4 offsets)
 M2L_ENTRIES = {1: 573, 2: 305}
+PEAK_TFLOPS = {"mixed": 157.3, "bf16": 2500.0, "fp64": 78.6}  # dense MFMA peaks of MI355X (FP32, BF16, FP64)
+PREC_NAMES = {"fp64": 0, "mixed": 1, "bf16": 2}
 
 
 def _row_class(scheme, k):
