@@ -73,3 +73,18 @@ def test_plan_without_gpu_reports_device_error():
     st = lib.fmm_plan(10.0, 3, 4, ctypes.byref(h))
     assert st == -3  # FMM_ERR_DEVICE
     assert "device" in lib.fmm_last_error(None).decode()
+
+
+def test_bench_cli_single_gpu_only():
+    # bench.py imports and parses on a machine without a GPU, and refuses a
+    # multi-GPU run with a message (this build runs on one GPU)
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--help"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0 and "--uv-scheme" in r.stdout
