@@ -33,54 +33,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 M2L_IL = 875  # interaction-list size per cell
-# list entries per cell of the FP32/FP64 kernel under the two symmetry schemes
-# of the library (operators of reflected offsets differ by signs only):
-# scheme 1 folds the (t, -t) pairs (302 pairs + 271 singles), scheme 2 the
-# orbits of the two-axis flips (305 orbits of 1 to 4 offsets)
-M2L_ENTRIES = {1: 573, 2: 305}
 PEAK_TFLOPS = {"mixed": 157.3, "bf16": 2500.0, "fp64": 78.6}  # dense MFMA peaks of MI355X (FP32, BF16, FP64)
 PREC_NAMES = {"fp64": 0, "mixed": 1, "bf16": 2}
 
 
-def _row_class(scheme, k):
-    n = int(math.isqrt(k))
-    r = k - n * n
-    m, im = (r + 1) // 2, r > 0 and r % 2 == 0
-    return n & 1 if scheme == 1 else 2 * (m & 1) + ((n & 1) ^ int(im))
-
-
-def _class_blocks(p, scheme):
-    K = (p + 1) ** 2
-    counts = [0] * (2 if scheme == 1 else 4)
-    for k in range(K):
-        counts[_row_class(scheme, k)] += 1
-    return [(c + 15) // 16 for c in counts]
-
-
-def m2l_scheme(p):
-    """The scheme the library picks for order p: the one with fewer entries x
-    padded row blocks (its rule in m2l_scheme, k_m2l.hip)."""
-    return 2 if M2L_ENTRIES[2] * sum(_class_blocks(p, 2)) < M2L_ENTRIES[1] * sum(_class_blocks(p, 1)) else 1
-
-
-def leaf_kernel(prec_name, p):
-    """Name of the finest-level M2L kernel (first row group) for this order."""
+def leaf_kernel(prec_name, info):
+    """Name of the finest-level M2L kernel; info = fmm_plan_info of the plan.
+    The FP32/FP64 kernel takes the symmetry-folded list (pairs or orbits of
+    reflected offsets) in info["m2l_launches"] launches (row-class groups)."""
     if prec_name == "bf16":
         return "k_m2l_bf16<false>"
     t = "double" if prec_name == "fp64" else "float"
-    if m2l_scheme(p) == 2:
-        b = _class_blocks(p, 2)
-        nrb = min(11, b[0] + b[1])
-        return f"k_m2l_lds<{t}, false, {nrb}> x2 (row-class halves)"
-    return f"k_m2l_lds<{t}, false, {min(11, sum(_class_blocks(p, 1)))}>"
+    kind = "orbit" if info["m2l_scheme"] == 2 else "pair"
+    return f"k_m2l_lds<{t}, false> x{info['m2l_launches']} ({kind} list, {info['m2l_entries']} entries)"
 
 
-def m2l_flops(p, level, prec_name="mixed"):
-    """Algorithmic M2L flops of one level: 2 K^2 per (target, list entry); the
-    FP32/FP64 kernels take one symmetry-folded entry as one operator product,
-    the BF16 kernel every offset."""
+def m2l_entries(prec_name, info):
+    return M2L_IL if prec_name == "bf16" else info["m2l_entries"]
+
+
+def m2l_flops(p, level, entries):
+    """Algorithmic M2L flops of one level: 2 K^2 per (target, list entry), an
+    entry being one operator product (an offset for the BF16 kernel, a folded
+    pair or orbit of offsets for the FP32/FP64 kernel)."""
     K = (p + 1) ** 2
-    entries = M2L_IL if prec_name == "bf16" else M2L_ENTRIES[m2l_scheme(p)]
     return 2.0 * K * K * entries * 8 ** level
 
 
@@ -177,17 +153,19 @@ def run_single(args, w, p, prec_name, steps, warmup, fp64_leg, cpu_leg):
 
     # dominant kernel: M2L at the finest level; algorithmic flops per launch
     # divided by its event-timed average duration on the plan's stream
-    flops_leaf = m2l_flops(p, w.levels, prec_name)
+    info = F.fmm_plan_info(plan)
+    entries = m2l_entries(prec_name, info)
+    flops_leaf = m2l_flops(p, w.levels, entries)
     m2l_ms = st["m2l_leaf"]
     achieved = flops_leaf / (m2l_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec_name]
-    kernel = leaf_kernel(prec_name, p)
+    kernel = leaf_kernel(prec_name, info)
     workload = f"{w.name} levels {w.levels} p {p}"
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": recorded_traffic(kernel, workload),
                 "kernel": f"{kernel} (M2L, level {w.levels})", "avg_ms": round(m2l_ms, 4),
-                "flops_per_launch": flops_leaf,
-                "list_entries_per_cell": M2L_IL if prec_name == "bf16" else M2L_ENTRIES[m2l_scheme(p)]}
+                "flops_per_level": flops_leaf,
+                "list_entries_per_cell": entries}
     desc = {"C3": "333,333 waters + one -1 ion", "C5": "1,000,000 waters + 8 ions (net +3)"}.get(w.name, w.name)
     metric = ("atom-evals/s (energy+forces) at 1M atoms, mixed vs FP64 FMM, rel err <=1e-5" if w.name == "C3"
               else f"atom-evals/s (energy+forces) on {w.name} ({w.n} atoms)")

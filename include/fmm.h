@@ -320,6 +320,22 @@ enum {
 fmm_status fmm_profile(fmm_plan_t plan, int enable);
 fmm_status fmm_profile_read(fmm_plan_t plan, double *ms, int64_t *calls);
 
+/*
+ * fmm_plan_info -- layout facts of a plan, for tools and benchmarks.
+ * Writes min(n, FMM_INFO_COUNT) int64 values to info (host):
+ *   [0] levels (0 for a batch plan: see fmm_batch_levels)   [1] p
+ *   [2] K = (p+1)^2   [3] Kp (K padded to 16)   [4] precision mode
+ *   [5] symmetry folding of the FP32/FP64 M2L interaction lists:
+ *       1 = (t, -t) pairs, 2 = orbits of the two-axis flips (the operators of
+ *       reflected offsets differ by signs only, so each pair or orbit is one
+ *       operator product per row class)
+ *   [6] M2L list entries per cell under that folding (573 or 305; the BF16
+ *       M2L always takes the 875 offsets)
+ *   [7] launches of the M2L kernel per full-list level
+ */
+#define FMM_INFO_COUNT 8
+fmm_status fmm_plan_info(fmm_plan_t plan, int64_t *info, int n);
+
 /* Message of the last failed call on this plan (never NULL; "" if none).
  * fmm_last_error(NULL) reports failures of fmm_plan itself. */
 const char *fmm_last_error(fmm_plan_t plan);

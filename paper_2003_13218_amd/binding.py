@@ -33,7 +33,7 @@ EXPORTED = (
     "fmm_potential_parts", "fmm_bin", "fmm_lattice_tensor", "fmm_profile", "fmm_profile_read",
     "fmm_last_error", "fmm_destroy", "fmm_version", "fmm_plan_batch", "fmm_energy_forces_batch",
     "fmm_solute_solvent_energy_batch", "fmm_autotune_batch", "fmm_batch_levels", "fmm_lambda_energy",
-    "fmm_lambda_energy_batch", "fmm_plan_options", "fmm_plan_softcore",
+    "fmm_lambda_energy_batch", "fmm_plan_options", "fmm_plan_softcore", "fmm_plan_info",
 )
 
 STAGES = ("sort", "gather", "p2m", "m2m", "lattice", "m2l", "m2l_leaf", "l2l", "l2p", "p2p", "final", "total")
@@ -66,6 +66,8 @@ def load():
         lib.fmm_plan_options.restype = ci
         lib.fmm_plan_softcore.argtypes = [vp, dbl, dbl, ci]
         lib.fmm_plan_softcore.restype = ci
+        lib.fmm_plan_info.argtypes = [vp, vp, ci]
+        lib.fmm_plan_info.restype = ci
         lib.fmm_energy_forces.argtypes = [vp, i64, vp, vp, ctypes.POINTER(dbl), vp, vp]
         lib.fmm_energy_forces.restype = ci
         lib.fmm_solute_solvent_energy.argtypes = [vp, vp, ctypes.POINTER(dbl)]
@@ -166,6 +168,17 @@ def fmm_plan_config(plan: Plan, precision: int = FMM_FP64, kappa: float = 0.0, s
 
 def fmm_plan_options(plan: Plan, boundary: int = FMM_BOUNDARY_CONDUCTING, uv_scheme: int = FMM_UV_SYMMETRIC):
     _check(load().fmm_plan_options(plan.handle, int(boundary), int(uv_scheme)), plan)
+
+
+INFO_KEYS = ("levels", "p", "K", "Kp", "precision", "m2l_scheme", "m2l_entries", "m2l_launches")
+
+
+def fmm_plan_info(plan: Plan) -> dict:
+    """Layout facts of a plan (see include/fmm.h), as a dict."""
+    import numpy as np
+    v = np.zeros(len(INFO_KEYS), dtype=np.int64)
+    _check(load().fmm_plan_info(plan.handle, v.ctypes.data_as(ctypes.c_void_p), len(INFO_KEYS)), plan)
+    return {k: int(x) for k, x in zip(INFO_KEYS, v)}
 
 
 def fmm_plan_softcore(plan: Plan, alpha: float, sigma: float = 1.0, c: int = 6):

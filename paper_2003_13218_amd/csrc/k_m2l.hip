@@ -84,14 +84,33 @@ static int scheme_blocks(int p, int scheme) {
     for (int c = 0; c < (scheme == 1 ? 2 : 4); ++c) b += (class_rows(p, scheme, c) + 15) / 16;
     return b;
 }
+// launches of the finest level: one per half of the classes (the two classes
+// sharing their partial sums), split into groups of at most 11 row blocks
+static int scheme_launches(int p, int scheme) {
+    int n = 0;
+    for (int h = 0; h < (scheme == 1 ? 1 : 2); ++h) {
+        const int c0 = (class_rows(p, scheme, 2 * h) + 15) / 16, c1 = (class_rows(p, scheme, 2 * h + 1) + 15) / 16;
+        if (c0 + c1 == 0) continue;
+        n += c0 + c1 <= 11 ? 1 : (c0 + 10) / 11 + (c1 + 10) / 11;
+    }
+    return n;
+}
+// The scheme with the smaller cost entries x (row blocks + multipole
+// fragments loaded per chunk over all launches): each launch gathers every
+// source of an entry (2 for pairs, 4 for orbits) for each column chunk.  On
+// the 3M-atom box this picks the pairs at p = 8 (41.8 vs 42.6 ms mixed, 71 vs
+// 79 ms FP64) and the orbits from p = 10 (84 vs 105 ms at p = 12).
 int m2l_scheme(int p) {
     static const int forced = [] {
         const char *v = std::getenv("FMM_M2L_SCHEME");
         return v ? std::atoi(v) : 0;
     }();
     if (forced == 1 || forced == 2) return forced;
-    return (int64_t)kM2LOrbitEntries * scheme_blocks(p, 2) < (int64_t)kM2LPairEntries * scheme_blocks(p, 1) ? 2 : 1;
+    const int64_t c1 = (int64_t)kM2LPairEntries * (scheme_blocks(p, 1) + 2 * scheme_launches(p, 1));
+    const int64_t c2 = (int64_t)kM2LOrbitEntries * (scheme_blocks(p, 2) + 4 * scheme_launches(p, 2));
+    return c2 < c1 ? 2 : 1;
 }
+int m2l_launches(int p) { return scheme_launches(p, m2l_scheme(p)); }
 int m2l_row_blocks(int p) { return scheme_blocks(p, m2l_scheme(p)); }
 int m2l_class_blocks(int p, int *blocks) {
     const int sch = m2l_scheme(p), nc = sch == 1 ? 2 : 4;

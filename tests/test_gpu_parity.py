@@ -111,6 +111,19 @@ def test_c1_fp64_forces_at_higher_order(fmm):
     assert rms_rel(ph.cpu().numpy(), o["phi"]) < 1e-6
 
 
+def test_plan_info_folding(fmm):
+    # the folding of the M2L lists the library reports: (t, -t) pairs below
+    # p = 9 except p = 7, orbits of the two-axis flips above; launches per level
+    expect = {4: (1, 573, 1), 7: (2, 305, 2), 8: (1, 573, 1), 12: (2, 305, 2), 16: (2, 305, 2), 20: (2, 305, 4)}
+    for p, (scheme, entries, launches) in expect.items():
+        plan = fmm.fmm_plan(10.0, 2, p)
+        info = fmm.fmm_plan_info(plan)
+        assert (info["p"], info["K"], info["Kp"]) == (p, (p + 1) ** 2, ((p + 1) ** 2 + 15) // 16 * 16)
+        assert (info["m2l_scheme"], info["m2l_entries"], info["m2l_launches"]) == (scheme, entries, launches), p
+        assert info["levels"] == 2
+        fmm.fmm_destroy(plan)
+
+
 @pytest.mark.parametrize("levels", [1, 2])
 def test_c1_mixed_shallow_trees(fmm, levels):
     # mixed mode on trees of 1 and 2 levels: the finest level is FP32 and takes
@@ -124,10 +137,11 @@ def test_c1_mixed_shallow_trees(fmm, levels):
     assert rms_rel(ph.cpu().numpy(), o["phi"]) < 1e-5
 
 
-@pytest.mark.parametrize("p,prec", [(13, 0), (14, 1), (20, 0)])
+@pytest.mark.parametrize("p,prec", [(7, 0), (9, 1), (13, 0), (14, 1), (20, 0)])
 def test_c1_orders_with_several_row_groups(fmm, p, prec):
-    # the M2L rows of these orders (196, 225 and 441 coefficients) do not fit
-    # one row group: even- and odd-degree rows run in groups of their own
+    # layouts of the folded M2L not met elsewhere: orbit lists with one row
+    # block per class (p = 7), two (9), four (13, 14: two launches of 8 blocks)
+    # and seven (20: 441 coefficients, four launches of one class each)
     w, o = ewald_full("C1")
     plan = _plan(fmm, w.box, w.levels, p, prec)
     e, f, ph = fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q), forces=True, phi=True)
