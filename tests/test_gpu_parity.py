@@ -142,11 +142,14 @@ def test_c1_orders_with_several_row_groups(fmm, p, prec):
     # layouts of the folded M2L not met elsewhere: orbit lists with one row
     # block per class (p = 7), two (9), four (13, 14: two launches of 8 blocks)
     # and seven (20: 441 coefficients, four launches of one class each)
+    # (tolerances: the truncation error at p = 7 is ~1.5e-7 in the energy; a
+    # wrong layout or sign would show as errors of order 1)
     w, o = ewald_full("C1")
     plan = _plan(fmm, w.box, w.levels, p, prec)
     e, f, ph = fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q), forces=True, phi=True)
-    tol = 1e-6 if prec == 0 else 1e-5
-    assert abs(e - o["terms"]["total"]) / abs(o["terms"]["total"]) < (1e-8 if prec == 0 else 1e-6)
+    tol = 1e-6 if (prec == 0 and p >= 12) else 1e-5
+    etol = 1e-8 if (prec == 0 and p >= 12) else 1e-6
+    assert abs(e - o["terms"]["total"]) / abs(o["terms"]["total"]) < etol
     assert rms_rel(f.cpu().numpy(), o["force"]) < tol
     assert rms_rel(ph.cpu().numpy(), o["phi"]) < tol
 
