@@ -331,7 +331,8 @@ fmm_status fmm_profile_read(fmm_plan_t plan, double *ms, int64_t *calls);
  *       operator product per row class)
  *   [6] M2L list entries per cell under that folding (573 or 305; the BF16
  *       M2L always takes the 875 offsets)
- *   [7] launches of the M2L kernel per full-list level
+ *   [7] launches of the M2L kernel per full-list level in the plan's
+ *       precision (the finest level: FP32 in the mixed modes)
  */
 #define FMM_INFO_COUNT 8
 fmm_status fmm_plan_info(fmm_plan_t plan, int64_t *info, int n);

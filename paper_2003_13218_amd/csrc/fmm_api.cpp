@@ -481,7 +481,8 @@ extern "C" fmm_status fmm_plan_info(fmm_plan_t pl, int64_t *info, int n) {
     if (!pl) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan_info: plan is NULL");
     if (n < 0 || (n > 0 && !info)) return fail(pl, FMM_ERR_INVALID, "fmm_plan_info: bad info array");
     const int64_t v[FMM_INFO_COUNT] = {pl->is_batch ? 0 : pl->levels, pl->p, pl->K, pl->Kp, pl->prec,
-                                       m2l_scheme(pl->p), m2l_list_entries(pl->p), m2l_launches(pl->p)};
+                                       m2l_scheme(pl->p), m2l_list_entries(pl->p),
+                                       m2l_launches(pl->p, pl->prec == FMM_FP64)};
     for (int i = 0; i < n && i < FMM_INFO_COUNT; ++i) info[i] = v[i];
     return FMM_OK;
 }

@@ -169,7 +169,7 @@ int m2l_row_blocks(int p);
 int m2l_class_blocks(int p, int *blocks /*4*/);
 int m2l_list_entries(int p);
 int m2l_list_width(int p);
-int m2l_launches(int p);  // launches of the LDS kernel for one full-list level
+int m2l_launches(int p, bool fp64);  // launches of the LDS kernel for one full-list level
 inline int m2l_flip_copies(int p) { return m2l_scheme(p) == 1 ? 1 : 3; }
 // map[16 * m2l_row_blocks] = storage row of each operator row (every row of
 // 0 .. Kp-1 once, the padding rows K .. Kp-1 on zero operator rows) or -1

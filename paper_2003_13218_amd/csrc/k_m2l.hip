@@ -35,6 +35,14 @@ namespace fmm {
 
 constexpr int kRowBlocksPerWave = 11;  // 176 rows: K <= 169 (p <= 12) in one row group
 constexpr int kMaxRowGroups = 16;
+// orbit lists whose four row classes fit this many blocks run in one launch
+// (the four source fragments gathered once for all classes)
+// FP32 orbit lists whose four row classes fit this many blocks run in one
+// launch, the four source fragments gathered once for all classes (measured on
+// the 1M-atom box, p = 12: 8.22 vs 8.42 ms for the level); FP64 keeps two
+// launches (one launch of 12 FP64 row blocks: 16.1 vs 14.5 ms)
+constexpr int kAllClassBlocks = 12;
+static bool one_launch(int blocks_per_class, bool fp64) { return !fp64 && 4 * blocks_per_class <= kAllClassBlocks; }
 
 // ---------------------------------------------------------------------------
 // Symmetries of the M2L operators.  Reflecting the translation in any set of
@@ -84,9 +92,16 @@ static int scheme_blocks(int p, int scheme) {
     for (int c = 0; c < (scheme == 1 ? 2 : 4); ++c) b += (class_rows(p, scheme, c) + 15) / 16;
     return b;
 }
-// launches of the finest level: one per half of the classes (the two classes
-// sharing their partial sums), split into groups of at most 11 row blocks
-static int scheme_launches(int p, int scheme) {
+// launches of a full-list level: one for all classes (FP32, small orders), or
+// one per half of the classes (the two classes sharing their partial sums),
+// split into groups of at most 11 row blocks
+static int scheme_launches(int p, int scheme, bool fp64) {
+    if (scheme == 2) {
+        const int b0 = (class_rows(p, 2, 0) + 15) / 16;
+        bool equal = true;
+        for (int c = 1; c < 4; ++c) equal = equal && (class_rows(p, 2, c) + 15) / 16 == b0;
+        if (equal && one_launch(b0, fp64)) return 1;
+    }
     int n = 0;
     for (int h = 0; h < (scheme == 1 ? 1 : 2); ++h) {
         const int c0 = (class_rows(p, scheme, 2 * h) + 15) / 16, c1 = (class_rows(p, scheme, 2 * h + 1) + 15) / 16;
@@ -106,11 +121,11 @@ int m2l_scheme(int p) {
         return v ? std::atoi(v) : 0;
     }();
     if (forced == 1 || forced == 2) return forced;
-    const int64_t c1 = (int64_t)kM2LPairEntries * (scheme_blocks(p, 1) + 2 * scheme_launches(p, 1));
-    const int64_t c2 = (int64_t)kM2LOrbitEntries * (scheme_blocks(p, 2) + 4 * scheme_launches(p, 2));
+    const int64_t c1 = (int64_t)kM2LPairEntries * (scheme_blocks(p, 1) + 2 * scheme_launches(p, 1, false));
+    const int64_t c2 = (int64_t)kM2LOrbitEntries * (scheme_blocks(p, 2) + 4 * scheme_launches(p, 2, false));
     return c2 < c1 ? 2 : 1;
 }
-int m2l_launches(int p) { return scheme_launches(p, m2l_scheme(p)); }
+int m2l_launches(int p, bool fp64) { return scheme_launches(p, m2l_scheme(p), fp64); }
 int m2l_row_blocks(int p) { return scheme_blocks(p, m2l_scheme(p)); }
 int m2l_class_blocks(int p, int *blocks) {
     const int sch = m2l_scheme(p), nc = sch == 1 ? 2 : 4;
@@ -477,6 +492,7 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
     using R = typename P::R;
     constexpr bool F64 = P::kFlush64;
     constexpr int NSRC = SYM == 0 ? 1 : (SYM == 1 ? 2 : 4);       // sources per list entry
+    static_assert(SYM != 4 || NRB == 4 * NE, "all four classes: NE blocks each");
     constexpr int NENT = SYM == 0 ? kILSize : (SYM == 1 ? kM2LPairEntries : kM2LOrbitEntries);
     constexpr int CHUNK = NRB * 64;             // fragments per chunk
     constexpr int PC = (CHUNK + 255) / 256;     // fragment loads per thread per chunk
@@ -616,6 +632,21 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
                 const B b = P::to_b(bcur[u][0]);
 #pragma unroll
                 for (int rb = 0; rb < NRB; ++rb) acc[rb] = P::mma(a[rb], b, acc[rb]);
+            } else if constexpr (SYM == 4) {
+                // all four classes of the orbit list (NE blocks each):
+                // (w0 + w1) +- (w2 + w3), (w0 - w1) +- (w2 - w3)
+                B v[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const S xp = bcur[u][0][j] + bcur[u][1][j], xm = bcur[u][0][j] - bcur[u][1][j];
+                    const S yp = bcur[u][2][j] + bcur[u][3][j], ym = bcur[u][2][j] - bcur[u][3][j];
+                    v[0][j] = xp + yp;
+                    v[1][j] = xp - yp;
+                    v[2][j] = xm + ym;
+                    v[3][j] = xm - ym;
+                }
+#pragma unroll
+                for (int rb = 0; rb < NRB; ++rb) acc[rb] = P::mma(a[rb], v[rb / NE], acc[rb]);
             } else {
                 // the class combinations sum_s chi(s) D_s M_s of the entry:
                 // pairs: w0 +- w1; orbits: (w0 +- w1) + (w2 +- w3) for the
@@ -688,7 +719,7 @@ struct RowGroup {
 // plain storage-ordered operators with NB row blocks (scheme 0).  A group
 // holds at most kRowBlocksPerWave blocks and one or two classes of the same
 // half (the two classes that share the partial sums w0 +- w1 and w2 +- w3).
-static int row_groups(int scheme, int p, int NB, RowGroup *g) {
+static int row_groups(int scheme, int p, int NB, bool fp64, RowGroup *g) {
     int ng = 0;
     auto chunks = [&](int from, int n, bool first, int sym) {
         for (int r = 0; r < n; r += kRowBlocksPerWave) {
@@ -702,6 +733,10 @@ static int row_groups(int scheme, int p, int NB, RowGroup *g) {
     }
     int b[4];
     const int nc = m2l_class_blocks(p, b);
+    if (nc == 4 && b[0] == b[1] && b[0] == b[2] && b[0] == b[3] && one_launch(b[0], fp64)) {
+        g[ng++] = RowGroup{0, 4 * b[0], b[0], 4};
+        return ng;
+    }
     int at = 0;
     for (int h = 0; h < nc / 2; ++h) {
         const int c0 = b[2 * h], c1 = b[2 * h + 1], sym = scheme == 1 ? 1 : 2 + h;
@@ -770,6 +805,9 @@ static hipError_t launch_lds(const void *ops, const int32_t *il, const int32_t *
         FMM_M2L_LDS_CASE(1, 9, 5)
         FMM_M2L_LDS_CASE(1, 10, 5)
         FMM_M2L_LDS_CASE(1, 11, 6)
+        FMM_M2L_LDS_CASE(4, 4, 1)
+        FMM_M2L_LDS_CASE(4, 8, 2)
+        FMM_M2L_LDS_CASE(4, 12, 3)
         FMM_M2L_LDS_CASE(2, 2, 1)
         FMM_M2L_LDS_CASE(2, 4, 2)
         FMM_M2L_LDS_CASE(2, 6, 3)
@@ -879,7 +917,7 @@ hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const 
     const int nh_bits = level - 1;
     const int nslices = partial ? m2l_slices(level) : 1;
     RowGroup grp[kMaxRowGroups];
-    const int ng = row_groups(0, p, NB, grp);
+    const int ng = row_groups(0, p, NB, false, grp);
     hipError_t e = launch_lds<PolBf16>(ops, il, offs, nullptr, M, M, M, 0, nslices > 1 ? partial : L, nh_bits, NB,
                                        bf16_chunks(p), Kp, nslices, grp, ng, s);
     if (e != hipSuccess || nslices == 1) return e;
@@ -937,7 +975,7 @@ hipError_t launch_m2l(int level, const T *ops, const int32_t *list, const int32_
         hipLaunchKernelGGL(k_m2l_flip<T>, dim3((unsigned)g), dim3(256), 0, s, M, Mflip, n, Kp, scheme,
                            m2l_flip_copies(p));
         RowGroup grp[kMaxRowGroups];
-        const int ng = row_groups(scheme, p, m2l_row_blocks(p), grp);
+        const int ng = row_groups(scheme, p, m2l_row_blocks(p), sizeof(T) == 8, grp);
         const hipError_t e = launch_lds<PolMfma<T>>(ops, list, offs, rowmap, M, Mflip, zeros, n,
                                                      nslices > 1 ? partial : L, nh_bits, m2l_row_blocks(p), NB, Kp,
                                                      nslices, grp, ng, s);

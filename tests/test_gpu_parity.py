@@ -112,15 +112,20 @@ def test_c1_fp64_forces_at_higher_order(fmm):
 
 
 def test_plan_info_folding(fmm):
-    # the folding of the M2L lists the library reports: (t, -t) pairs below
-    # p = 9 except p = 7, orbits of the two-axis flips above; launches per level
-    expect = {4: (1, 573, 1), 7: (2, 305, 2), 8: (1, 573, 1), 12: (2, 305, 2), 16: (2, 305, 2), 20: (2, 305, 4)}
-    for p, (scheme, entries, launches) in expect.items():
+    # the folding of the M2L lists the library reports: (t, -t) pairs for
+    # p = 1..4, orbits of the two-axis flips otherwise; launches per level in
+    # FP64 (two class halves, or more groups) and in the mixed mode (one launch
+    # for all four classes while they fit 12 row blocks)
+    expect = {4: (1, 573, 1, 1), 7: (2, 305, 2, 1), 8: (2, 305, 2, 1), 12: (2, 305, 2, 1), 16: (2, 305, 2, 2),
+              20: (2, 305, 4, 4)}
+    for p, (scheme, entries, l64, l32) in expect.items():
         plan = fmm.fmm_plan(10.0, 2, p)
         info = fmm.fmm_plan_info(plan)
         assert (info["p"], info["K"], info["Kp"]) == (p, (p + 1) ** 2, ((p + 1) ** 2 + 15) // 16 * 16)
-        assert (info["m2l_scheme"], info["m2l_entries"], info["m2l_launches"]) == (scheme, entries, launches), p
+        assert (info["m2l_scheme"], info["m2l_entries"], info["m2l_launches"]) == (scheme, entries, l64), p
         assert info["levels"] == 2
+        fmm.fmm_plan_config(plan, fmm.FMM_MIXED)
+        assert fmm.fmm_plan_info(plan)["m2l_launches"] == l32, p
         fmm.fmm_destroy(plan)
 
 
