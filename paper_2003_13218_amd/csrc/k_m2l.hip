@@ -853,20 +853,31 @@ __global__ void k_m2l_reduce(const T *__restrict__ partial, T *__restrict__ L, i
 // Slices per level: enough workgroups (>= ~512) to fill 256 CUs at two
 // resident workgroups each; levels >= 5 have enough targets on their own.
 int m2l_slices(int level) {
-    static const int leaf = [] {
-        const char *v = std::getenv("FMM_M2L_FINE_SLICES");
-        const int k = v ? std::atoi(v) : 0;
-        return (k == 1 || k == 2 || k == 4 || k == 8) ? k : 1;
+    // tuning: FMM_M2L_SLICES = "s1,s2,s3,s4,s5" overrides the slice counts of
+    // levels 1..5 (and deeper) with powers of two up to 64
+    static const std::vector<int> forced = [] {
+        std::vector<int> v;
+        if (const char *e = std::getenv("FMM_M2L_SLICES")) {
+            const char *c = e;
+            while (*c) {
+                const int k = std::atoi(c);
+                v.push_back((k >= 1 && k <= 64 && (k & (k - 1)) == 0) ? k : 0);
+                while (*c && *c != ',') ++c;
+                if (*c == ',') ++c;
+            }
+        }
+        return v;
     }();
+    const int i = std::min(level, 5) - 1;
+    if (i >= 0 && i < (int)forced.size() && forced[i] > 0) return forced[i];
     switch (level) {
         case 1: return 64;
         case 2: return 64;
         case 3: return 64;
         case 4: return 32;
-        default: return leaf;
+        default: return 1;
     }
 }
-
 
 // ---------------------------------------------------------------------------
 // M2L with BF16 operands (precision mode FMM_MIXED_BF16_M2L): the same
