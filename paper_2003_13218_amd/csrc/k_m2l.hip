@@ -35,8 +35,6 @@ namespace fmm {
 
 constexpr int kRowBlocksPerWave = 11;  // 176 rows: K <= 169 (p <= 12) in one row group
 constexpr int kMaxRowGroups = 16;
-// orbit lists whose four row classes fit this many blocks run in one launch
-// (the four source fragments gathered once for all classes)
 // FP32 orbit lists whose four row classes fit this many blocks run in one
 // launch, the four source fragments gathered once for all classes (measured on
 // the 1M-atom box, p = 12: 8.22 vs 8.42 ms for the level); FP64 keeps two
@@ -476,15 +474,25 @@ template <typename P, int NRB> constexpr int stage_chunks() {
 // the others the second (compile-time constants).  Sources: M for the entry's
 // first offset, the sign-flipped copies Mflip + f * fstride (D_s M of the
 // group element s of slot f + 1) for the others, zeros for an absent image.
+//
+// Occupancy: left to itself the compiler gives the FP32 all-classes variant
+// (12 row blocks: 48 FP32 accumulators, 96 FP64 ones, 48 operator fragment
+// registers) 256 VGPRs plus a few AGPRs, i.e. one wavefront per SIMD, and the
+// multipole gathers of a stage stall its matrix core.  Capped at 256 registers
+// (232 once the operator fragment reads interleave with the MFMAs, below) two
+// wavefronts per SIMD hide each other's waits: 8.2 -> 6.7 ms for the finest
+// level of the 1M-atom box.  The FP64 half-class variants stay at two wavefronts: squeezed
+// to three they spill inside the stage and lose (measured).
+template <typename P, int NRB, int SYM> constexpr int m2l_min_waves() {
+    return (sizeof(typename P::S) == 4 && SYM == 4 && NRB == 12) ? 2 : 1;
+}
+
 template <typename P, bool SPLIT, int NRB, int U, int NE, int SYM>
-__global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict__ ops,
-                                                 const int32_t *__restrict__ il, const int32_t *__restrict__ offs,
-                                                 const int32_t *__restrict__ rowmap,
-                                                 const typename P::S *__restrict__ M,
-                                                 const typename P::S *__restrict__ Mflip,
-                                                 const typename P::S *__restrict__ zeros, int64_t fstride,
-                                                 typename P::S *__restrict__ L, int nh_bits, int NB, int NKC, int Kp,
-                                                 int rb0, int nslices_arg) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_waves<P, NRB, SYM>()))) void k_m2l_lds(
+    const typename P::A *__restrict__ ops, const int32_t *__restrict__ il, const int32_t *__restrict__ offs,
+    const int32_t *__restrict__ rowmap, const typename P::S *__restrict__ M, const typename P::S *__restrict__ Mflip,
+    const typename P::S *__restrict__ zeros, int64_t fstride, typename P::S *__restrict__ L, int nh_bits, int NB,
+    int NKC, int Kp, int rb0, int nslices_arg) {
     using S = typename P::S;
     using A = typename P::A;
     using B = typename P::B;
@@ -626,8 +634,11 @@ __global__ __launch_bounds__(256) void k_m2l_lds(const typename P::A *__restrict
             for (int rb = 0; rb < NRB; ++rb) a[rb] = lds[cur][u * CHUNK + rb * 64 + lane];
             // all 16-byte fragment reads issued before the first MFMA (FP64
             // fragments are twice as large: there the compiler's interleaving
-            // of reads and MFMAs is kept, measured faster)
-            if constexpr (sizeof(A) == 16) __builtin_amdgcn_sched_barrier(0);
+            // of reads and MFMAs is kept, measured faster).  Not for the
+            // all-classes variant: its 12 fragments held at once would push it
+            // past 256 registers (spills), and at two wavefronts per SIMD the
+            // interleaved reads are hidden (6.62 -> 6.38 ms, 1M-atom leaf level)
+            if constexpr (sizeof(A) == 16 && SYM != 4) __builtin_amdgcn_sched_barrier(0);
             if constexpr (SYM == 0) {
                 const B b = P::to_b(bcur[u][0]);
 #pragma unroll
