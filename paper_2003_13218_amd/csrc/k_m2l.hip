@@ -606,11 +606,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
-    for (int st = 0; st < nstage; ++st) {
-        const int cur = st & 1;
+    // One stage: prefetch the next one (operators to registers, multipole
+    // fragments to bnext), run this one from LDS buffer cur and bcur, publish
+    // the prefetched operators in LDS buffer cur ^ 1.  The loop below calls it
+    // twice per iteration with the two fragment sets swapped, so no register
+    // copy moves bnext into bcur.
+    auto stage = [&](const int cur, R (&bcur)[U][NSRC], R (&bnext)[U][NSRC]) __attribute__((always_inline)) {
         // prefetch the next stage (past the end: harmless re-reads)
         A pre[U][PC];
-        R bnext[U][NSRC];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -700,10 +703,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
 #pragma unroll
             for (int v = 0; v < PC - 1; ++v) lds[cur ^ 1][u * CHUNK + tid + 256 * v] = pre[u][v];
             if (last_in) lds[cur ^ 1][u * CHUNK + e_last] = pre[u][PC - 1];
-#pragma unroll
-            for (int f = 0; f < NSRC; ++f) bcur[u][f] = bnext[u][f];
         }
         __syncthreads();
+    };
+    R bnext[U][NSRC];
+    for (int st = 0; st < nstage; st += 2) {
+        stage(0, bcur, bnext);
+        if (st + 1 == nstage) break;
+        stage(1, bnext, bcur);
     }
 
     if (!valid) return;
