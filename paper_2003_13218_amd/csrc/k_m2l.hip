@@ -515,7 +515,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
     const int slice = rest % nslices;
     const int tile = rest / nslices;
     const uint32_t ntarget = 1u << (3 * nh_bits);
-    const uint32_t nmask = (2u << nh_bits) - 1u;
 
     const uint32_t Pt = (uint32_t)tile * 64 + (uint32_t)wid * 16 + (lane & 15);
     const bool valid = Pt < ntarget;
@@ -540,11 +539,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
         size_t base;         // first fragment of the chunk
         const S *src[NSRC];  // this lane's coefficients of each source multipole
     };
+    // Source cells by dilated-integer addition: the target's Morton bits of
+    // one axis with every other bit set, plus the spread (10-bit two's
+    // complement) offset of that axis, carry through the other axes' bits; the
+    // axis mask keeps the level's bits, i.e. the sum mod 2^l (periodic wrap).
+    // The offsets are wave-uniform, so their spreading runs on the scalar unit.
+    const uint32_t lvl = (8u << (3 * nh_bits)) - 1u;
+    const uint32_t zm = 0x09249249u & lvl, ym = (0x09249249u << 1) & lvl, xm = (0x09249249u << 2) & lvl;
+    const uint32_t tdx = (spread3(tx) << 2) | ~xm, tdy = (spread3(ty) << 1) | ~ym, tdz = spread3(tz) | ~zm;
     auto source = [&](const S *base, int oid) {
-        const uint32_t sx = (tx + (uint32_t)offs[3 * oid]) & nmask;
-        const uint32_t sy = (ty + (uint32_t)offs[3 * oid + 1]) & nmask;
-        const uint32_t sz = (tz + (uint32_t)offs[3 * oid + 2]) & nmask;
-        return base + (size_t)morton3(sx, sy, sz) * Kp + kq;
+        const uint32_t cx = (tdx + (spread3((uint32_t)offs[3 * oid]) << 2)) & xm;
+        const uint32_t cy = (tdy + (spread3((uint32_t)offs[3 * oid + 1]) << 1)) & ym;
+        const uint32_t cz = (tdz + spread3((uint32_t)offs[3 * oid + 2])) & zm;
+        return base + (size_t)(cx | cy | cz) * Kp + kq;
     };
     auto set_t = [&](Cursor &c, int t) {
         c.t = t;
@@ -566,6 +573,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
     // the multipole fragment of the cursor's chunk: zero past the list (only
     // reachable inside a stage when U > 1) and past Kp (only for 32-wide
     // chunks, whose last one may stick out of the padded row)
+    // operator fragment i of the cursor's chunk: a wave-uniform chunk base
+    // plus a small per-lane byte offset, so the load takes the scalar base +
+    // 32-bit vector offset form and the chunk advance stays on the scalar unit
+    // (the empty asm keeps the offset's widening inside the loop body, where
+    // instruction selection can see it; hoisted, it became a 64-bit vector add
+    // per load)
+    auto op_frag = [&](const Cursor &c, int i) -> A {
+        const char *chunk = reinterpret_cast<const char *>(ops + c.base);
+        uint32_t off = (uint32_t)i * (uint32_t)sizeof(A);
+        asm volatile("" : "+v"(off));
+        return *reinterpret_cast<const A *>(chunk + off);
+    };
     auto frag_b = [&](const Cursor &c, const S *src) -> R {
         bool in = true;
         if constexpr (U > 1) in = c.t < t1;
@@ -594,8 +613,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
-        for (int v = 0; v < PC - 1; ++v) lds[0][u * CHUNK + tid + 256 * v] = ops[pc.base + tid + 256 * v];
-        const A x = ops[pc.base + e_last];
+        for (int v = 0; v < PC - 1; ++v) lds[0][u * CHUNK + tid + 256 * v] = op_frag(pc, tid + 256 * v);
+        const A x = op_frag(pc, e_last);
         if (last_in) lds[0][u * CHUNK + e_last] = x;
 #pragma unroll
         for (int f = 0; f < NSRC; ++f) bcur[u][f] = frag_b(pc, pc.src[f]);
@@ -617,8 +636,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll
-            for (int v = 0; v < PC - 1; ++v) pre[u][v] = ops[pc.base + tid + 256 * v];
-            pre[u][PC - 1] = ops[pc.base + e_last];
+            for (int v = 0; v < PC - 1; ++v) pre[u][v] = op_frag(pc, tid + 256 * v);
+            pre[u][PC - 1] = op_frag(pc, e_last);
 #pragma unroll
             for (int f = 0; f < NSRC; ++f) bnext[u][f] = frag_b(pc, pc.src[f]);
             // compiler-only barrier: keeps the loads above the cursor update
