@@ -26,7 +26,17 @@ namespace fmm {
 
 template <typename T> __device__ inline T rsqrt_t(T x);
 template <> __device__ inline float rsqrt_t<float>(float x) { return __builtin_amdgcn_rsqf(x); }
-template <> __device__ inline double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
+// FP64: the hardware estimate y0 of 1/sqrt(x), refined once in the series
+// 1/sqrt(x) = y0 (1 - e)^(-1/2) = y0 (1 + e/2 + 3 e^2/8 + ...), e = 1 - x y0^2
+// (Newton's step for the reciprocal square root with its second-order term):
+// the relative error falls from |e| to about 5|e|^3/16, below rounding for any
+// estimate good to 2^-18.  A correctly rounded 1/sqrt(x) (a square root and a
+// division) costs about three times as many instructions.
+template <> __device__ inline double rsqrt_t<double>(double x) {
+    const double y0 = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y0, y0, 1.0);
+    return fma(y0 * e, fma(0.375, e, 0.5), y0);
+}
 
 template <typename T> struct Vec4 { typedef T type __attribute__((ext_vector_type(4))); };
 
