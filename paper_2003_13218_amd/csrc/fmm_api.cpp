@@ -77,6 +77,8 @@ struct fmm_plan {
     double kappa = 0.0;
     hipStream_t stream = nullptr;
     hipStream_t side = nullptr;                      // near field, concurrent with the far field
+    hipStream_t side_up = nullptr;                   // upper M2L levels, concurrent with the lower ones
+    hipEvent_t ev_up_fork = nullptr, ev_up_join = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;  // main -> side after the repack, side -> main
     int device = 0;
     std::string err;
@@ -100,6 +102,7 @@ struct fmm_plan {
     DeviceBuf key, count, cursor, start, perm, scan, xq, xq_u, xs, Mlev, Llev, M0, L0, m2l_part;
     DeviceBuf pstart, xqp;  // near-field copy of xq, leaves padded to the P2P group count
     DeviceBuf mflip;        // sign-flipped multipoles of the level in M2L (symmetry-folded list)
+    DeviceBuf m2l_part_up, mflip_up;  // the same two scratch buffers for the upper levels on side_up
     DeviceBuf phi_nf, field_nf, phi_ff, field_ff, phi_u, field_u, nfuv, partials, scalars, flag;
     DeviceBuf sflag;    // sparse solute pass: one flag per cell, level 0 first, then levels 1..L
     DeviceBuf mask_sw;  // exchanged solute mask (FMM_UV_SWAP)
@@ -308,6 +311,15 @@ static int top_fp64_levels(fmm_plan_t pl) {
     return std::min(pl->levels - 1, pl->top_fp64);
 }
 
+// M2L levels 1..upper_m2l_levels(pl) run on the plan's second side stream,
+// concurrently with the two finest levels on the plan stream (they read
+// different multipoles and write different locals; each stream has its own
+// split-K and sign-flip scratch).  They are the FP64 top of the tree in mixed
+// mode: small launches that leave most of the chip idle when run alone.
+static int upper_m2l_levels(fmm_plan_t pl) {
+    return std::max(0, std::min(top_fp64_levels(pl), pl->levels - 2));
+}
+
 // want64: the FP64 operators are needed whatever the precision (sparse pass)
 static fmm_status ensure_m2l_ops(fmm_plan_t pl, bool want64 = false) {
     const bool needalias = top_fp64_levels(pl) > 0 || want64;
@@ -430,8 +442,11 @@ static fmm_status plan_create(double box, int levels, int p, const std::shared_p
     }
     if ((st = upload_lattice(pl)) != FMM_OK) return bail(st);
     if (hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&pl->side_up, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&pl->ev_up_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&pl->ev_up_join, hipEventDisableTiming) != hipSuccess) {
         fail(pl, FMM_ERR_DEVICE, "fmm_plan: stream or event creation failed");
         return bail(FMM_ERR_DEVICE);
     }
@@ -517,12 +532,18 @@ static fmm_status ensure_workspace(fmm_plan_t pl, int64_t n) {
     if (!pl->tree_ready) {
         const int64_t cells = level_offset(pl->levels + 1);
         const size_t tb = sizeof(double) * (size_t)cells * pl->Kp;
-        int64_t part = 0;
+        int64_t part = 0, part_up = 0;
         for (int l = 1; l <= pl->levels; ++l)
             if (m2l_slices(l) > 1) part = std::max(part, (int64_t)m2l_slices(l) * level_cells(l));
+        const int lup = upper_m2l_levels(pl);
+        for (int l = 1; l <= lup; ++l)
+            if (m2l_slices(l) > 1) part_up = std::max(part_up, (int64_t)m2l_slices(l) * level_cells(l));
+        const size_t flip_up = (size_t)m2l_flip_copies(pl->p) * (lup > 0 ? level_cells(lup) : 1) * pl->Kp;
         if (!pl->Mlev.ensure(tb) || !pl->Llev.ensure(tb) || !pl->M0.ensure(sizeof(double) * pl->Kp) ||
             !pl->mflip.ensure(sizeof(double) * (size_t)m2l_flip_copies(pl->p) * nleaf * pl->Kp) ||
             !pl->m2l_part.ensure(sizeof(double) * (size_t)std::max<int64_t>(part, 1) * pl->Kp) ||
+            !pl->mflip_up.ensure(sizeof(double) * flip_up) ||
+            !pl->m2l_part_up.ensure(sizeof(double) * (size_t)std::max<int64_t>(part_up, 1) * pl->Kp) ||
             !pl->L0.ensure(sizeof(double) * pl->Kp) || !pl->count.ensure(sizeof(uint32_t) * nleaf) ||
             !pl->cursor.ensure(sizeof(uint32_t) * nleaf) || !pl->start.ensure(sizeof(int32_t) * (nleaf + 1)) ||
             !pl->pstart.ensure(sizeof(int32_t) * (nleaf + 1)) ||
@@ -611,28 +632,43 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
     HIPCHK(pl, launch_lattice(pl->M0.as<double>(), pl->L0.as<double>(), pl->lat.as<double>(), p, Kp, s), "lattice");
     stage_end(pl, FMM_STAGE_LATTICE);
     stage_begin(pl, FMM_STAGE_M2L);
+    // levels 1..lup on the second side stream, beside the finer levels (not
+    // inside a batch, whose boxes already run as parallel graph branches)
+    const int lup = pl->in_batch ? 0 : upper_m2l_levels(pl);
+    if (lup > 0) {
+        HIPCHK(pl, hipEventRecord(pl->ev_up_fork, s), "event record");
+        HIPCHK(pl, hipStreamWaitEvent(pl->side_up, pl->ev_up_fork, 0), "stream wait");
+    }
     for (int l = 1; l <= L; ++l) {
         if (l == L) stage_begin(pl, FMM_STAGE_M2L_LEAF);
+        const bool up = l <= lup;
+        hipStream_t ls = up ? pl->side_up : s;
+        DeviceBuf &part = up ? pl->m2l_part_up : pl->m2l_part;
+        DeviceBuf &flip = up ? pl->mflip_up : pl->mflip;
         hipError_t e;
         const OpSet &o = *pl->op;
         if (l <= top && l <= 2)
             e = launch_m2l<double>(l, o.alias_ops[l - 1].as<double>(), o.alias_il[l - 1].as<int32_t>(),
                                    o.alias_off[l - 1].as<int32_t>(), nullptr, MD(l), nullptr, nullptr, LD(l),
-                                   pl->m2l_part.as<double>(), p, Kp, s, 1 << (3 * l));
+                                   part.as<double>(), p, Kp, ls, 1 << (3 * l));
         else if (l <= top)
             e = launch_m2l<double>(l, o.ops64.as<double>(), o.pairs.as<int32_t>(), o.offv.as<int32_t>(),
-                                   o.rowmap.as<int32_t>(), MD(l), pl->mflip.as<double>(), o.zeros.as<double>(),
-                                   LD(l), pl->m2l_part.as<double>(), p, Kp, s);
+                                   o.rowmap.as<int32_t>(), MD(l), flip.as<double>(), o.zeros.as<double>(), LD(l),
+                                   part.as<double>(), p, Kp, ls);
         else if (!TD && pl->prec == FMM_MIXED_BF16_M2L)
             e = launch_m2l_bf16(l, pl->op->opsbf.ptr, pl->op->il.as<int32_t>(), pl->op->offv.as<int32_t>(),
                                 reinterpret_cast<const float *>(MT(l)), reinterpret_cast<float *>(LT(l)),
-                                pl->m2l_part.as<float>(), p, Kp, s);
+                                part.as<float>(), p, Kp, ls);
         else
             e = launch_m2l<T>(l, sizeof(T) == 8 ? (const T *)o.ops64.ptr : (const T *)o.ops32.ptr,
                               o.pairs.as<int32_t>(), o.offv.as<int32_t>(), o.rowmap.as<int32_t>(), MT(l),
-                              pl->mflip.as<T>(), o.zeros.as<T>(), LT(l), pl->m2l_part.as<T>(), p, Kp, s);
+                              flip.as<T>(), o.zeros.as<T>(), LT(l), part.as<T>(), p, Kp, ls);
         HIPCHK(pl, e, "M2L");
         if (l == L) stage_end(pl, FMM_STAGE_M2L_LEAF);
+    }
+    if (lup > 0) {
+        HIPCHK(pl, hipEventRecord(pl->ev_up_join, pl->side_up), "event record");
+        HIPCHK(pl, hipStreamWaitEvent(s, pl->ev_up_join, 0), "stream wait");
     }
     stage_end(pl, FMM_STAGE_M2L);
     stage_begin(pl, FMM_STAGE_L2L);
@@ -1160,7 +1196,7 @@ extern "C" void fmm_destroy(fmm_plan_t pl) {
     }
     DeviceBuf *bufs[] = {&pl->lat, &pl->key,
                          &pl->count, &pl->cursor, &pl->start, &pl->pstart, &pl->xqp, &pl->perm, &pl->scan, &pl->xq, &pl->xq_u, &pl->xs, &pl->m2l_part,
-                         &pl->Mlev, &pl->Llev, &pl->mflip, &pl->M0, &pl->L0, &pl->phi_nf, &pl->field_nf, &pl->phi_ff,
+                         &pl->Mlev, &pl->Llev, &pl->mflip, &pl->m2l_part_up, &pl->mflip_up, &pl->M0, &pl->L0, &pl->phi_nf, &pl->field_nf, &pl->phi_ff,
                          &pl->field_ff, &pl->phi_u, &pl->field_u, &pl->nfuv, &pl->partials, &pl->scalars, &pl->flag,
                          &pl->sflag, &pl->mask_sw, &pl->mask_s, &pl->nfsc, &pl->nfdl};
     for (DeviceBuf *b : bufs) b->release();
@@ -1168,7 +1204,10 @@ extern "C" void fmm_destroy(fmm_plan_t pl) {
     if (pl->h_scalars) (void)hipHostFree(pl->h_scalars);
     if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
     if (pl->ev_join) (void)hipEventDestroy(pl->ev_join);
+    if (pl->ev_up_fork) (void)hipEventDestroy(pl->ev_up_fork);
+    if (pl->ev_up_join) (void)hipEventDestroy(pl->ev_up_join);
     if (pl->side) (void)hipStreamDestroy(pl->side);
+    if (pl->side_up) (void)hipStreamDestroy(pl->side_up);
     pl->op.reset();
     delete pl;
 }
