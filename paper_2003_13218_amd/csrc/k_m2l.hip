@@ -491,8 +491,8 @@ template <typename P, bool SPLIT, int NRB, int U, int NE, int SYM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_waves<P, NRB, SYM>()))) void k_m2l_lds(
     const typename P::A *__restrict__ ops, const int32_t *__restrict__ il, const int32_t *__restrict__ offs,
     const int32_t *__restrict__ rowmap, const typename P::S *__restrict__ M, const typename P::S *__restrict__ Mflip,
-    const typename P::S *__restrict__ zeros, int64_t fstride, typename P::S *__restrict__ L, int nh_bits, int NB,
-    int NKC, int Kp, int rb0, int nslices_arg) {
+    const typename P::S *__restrict__ zeros, int64_t fstride, typename P::S *__restrict__ L, double *__restrict__ L64,
+    int nh_bits, int NB, int NKC, int Kp, int rb0, int nslices_arg) {
     using S = typename P::S;
     using A = typename P::A;
     using B = typename P::B;
@@ -733,15 +733,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
     }
 
     if (!valid) return;
-    S *out = L + (size_t)slice * ((size_t)8 << (3 * nh_bits)) * Kp;
+    // FP32 operands with FP64 accumulators: split-K partials stay in FP64 (a
+    // slice's sum rounded to FP32 before the slices cancel each other was
+    // the largest FP32 error of the upper levels)
+    constexpr bool OUT64 = SPLIT && F64;
+    const size_t slice_off = (size_t)slice * ((size_t)8 << (3 * nh_bits)) * Kp;
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int prow = 16 * (rb0 + rb) + Mfma<S>::row(lane, r);
             const int row = SYM != 0 ? rowmap[prow] : prow;
-            if (row >= 0)
-                out[(size_t)tcell * Kp + row] = F64 ? (S)(hi[rb][r] + (double)acc[rb][r]) : (S)acc[rb][r];
+            if (row < 0) continue;
+            if constexpr (OUT64)
+                L64[slice_off + (size_t)tcell * Kp + row] = hi[rb][r] + (double)acc[rb][r];
+            else
+                L[slice_off + (size_t)tcell * Kp + row] = F64 ? (S)(hi[rb][r] + (double)acc[rb][r]) : (S)acc[rb][r];
         }
 }
 
@@ -795,8 +802,8 @@ static int row_groups(int scheme, int p, int NB, bool fp64, RowGroup *g) {
 template <typename P>
 static hipError_t launch_lds(const void *ops, const int32_t *il, const int32_t *offs, const int32_t *rowmap,
                              const typename P::S *M, const typename P::S *Mflip, const typename P::S *zeros,
-                             int64_t fstride, typename P::S *out, int nh_bits, int NB, int NKC, int Kp, int nslices,
-                             const RowGroup *groups, int ng, hipStream_t s) {
+                             int64_t fstride, typename P::S *out, double *out64, int nh_bits, int NB, int NKC, int Kp,
+                             int nslices, const RowGroup *groups, int ng, hipStream_t s) {
     using A = typename P::A;
     const int64_t ntile = (((int64_t)1 << (3 * nh_bits)) + 63) / 64;
     const int64_t grid = 8 * ntile * nslices;
@@ -808,12 +815,12 @@ static hipError_t launch_lds(const void *ops, const int32_t *il, const int32_t *
 #define FMM_M2L_LDS_LAUNCH(SYM, N, NE)                                                                          \
     if (nslices > 1)                                                                                            \
         hipLaunchKernelGGL((k_m2l_lds<P, true, N, stage_chunks<P, N>(), NE, SYM>), dim3((unsigned)grid),       \
-                           dim3(256), 0, s, o, il, offs, rowmap, M, Mflip, zeros, fstride, out, nh_bits, NB, NKC, \
-                           Kp, rb0, nslices);                                                                   \
+                           dim3(256), 0, s, o, il, offs, rowmap, M, Mflip, zeros, fstride, out, out64, nh_bits,   \
+                           NB, NKC, Kp, rb0, nslices);                                                          \
     else                                                                                                        \
         hipLaunchKernelGGL((k_m2l_lds<P, false, N, stage_chunks<P, N>(), NE, SYM>), dim3((unsigned)grid),      \
-                           dim3(256), 0, s, o, il, offs, rowmap, M, Mflip, zeros, fstride, out, nh_bits, NB, NKC, \
-                           Kp, rb0, 1);
+                           dim3(256), 0, s, o, il, offs, rowmap, M, Mflip, zeros, fstride, out, out64, nh_bits,   \
+                           NB, NKC, Kp, rb0, 1);
 #define FMM_M2L_LDS_CASE(SYM, N, NE)                                                                            \
     if (!launched && sym == SYM && nrb == N && ne == NE && (SYM == 0) == !P::kPaired) {                        \
         if constexpr ((SYM == 0) == !P::kPaired) {                                                              \
@@ -876,14 +883,15 @@ static hipError_t launch_lds(const void *ops, const int32_t *il, const int32_t *
     return hipSuccess;
 }
 
-// Sum of the split-K partial results in slice order (deterministic).
-template <typename T>
-__global__ void k_m2l_reduce(const T *__restrict__ partial, T *__restrict__ L, int nslices, int64_t elems) {
+// Sum of the split-K partial results in slice order (deterministic), in the
+// partials' type, rounded once to the level's type.
+template <typename P, typename T>
+__global__ void k_m2l_reduce(const P *__restrict__ partial, T *__restrict__ L, int nslices, int64_t elems) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < elems;
          i += (int64_t)gridDim.x * blockDim.x) {
-        T acc = 0;
+        P acc = 0;
         for (int k = 0; k < nslices; ++k) acc += partial[(size_t)k * elems + i];
-        L[i] = acc;
+        L[i] = (T)acc;
     }
 }
 
@@ -969,13 +977,13 @@ hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const 
     const int nslices = partial ? m2l_slices(level) : 1;
     RowGroup grp[kMaxRowGroups];
     const int ng = row_groups(0, p, NB, false, grp);
-    hipError_t e = launch_lds<PolBf16>(ops, il, offs, nullptr, M, M, M, 0, nslices > 1 ? partial : L, nh_bits, NB,
+    hipError_t e = launch_lds<PolBf16>(ops, il, offs, nullptr, M, M, M, 0, nslices > 1 ? partial : L, nullptr, nh_bits, NB,
                                        bf16_chunks(p), Kp, nslices, grp, ng, s);
     if (e != hipSuccess || nslices == 1) return e;
     const int64_t elems = ((int64_t)8 << (3 * nh_bits)) * Kp;
     int64_t g = (elems + 255) / 256;
     if (g > 65535) g = 65535;
-    hipLaunchKernelGGL(k_m2l_reduce<float>, dim3((unsigned)g), dim3(256), 0, s, partial, L, nslices, elems);
+    hipLaunchKernelGGL((k_m2l_reduce<float, float>), dim3((unsigned)g), dim3(256), 0, s, partial, L, nslices, elems);
     return hipGetLastError();
 }
 
@@ -1016,6 +1024,7 @@ hipError_t launch_m2l(int level, const T *ops, const int32_t *list, const int32_
     const int nh_bits = level - 1;
     const int64_t ntarget = (int64_t)1 << (3 * nh_bits);
     const int nslices = partial ? std::min(m2l_slices(level), nil) : 1;
+    double *part64 = nullptr;
     if (nil == kILSize) {
         if (!rowmap || !Mflip || !zeros) return hipErrorInvalidValue;
         const int scheme = m2l_scheme(p);
@@ -1027,9 +1036,11 @@ hipError_t launch_m2l(int level, const T *ops, const int32_t *list, const int32_
                            m2l_flip_copies(p));
         RowGroup grp[kMaxRowGroups];
         const int ng = row_groups(scheme, p, m2l_row_blocks(p), sizeof(T) == 8, grp);
+        // FP32 operands: FP64 split-K partials (the buffer holds doubles)
+        part64 = (sizeof(T) == 4 && nslices > 1) ? reinterpret_cast<double *>(partial) : nullptr;
         const hipError_t e = launch_lds<PolMfma<T>>(ops, list, offs, rowmap, M, Mflip, zeros, n,
-                                                     nslices > 1 ? partial : L, nh_bits, m2l_row_blocks(p), NB, Kp,
-                                                     nslices, grp, ng, s);
+                                                     nslices > 1 ? partial : L, part64, nh_bits, m2l_row_blocks(p), NB,
+                                                     Kp, nslices, grp, ng, s);
         if (e != hipSuccess) return e;
     } else {
         int R = 1;
@@ -1046,7 +1057,10 @@ hipError_t launch_m2l(int level, const T *ops, const int32_t *list, const int32_
     const int64_t elems = ((int64_t)8 << (3 * nh_bits)) * Kp;
     int64_t g = (elems + 255) / 256;
     if (g > 65535) g = 65535;
-    hipLaunchKernelGGL(k_m2l_reduce<T>, dim3((unsigned)g), dim3(256), 0, s, partial, L, nslices, elems);
+    if (part64)
+        hipLaunchKernelGGL((k_m2l_reduce<double, T>), dim3((unsigned)g), dim3(256), 0, s, part64, L, nslices, elems);
+    else
+        hipLaunchKernelGGL((k_m2l_reduce<T, T>), dim3((unsigned)g), dim3(256), 0, s, partial, L, nslices, elems);
     return hipGetLastError();
 }
 template hipError_t launch_m2l<float>(int, const float *, const int32_t *, const int32_t *, const int32_t *,
