@@ -897,9 +897,10 @@ __global__ void k_m2l_reduce(const P *__restrict__ partial, T *__restrict__ L, i
 
 // Slices per level: enough workgroups (>= ~512) to fill 256 CUs at two
 // resident workgroups each; levels >= 5 have enough targets on their own.
-// (Level 4 at 8 slices, one resident round of the two-wavefront kernel, was
-// 0.06 ms faster on the 1M-atom box but its longer FP32 partial sums moved the
-// ion's potential error in mixed mode from below to above 1e-5 relative.)
+// Level 4 (FP32 all-classes kernel, two workgroups per CU): 8 slices = 512
+// workgroups, one resident round; with the partials in FP64 the slicing no
+// longer changes the result (1M-atom box: 10.05 ms per step against 10.13 /
+// 10.23 with 16 / 32 slices, identical errors).
 int m2l_slices(int level) {
     // tuning: FMM_M2L_SLICES = "s1,s2,s3,s4,s5" overrides the slice counts of
     // levels 1..5 (and deeper) with powers of two up to 64
@@ -922,7 +923,7 @@ int m2l_slices(int level) {
         case 1: return 64;
         case 2: return 64;
         case 3: return 64;
-        case 4: return 32;
+        case 4: return 8;
         default: return 1;
     }
 }
