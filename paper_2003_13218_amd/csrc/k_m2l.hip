@@ -680,6 +680,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
                 }
 #pragma unroll
                 for (int rb = 0; rb < NRB; ++rb) acc[rb] = P::mma(a[rb], v[rb / NE], acc[rb]);
+                // 16-byte fragments: read one row-block pair ahead of the eight
+                // MFMAs that use it, so the LDS latency hides behind the pair
+                // before (left to itself the compiler issued each pair's reads
+                // right after the previous pair's last MFMA and waited on them:
+                // leaf level 6.04 -> 5.88 ms)
+                if constexpr (sizeof(A) == 16) {
+                    __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);  // LDS reads
+#pragma unroll
+                    for (int g = 0; g < NRB / 2; ++g) {
+                        __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);  // MFMA
+                        if (g + 2 < NRB / 2) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+                    }
+                }
             } else {
                 // the class combinations sum_s chi(s) D_s M_s of the entry:
                 // pairs: w0 +- w1; orbits: (w0 +- w1) + (w2 +- w3) for the
