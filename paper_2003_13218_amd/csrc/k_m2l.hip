@@ -469,7 +469,8 @@ template <typename P, int NRB> constexpr int stage_chunks() {
 // order by k_m2l_reduce), compiled separately so profiles tell levels apart.
 // ---------------------------------------------------------------------------
 // SYM: 0 plain list (one source per entry); 1 pairs (t, -t); 2 / 3 orbits of
-// the two-axis flips, first / second half of the row classes.  The first NE
+// the two-axis flips, first / second half of the row classes; 4 orbits, all
+// four row classes in one launch (NE blocks each).  For SYM 1-3 the first NE
 // row blocks of the group take the first combination of the entry's sources,
 // the others the second (compile-time constants).  Sources: M for the entry's
 // first offset, the sign-flipped copies Mflip + f * fstride (D_s M of the
@@ -479,10 +480,10 @@ template <typename P, int NRB> constexpr int stage_chunks() {
 // (12 row blocks: 48 FP32 accumulators, 96 FP64 ones, 48 operator fragment
 // registers) 256 VGPRs plus a few AGPRs, i.e. one wavefront per SIMD, and the
 // multipole gathers of a stage stall its matrix core.  Capped at 256 registers
-// (232 once the operator fragment reads interleave with the MFMAs, below) two
+// (237 once the operator fragment reads interleave with the MFMAs, below) two
 // wavefronts per SIMD hide each other's waits: 8.2 -> 6.7 ms for the finest
-// level of the 1M-atom box.  The FP64 half-class variants stay at two wavefronts: squeezed
-// to three they spill inside the stage and lose (measured).
+// level of the 1M-atom box.  The FP64 half-class variants stay at two
+// wavefronts: squeezed to three they spill inside the stage and lose.
 template <typename P, int NRB, int SYM> constexpr int m2l_min_waves() {
     return (sizeof(typename P::S) == 4 && SYM == 4 && NRB == 12) ? 2 : 1;
 }
