@@ -904,6 +904,7 @@ __global__ void k_m2l_reduce(const P *__restrict__ partial, T *__restrict__ L, i
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < elems;
          i += (int64_t)gridDim.x * blockDim.x) {
         P acc = 0;
+#pragma unroll 8
         for (int k = 0; k < nslices; ++k) acc += partial[(size_t)k * elems + i];
         L[i] = (T)acc;
     }
@@ -1018,13 +1019,23 @@ __device__ inline int flip_sign(int scheme, int f, int k) {
     return odd ? -1 : 1;
 }
 
+// A thread owns coefficient k of every cell its block visits (the block
+// spans one padded row, blockDim >= Kp), so its signs are computed once.
 template <typename T>
-__global__ void k_m2l_flip(const T *__restrict__ M, T *__restrict__ Mflip, int64_t n, int Kp, int scheme,
+__global__ void k_m2l_flip(const T *__restrict__ M, T *__restrict__ Mflip, int64_t ncell, int Kp, int scheme,
                            int ncopy) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int k = (int)(i % Kp);
+    const int k = threadIdx.x;
+    if (k >= Kp) return;
+    bool neg[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) neg[f] = f < ncopy && flip_sign(scheme, f, k) < 0;
+    const int64_t n = ncell * Kp;
+    for (int64_t c = blockIdx.x; c < ncell; c += gridDim.x) {
+        const int64_t i = c * Kp + k;
         const T v = M[i];
-        for (int f = 0; f < ncopy; ++f) Mflip[(size_t)f * n + i] = flip_sign(scheme, f, k) < 0 ? -v : v;
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+            if (f < ncopy) Mflip[(size_t)f * n + i] = neg[f] ? -v : v;
     }
 }
 
@@ -1044,10 +1055,12 @@ hipError_t launch_m2l(int level, const T *ops, const int32_t *list, const int32_
         if (!rowmap || !Mflip || !zeros) return hipErrorInvalidValue;
         const int scheme = m2l_scheme(p);
         if (scheme == 1 && m2l_row_blocks(p) > kRowBlocksPerWave) return hipErrorInvalidValue;
-        const int64_t n = ((int64_t)8 << (3 * nh_bits)) * Kp;
-        int64_t g = (n + 255) / 256;
-        if (g > 65535) g = 65535;
-        hipLaunchKernelGGL(k_m2l_flip<T>, dim3((unsigned)g), dim3(256), 0, s, M, Mflip, n, Kp, scheme,
+        const int64_t ncell = (int64_t)8 << (3 * nh_bits);
+        const int64_t n = ncell * Kp;
+        if (Kp > 1024) return hipErrorInvalidValue;
+        const int fb = (Kp + 63) / 64 * 64;
+        const int64_t g = ncell < 16384 ? ncell : 16384;
+        hipLaunchKernelGGL(k_m2l_flip<T>, dim3((unsigned)g), dim3(fb), 0, s, M, Mflip, ncell, Kp, scheme,
                            m2l_flip_copies(p));
         RowGroup grp[kMaxRowGroups];
         const int ng = row_groups(scheme, p, m2l_row_blocks(p), sizeof(T) == 8, grp);
