@@ -75,6 +75,35 @@ def test_p2p_matches_direct_nearfield(fmm, name, prec, tol):
     assert rms_rel(fn.cpu().numpy(), field) < tol
 
 
+@pytest.mark.parametrize("occ", [2, 4, 20, 60])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-6)])
+def test_p2p_uneven_leaves(fmm, occ, prec, tol):
+    # Leaf counts from empty to several times the mean, at mean occupancies
+    # that select each source-group count of the near-field kernel (16, 8, 4,
+    # 2 groups): full target chunks, half-size last chunks with twice the
+    # groups, and leaves padded to the group count all occur.  Atoms sit on
+    # distinct sites of a 0.71 A grid (jittered by at most 0.1 A), drawn with
+    # weights peaked around four centres.
+    rng = np.random.default_rng(300 + occ)
+    box, levels = 20.0, 2
+    n = occ * 64
+    g = (np.arange(28) + 0.5) * (box / 28)
+    sites = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    cen = rng.uniform(0, box, (4, 3))
+    d2 = ((sites[:, None, :] - cen[None]) ** 2).sum(-1)
+    wgt = 1.0 + 20.0 * np.exp(-d2 / 8.0).sum(1)
+    pick = rng.choice(len(sites), n, replace=False, p=wgt / wgt.sum())
+    pos = sites[pick] + rng.uniform(-0.1, 0.1, (n, 3))
+    q = rng.uniform(-1, 1, n)
+    counts = np.bincount(oracle.bin_reference(pos, box, levels)[1], minlength=64)
+    assert counts.min() < occ / 2 and counts.max() > 2 * occ  # uneven for real
+    plan = _plan(fmm, box, levels, 2, prec)
+    pn, fn, _, _ = fmm.fmm_potential_parts(plan, _t(pos), _t(q))
+    phi, field = oracle.nearfield(pos, q, box, levels)
+    assert rms_rel(pn.cpu().numpy(), phi) < tol
+    assert rms_rel(fn.cpu().numpy(), field) < tol
+
+
 def test_p2p_shallow_tree_repeats_images(fmm):
     # levels = 1: the +-2 block wraps the 2-leaf axis several times; every
     # image must be visited, none deduplicated
