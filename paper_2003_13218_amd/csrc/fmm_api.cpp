@@ -441,9 +441,7 @@ static fmm_status plan_create(double box, int levels, int p, const std::shared_p
         }
     }
     if ((st = upload_lattice(pl)) != FMM_OK) return bail(st);
-    if (hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&pl->side_up, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
+    if (hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&pl->ev_up_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&pl->ev_up_join, hipEventDisableTiming) != hipSuccess) {
@@ -593,6 +591,23 @@ static fmm_status sort_atoms(fmm_plan_t pl, int64_t n, const double *pos, const 
 
 // a3 - a8 on the repacked atoms xq: far-field potential and field per sorted
 // atom.  Leaf level in the mode's type T; levels 1..top in FP64; level 0 FP64.
+// The two side streams of a single-box plan, created at its first
+// evaluation.  Sub-plans of a batch never fork and create none: every stream
+// takes one of the device's few hardware queues in turn, and unused streams
+// created beside the batch's per-box streams pushed several boxes onto one
+// queue (32-window batch: energies and forces 10.6 -> 13.8 ms).
+static fmm_status ensure_side_streams(fmm_plan_t pl) {
+    if (!pl->side && hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking) != hipSuccess) {
+        pl->side = nullptr;
+        return fail(pl, FMM_ERR_DEVICE, "side stream creation failed");
+    }
+    if (!pl->side_up && hipStreamCreateWithFlags(&pl->side_up, hipStreamNonBlocking) != hipSuccess) {
+        pl->side_up = nullptr;
+        return fail(pl, FMM_ERR_DEVICE, "side stream creation failed");
+    }
+    return FMM_OK;
+}
+
 template <typename T>
 static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field) {
     hipStream_t s = pl->stream;
@@ -636,6 +651,8 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
     // inside a batch, whose boxes already run as parallel graph branches)
     const int lup = pl->in_batch ? 0 : upper_m2l_levels(pl);
     if (lup > 0) {
+        fmm_status ss = ensure_side_streams(pl);
+        if (ss != FMM_OK) return ss;
         HIPCHK(pl, hipEventRecord(pl->ev_up_fork, s), "event record");
         HIPCHK(pl, hipStreamWaitEvent(pl->side_up, pl->ev_up_fork, 0), "stream wait");
     }
@@ -727,6 +744,10 @@ static fmm_status run_fields(fmm_plan_t pl, int64_t n, const double *pos, const 
     // parallel graph branch per box, and the nested fork inside a captured
     // graph is not used (one such run ended in a host-side crash).
     const bool fork = !pl->in_batch;
+    if (fork) {
+        fmm_status ss = ensure_side_streams(pl);
+        if (ss != FMM_OK) return ss;
+    }
     hipStream_t ns = fork ? pl->side : s;
     auto near_field = [&]() -> fmm_status {
         if (fork) {
