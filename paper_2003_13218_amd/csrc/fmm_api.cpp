@@ -630,36 +630,43 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
     stage_begin(pl, FMM_STAGE_P2M);
     HIPCHK(pl, launch_p2m<T>(level_cells(L), xq, pl->start.as<int32_t>(), MT(L), p, Kp, 1.0 / h_leaf, s), "P2M");
     stage_end(pl, FMM_STAGE_P2M);
-    stage_begin(pl, FMM_STAGE_M2M);
-    for (int l = L - 1; l >= 1; --l) {
-        const int64_t nc = level_cells(l);
-        hipError_t e;
-        if (l > top) e = launch_m2m_mfma<T, T>(nc, MT(l + 1), MT(l), m2m_ops(TD), p, Kp, s);
-        else if (l + 1 > top) e = launch_m2m_mfma<T, double>(nc, MT(l + 1), MD(l), m2m_ops(true), p, Kp, s);
-        else e = launch_m2m_mfma<double, double>(nc, MD(l + 1), MD(l), m2m_ops(true), p, Kp, s);
-        HIPCHK(pl, e, "M2M");
-    }
-    HIPCHK(pl, (top >= 1 ? launch_m2m_mfma<double, double>(1, MD(1), pl->M0.as<double>(), m2m_ops(true), p, Kp, s)
-                         : launch_m2m_mfma<T, double>(1, MT(1), pl->M0.as<double>(), m2m_ops(true), p, Kp, s)),
-           "M2M");
-    stage_end(pl, FMM_STAGE_M2M);
-    stage_begin(pl, FMM_STAGE_LATTICE);
-    HIPCHK(pl, launch_lattice(pl->M0.as<double>(), pl->L0.as<double>(), pl->lat.as<double>(), p, Kp, s), "lattice");
-    stage_end(pl, FMM_STAGE_LATTICE);
-    stage_begin(pl, FMM_STAGE_M2L);
-    // levels 1..lup on the second side stream, beside the finer levels (not
-    // inside a batch, whose boxes already run as parallel graph branches)
+    // Levels 1..lup (the upper tree: M2M, the level-0 lattice operator, M2L)
+    // run on the second side stream once the M2M has produced level lup + 1,
+    // beside the M2L of the two finest levels on the plan stream (not inside a
+    // batch, whose boxes already run as parallel graph branches).  The upper
+    // tree's small launches wait behind the near field for CU slots; off the
+    // plan stream they no longer hold back the finest levels.
     const int lup = pl->in_batch ? 0 : upper_m2l_levels(pl);
     if (lup > 0) {
         fmm_status ss = ensure_side_streams(pl);
         if (ss != FMM_OK) return ss;
-        HIPCHK(pl, hipEventRecord(pl->ev_up_fork, s), "event record");
-        HIPCHK(pl, hipStreamWaitEvent(pl->side_up, pl->ev_up_fork, 0), "stream wait");
     }
+    hipStream_t su = lup > 0 ? pl->side_up : s;
+    auto m2m = [&](int l, hipStream_t ms) {
+        const int64_t nc = level_cells(l);
+        if (l > top) return launch_m2m_mfma<T, T>(nc, MT(l + 1), MT(l), m2m_ops(TD), p, Kp, ms);
+        if (l + 1 > top) return launch_m2m_mfma<T, double>(nc, MT(l + 1), MD(l), m2m_ops(true), p, Kp, ms);
+        return launch_m2m_mfma<double, double>(nc, MD(l + 1), MD(l), m2m_ops(true), p, Kp, ms);
+    };
+    stage_begin(pl, FMM_STAGE_M2M);
+    for (int l = L - 1; l > lup; --l) HIPCHK(pl, m2m(l, s), "M2M");
+    if (lup > 0) {
+        HIPCHK(pl, hipEventRecord(pl->ev_up_fork, s), "event record");
+        HIPCHK(pl, hipStreamWaitEvent(su, pl->ev_up_fork, 0), "stream wait");
+    }
+    for (int l = lup; l >= 1; --l) HIPCHK(pl, m2m(l, su), "M2M");
+    HIPCHK(pl, (top >= 1 ? launch_m2m_mfma<double, double>(1, MD(1), pl->M0.as<double>(), m2m_ops(true), p, Kp, su)
+                         : launch_m2m_mfma<T, double>(1, MT(1), pl->M0.as<double>(), m2m_ops(true), p, Kp, su)),
+           "M2M");
+    stage_end(pl, FMM_STAGE_M2M, su);
+    stage_begin(pl, FMM_STAGE_LATTICE, su);
+    HIPCHK(pl, launch_lattice(pl->M0.as<double>(), pl->L0.as<double>(), pl->lat.as<double>(), p, Kp, su), "lattice");
+    stage_end(pl, FMM_STAGE_LATTICE, su);
+    stage_begin(pl, FMM_STAGE_M2L);
     for (int l = 1; l <= L; ++l) {
         if (l == L) stage_begin(pl, FMM_STAGE_M2L_LEAF);
         const bool up = l <= lup;
-        hipStream_t ls = up ? pl->side_up : s;
+        hipStream_t ls = up ? su : s;
         DeviceBuf &part = up ? pl->m2l_part_up : pl->m2l_part;
         DeviceBuf &flip = up ? pl->mflip_up : pl->mflip;
         hipError_t e;
