@@ -25,8 +25,12 @@
  *           current when the plan was created; the caller owns it.  Scalars
  *           marked "host" are host memory.  Device arrays are FP64,
  *           array-of-structs where 3-vectors are involved ([n][3]).
- *   Streams all GPU work of a plan runs on the plan's stream (default: the
- *           null stream); a call returns after its result is on the host.
+ *   Streams a call's GPU work is ordered on the plan's stream (default: the
+ *           null stream): it starts after the work queued there before the
+ *           call, and everything it does (including the near field and the
+ *           upper tree, which a single-box plan runs on two streams of its
+ *           own, created at its first evaluation and joined back) is done
+ *           before the call returns with its result on the host.
  *   Threads a plan is not thread-safe; distinct plans are independent.
  *   Errors  every call returns a negative fmm_status on failure and leaves a
  *           message in fmm_last_error(plan); nothing is thrown across the ABI.
