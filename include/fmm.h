@@ -29,8 +29,13 @@
  *           null stream): it starts after the work queued there before the
  *           call, and everything it does (including the near field and the
  *           upper tree, which a single-box plan runs on two streams of its
- *           own, created at its first evaluation and joined back) is done
- *           before the call returns with its result on the host.
+ *           own, created with the plan and joined back) is done before the
+ *           call returns with its result on the host.  No evaluation creates
+ *           a stream.
+ *   Config  the library reads no environment variables: every choice that
+ *           changes numerics or schedules is an argument of fmm_plan,
+ *           fmm_plan_config, fmm_plan_options, fmm_plan_tuning or
+ *           fmm_plan_softcore, and fmm_plan_info reports it.
  *   Threads a plan is not thread-safe; distinct plans are independent.
  *   Errors  every call returns a negative fmm_status on failure and leaves a
  *           message in fmm_last_error(plan); nothing is thrown across the ABI.
@@ -66,7 +71,10 @@ typedef enum {
     /* as FMM_MIXED, but the FP32 levels' M2L takes BF16 operands (operators
      * and multipoles rounded to bfloat16, 8 significant bits) with FP32
      * accumulation on the matrix cores: a precision/speed trade-off whose
-     * far-field error is of the order of the BF16 unit roundoff 2^-8 */
+     * far-field error is of the order of the BF16 unit roundoff 2^-8.  It
+     * does NOT meet the 1e-5 accuracy of the other modes: on water boxes
+     * the RMS relative potential error is about 1.4e-2 and the force error
+     * about 4e-4 at every order p */
     FMM_MIXED_BF16_M2L = 2
 } fmm_precision;
 
@@ -94,6 +102,29 @@ fmm_status fmm_plan(double box, int levels, int p, fmm_plan_t *out);
  * the cached state used by fmm_solute_solvent_energy.
  */
 fmm_status fmm_plan_config(fmm_plan_t plan, int precision, double kappa, void *hip_stream);
+
+/*
+ * fmm_plan_tuning -- schedule and precision split of the plan's tree.
+ *   fp64_levels  in the mixed modes, tree levels 1 .. fp64_levels run in
+ *                FP64 (M2M, M2L, L2L; clamped to levels - 1); default 3.  At
+ *                shallow levels the cells are large and their M2L terms
+ *                cancel strongly, so FP32 there costs accuracy: on the
+ *                1,000,000-atom water box (levels 5, p 12) the default
+ *                gives an RMS potential error of 1.8e-6 against the FP64
+ *                Ewald sum, 4 gives 7e-7 at about 0.8 ms more per
+ *                evaluation.  Ignored in FMM_FP64 (everything is FP64).
+ *                -1 keeps the current value.
+ *   p2p_groups   source groups of the near-field kernel (1, 2, 4, 8, 16; the
+ *                atoms of a leaf are split in that many target chunks of
+ *                64 / groups slots), or 0 to choose from the mean leaf
+ *                occupancy (default); -1 keeps the current value.  Changes
+ *                the schedule only: results are identical up to the order of
+ *                FP64 partial sums.
+ * On a batch plan it applies to every box (fmm_autotune_batch then replaces
+ * the group counts).  Clears the cached state used by
+ * fmm_solute_solvent_energy.  FMM_ERR_INVALID for other values.
+ */
+fmm_status fmm_plan_tuning(fmm_plan_t plan, int fp64_levels, int p2p_groups);
 
 /* Boundary condition at infinity (Appendix A, eq. surfdipole). */
 typedef enum {
@@ -337,8 +368,13 @@ fmm_status fmm_profile_read(fmm_plan_t plan, double *ms, int64_t *calls);
  *       M2L always takes the 875 offsets)
  *   [7] launches of the M2L kernel per full-list level in the plan's
  *       precision (the finest level: FP32 in the mixed modes)
+ *   [8] tree levels run in FP64 (1 .. [8]; all of them in FMM_FP64; for a
+ *       batch plan the fmm_plan_tuning setting)
+ *   [9] near-field source groups set by fmm_plan_tuning (0 = automatic)
+ *   [10] operator rows the matrix cores run per list entry of the FP32/FP64
+ *       M2L (each row class padded to whole 16-row blocks; >= K)
  */
-#define FMM_INFO_COUNT 8
+#define FMM_INFO_COUNT 11
 fmm_status fmm_plan_info(fmm_plan_t plan, int64_t *info, int n);
 
 /* Message of the last failed call on this plan (never NULL; "" if none).

@@ -20,7 +20,6 @@ Contents
 ``shell_sum_energy``  brute-force spherical image-shell sum for tiny inputs.
 ``solid_harmonics``   complex regular/irregular solid harmonics from their
                    definition via associated Legendre functions.
-``direct_potential`` free-space sum of q/r (for expansion checks).
 """
 from __future__ import annotations
 
@@ -347,18 +346,6 @@ def shell_sum_energy(pos, q, box, R, xi=XI_SC, mask=None, lam=0.0, surface=True)
     m = np.asarray(mask).reshape(-1) != 0
     qu, qv = q[m].sum(), q[~m].sum()
     return e - xi * (qu * qu + qv * qv + 2.0 * (1.0 - lam) * qu * qv) / (2.0 * box)
-
-
-def direct_potential(targets, sources, q):
-    """Free-space potential sum_j q_j / |t - s_j| and field sum q_j (t - s_j)/|t - s_j|^3."""
-    t = np.asarray(targets, dtype=np.float64).reshape(-1, 3)
-    s = np.asarray(sources, dtype=np.float64).reshape(-1, 3)
-    q = np.asarray(q, dtype=np.float64).reshape(-1)
-    d = t[:, None, :] - s[None, :, :]
-    r = np.sqrt((d * d).sum(-1))
-    phi = (q[None, :] / r).sum(1)
-    field = (q[None, :, None] * d / (r ** 3)[..., None]).sum(1)
-    return phi, field
 
 
 def solid_harmonics(vec, nmax):

@@ -33,7 +33,7 @@ EXPORTED = (
     "fmm_potential_parts", "fmm_bin", "fmm_lattice_tensor", "fmm_profile", "fmm_profile_read",
     "fmm_last_error", "fmm_destroy", "fmm_version", "fmm_plan_batch", "fmm_energy_forces_batch",
     "fmm_solute_solvent_energy_batch", "fmm_autotune_batch", "fmm_batch_levels", "fmm_lambda_energy",
-    "fmm_lambda_energy_batch", "fmm_plan_options", "fmm_plan_softcore", "fmm_plan_info",
+    "fmm_lambda_energy_batch", "fmm_plan_options", "fmm_plan_softcore", "fmm_plan_info", "fmm_plan_tuning",
 )
 
 STAGES = ("sort", "gather", "p2m", "m2m", "lattice", "m2l", "m2l_leaf", "l2l", "l2p", "p2p", "final", "total")
@@ -64,6 +64,8 @@ def load():
         lib.fmm_plan_config.restype = ci
         lib.fmm_plan_options.argtypes = [vp, ci, ci]
         lib.fmm_plan_options.restype = ci
+        lib.fmm_plan_tuning.argtypes = [vp, ci, ci]
+        lib.fmm_plan_tuning.restype = ci
         lib.fmm_plan_softcore.argtypes = [vp, dbl, dbl, ci]
         lib.fmm_plan_softcore.restype = ci
         lib.fmm_plan_info.argtypes = [vp, vp, ci]
@@ -170,7 +172,8 @@ def fmm_plan_options(plan: Plan, boundary: int = FMM_BOUNDARY_CONDUCTING, uv_sch
     _check(load().fmm_plan_options(plan.handle, int(boundary), int(uv_scheme)), plan)
 
 
-INFO_KEYS = ("levels", "p", "K", "Kp", "precision", "m2l_scheme", "m2l_entries", "m2l_launches")
+INFO_KEYS = ("levels", "p", "K", "Kp", "precision", "m2l_scheme", "m2l_entries", "m2l_launches", "fp64_levels",
+             "p2p_groups", "m2l_rows")
 
 
 def fmm_plan_info(plan: Plan) -> dict:
@@ -179,6 +182,11 @@ def fmm_plan_info(plan: Plan) -> dict:
     v = np.zeros(len(INFO_KEYS), dtype=np.int64)
     _check(load().fmm_plan_info(plan.handle, v.ctypes.data_as(ctypes.c_void_p), len(INFO_KEYS)), plan)
     return {k: int(x) for k, x in zip(INFO_KEYS, v)}
+
+
+def fmm_plan_tuning(plan: Plan, fp64_levels: int = -1, p2p_groups: int = -1):
+    """Mixed-mode FP64 tree levels and near-field source groups (-1 keeps a value)."""
+    _check(load().fmm_plan_tuning(plan.handle, int(fp64_levels), int(p2p_groups)), plan)
 
 
 def fmm_plan_softcore(plan: Plan, alpha: float, sigma: float = 1.0, c: int = 6):

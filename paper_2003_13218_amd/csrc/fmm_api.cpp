@@ -5,7 +5,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
-#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <functional>
@@ -25,13 +24,16 @@ thread_local std::string g_plan_error;
 struct DeviceBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    bool borrowed = false;  // a view of memory the buffer does not own (never freed or grown)
     void release() {
-        if (ptr) (void)hipFree(ptr);
+        if (ptr && !borrowed) (void)hipFree(ptr);
         ptr = nullptr;
         bytes = 0;
+        borrowed = false;
     }
     bool ensure(size_t b) {
         if (b <= bytes && ptr) return true;
+        if (borrowed) return false;
         release();
         if (b == 0) b = 16;
         if (hipMalloc(&ptr, b) != hipSuccess) { ptr = nullptr; bytes = 0; return false; }
@@ -177,6 +179,7 @@ static int64_t level_offset(int l) {
 
 static bool rec_uploaded[64] = {false};
 
+
 static void batch_drop_graphs(fmm_plan_t pl) {
     for (auto *g : {&pl->g_ef, &pl->g_uv}) {
         if (g->exec) (void)hipGraphExecDestroy(g->exec);
@@ -320,15 +323,29 @@ static int upper_m2l_levels(fmm_plan_t pl) {
     return std::max(0, std::min(top_fp64_levels(pl), pl->levels - 2));
 }
 
-// want64: the FP64 operators are needed whatever the precision (sparse pass)
+// The M2L operator sets the plan's current mode needs; want64: the FP64
+// operators whatever the precision (sparse solute pass).
+struct OpNeeds {
+    bool alias, f64, f32, bf;
+};
+static OpNeeds m2l_needs(fmm_plan_t pl, bool want64) {
+    OpNeeds n;
+    n.alias = top_fp64_levels(pl) > 0 || want64;
+    n.f64 = n.alias || want64;
+    n.f32 = pl->prec == FMM_MIXED;
+    n.bf = pl->prec == FMM_MIXED_BF16_M2L;
+    return n;
+}
+static bool m2l_ops_ready(fmm_plan_t pl, bool want64) {
+    const OpNeeds n = m2l_needs(pl, want64);
+    return (!n.f64 || pl->op->ops64.ptr) && (!n.alias || pl->op->alias_ops[0].ptr) && (!n.f32 || pl->op->ops32.ptr) &&
+           (!n.bf || pl->op->opsbf.ptr);
+}
+
 static fmm_status ensure_m2l_ops(fmm_plan_t pl, bool want64 = false) {
-    const bool needalias = top_fp64_levels(pl) > 0 || want64;
-    const bool need64 = needalias || want64;
-    const bool need32 = pl->prec == FMM_MIXED;
-    const bool needbf = pl->prec == FMM_MIXED_BF16_M2L;
-    if ((!need64 || pl->op->ops64.ptr) && (!needalias || pl->op->alias_ops[0].ptr) && (!need32 || pl->op->ops32.ptr) &&
-        (!needbf || pl->op->opsbf.ptr))
-        return FMM_OK;
+    if (m2l_ops_ready(pl, want64)) return FMM_OK;
+    const OpNeeds nd = m2l_needs(pl, want64);
+    const bool needalias = nd.alias, need64 = nd.f64, need32 = nd.f32, needbf = nd.bf;
     std::vector<double> rm;
     build_m2l_all(pl->p, pl->op->offs, rm);
     const size_t ne = m2l_ops_elems<float>(pl->p);
@@ -395,7 +412,11 @@ static fmm_status ensure_m2l_ops(fmm_plan_t pl, bool want64 = false) {
     return FMM_OK;
 }
 
-static fmm_status plan_create(double box, int levels, int p, const std::shared_ptr<OpSet> &shared,
+static fmm_status ensure_side_streams(fmm_plan_t pl);
+
+// member: a box of a batch plan (or an autotuning candidate for one), which
+// never forks and so gets no side streams
+static fmm_status plan_create(double box, int levels, int p, const std::shared_ptr<OpSet> &shared, bool member,
                               fmm_plan_t *out) {
     *out = nullptr;
     if (!(box > 0.0) || !std::isfinite(box)) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan: box must be finite and > 0");
@@ -422,7 +443,6 @@ static fmm_status plan_create(double box, int levels, int p, const std::shared_p
         fmm_destroy(pl);
         return s;
     };
-    if (const char *v = std::getenv("FMM_TOP_FP64")) pl->top_fp64 = std::max(0, std::atoi(v));
     if (pl->device < 64 && !rec_uploaded[pl->device]) {
         RecTables t;
         build_rec_tables(&t);
@@ -453,13 +473,28 @@ static fmm_status plan_create(double box, int levels, int p, const std::shared_p
         fail(pl, FMM_ERR_NOMEM, "fmm_plan: pinned host allocation");
         return bail(FMM_ERR_NOMEM);
     }
+    pl->in_batch = member;
+    // A single-box plan forks the near field and the upper tree onto two
+    // streams of its own: they are made here, with the plan, so that no
+    // evaluation (captured into a graph or not) ever creates a stream.
+    if (!member && (st = ensure_side_streams(pl)) != FMM_OK) return bail(st);
     *out = pl;
     return FMM_OK;
 }
 
 extern "C" fmm_status fmm_plan(double box, int levels, int p, fmm_plan_t *out) {
     if (!out) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan: out is NULL");
-    return plan_create(box, levels, p, nullptr, out);
+    fmm_status st = plan_create(box, levels, p, nullptr, false, out);
+    if (st != FMM_OK) return st;
+    // the operators of the default precision are uploaded with the plan
+    // (fmm_plan_config and fmm_plan_tuning add what a new mode needs), so an
+    // evaluation allocates only its per-call workspace
+    if ((st = ensure_m2l_ops(*out, false)) != FMM_OK) {
+        g_plan_error = (*out)->err;
+        fmm_destroy(*out);
+        *out = nullptr;
+    }
+    return st;
 }
 
 extern "C" fmm_status fmm_plan_config(fmm_plan_t pl, int precision, double kappa, void *hip_stream) {
@@ -487,7 +522,31 @@ extern "C" fmm_status fmm_plan_config(fmm_plan_t pl, int precision, double kappa
         fmm_status st = upload_lattice(pl);
         if (st != FMM_OK) return st;
     }
-    return FMM_OK;
+    HIPCHK(pl, hipSetDevice(pl->device), "hipSetDevice");
+    return ensure_m2l_ops(pl, false);
+}
+
+extern "C" fmm_status fmm_plan_tuning(fmm_plan_t pl, int fp64_levels, int p2p_groups) {
+    if (!pl) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan_tuning: plan is NULL");
+    if (fp64_levels < -1 || fp64_levels > kMaxLevels)
+        return fail(pl, FMM_ERR_INVALID, "fmm_plan_tuning: fp64_levels must be in [-1, 10]");
+    if (p2p_groups != -1 && p2p_groups != 0 && p2p_groups != 1 && p2p_groups != 2 && p2p_groups != 4 &&
+        p2p_groups != 8 && p2p_groups != kMaxP2PGroups)
+        return fail(pl, FMM_ERR_INVALID, "fmm_plan_tuning: p2p_groups must be -1, 0, 1, 2, 4, 8 or 16");
+    auto set = [&](fmm_plan_t b) {
+        if (fp64_levels >= 0) b->top_fp64 = fp64_levels;
+        if (p2p_groups >= 0) b->p2p_g = p2p_groups;
+        b->have_state = false;
+    };
+    set(pl);
+    for (fmm_plan_t b : pl->sub) set(b);
+    if (pl->is_batch) {
+        pl->batch_state = false;
+        batch_drop_graphs(pl);
+        return FMM_OK;
+    }
+    HIPCHK(pl, hipSetDevice(pl->device), "hipSetDevice");
+    return ensure_m2l_ops(pl, false);
 }
 
 extern "C" fmm_status fmm_plan_info(fmm_plan_t pl, int64_t *info, int n) {
@@ -495,7 +554,9 @@ extern "C" fmm_status fmm_plan_info(fmm_plan_t pl, int64_t *info, int n) {
     if (n < 0 || (n > 0 && !info)) return fail(pl, FMM_ERR_INVALID, "fmm_plan_info: bad info array");
     const int64_t v[FMM_INFO_COUNT] = {pl->is_batch ? 0 : pl->levels, pl->p, pl->K, pl->Kp, pl->prec,
                                        m2l_scheme(pl->p), m2l_list_entries(pl->p),
-                                       m2l_launches(pl->p, pl->prec == FMM_FP64)};
+                                       m2l_launches(pl->p, pl->prec == FMM_FP64),
+                                       pl->is_batch ? pl->top_fp64 : top_fp64_levels(pl), pl->p2p_g,
+                                       16 * (int64_t)m2l_row_blocks(pl->p)};
     for (int i = 0; i < n && i < FMM_INFO_COUNT; ++i) info[i] = v[i];
     return FMM_OK;
 }
@@ -525,45 +586,81 @@ extern "C" fmm_status fmm_plan_options(fmm_plan_t pl, int boundary, int uv_schem
 // ---------------------------------------------------------------------------
 // Evaluation
 // ---------------------------------------------------------------------------
-static fmm_status ensure_workspace(fmm_plan_t pl, int64_t n) {
+// The per-call workspace, as (buffer, bytes, used by fmm_energy_forces):
+// the tree part depends on the plan only, the atom part on n.
+struct WsItem {
+    DeviceBuf *buf;
+    size_t bytes;
+    bool eval;  // needed by an energy / forces evaluation (else only by the solute-solvent pass)
+};
+static void tree_layout(fmm_plan_t pl, std::vector<WsItem> &v) {
     const int64_t nleaf = level_cells(pl->levels);
+    const int64_t cells = level_offset(pl->levels + 1);
+    const size_t tb = sizeof(double) * (size_t)cells * pl->Kp;
+    // M2L scratch of the plan stream (any level) and of the upper-level side
+    // stream.  Sized for the largest need of every precision and tuning the
+    // plan can be switched to without a new plan: the side stream takes at
+    // most levels 1 .. levels - 2 (upper_m2l_levels).
+    size_t part = 8, part_up = 8;
+    for (int l = 1; l <= pl->levels; ++l) {
+        const size_t b = m2l_partial_bytes(l, pl->p, kILSize, sizeof(double));
+        part = std::max(part, b);
+        if (l <= pl->levels - 2) part_up = std::max(part_up, b);
+    }
+    const int lup_max = std::max(0, pl->levels - 2);
+    v.push_back({&pl->Mlev, tb, true});
+    v.push_back({&pl->Llev, tb, true});
+    v.push_back({&pl->M0, sizeof(double) * pl->Kp, true});
+    v.push_back({&pl->L0, sizeof(double) * pl->Kp, true});
+    v.push_back({&pl->mflip, m2l_flip_bytes(pl->levels, pl->p, sizeof(double)), true});
+    v.push_back({&pl->m2l_part, part, true});
+    v.push_back({&pl->mflip_up, lup_max > 0 ? m2l_flip_bytes(lup_max, pl->p, sizeof(double)) : 8, true});
+    v.push_back({&pl->m2l_part_up, part_up, true});
+    v.push_back({&pl->count, sizeof(uint32_t) * nleaf, true});
+    v.push_back({&pl->cursor, sizeof(uint32_t) * nleaf, true});
+    v.push_back({&pl->start, sizeof(int32_t) * (nleaf + 1), true});
+    v.push_back({&pl->pstart, sizeof(int32_t) * (nleaf + 1), true});
+    v.push_back({&pl->scan, sizeof(int32_t) * scan_scratch_len(nleaf), true});
+    v.push_back({&pl->scalars, sizeof(double) * kScalars, true});
+    v.push_back({&pl->flag, sizeof(int) * 4, true});
+    v.push_back({&pl->partials, sizeof(double) * 2 * 6 * 1024, true});
+    v.push_back({&pl->sflag, sizeof(uint32_t) * (size_t)(1 + cells), false});
+}
+static void atom_layout(fmm_plan_t pl, int64_t n, std::vector<WsItem> &v) {
+    const int64_t nleaf = level_cells(pl->levels);
+    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    v.push_back({&pl->key, sizeof(uint32_t) * nn, true});
+    v.push_back({&pl->perm, sizeof(int32_t) * nn, true});
+    v.push_back({&pl->xq, sizeof(double) * 4 * nn, true});
+    v.push_back({&pl->xs, sizeof(double) * 4 * nn, true});
+    v.push_back({&pl->xqp, sizeof(double) * 4 * (nn + (size_t)kMaxP2PGroups * nleaf), true});
+    v.push_back({&pl->phi_nf, sizeof(double) * nn, true});
+    v.push_back({&pl->field_nf, sizeof(double) * 3 * nn, true});
+    v.push_back({&pl->phi_ff, sizeof(double) * nn, true});
+    v.push_back({&pl->field_ff, sizeof(double) * 3 * nn, true});
+    v.push_back({&pl->xq_u, sizeof(double) * 4 * nn, false});
+    v.push_back({&pl->phi_u, sizeof(double) * nn, false});
+    v.push_back({&pl->field_u, sizeof(double) * 3 * nn, false});
+    v.push_back({&pl->nfuv, sizeof(double) * nn, false});
+    v.push_back({&pl->mask_sw, nn, false});
+    v.push_back({&pl->mask_s, nn, false});
+    v.push_back({&pl->nfsc, sizeof(double) * nn, false});
+    v.push_back({&pl->nfdl, sizeof(double) * nn, false});
+}
+
+static fmm_status ensure_workspace(fmm_plan_t pl, int64_t n) {
+    std::vector<WsItem> v;
     if (!pl->tree_ready) {
-        const int64_t cells = level_offset(pl->levels + 1);
-        const size_t tb = sizeof(double) * (size_t)cells * pl->Kp;
-        int64_t part = 0, part_up = 0;
-        for (int l = 1; l <= pl->levels; ++l)
-            if (m2l_slices(l) > 1) part = std::max(part, (int64_t)m2l_slices(l) * level_cells(l));
-        const int lup = upper_m2l_levels(pl);
-        for (int l = 1; l <= lup; ++l)
-            if (m2l_slices(l) > 1) part_up = std::max(part_up, (int64_t)m2l_slices(l) * level_cells(l));
-        const size_t flip_up = (size_t)m2l_flip_copies(pl->p) * (lup > 0 ? level_cells(lup) : 1) * pl->Kp;
-        if (!pl->Mlev.ensure(tb) || !pl->Llev.ensure(tb) || !pl->M0.ensure(sizeof(double) * pl->Kp) ||
-            !pl->mflip.ensure(sizeof(double) * (size_t)m2l_flip_copies(pl->p) * nleaf * pl->Kp) ||
-            !pl->m2l_part.ensure(sizeof(double) * (size_t)std::max<int64_t>(part, 1) * pl->Kp) ||
-            !pl->mflip_up.ensure(sizeof(double) * flip_up) ||
-            !pl->m2l_part_up.ensure(sizeof(double) * (size_t)std::max<int64_t>(part_up, 1) * pl->Kp) ||
-            !pl->L0.ensure(sizeof(double) * pl->Kp) || !pl->count.ensure(sizeof(uint32_t) * nleaf) ||
-            !pl->cursor.ensure(sizeof(uint32_t) * nleaf) || !pl->start.ensure(sizeof(int32_t) * (nleaf + 1)) ||
-            !pl->pstart.ensure(sizeof(int32_t) * (nleaf + 1)) ||
-            !pl->scan.ensure(sizeof(int32_t) * scan_scratch_len(nleaf)) ||
-            !pl->scalars.ensure(sizeof(double) * kScalars) || !pl->flag.ensure(sizeof(int) * 4) ||
-            !pl->partials.ensure(sizeof(double) * 2 * 6 * 1024) ||
-            !pl->sflag.ensure(sizeof(uint32_t) * (size_t)(1 + cells)))
-            return fail(pl, FMM_ERR_NOMEM, "tree workspace allocation");
+        tree_layout(pl, v);
+        for (const WsItem &w : v)
+            if (!w.buf->ensure(w.bytes)) return fail(pl, FMM_ERR_NOMEM, "tree workspace allocation");
         pl->tree_ready = true;
     }
     if (n > pl->cap_n) {
-        const size_t nn = (size_t)std::max<int64_t>(n, 1);
-        if (!pl->key.ensure(sizeof(uint32_t) * nn) || !pl->perm.ensure(sizeof(int32_t) * nn) ||
-            !pl->xq.ensure(sizeof(double) * 4 * nn) || !pl->xq_u.ensure(sizeof(double) * 4 * nn) ||
-            !pl->xs.ensure(sizeof(double) * 4 * nn) ||
-            !pl->xqp.ensure(sizeof(double) * 4 * (nn + (size_t)kMaxP2PGroups * nleaf)) ||
-            !pl->phi_nf.ensure(sizeof(double) * nn) || !pl->field_nf.ensure(sizeof(double) * 3 * nn) ||
-            !pl->phi_ff.ensure(sizeof(double) * nn) || !pl->field_ff.ensure(sizeof(double) * 3 * nn) ||
-            !pl->phi_u.ensure(sizeof(double) * nn) || !pl->field_u.ensure(sizeof(double) * 3 * nn) ||
-            !pl->nfuv.ensure(sizeof(double) * nn) || !pl->mask_sw.ensure(nn) || !pl->mask_s.ensure(nn) ||
-            !pl->nfsc.ensure(sizeof(double) * nn) || !pl->nfdl.ensure(sizeof(double) * nn))
-            return fail(pl, FMM_ERR_NOMEM, "per-atom workspace allocation");
+        v.clear();
+        atom_layout(pl, n, v);
+        for (const WsItem &w : v)
+            if (!w.buf->ensure(w.bytes)) return fail(pl, FMM_ERR_NOMEM, "per-atom workspace allocation");
         pl->cap_n = n;
     }
     return FMM_OK;
@@ -591,8 +688,9 @@ static fmm_status sort_atoms(fmm_plan_t pl, int64_t n, const double *pos, const 
 
 // a3 - a8 on the repacked atoms xq: far-field potential and field per sorted
 // atom.  Leaf level in the mode's type T; levels 1..top in FP64; level 0 FP64.
-// The two side streams of a single-box plan, created at its first
-// evaluation.  Sub-plans of a batch never fork and create none: every stream
+// The two side streams of a single-box plan, created with the plan (an
+// evaluation never creates a stream, so none is made while a graph is being
+// captured).  Sub-plans of a batch never fork and create none: every stream
 // takes one of the device's few hardware queues in turn, and unused streams
 // created beside the batch's per-box streams pushed several boxes onto one
 // queue (32-window batch: energies and forces 10.6 -> 13.8 ms).
@@ -637,10 +735,7 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
     // tree's small launches wait behind the near field for CU slots; off the
     // plan stream they no longer hold back the finest levels.
     const int lup = pl->in_batch ? 0 : upper_m2l_levels(pl);
-    if (lup > 0) {
-        fmm_status ss = ensure_side_streams(pl);
-        if (ss != FMM_OK) return ss;
-    }
+    if (lup > 0 && !pl->side_up) return fail(pl, FMM_ERR_STATE, "plan has no side stream for the upper tree");
     hipStream_t su = lup > 0 ? pl->side_up : s;
     auto m2m = [&](int l, hipStream_t ms) {
         const int64_t nc = level_cells(l);
@@ -673,20 +768,23 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
         const OpSet &o = *pl->op;
         if (l <= top && l <= 2)
             e = launch_m2l<double>(l, o.alias_ops[l - 1].as<double>(), o.alias_il[l - 1].as<int32_t>(),
-                                   o.alias_off[l - 1].as<int32_t>(), nullptr, MD(l), nullptr, nullptr, LD(l),
-                                   part.as<double>(), p, Kp, ls, 1 << (3 * l));
+                                   o.alias_off[l - 1].as<int32_t>(), nullptr, MD(l), nullptr, 0, nullptr, LD(l),
+                                   part.as<double>(), part.bytes, p, Kp, ls, 1 << (3 * l));
         else if (l <= top)
             e = launch_m2l<double>(l, o.ops64.as<double>(), o.pairs.as<int32_t>(), o.offv.as<int32_t>(),
-                                   o.rowmap.as<int32_t>(), MD(l), flip.as<double>(), o.zeros.as<double>(), LD(l),
-                                   part.as<double>(), p, Kp, ls);
+                                   o.rowmap.as<int32_t>(), MD(l), flip.as<double>(), flip.bytes, o.zeros.as<double>(),
+                                   LD(l), part.as<double>(), part.bytes, p, Kp, ls);
         else if (!TD && pl->prec == FMM_MIXED_BF16_M2L)
             e = launch_m2l_bf16(l, pl->op->opsbf.ptr, pl->op->il.as<int32_t>(), pl->op->offv.as<int32_t>(),
                                 reinterpret_cast<const float *>(MT(l)), reinterpret_cast<float *>(LT(l)),
-                                part.as<float>(), p, Kp, ls);
+                                part.as<float>(), part.bytes, p, Kp, ls);
         else
             e = launch_m2l<T>(l, sizeof(T) == 8 ? (const T *)o.ops64.ptr : (const T *)o.ops32.ptr,
                               o.pairs.as<int32_t>(), o.offv.as<int32_t>(), o.rowmap.as<int32_t>(), MT(l),
-                              flip.as<T>(), o.zeros.as<T>(), LT(l), part.as<T>(), p, Kp, ls);
+                              flip.as<T>(), flip.bytes, o.zeros.as<T>(), LT(l), part.as<T>(), part.bytes, p, Kp, ls);
+        if (e == hipErrorInvalidValue)
+            return fail(pl, FMM_ERR_DEVICE, "M2L level " + std::to_string(l) +
+                                                ": launch shape or scratch capacity rejected by the launcher");
         HIPCHK(pl, e, "M2L");
         if (l == L) stage_end(pl, FMM_STAGE_M2L_LEAF);
     }
@@ -716,11 +814,6 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
 }
 
 static int p2p_groups(int64_t n, int levels) {
-    static const int forced = [] {
-        const char *v = std::getenv("FMM_P2P_GROUPS");
-        return v ? std::atoi(v) : 0;
-    }();
-    if (forced == 1 || forced == 2 || forced == 4 || forced == 8 || forced == kMaxP2PGroups) return forced;
     // 4 groups of 16 target slots fit the 10-40 atom leaves of water boxes at
     // 4-7 A leaf edges best (measured: 30 atoms/leaf G 4 < 2 < 8; 11 atoms/leaf
     // G 4 < 8); sparse leaves take more groups, crowded ones fewer
@@ -751,10 +844,7 @@ static fmm_status run_fields(fmm_plan_t pl, int64_t n, const double *pos, const 
     // parallel graph branch per box, and the nested fork inside a captured
     // graph is not used (one such run ended in a host-side crash).
     const bool fork = !pl->in_batch;
-    if (fork) {
-        fmm_status ss = ensure_side_streams(pl);
-        if (ss != FMM_OK) return ss;
-    }
+    if (fork && !pl->side) return fail(pl, FMM_ERR_STATE, "plan has no side stream for the near field");
     hipStream_t ns = fork ? pl->side : s;
     auto near_field = [&]() -> fmm_status {
         if (fork) {
@@ -1299,10 +1389,9 @@ extern "C" fmm_status fmm_plan_batch(int nbox, const double *box, const int64_t 
         if (natoms && natoms[w] < 0) return bail(FMM_ERR_INVALID, "fmm_plan_batch: natoms must be >= 0");
         const int L = levels ? levels[w] : model_levels(natoms[w], p, FMM_MIXED);
         fmm_plan_t b = nullptr;
-        fmm_status st = plan_create(box[w], L, p, ops, &b);
+        fmm_status st = plan_create(box[w], L, p, ops, true, &b);
         if (st != FMM_OK) return bail(st, "fmm_plan_batch: box " + std::to_string(w) + ": " + g_plan_error);
         ops = b->op;
-        b->in_batch = true;
         pl->sub.push_back(b);
         pl->sub_natoms.push_back(natoms ? natoms[w] : -1);
         hipStream_t x = nullptr;
@@ -1580,11 +1669,12 @@ extern "C" fmm_status fmm_autotune_batch(fmm_plan_t pl, const int64_t *offsets, 
         for (int L = std::max(1, cur->levels - 1); L <= std::min(kMaxLevels, cur->levels + 1) && st == FMM_OK; ++L) {
             fmm_plan_t b = nullptr;
             if (L == cur->levels) b = cur;
-            else if ((st = plan_create(cur->box, L, pl->p, pl->op, &b)) != FMM_OK) {
+            else if ((st = plan_create(cur->box, L, pl->p, pl->op, true, &b)) != FMM_OK) {
                 pl->err = "autotune box " + std::to_string(w) + ": " + g_plan_error;
                 break;
             }
-            b->in_batch = true;
+            b->top_fp64 = cur->top_fp64;
+            b->boundary = cur->boundary;
             b->prec = pl->prec;
             b->stream = pl->sub_stream[w];
             for (int g : {2, 4, 8}) {
@@ -1601,11 +1691,16 @@ extern "C" fmm_status fmm_autotune_batch(fmm_plan_t pl, const int64_t *offsets, 
         if (st != FMM_OK) break;
         if (best_L != cur->levels) {
             fmm_plan_t b = nullptr;
-            if ((st = plan_create(cur->box, best_L, pl->p, pl->op, &b)) != FMM_OK) {
+            if ((st = plan_create(cur->box, best_L, pl->p, pl->op, true, &b)) != FMM_OK) {
                 pl->err = "autotune box " + std::to_string(w) + ": " + g_plan_error;
                 break;
             }
-            b->in_batch = true;
+            b->top_fp64 = cur->top_fp64;
+            b->boundary = cur->boundary;
+            b->uv_scheme = cur->uv_scheme;
+            b->sc_alpha = cur->sc_alpha;
+            b->sc_sigma = cur->sc_sigma;
+            b->sc_c = cur->sc_c;
             b->prec = pl->prec;
             b->stream = pl->sub_stream[w];
             fmm_destroy(cur);

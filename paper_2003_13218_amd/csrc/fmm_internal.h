@@ -155,11 +155,17 @@ hipError_t launch_l2l_sparse(int64_t nchild, const uint32_t *flag, const double 
 //     elements (the source of an absent image);
 //   nil < 875 (the aliased levels 1 and 2): `list` holds 8 x nil operator ids
 //     of operators in the plain swizzle_ops layout; rowmap, Mflip, zeros unused.
+// flip_cap / part_cap: bytes available in Mflip / partial; a launch that
+// would need more returns hipErrorInvalidValue before touching the GPU.
 int m2l_slices(int level);
+// bytes of the sign-flipped copies of one full-list level of elem-byte
+// coefficients, and of its split-K partials (0 when it is not split)
+size_t m2l_flip_bytes(int level, int p, size_t elem);
+size_t m2l_partial_bytes(int level, int p, int nil, size_t elem);
 template <typename T>
 hipError_t launch_m2l(int level, const T *ops, const int32_t *list, const int32_t *offs, const int32_t *rowmap,
-                      const T *M, T *Mflip, const T *zeros, T *L, T *partial, int p, int Kp, hipStream_t s,
-                      int nil = kILSize);
+                      const T *M, T *Mflip, size_t flip_cap, const T *zeros, T *L, T *partial, size_t part_cap, int p,
+                      int Kp, hipStream_t s, int nil = kILSize);
 // Symmetry scheme of the full-list operators for order p (1: (t, -t) pairs,
 // 2: orbits of the two-axis flips), their row blocks (rows grouped by class,
 // each class padded to 16), the blocks per class (returns the class count),
@@ -184,7 +190,7 @@ void swizzle_m2l_ops(int p, const double *ops_rowmajor /*1206 x K x K*/, T *out)
 size_t m2l_bf16_ops_elems(int p);
 void swizzle_m2l_ops_bf16(int p, const double *ops_rowmajor, uint16_t *out);
 hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const int32_t *offs, const float *M,
-                           float *L, float *partial, int p, int Kp, hipStream_t s);
+                           float *L, float *partial, size_t part_cap, int p, int Kp, hipStream_t s);
 // any nops row-major K x K operators into the matrix-core lane order
 template <typename T>
 void swizzle_ops(int p, int nops, const double *ops_rowmajor, T *out);

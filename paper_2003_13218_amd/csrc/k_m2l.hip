@@ -114,11 +114,6 @@ static int scheme_launches(int p, int scheme, bool fp64) {
 // the 3M-atom box this picks the pairs at p = 8 (41.8 vs 42.6 ms mixed, 71 vs
 // 79 ms FP64) and the orbits from p = 10 (84 vs 105 ms at p = 12).
 int m2l_scheme(int p) {
-    static const int forced = [] {
-        const char *v = std::getenv("FMM_M2L_SCHEME");
-        return v ? std::atoi(v) : 0;
-    }();
-    if (forced == 1 || forced == 2) return forced;
     const int64_t c1 = (int64_t)kM2LPairEntries * (scheme_blocks(p, 1) + 2 * scheme_launches(p, 1, false));
     const int64_t c2 = (int64_t)kM2LOrbitEntries * (scheme_blocks(p, 2) + 4 * scheme_launches(p, 2, false));
     return c2 < c1 ? 2 : 1;
@@ -928,23 +923,6 @@ __global__ void k_m2l_reduce(const P *__restrict__ partial, T *__restrict__ L, i
 // longer changes the result (1M-atom box: 10.05 ms per step against 10.13 /
 // 10.23 with 16 / 32 slices, identical errors).
 int m2l_slices(int level) {
-    // tuning: FMM_M2L_SLICES = "s1,s2,s3,s4,s5" overrides the slice counts of
-    // levels 1..5 (and deeper) with powers of two up to 64
-    static const std::vector<int> forced = [] {
-        std::vector<int> v;
-        if (const char *e = std::getenv("FMM_M2L_SLICES")) {
-            const char *c = e;
-            while (*c) {
-                const int k = std::atoi(c);
-                v.push_back((k >= 1 && k <= 64 && (k & (k - 1)) == 0) ? k : 0);
-                while (*c && *c != ',') ++c;
-                if (*c == ',') ++c;
-            }
-        }
-        return v;
-    }();
-    const int i = std::min(level, 5) - 1;
-    if (i >= 0 && i < (int)forced.size() && forced[i] > 0) return forced[i];
     switch (level) {
         case 1: return 64;
         case 2: return 64;
@@ -952,6 +930,18 @@ int m2l_slices(int level) {
         case 4: return 8;
         default: return 1;
     }
+}
+
+size_t m2l_flip_bytes(int level, int p, size_t elem) {
+    return (size_t)m2l_flip_copies(p) * ((size_t)1 << (3 * level)) * (size_t)padded_coeffs(p) * elem;
+}
+
+size_t m2l_partial_bytes(int level, int p, int nil, size_t elem) {
+    const int nslices = std::min(m2l_slices(level), nil);
+    if (nslices <= 1) return 0;
+    // FP32 operands on the full list keep their split-K partials in FP64
+    const size_t pe = (elem == 4 && nil == kILSize) ? 8 : elem;
+    return (size_t)nslices * ((size_t)1 << (3 * level)) * (size_t)padded_coeffs(p) * pe;
 }
 
 // ---------------------------------------------------------------------------
@@ -998,10 +988,13 @@ void swizzle_m2l_ops_bf16(int p, const double *ops, uint16_t *out) {
 }
 
 hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const int32_t *offs, const float *M,
-                           float *L, float *partial, int p, int Kp, hipStream_t s) {
+                           float *L, float *partial, size_t part_cap, int p, int Kp, hipStream_t s) {
     const int NB = Kp / 16;
     const int nh_bits = level - 1;
     const int nslices = partial ? m2l_slices(level) : 1;
+    // the caller's split-K buffer must hold every slice (checked on the host)
+    if (nslices > 1 && part_cap < (size_t)nslices * ((size_t)8 << (3 * nh_bits)) * (size_t)Kp * sizeof(float))
+        return hipErrorInvalidValue;
     RowGroup grp[kMaxRowGroups];
     const int ng = row_groups(0, p, NB, false, grp);
     hipError_t e = launch_lds<PolBf16>(ops, il, offs, nullptr, M, M, M, 0, nslices > 1 ? partial : L, nullptr, nh_bits, NB,
@@ -1055,12 +1048,17 @@ __global__ void k_m2l_flip(const T *__restrict__ M, T *__restrict__ Mflip, int64
 // and 2 (nil = 8 or 64 pre-summed operators) on the offset-split kernel.
 template <typename T>
 hipError_t launch_m2l(int level, const T *ops, const int32_t *list, const int32_t *offs, const int32_t *rowmap,
-                      const T *M, T *Mflip, const T *zeros, T *L, T *partial, int p, int Kp, hipStream_t s, int nil) {
+                      const T *M, T *Mflip, size_t flip_cap, const T *zeros, T *L, T *partial, size_t part_cap, int p,
+                      int Kp, hipStream_t s, int nil) {
     constexpr int CB = Mfma<T>::CB;
     const int NB = Kp / 16;
     const int nh_bits = level - 1;
     const int64_t ntarget = (int64_t)1 << (3 * nh_bits);
     const int nslices = partial ? std::min(m2l_slices(level), nil) : 1;
+    // scratch capacities, checked on the host before anything is launched:
+    // the split-K partials and the sign-flipped multipole copies of the level
+    if (nslices > 1 && part_cap < m2l_partial_bytes(level, p, nil, sizeof(T))) return hipErrorInvalidValue;
+    if (nil == kILSize && flip_cap < m2l_flip_bytes(level, p, sizeof(T))) return hipErrorInvalidValue;
     double *part64 = nullptr;
     if (nil == kILSize) {
         if (!rowmap || !Mflip || !zeros) return hipErrorInvalidValue;
@@ -1103,10 +1101,10 @@ hipError_t launch_m2l(int level, const T *ops, const int32_t *list, const int32_
     return hipGetLastError();
 }
 template hipError_t launch_m2l<float>(int, const float *, const int32_t *, const int32_t *, const int32_t *,
-                                      const float *, float *, const float *, float *, float *, int, int, hipStream_t,
-                                      int);
+                                      const float *, float *, size_t, const float *, float *, float *, size_t, int, int,
+                                      hipStream_t, int);
 template hipError_t launch_m2l<double>(int, const double *, const int32_t *, const int32_t *, const int32_t *,
-                                       const double *, double *, const double *, double *, double *, int, int,
-                                       hipStream_t, int);
+                                       const double *, double *, size_t, const double *, double *, double *, size_t,
+                                       int, int, hipStream_t, int);
 
 }  // namespace fmm

@@ -3,9 +3,11 @@
 
 The batch runs the same kernels as the single-box path, so with equal tree
 depths and P2P group counts its energies, forces and solute-solvent energies
-must equal one single-box plan per box bit for bit; the smallest windows are
-also checked against the FP64 Ewald oracle (energy and e_uv, mixed-precision
-tolerance 1e-5 in the unit used by the single-box tests).
+must equal one single-box plan per box bit for bit.  All 32 windows, at the
+depths and near-field groups the autotuner picks and with both solute-solvent
+schemes, are checked against the FP64 Ewald oracle values stored by
+tests/golden/make_c4_windows.py (energy, forces on a sample, e_uv; mixed
+precision tolerance 1e-5, e_uv in the unit used by the single-box tests).
 """
 import numpy as np
 import pytest
@@ -169,3 +171,56 @@ def test_batch_lambda_energy(fmm, windows):
         fmm.fmm_energy_forces(single, _t(w.pos), _t(w.q), forces=False)
         v, d = fmm.fmm_lambda_energy(single, _t(w.mask), lams[k])
         assert V[k] == v and D[k] == d
+
+
+def _c4_golden():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "c4_windows_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/c4_windows_oracle.npz not generated")
+    return np.load(path)
+
+
+@pytest.fixture(scope="module")
+def c4_tuned(fmm, windows):
+    # the 32-window batch exactly as the benchmark runs it: mixed precision,
+    # p 10, depths and near-field groups from the cost model refined by the
+    # autotuner on these inputs
+    off, pos, q, mask = _concat(windows)
+    plan = fmm.fmm_plan_batch([w.box for w in windows], 10, natoms=[w.n for w in windows])
+    fmm.fmm_plan_config(plan, fmm.FMM_MIXED)
+    tp, tq, tm = _t(pos), _t(q), _t(mask)
+    levels, groups = fmm.fmm_autotune_batch(plan, off, tp, tq)
+    print("C4 tuned levels", levels.tolist(), "groups", groups.tolist())
+    return plan, off, tp, tq, tm
+
+
+@pytest.mark.parametrize("scheme", [0, 1])  # FMM_UV_SYMMETRIC, FMM_UV_SPARSE
+def test_c4_all_windows_vs_oracle(fmm, windows, c4_tuned, scheme):
+    # every window of the batched workload against the FP64 Ewald oracle
+    # (tests/golden/make_c4_windows.py): energy relative <= 1e-5, force RMS
+    # relative over the stored 200-atom sample + ion <= 1e-5, e_uv <= 1e-5 in
+    # the solute-solvent unit sum_u |q| x rms(phi)
+    ref = _c4_golden()
+    plan, off, tp, tq, tm = c4_tuned
+    assert ref["n"].tolist() == [w.n for w in windows]
+    fmm.fmm_plan_options(plan, fmm.FMM_BOUNDARY_CONDUCTING, scheme)
+    E, F = fmm.fmm_energy_forces_batch(plan, off, tp, tq)
+    U = fmm.fmm_solute_solvent_energy_batch(plan, tm)
+    F = F.cpu().numpy()
+    worst = [0.0, 0.0, 0.0]
+    for k, w in enumerate(windows):
+        s0, s1 = ref["off"][k], ref["off"][k + 1]
+        idx = ref["idx"][s0:s1]
+        assert w.mask[idx].sum() == 1  # the ion is in the sample
+        e_rel = abs(E[k] - ref["energy"][k]) / abs(ref["energy"][k])
+        f = F[off[k]:off[k + 1]][idx]
+        fr = ref["force"][s0:s1]
+        f_rel = float(np.sqrt(((f - fr) ** 2).sum() / (fr ** 2).sum()))
+        scale = float(np.sum(np.abs(w.q[w.mask == 1]))) * ref["rms_phi"][k]
+        u_err = abs(U[k] - ref["e_uv"][k]) / max(scale, 1e-12) if scale > 0 else abs(U[k])
+        worst = [max(worst[0], e_rel), max(worst[1], f_rel), max(worst[2], u_err)]
+        assert e_rel < 1e-5, (k, e_rel)
+        assert f_rel < 1e-5, (k, f_rel)
+        assert u_err < 1e-5, (k, U[k], ref["e_uv"][k])
+    print(f"C4 scheme {scheme}: worst E rel {worst[0]:.2e}, F rms rel {worst[1]:.2e}, e_uv {worst[2]:.2e}")
