@@ -186,6 +186,32 @@ fmm_status fmm_energy_forces(fmm_plan_t plan, int64_t n, const double *pos, cons
                              double *energy, double *forces, double *phi);
 
 /*
+ * fmm_energy_forces_noalloc -- fmm_energy_forces for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, same kernels and the same
+ * results bit for bit; it calls no hipMalloc, hipFree or allocating library
+ * routine.  Its per-call workspace (sorted atoms, expansions, M2L scratch,
+ * near-field copy, reductions) is carved from one fixed array of
+ * FMM_NOALLOC_SCRATCH_BYTES bytes of device memory that the library holds on
+ * each GPU it runs on until the process ends, shared by every plan and call
+ * on that GPU and keeping the last call's contents (every piece is written
+ * before it is read).  Calls that overlap on one GPU (two threads, or two
+ * plans on different streams) race on it: the caller serialises them.
+ * The plan's operators must be on the device already (fmm_plan,
+ * fmm_plan_config and fmm_plan_tuning upload them; FMM_ERR_STATE otherwise).
+ * A workspace larger than the array gives FMM_ERR_INVALID before any GPU
+ * work, with the bytes needed in fmm_last_error: about 170 bytes per atom
+ * plus, per tree, 16 (8^(levels+1) / 7) Kp bytes for the expansions and the
+ * M2L scratch of the deepest level (3 x 8^levels x 8 Kp bytes) and of the
+ * split-K levels; e.g. 30,000 atoms at levels 4, p 10 fit, 1,000,000 atoms at
+ * levels 5, p 12 do not.  No state is kept for fmm_solute_solvent_energy (it
+ * returns FMM_ERR_STATE after this call).  Batch plans are rejected.
+ */
+#define FMM_NOALLOC_SCRATCH_BYTES (128ull << 20)
+fmm_status fmm_energy_forces_noalloc(fmm_plan_t plan, int64_t n, const double *pos, const double *q,
+                                     double *energy, double *forces, double *phi);
+
+/*
  * fmm_solute_solvent_energy -- the solute-solvent interaction energy
  *   e_uv = E(u + Bu  U  v + Bv) - E(u + Bu) - E(v + Bv)
  * for the partition mask[i] = 1 (solute u) / 0 (solvent v), each part with

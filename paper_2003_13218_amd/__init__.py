@@ -13,4 +13,5 @@ from .binding import (FMM_FP64, FMM_MIXED, FMM_MIXED_BF16_M2L, FMM_BOUNDARY_COND
                       fmm_solute_solvent_energy, fmm_version, fmm_plan_batch, fmm_energy_forces_batch,
                       fmm_solute_solvent_energy_batch, fmm_autotune_batch, fmm_batch_levels,
                       fmm_lambda_energy, fmm_lambda_energy_batch, fmm_plan_options,
-                      fmm_plan_softcore, fmm_plan_info, fmm_plan_tuning)
+                      fmm_plan_softcore, fmm_plan_info, fmm_plan_tuning,
+                      fmm_energy_forces_noalloc)

@@ -34,6 +34,7 @@ EXPORTED = (
     "fmm_last_error", "fmm_destroy", "fmm_version", "fmm_plan_batch", "fmm_energy_forces_batch",
     "fmm_solute_solvent_energy_batch", "fmm_autotune_batch", "fmm_batch_levels", "fmm_lambda_energy",
     "fmm_lambda_energy_batch", "fmm_plan_options", "fmm_plan_softcore", "fmm_plan_info", "fmm_plan_tuning",
+    "fmm_energy_forces_noalloc",
 )
 
 STAGES = ("sort", "gather", "p2m", "m2m", "lattice", "m2l", "m2l_leaf", "l2l", "l2p", "p2p", "final", "total")
@@ -72,6 +73,8 @@ def load():
         lib.fmm_plan_info.restype = ci
         lib.fmm_energy_forces.argtypes = [vp, i64, vp, vp, ctypes.POINTER(dbl), vp, vp]
         lib.fmm_energy_forces.restype = ci
+        lib.fmm_energy_forces_noalloc.argtypes = [vp, i64, vp, vp, ctypes.POINTER(dbl), vp, vp]
+        lib.fmm_energy_forces_noalloc.restype = ci
         lib.fmm_solute_solvent_energy.argtypes = [vp, vp, ctypes.POINTER(dbl)]
         lib.fmm_solute_solvent_energy.restype = ci
         lib.fmm_potential_parts.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
@@ -206,6 +209,20 @@ def fmm_energy_forces(plan: Plan, pos, q, forces=True, phi=False):
                                     _dptr(f, torch.float64, (3,), "forces"),
                                     _dptr(ph, torch.float64, (), "phi")), plan)
     return e.value, f, ph
+
+
+def fmm_energy_forces_noalloc(plan: Plan, pos, q, forces=None, phi=None):
+    """fmm_energy_forces on the library's fixed device scratch (no allocation in
+    the library).  forces / phi: caller-owned output tensors ((n, 3) and (n,)
+    float64) or None.  Returns the energy."""
+    import torch
+    n = int(q.shape[0])
+    e = ctypes.c_double()
+    _check(load().fmm_energy_forces_noalloc(plan.handle, n, _dptr(pos, torch.float64, (3,), "pos"),
+                                            _dptr(q, torch.float64, (), "q"), ctypes.byref(e),
+                                            _dptr(forces, torch.float64, (3,), "forces"),
+                                            _dptr(phi, torch.float64, (), "phi")), plan)
+    return e.value
 
 
 def fmm_solute_solvent_energy(plan: Plan, mask) -> float:

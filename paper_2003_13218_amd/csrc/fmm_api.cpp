@@ -9,6 +9,7 @@
 #include <string>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -179,6 +180,29 @@ static int64_t level_offset(int l) {
 
 static bool rec_uploaded[64] = {false};
 
+// ---------------------------------------------------------------------------
+// Scratch of fmm_energy_forces_noalloc: one fixed array in device memory per
+// GPU (the module's own copy on each device), shared by every plan and call
+// on that device.  Host code never uses the array's name as an address: its
+// device address is taken once per device, with that device current, when
+// the first plan is made there, and only that address is passed on.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = (size_t)FMM_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64] = {};
+static hipError_t g_scratch_err[64] = {};
+
+// with `device` current
+static void scratch_setup(int device) {
+    if (device < 0 || device >= 64) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && ptr) g_scratch_ptr[device] = ptr;
+    else g_scratch_err[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+}
 
 static void batch_drop_graphs(fmm_plan_t pl) {
     for (auto *g : {&pl->g_ef, &pl->g_uv}) {
@@ -443,6 +467,7 @@ static fmm_status plan_create(double box, int levels, int p, const std::shared_p
         fmm_destroy(pl);
         return s;
     };
+    scratch_setup(pl->device);
     if (pl->device < 64 && !rec_uploaded[pl->device]) {
         RecTables t;
         build_rec_tables(&t);
@@ -978,6 +1003,67 @@ extern "C" fmm_status fmm_energy_forces(fmm_plan_t pl, int64_t n, const double *
         pl->have_state = true;
         pl->n_state = n;
     }
+    return st;
+}
+
+// Evaluation on the library's fixed device scratch instead of the plan's own
+// workspace: the plan's workspace buffers are pointed at consecutive
+// 256-byte-aligned pieces of the scratch for the duration of the call and
+// put back on every return path.
+struct ScratchViews {
+    std::vector<std::pair<DeviceBuf *, DeviceBuf>> saved;
+    ~ScratchViews() {
+        for (auto &s : saved) *s.first = s.second;
+    }
+};
+
+extern "C" fmm_status fmm_energy_forces_noalloc(fmm_plan_t pl, int64_t n, const double *pos, const double *q,
+                                                double *energy, double *forces, double *phi) {
+    fmm_status st = check_eval_args(pl, n, pos, q);
+    if (st != FMM_OK) return st;
+    if (!energy) return fail(pl, FMM_ERR_INVALID, "energy must be non-NULL");
+    pl->have_state = false;
+    if (n == 0) {
+        *energy = 0.0;
+        pl->last_energy = 0.0;
+        return FMM_OK;
+    }
+    HIPCHK(pl, hipSetDevice(pl->device), "hipSetDevice");
+    if (pl->device < 0 || pl->device >= 64 || !g_scratch_ptr[pl->device])
+        return hip_fail(pl, pl->device >= 0 && pl->device < 64 ? g_scratch_err[pl->device] : hipErrorInvalidDevice,
+                        "fmm_energy_forces_noalloc: device address of the scratch array");
+    if (!m2l_ops_ready(pl, false))
+        return fail(pl, FMM_ERR_STATE, "fmm_energy_forces_noalloc: the operators of the current mode are not on the "
+                                       "device (fmm_plan, fmm_plan_config and fmm_plan_tuning upload them)");
+    std::vector<WsItem> items;
+    tree_layout(pl, items);
+    atom_layout(pl, n, items);
+    size_t need = 0;
+    for (const WsItem &w : items)
+        if (w.eval) need = (need + 255) / 256 * 256 + w.bytes;
+    if (need > kNoAllocScratchBytes)
+        return fail(pl, FMM_ERR_INVALID,
+                    "fmm_energy_forces_noalloc: " + std::to_string(n) + " atoms on this plan need " +
+                        std::to_string(need) + " bytes of scratch, more than the " +
+                        std::to_string(kNoAllocScratchBytes) + " available");
+    char *base = static_cast<char *>(g_scratch_ptr[pl->device]);
+    ScratchViews views;
+    size_t at = 0;
+    for (const WsItem &w : items) {
+        if (!w.eval) continue;
+        at = (at + 255) / 256 * 256;
+        views.saved.emplace_back(w.buf, *w.buf);
+        w.buf->ptr = base + at;
+        w.buf->bytes = w.bytes;
+        w.buf->borrowed = true;
+        at += w.bytes;
+    }
+    stage_reset(pl);
+    st = pl->prec == FMM_FP64 ? energy_forces_t<double>(pl, n, pos, q, energy, forces, phi)
+                              : energy_forces_t<float>(pl, n, pos, q, energy, forces, phi);
+    // the sorted atoms live in the shared scratch, which the next call on this
+    // device overwrites: no state is kept for fmm_solute_solvent_energy
+    pl->have_state = false;
     return st;
 }
 
