@@ -89,71 +89,120 @@ __device__ inline void regular_hat_foreach(T x, T y, T z, int p, F &&f) {
 
 // ---------------------------------------------------------------------------
 // P2M (eq. P2M): M~_n^m(leaf) = sum_j q_j conj(R^_n^m((r_j - c)/h)).
-// One workgroup (one wavefront) per leaf; each lane evaluates one atom's
-// harmonics into LDS, then lanes sum columns.  Deterministic order.
+// One thread per (leaf, pair of orders {m, P - m}): the two columns n >= m of
+// the pair hold P + 2 coefficients together whatever m is, so every thread
+// does the same work per atom -- the two sectoral values (P steps of their
+// recurrence) and P + 2 steps of the three-term recurrence in n, down column m
+// and then down column P - m.  The middle column m = P/2 (P even) is a thread
+// of its own.  Each thread walks its leaf's atoms in sorted order and keeps
+// its P + 2 complex sums in FP64 registers (rounded once on store): no LDS,
+// no cross-lane reduction, and every leaf (empty ones too) is written.
 // ---------------------------------------------------------------------------
-constexpr int kMaxKPerLane = (num_coeffs(kMaxP) + 63) / 64;
+template <int P> constexpr int p2m_threads() { return P / 2 + 1; }
 
-template <typename T>
-__global__ __launch_bounds__(64) void k_p2m(int64_t nleaf, const T *__restrict__ xq,
-                                            const int32_t *__restrict__ start, T *__restrict__ M,
-                                            int p, int K, int Kp, T inv_h, int chunk) {
-    extern __shared__ unsigned char smem_raw[];
-    T *sm = reinterpret_cast<T *>(smem_raw);
-    const int tid = threadIdx.x;
-    for (int64_t leaf = blockIdx.x; leaf < nleaf; leaf += gridDim.x) {
-        const int32_t s0 = start[leaf], s1 = start[leaf + 1];
-        double acc[kMaxKPerLane];  // leaf sums in FP64 (rounded once on store)
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_p2m(int64_t nleaf, const T *__restrict__ xq,
+                                             const int32_t *__restrict__ start, T *__restrict__ M, int Kp,
+                                             T inv_h) {
+    constexpr int NT = p2m_threads<P>();  // threads per leaf
+    constexpr int NS = P + 2;             // coefficients of a column pair
+    constexpr int K = (P + 1) * (P + 1);
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t leaf = gid / NT;
+    if (leaf >= nleaf) return;
+    const int mA = (int)(gid - leaf * NT), mB = P - mA;
+    const int nA = P + 1 - mA;             // steps down column mA (n = mA .. P)
+    const int ns = mB != mA ? NS : nA;     // steps of this thread
+    // per step: its order m, degree n and recurrence weights (z and r^2)
+    T ca[NS], cb[NS];
 #pragma unroll
-        for (int u = 0; u < kMaxKPerLane; ++u) acc[u] = 0;
-        for (int32_t base = s0; base < s1; base += chunk) {
-            const int cnt = min(chunk, s1 - base);
-            if (tid < cnt) {
-                const T *a = xq + 4 * (int64_t)(base + tid);
-                const T x = a[0] * inv_h, y = a[1] * inv_h, z = a[2] * inv_h, q = a[3];
-                T *row = sm + (size_t)tid * K;
-                regular_hat_foreach<T>(x, y, z, p, [&](int n, int m, T re, T im) {
-                    if (m == 0) row[n * n] = q * re;
-                    else {
-                        row[n * n + 2 * m - 1] = q * re;
-                        row[n * n + 2 * m] = -q * im;
-                    }
-                });
-            }
-            __syncthreads();
-#pragma unroll
-            for (int u = 0; u < kMaxKPerLane; ++u) {
-                const int j = tid + 64 * u;
-                if (j < K)
-                    for (int a = 0; a < cnt; ++a) acc[u] += (double)sm[(size_t)a * K + j];
-            }
-            __syncthreads();
-        }
-#pragma unroll
-        for (int u = 0; u < kMaxKPerLane; ++u) {
-            const int j = tid + 64 * u;
-            if (j < Kp) M[leaf * Kp + j] = j < K ? (T)acc[u] : (T)0;
-        }
-        // Kp may exceed 64 * kMaxKPerLane only if K does; padded tail:
-        for (int j = 64 * kMaxKPerLane + tid; j < Kp; j += 64) M[leaf * Kp + j] = 0;
+    for (int st = 0; st < NS; ++st) {
+        const int m = st < nA ? mA : mB;
+        const int n = st < nA ? mA + st : mB + (st - nA);
+        const int o = n - m;
+        ca[st] = o == 1 ? Rec<T>::d(m) : (o >= 2 ? Rec<T>::a(n * (n + 1) / 2 + m) : (T)0);
+        cb[st] = o >= 2 ? Rec<T>::b(n * (n + 1) / 2 + m) : (T)0;
     }
+    double are[NS], aim[NS];
+#pragma unroll
+    for (int st = 0; st < NS; ++st) are[st] = aim[st] = 0.0;
+    const int32_t s0 = start[leaf], s1 = start[leaf + 1];
+    for (int32_t s = s0; s < s1; ++s) {
+        const T *a = xq + 4 * (int64_t)s;
+        const T x = a[0] * inv_h, y = a[1] * inv_h, z = a[2] * inv_h, q = a[3];
+        const T r2 = x * x + y * y + z * z;
+        // sectoral values R^_mA^mA and R^_mB^mB (mA <= mB)
+        T sre = 1, sim = 0, Are = 1, Aim = 0;
+#pragma unroll
+        for (int k = 1; k <= P; ++k) {
+            const T c = -Rec<T>::c(k);
+            const T nre = c * (x * sre - y * sim);
+            const T nim = c * (x * sim + y * sre);
+            // past mB the value is kept (the same P steps for every thread)
+            sre = k <= mB ? nre : sre;
+            sim = k <= mB ? nim : sim;
+            if (k == mA) { Are = sre; Aim = sim; }
+        }
+        T p1re = 0, p1im = 0, p2re = 0, p2im = 0;
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            const bool first = st == 0 || st == nA;
+            T vre = ca[st] * z * p1re - cb[st] * r2 * p2re;
+            T vim = ca[st] * z * p1im - cb[st] * r2 * p2im;
+            if (first) {
+                vre = st == 0 ? Are : sre;
+                vim = st == 0 ? Aim : sim;
+            }
+            p2re = first ? (T)0 : p1re;
+            p2im = first ? (T)0 : p1im;
+            p1re = vre;
+            p1im = vim;
+            are[st] += (double)(q * vre);
+            aim[st] += (double)(q * vim);
+        }
+    }
+    T *Ml = M + leaf * Kp;
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+        const int m = st < nA ? mA : mB;
+        const int n = st < nA ? mA + st : mB + (st - nA);
+        if (st < ns) {
+            if (m == 0) {
+                Ml[n * n] = (T)are[st];
+            } else {
+                Ml[n * n + 2 * m - 1] = (T)are[st];
+                Ml[n * n + 2 * m] = (T)(-aim[st]);
+            }
+        }
+    }
+    if (mA == 0)
+        for (int k = K; k < Kp; ++k) Ml[k] = (T)0;
+}
+
+template <typename T, int P>
+static hipError_t launch_p2m_p(int64_t nleaf, const void *xq, const int32_t *start, T *M, int Kp, double inv_h,
+                               hipStream_t s) {
+    const int64_t nthreads = nleaf * p2m_threads<P>();
+    const int64_t g = (nthreads + 255) / 256;
+    hipLaunchKernelGGL((k_p2m<T, P>), dim3((unsigned)g), dim3(256), 0, s, nleaf, (const T *)xq, start, M, Kp,
+                       (T)inv_h);
+    return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_p2m(int64_t nleaf, const void *xq, const int32_t *start, T *M, int p, int Kp,
                       double inv_h, hipStream_t s) {
-    const int K = num_coeffs(p);
-    // atoms staged per pass: at most 32 (one pass for the 10-30 atoms of a
-    // typical leaf) and at most 32 KB of LDS, so that several single-wave
-    // workgroups share a CU and hide each other's latency
-    int chunk = (int)(32768 / ((size_t)K * sizeof(T)));
-    if (chunk > 32) chunk = 32;
-    if (chunk < 1) chunk = 1;
-    const size_t lds = (size_t)chunk * K * sizeof(T);
-    int64_t g = nleaf < 1048576 ? nleaf : 1048576;
-    hipLaunchKernelGGL(k_p2m<T>, dim3((unsigned)g), dim3(64), lds, s, nleaf, (const T *)xq, start, M, p,
-                       K, Kp, (T)inv_h, chunk);
-    return hipGetLastError();
+    if (nleaf * (p / 2 + 1) > ((int64_t)0xffffffff) * 256) return hipErrorInvalidValue;
+    switch (p) {
+#define FMM_P2M_CASE(P) \
+    case P: return launch_p2m_p<T, P>(nleaf, xq, start, M, Kp, inv_h, s);
+        FMM_P2M_CASE(0) FMM_P2M_CASE(1) FMM_P2M_CASE(2) FMM_P2M_CASE(3) FMM_P2M_CASE(4) FMM_P2M_CASE(5)
+        FMM_P2M_CASE(6) FMM_P2M_CASE(7) FMM_P2M_CASE(8) FMM_P2M_CASE(9) FMM_P2M_CASE(10) FMM_P2M_CASE(11)
+        FMM_P2M_CASE(12) FMM_P2M_CASE(13) FMM_P2M_CASE(14) FMM_P2M_CASE(15) FMM_P2M_CASE(16) FMM_P2M_CASE(17)
+        FMM_P2M_CASE(18) FMM_P2M_CASE(19) FMM_P2M_CASE(20)
+#undef FMM_P2M_CASE
+        default: return hipErrorInvalidValue;
+    }
 }
 template hipError_t launch_p2m<float>(int64_t, const void *, const int32_t *, float *, int, int, double,
                                       hipStream_t);
