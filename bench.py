@@ -327,6 +327,16 @@ def run_batch(args):
             fn()
         torch.cuda.synchronize()
         split[name] = round(1e3 * (time.perf_counter() - t1) / args.steps, 3)
+    # the other solute-solvent scheme, timed the same way
+    other = "symmetric" if args.uv_scheme == "sparse" else "sparse"
+    F.fmm_plan_options(plan, F.FMM_BOUNDARY_CONDUCTING, UV_SCHEMES[other])
+    U_other = F.fmm_solute_solvent_energy_batch(plan, mask)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        F.fmm_solute_solvent_energy_batch(plan, mask)
+    torch.cuda.synchronize()
+    split[f"solute_solvent_{other}"] = round(1e3 * (time.perf_counter() - t1) / args.steps, 3)
     print(f"[bench] C4 split (ms/call): {split}", file=sys.stderr, flush=True)
     return {
         "metric": "atom-evals/s (energy+forces+solute-solvent energy), 32 charging windows, one graph launch each",
@@ -339,7 +349,7 @@ def run_batch(args):
                    "model_levels": model_levels.tolist(), "tuned_levels": levels.tolist(),
                    "tuned_p2p_groups": groups.tolist(), "autotune_s": round(t_tune, 2)},
         "split_ms": split,
-        "energies": E.tolist(), "e_uv": U.tolist(),
+        "energies": E.tolist(), "e_uv": U.tolist(), f"e_uv_{other}": U_other.tolist(),
         "roofline": None,
     }
 
@@ -353,7 +363,7 @@ def main():
     ap.add_argument("--p", type=int, default=0, help="expansion order (default: the workload's)")
     ap.add_argument("--prec", default="mixed", choices=list(PREC_NAMES))
     ap.add_argument("--sweep", action="store_true", help="C5: p x precision sweep")
-    ap.add_argument("--uv-scheme", default="symmetric", choices=list(UV_SCHEMES),
+    ap.add_argument("--uv-scheme", default="sparse", choices=list(UV_SCHEMES),
                     help="C4: far-field scheme of the solute-solvent energy")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

@@ -111,6 +111,14 @@ struct fmm_plan {
     DeviceBuf mask_sw;  // exchanged solute mask (FMM_UV_SWAP)
     DeviceBuf mask_s;   // solute mask in sorted order
     DeviceBuf nfsc, nfdl;  // soft-core near-field u-v sums per solute atom
+    // solute-solvent stage tables (UvBox entries + block tables) and the host
+    // copy of what was last uploaded
+    DeviceBuf uvtab;
+    std::vector<unsigned char> uvtab_host;
+    // batch plans: the boxes' solute-solvent scalar blocks, contiguous, and
+    // their pinned host mirror
+    DeviceBuf uvsc;
+    double *h_uvsc = nullptr;
     // soft-core near-field u-v pairs of the lambda-coupled energy (alpha 0: off)
     double sc_alpha = 0.0, sc_sigma = 1.0;
     int sc_c = 6;
@@ -648,7 +656,7 @@ static void tree_layout(fmm_plan_t pl, std::vector<WsItem> &v) {
     v.push_back({&pl->scan, sizeof(int32_t) * scan_scratch_len(nleaf), true});
     v.push_back({&pl->scalars, sizeof(double) * kScalars, true});
     v.push_back({&pl->flag, sizeof(int) * 4, true});
-    v.push_back({&pl->partials, sizeof(double) * 2 * 6 * 1024, true});
+    v.push_back({&pl->partials, sizeof(double) * 2 * 16 * 1024, true});
     v.push_back({&pl->sflag, sizeof(uint32_t) * (size_t)(1 + cells), false});
 }
 static void atom_layout(fmm_plan_t pl, int64_t n, std::vector<WsItem> &v) {
@@ -1105,95 +1113,189 @@ extern "C" fmm_status fmm_potential_parts(fmm_plan_t pl, int64_t n, const double
     return st;
 }
 
-// Pass 2 of the one-sided scheme (FMM_UV_SPARSE): the far-field potential of
-// the masked charges alone, at the masked atoms alone, into phi_u (0 at the
-// others).  The tree of those charges is non-zero only in the cells above the
-// leaves that hold them, and their potential is wanted only in the same
-// leaves, so every stage runs over the flagged cells (all in FP64, in the
-// level arrays of pass 1, which are free again): the dense algorithm
-// restricted to the cells whose terms are not identically zero.
-static fmm_status sparse_solute_field(fmm_plan_t pl, const uint8_t *mask) {
+// ---------------------------------------------------------------------------
+// The solute-solvent pass (eq. FMMcalc) of one box or of every box of a batch,
+// each stage one launch for all boxes (block tables built here).
+//   FMM_UV_SPARSE: the far field of the masked charges alone, at the masked
+//     atoms alone (phi_u, 0 at the others): the tree of those charges is
+//     non-zero only in the cells above the leaves that hold them, and their
+//     potential is wanted only in the same leaves, so every stage runs over
+//     the flagged cells (all in FP64, in the level arrays of the evaluation,
+//     which are free again): the dense algorithm restricted to the cells
+//     whose terms are not identically zero.
+//   FMM_UV_SYMMETRIC: a dense far-field pass over the masked charges per box
+//     (far_field), before the shared stages.
+// Shared stages: solute flags in sorted order, near-field u-v pairs, sums.
+// ---------------------------------------------------------------------------
+enum { kStFill, kStAtom, kStLeaf, kStLat, kStRed, kStOne, kStFixed };  // then M2M steps, then levels
+
+struct UvTables {
+    std::vector<UvBox> box;
+    int maxL = 0;
+    std::vector<int64_t> tab;    // tables of nbox + 1 block starts
+    std::vector<int64_t> total;  // blocks of each table
+    int ntab() const { return kStFixed + 2 * maxL; }
+    int m2m(int step) const { return kStFixed + step - 1; }
+    int lvl(int l) const { return kStFixed + maxL + l - 1; }
+};
+
+static int64_t uv_blocks(int k, const UvTables &t, const UvBox &b) {
+    if (b.n == 0) return 0;
+    const int L = b.levels;
+    if (k == kStFill) return (1 + level_offset(L + 1) + 255) / 256;
+    if (k == kStAtom) return (b.n + 255) / 256;
+    if (k == kStLeaf) return level_cells(L);
+    if (k == kStLat) return (b.Kp + 63) / 64;
+    if (k == kStRed) return moments_blocks(b.n);
+    if (k == kStOne) return 1;
+    if (k < kStFixed + t.maxL) {
+        const int step = k - kStFixed + 1;
+        return L >= step ? level_cells(L - step) : 0;
+    }
+    const int l = k - kStFixed - t.maxL + 1;
+    return L >= l ? level_cells(l) : 0;
+}
+
+static void uv_build_tables(UvTables &t) {
+    const size_t nb = t.box.size();
+    t.maxL = 0;
+    for (const UvBox &b : t.box)
+        if (b.n > 0) t.maxL = std::max(t.maxL, b.levels);
+    t.tab.assign((size_t)t.ntab() * (nb + 1), 0);
+    t.total.assign(t.ntab(), 0);
+    for (int k = 0; k < t.ntab(); ++k) {
+        int64_t run = 0;
+        for (size_t w = 0; w < nb; ++w) {
+            t.tab[(size_t)k * (nb + 1) + w] = run;
+            run += uv_blocks(k, t, t.box[w]);
+        }
+        t.tab[(size_t)k * (nb + 1) + nb] = run;
+        t.total[k] = run;
+    }
+}
+
+// The UvBox entry of plan b (a single-box plan or a box of a batch) for its
+// last evaluation; mask: the box's rows of the caller's mask; lam >= 0 with a
+// soft-core set: the soft-core sums at lam; sc: the box's scalar block
+static UvBox uv_box(fmm_plan_t b, const uint8_t *mask, double lam, double *sc) {
+    UvBox u{};
+    u.n = b->n_state;
+    u.levels = b->levels;
+    u.p = b->p;
+    u.K = b->K;
+    u.Kp = b->Kp;
+    u.invert = (b->uv_scheme & FMM_UV_SWAP) ? 1 : 0;
+    const bool soft = lam >= 0.0 && b->sc_alpha > 0.0;
+    u.soft_c = soft ? b->sc_c : 0;
+    u.box = b->box;
+    u.h = b->box / (double)(1 << b->levels);
+    if (soft) {
+        const double sigc = std::pow(b->sc_sigma, (double)b->sc_c);
+        u.asc = b->sc_alpha * lam * sigc;
+        u.kd = b->sc_alpha * sigc / b->sc_c;
+    }
+    u.xs = b->xs.as<double>();
+    u.xq = b->xq.ptr;
+    u.key = b->key.as<uint32_t>();
+    u.perm = b->perm.as<int32_t>();
+    u.start = b->start.as<int32_t>();
+    u.mask = mask;
+    u.ms = b->mask_s.as<uint8_t>();
+    u.flag = b->sflag.as<uint32_t>();
+    u.M = b->Mlev.as<double>();
+    u.L = b->Llev.as<double>();
+    u.M0 = b->M0.as<double>();
+    u.L0 = b->L0.as<double>();
+    u.lat = b->lat.as<double>();
+    u.phi_uv = b->phi_ff.as<double>();
+    u.phi_u = b->phi_u.as<double>();
+    u.nfuv = b->nfuv.as<double>();
+    u.nfsc = b->nfsc.as<double>();
+    u.nfdl = b->nfdl.as<double>();
+    u.partials = b->partials.as<double>();
+    u.sc = sc;
+    return u;
+}
+
+// Uploads the tables into owner->uvtab (synchronously, before anything that
+// reads them is enqueued or captured; skipped when unchanged).
+static fmm_status uv_upload(fmm_plan_t owner, const UvTables &t) {
+    const size_t bb = sizeof(UvBox) * t.box.size(), tb = sizeof(int64_t) * t.tab.size();
+    std::vector<unsigned char> host(bb + tb);
+    std::memcpy(host.data(), t.box.data(), bb);
+    std::memcpy(host.data() + bb, t.tab.data(), tb);
+    if (host == owner->uvtab_host && owner->uvtab.ptr) return FMM_OK;
+    if (!owner->uvtab.ensure(host.size())) return fail(owner, FMM_ERR_NOMEM, "solute-solvent table allocation");
+    HIPCHK(owner, hipMemcpy(owner->uvtab.ptr, host.data(), host.size(), hipMemcpyHostToDevice), "table upload");
+    owner->uvtab_host.swap(host);
+    return FMM_OK;
+}
+
+// The shared stages (and, for FMM_UV_SPARSE, the sparse solute tree) of the
+// boxes of t, on stream s; ops: the plan's operator set (shared by all boxes)
+template <typename T>
+static fmm_status enqueue_uv_stages(fmm_plan_t owner, const UvTables &t, bool sparse, const OpSet &ops,
+                                    hipStream_t s) {
+    const int nb = (int)t.box.size();
+    if (t.maxL == 0) return FMM_OK;
+    const UvBox *dB = owner->uvtab.as<UvBox>();
+    const int64_t *tab0 = reinterpret_cast<const int64_t *>(owner->uvtab.as<unsigned char>() + sizeof(UvBox) * nb);
+    auto T_ = [&](int k) { return tab0 + (size_t)k * (nb + 1); };
+    const int p = t.box[0].p;
+    HIPCHK(owner, launch_uv_mask(dB, nb, T_(kStFill), t.total[kStFill], T_(kStAtom), t.total[kStAtom], s), "mask");
+    if (sparse) {
+        HIPCHK(owner, launch_uv_p2m(dB, nb, T_(kStLeaf), t.total[kStLeaf], s), "P2M");
+        for (int k = 1; k <= t.maxL; ++k)
+            HIPCHK(owner, launch_uv_m2m(dB, nb, k, T_(t.m2m(k)), t.total[t.m2m(k)], ops.tree64.ptr, s), "M2M");
+        HIPCHK(owner, launch_uv_lattice(dB, nb, T_(kStLat), t.total[kStLat], s), "lattice");
+        // levels 1 and 2 with the operators summed over aliased offsets (as
+        // the dense pass), where the 875 offsets reach only 8 or 64 source cells
+        for (int l = 1; l <= t.maxL; ++l) {
+            const bool alias = l <= 2;
+            HIPCHK(owner,
+                   launch_uv_m2l(dB, nb, l, T_(t.lvl(l)), t.total[t.lvl(l)],
+                                 alias ? ops.alias_il[l - 1].as<int32_t>() : ops.il.as<int32_t>(),
+                                 alias ? ops.alias_off[l - 1].as<int32_t>() : ops.offv.as<int32_t>(),
+                                 alias ? ops.alias_ops[l - 1].as<double>() : ops.ops64.as<double>(),
+                                 alias ? nullptr : ops.rowpos.as<int32_t>(), m2l_row_blocks(p),
+                                 alias ? 1 << (3 * l) : kILSize, s),
+                   "M2L");
+        }
+        for (int l = 1; l <= t.maxL; ++l)
+            HIPCHK(owner, launch_uv_l2l(dB, nb, l, T_(t.lvl(l)), t.total[t.lvl(l)], ops.tree64.ptr, s), "L2L");
+        HIPCHK(owner, launch_uv_l2p(dB, nb, T_(kStAtom), t.total[kStAtom], s), "L2P");
+    }
+    HIPCHK(owner, launch_uv_p2p<T>(dB, nb, T_(kStLeaf), t.total[kStLeaf], s), "P2P uv");
+    HIPCHK(owner, launch_uv_sums(dB, nb, T_(kStRed), t.total[kStRed], T_(kStOne), t.total[kStOne], s), "uv sums");
+    return FMM_OK;
+}
+
+// The dense second pass of FMM_UV_SYMMETRIC for one box, on its stream: the
+// far field of the masked charges (the solvent's with FMM_UV_SWAP)
+template <typename T>
+static fmm_status enqueue_uv_dense(fmm_plan_t pl, const uint8_t *mask) {
     hipStream_t s = pl->stream;
     const int64_t n = pl->n_state;
-    const int L = pl->levels, p = pl->p, K = pl->K, Kp = pl->Kp;
-    uint32_t *fl[kMaxLevels + 1];
-    fl[0] = pl->sflag.as<uint32_t>();
-    for (int l = 1; l <= L; ++l) fl[l] = pl->sflag.as<uint32_t>() + 1 + level_offset(l);
-    auto MD = [&](int l) { return pl->Mlev.as<double>() + (size_t)level_offset(l) * Kp; };
-    auto LD = [&](int l) { return pl->Llev.as<double>() + (size_t)level_offset(l) * Kp; };
-    const void *tree = pl->op->tree64.ptr;  // swizzled FP64 M2M (ids 0..7) then L2L (8..15)
-    const uint32_t *key = pl->key.as<uint32_t>();
-    const int32_t *perm = pl->perm.as<int32_t>();
-    HIPCHK(pl, launch_fill_u32(fl[L], 0u, level_cells(L), s), "fill");
-    HIPCHK(pl, launch_flags(n, mask, key, L, fl, s), "flags");
-    HIPCHK(pl, launch_p2m_sparse(level_cells(L), pl->xs.as<double>(), pl->start.as<int32_t>(), perm, mask, fl[L],
-                                 pl->box, L, p, Kp, MD(L), s), "P2M");
-    for (int l = L - 1; l >= 1; --l)
-        HIPCHK(pl, launch_m2m_sparse(level_cells(l), fl[l], fl[l + 1], MD(l + 1), MD(l), tree, K, Kp, false, s),
-               "M2M");
-    HIPCHK(pl, launch_m2m_sparse(1, fl[0], fl[1], MD(1), pl->M0.as<double>(), tree, K, Kp, true, s), "M2M");
-    HIPCHK(pl, launch_lattice(pl->M0.as<double>(), pl->L0.as<double>(), pl->lat.as<double>(), p, Kp, s), "lattice");
-    // levels 1 and 2 with the operators summed over aliased offsets (as the
-    // dense pass), where the 875 offsets reach only 8 or 64 source cells
-    for (int l = 1; l <= L; ++l) {
-        const OpSet &o = *pl->op;
-        const bool alias = l <= 2;
-        HIPCHK(pl, launch_m2l_sparse(l, fl[l], alias ? o.alias_il[l - 1].as<int32_t>() : o.il.as<int32_t>(),
-                                     alias ? o.alias_off[l - 1].as<int32_t>() : o.offv.as<int32_t>(),
-                                     alias ? o.alias_ops[l - 1].as<double>() : o.ops64.as<double>(),
-                                     alias ? nullptr : o.rowpos.as<int32_t>(), m2l_row_blocks(p), MD(l), LD(l), K, Kp,
-                                     alias ? 1 << (3 * l) : kILSize, s), "M2L");
+    if (pl->uv_scheme & FMM_UV_SWAP) {
+        HIPCHK(pl, launch_invert_mask(n, mask, pl->mask_sw.as<uint8_t>(), s), "mask");
+        mask = pl->mask_sw.as<uint8_t>();
     }
-    for (int l = 1; l <= L; ++l)
-        HIPCHK(pl, launch_l2l_sparse(level_cells(l), fl[l], l == 1 ? pl->L0.as<double>() : LD(l - 1), LD(l), tree, K,
-                                     Kp, s), "L2L");
-    HIPCHK(pl, launch_l2p_sparse(n, pl->xs.as<double>(), key, perm, mask, pl->box, L, p, Kp, LD(L),
-                                 pl->phi_u.as<double>(), s), "L2P");
-    return FMM_OK;
+    HIPCHK(pl, launch_mask_charges(n, pl->perm.as<int32_t>(), mask, pl->prec == FMM_FP64, pl->xq.ptr, pl->xq_u.ptr, s),
+           "mask charges");
+    return far_field<T>(pl, pl->xq_u.ptr, pl->phi_u.as<double>(), pl->field_u.as<T>());
 }
 
 // lam >= 0 with a soft-core set: also the soft-core near-field sums at lam
 template <typename T>
 static fmm_status enqueue_solute_solvent(fmm_plan_t pl, const uint8_t *mask, double lam = -1.0) {
-    hipStream_t s = pl->stream;
-    const int64_t n = pl->n_state;
     fmm_status st;
-    if (pl->uv_scheme & FMM_UV_SWAP) {
-        // u <-> v: the solvent becomes the masked set of the second pass
-        HIPCHK(pl, launch_invert_mask(n, mask, pl->mask_sw.as<uint8_t>(), s), "mask");
-        mask = pl->mask_sw.as<uint8_t>();
-    }
-    if (pl->uv_scheme & FMM_UV_SPARSE) {
-        if ((st = sparse_solute_field(pl, mask)) != FMM_OK) return st;
-    } else {
-        // pass 2 of eq. FMMcalc: far field of the solute atoms alone
-        HIPCHK(pl, launch_mask_charges(n, pl->perm.as<int32_t>(), mask, pl->prec == FMM_FP64, pl->xq.ptr,
-                                       pl->xq_u.ptr, s), "mask charges");
-        if ((st = far_field<T>(pl, pl->xq_u.ptr, pl->phi_u.as<double>(), pl->field_u.as<T>())) != FMM_OK) return st;
-    }
-    double *sc0 = pl->scalars.as<double>();
-    HIPCHK(pl, hipMemcpyAsync(sc0 + 20, pl->M0.ptr, sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
-    const double h_leaf = pl->box / (double)(1 << pl->levels);
-    const bool soft = lam >= 0.0 && pl->sc_alpha > 0.0;
-    SoftCore sco{};
-    if (soft) {
-        const double sigc = std::pow(pl->sc_sigma, (double)pl->sc_c);
-        sco = SoftCore{pl->sc_alpha * lam * sigc, pl->sc_alpha * sigc / pl->sc_c, pl->sc_c, pl->nfsc.as<double>(),
-                       pl->nfdl.as<double>()};
-    }
-    HIPCHK(pl, launch_p2p_uv<T>(n, pl->levels, pl->xq.ptr, pl->start.as<int32_t>(), pl->perm.as<int32_t>(), mask,
-                                pl->mask_s.as<uint8_t>(), h_leaf, pl->nfuv.as<double>(), soft ? &sco : nullptr, s),
-           "P2P uv");
-    const int nb = moments_blocks(n);
-    double *sc = pl->scalars.as<double>();
-    HIPCHK(pl, launch_uv_sums<T>(n, pl->perm.as<int32_t>(), pl->xs.as<double>(), mask, pl->phi_ff.as<double>(),
-                                 pl->phi_u.as<double>(), pl->nfuv.as<double>(), soft ? pl->nfsc.as<double>() : nullptr,
-                                 soft ? pl->nfdl.as<double>() : nullptr, pl->partials.as<double>(), nb, sc + 40, s),
-           "uv sums");
-    HIPCHK(pl, launch_moments(n, pl->xs.as<double>(), pl->perm.as<int32_t>(), mask, 1, pl->partials.as<double>(), nb,
-                              sc + 24, s), "moments");
-    HIPCHK(pl, launch_moments(n, pl->xs.as<double>(), pl->perm.as<int32_t>(), mask, 0, pl->partials.as<double>(), nb,
-                              sc + 32, s), "moments");
+    const bool sparse = (pl->uv_scheme & FMM_UV_SPARSE) != 0;
+    UvTables t;
+    t.box.push_back(uv_box(pl, mask, lam, pl->scalars.as<double>()));
+    uv_build_tables(t);
+    if ((st = uv_upload(pl, t)) != FMM_OK) return st;
+    if (!sparse && (st = enqueue_uv_dense<T>(pl, mask)) != FMM_OK) return st;
+    if ((st = enqueue_uv_stages<T>(pl, t, sparse, *pl->op, pl->stream)) != FMM_OK) return st;
     return enqueue_readback(pl, 46);
 }
 
@@ -1395,6 +1497,9 @@ extern "C" void fmm_destroy(fmm_plan_t pl) {
         if (pl->fork) (void)hipEventDestroy(pl->fork);
         if (pl->input_ready) (void)hipEventDestroy(pl->input_ready);
         if (pl->own_stream) (void)hipStreamDestroy(pl->own_stream);
+        pl->uvtab.release();
+        pl->uvsc.release();
+        if (pl->h_uvsc) (void)hipHostFree(pl->h_uvsc);
         delete pl;
         return;
     }
@@ -1402,7 +1507,7 @@ extern "C" void fmm_destroy(fmm_plan_t pl) {
                          &pl->count, &pl->cursor, &pl->start, &pl->pstart, &pl->xqp, &pl->perm, &pl->scan, &pl->xq, &pl->xq_u, &pl->xs, &pl->m2l_part,
                          &pl->Mlev, &pl->Llev, &pl->mflip, &pl->m2l_part_up, &pl->mflip_up, &pl->M0, &pl->L0, &pl->phi_nf, &pl->field_nf, &pl->phi_ff,
                          &pl->field_ff, &pl->phi_u, &pl->field_u, &pl->nfuv, &pl->partials, &pl->scalars, &pl->flag,
-                         &pl->sflag, &pl->mask_sw, &pl->mask_s, &pl->nfsc, &pl->nfdl};
+                         &pl->sflag, &pl->mask_sw, &pl->mask_s, &pl->nfsc, &pl->nfdl, &pl->uvtab};
     for (DeviceBuf *b : bufs) b->release();
     free_events(pl);
     if (pl->h_scalars) (void)hipHostFree(pl->h_scalars);
@@ -1470,6 +1575,12 @@ extern "C" fmm_status fmm_plan_batch(int nbox, const double *box, const int64_t 
         hipEventCreateWithFlags(&pl->input_ready, hipEventDisableTiming) != hipSuccess)
         return bail(FMM_ERR_DEVICE, "fmm_plan_batch: stream or event creation failed");
     pl->stream = pl->own_stream;
+    if (!pl->uvsc.ensure(sizeof(double) * kScalars * (size_t)nbox) ||
+        hipHostMalloc((void **)&pl->h_uvsc, sizeof(double) * kScalars * (size_t)nbox, hipHostMallocDefault) !=
+            hipSuccess) {
+        pl->h_uvsc = nullptr;
+        return bail(FMM_ERR_NOMEM, "fmm_plan_batch: scalar buffers");
+    }
     std::shared_ptr<OpSet> ops;
     for (int w = 0; w < nbox; ++w) {
         if (natoms && natoms[w] < 0) return bail(FMM_ERR_INVALID, "fmm_plan_batch: natoms must be >= 0");
@@ -1519,9 +1630,15 @@ static fmm_status check_batch_offsets(fmm_plan_t pl, const int64_t *off) {
 // Capture `enqueue(w)` for every non-empty box as parallel branches of one
 // graph (fork from and join into the batch stream), or reuse the graph that
 // was captured for the same key.  Launches it; the caller synchronises.
-template <typename F>
+struct NoTail {
+    fmm_status operator()() const { return FMM_OK; }
+};
+
+// branches: false to capture no per-box branch (only the tail); tail: work
+// enqueued on the batch stream after every branch has joined it
+template <typename F, typename G = NoTail>
 static fmm_status batch_run(fmm_plan_t pl, fmm_plan::Graph &g, const std::vector<int64_t> &key,
-                            const int64_t *off, F enqueue) {
+                            const int64_t *off, F enqueue, bool branches = true, G tail = G()) {
     hipStream_t cs = pl->stream;
     if (!g.exec || g.key != key) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -1530,7 +1647,7 @@ static fmm_status batch_run(fmm_plan_t pl, fmm_plan::Graph &g, const std::vector
         HIPCHK(pl, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "graph capture");
         fmm_status st = FMM_OK;
         hipError_t e = hipEventRecord(pl->fork, cs);
-        for (size_t w = 0; w < pl->sub.size() && st == FMM_OK && e == hipSuccess; ++w) {
+        for (size_t w = 0; branches && w < pl->sub.size() && st == FMM_OK && e == hipSuccess; ++w) {
             if (off[w + 1] == off[w]) continue;
             fmm_plan_t b = pl->sub[w];
             b->stream = pl->sub_stream[w];
@@ -1544,6 +1661,7 @@ static fmm_status batch_run(fmm_plan_t pl, fmm_plan::Graph &g, const std::vector
             e = hipEventRecord(pl->sub_done[w], b->stream);
             if (e == hipSuccess) e = hipStreamWaitEvent(cs, pl->sub_done[w], 0);
         }
+        if (st == FMM_OK && e == hipSuccess) st = tail();
         hipGraph_t graph = nullptr;
         const hipError_t ec = hipStreamEndCapture(cs, &graph);
         if (st != FMM_OK) {
@@ -1665,18 +1783,51 @@ static fmm_status solute_solvent_batch(fmm_plan_t pl, const uint8_t *mask, const
     }
     key.push_back(soft ? 1 : 0);
     for (fmm_plan_t b : pl->sub) b->uv_d0 = b->uv_dsc = b->uv_dl = 0.0;
-    fmm_status st = batch_run(pl, pl->g_uv, key, off, [&](size_t w) -> fmm_status {
+    // every box's stages in one launch per stage; the symmetric scheme first
+    // runs each box's dense second pass as a parallel branch
+    const bool sparse = (pl->uv_scheme & FMM_UV_SPARSE) != 0;
+    UvTables t;
+    for (size_t w = 0; w < nb; ++w) {
         fmm_plan_t b = pl->sub[w];
-        const double lam = soft ? lams[w] : -1.0;
-        return b->prec == FMM_FP64 ? enqueue_solute_solvent<double>(b, mask + off[w], lam)
-                                   : enqueue_solute_solvent<float>(b, mask + off[w], lam);
-    });
+        UvBox u = uv_box(b, mask ? mask + off[w] : nullptr, soft ? lams[w] : -1.0, pl->uvsc.as<double>() + w * kScalars);
+        if (off[w + 1] == off[w]) u.n = 0;
+        t.box.push_back(u);
+    }
+    uv_build_tables(t);
+    void *const tab_before = pl->uvtab.ptr;
+    fmm_status st = uv_upload(pl, t);
+    if (st != FMM_OK) return st;
+    if (pl->uvtab.ptr != tab_before && pl->g_uv.exec) {  // a captured graph reads the old table
+        (void)hipGraphExecDestroy(pl->g_uv.exec);
+        pl->g_uv.exec = nullptr;
+        pl->g_uv.key.clear();
+    }
+    const bool fp64 = pl->prec == FMM_FP64;
+    st = batch_run(
+        pl, pl->g_uv, key, off,
+        [&](size_t w) -> fmm_status {
+            fmm_plan_t b = pl->sub[w];
+            return fp64 ? enqueue_uv_dense<double>(b, mask + off[w]) : enqueue_uv_dense<float>(b, mask + off[w]);
+        },
+        !sparse,
+        [&]() -> fmm_status {
+            const fmm_status s2 = fp64 ? enqueue_uv_stages<double>(pl, t, sparse, *pl->op, pl->stream)
+                                       : enqueue_uv_stages<float>(pl, t, sparse, *pl->op, pl->stream);
+            if (s2 != FMM_OK) return s2;
+            HIPCHK(pl, hipMemcpyAsync(pl->h_uvsc, pl->uvsc.ptr, sizeof(double) * kScalars * nb, hipMemcpyDeviceToHost,
+                                      pl->stream),
+                   "readback");
+            return FMM_OK;
+        });
     if (st != FMM_OK) return st;
     HIPCHK(pl, hipStreamSynchronize(pl->stream), "synchronize");
     for (size_t w = 0; w < nb; ++w) {
         e_uv[w] = 0.0;
         if (off[w + 1] == off[w]) continue;
-        if ((st = finish_solute_solvent(pl->sub[w], &e_uv[w])) != FMM_OK) {
+        fmm_plan_t b = pl->sub[w];
+        std::memcpy(b->h_scalars, pl->h_uvsc + w * kScalars, sizeof(double) * 46);
+        std::memset(&b->h_scalars[kScalars - 1], 0, sizeof(double));  // no input-check flag in this pass
+        if ((st = finish_solute_solvent(b, &e_uv[w])) != FMM_OK) {
             pl->err = "box " + std::to_string(w) + ": " + pl->sub[w]->err;
             return st;
         }

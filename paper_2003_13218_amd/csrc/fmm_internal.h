@@ -114,32 +114,88 @@ template <typename T>
 hipError_t launch_l2p(int64_t nleaf, const void *xq, const int32_t *start, const T *L, int p,
                       int Kp, double h, double *phi, T *field, hipStream_t s);
 
-// Sparse far field of the solute charges (one-sided solute-solvent scheme),
-// FP64, restricted to the cells above the leaves that hold solute atoms.
-// flag[l] (l = 0..levels) points at the 8^l cell flags of level l.
-hipError_t launch_flags(int64_t n, const uint8_t *mask, const uint32_t *key, int levels, uint32_t *const *flag,
-                        hipStream_t s);
-// k_expand.hip: P2M of the solute atoms of flagged leaves from the FP64
-// centred positions xs (sorted order), and L2P at the solute atoms (phi = 0
-// at the others)
-hipError_t launch_p2m_sparse(int64_t nleaf, const double *xs, const int32_t *start, const int32_t *perm,
-                             const uint8_t *mask, const uint32_t *flag, double box, int levels, int p, int Kp,
-                             double *M, hipStream_t s);
-hipError_t launch_l2p_sparse(int64_t n, const double *xs, const uint32_t *key, const int32_t *perm,
-                             const uint8_t *mask, double box, int levels, int p, int Kp, const double *L, double *phi,
-                             hipStream_t s);
+// ---------------------------------------------------------------------------
+// The solute-solvent pass of several boxes, one launch per stage for all of
+// them (a batch plan; a single-box plan is a batch of one box).  UvBox holds
+// one box's arrays in device memory; a stage launch takes the table of boxes
+// and, per box, the first block of that box in the launch (nbox + 1 int64,
+// non-decreasing): block b works for the box w with start[w] <= b < start[w+1].
+// ---------------------------------------------------------------------------
+struct UvBox {
+    int64_t n;          // atoms of the box
+    int levels, p, K, Kp;
+    int invert;         // solute = atoms with mask == 0 (u and v exchanged)
+    int soft_c;         // soft-core exponent c, 0: no soft-core sums
+    double box, h;      // box edge, leaf edge
+    double asc, kd;     // soft-core alpha lambda sigma^c and alpha sigma^c / c
+    const double *xs;   // sorted: wrapped position from the box centre, q (FP64)
+    const void *xq;     // sorted: leaf-local position, q (the evaluation's type)
+    const uint32_t *key;    // leaf key by original index
+    const int32_t *perm;    // sorted -> original index
+    const int32_t *start;   // leaf ranges (8^levels + 1)
+    const uint8_t *mask;    // caller's order, nonzero = solute
+    uint8_t *ms;            // solute flag in sorted order (written by the mask stage)
+    uint32_t *flag;         // cell flags: level 0 at [0], level l >= 1 at [1 + sum_{k<l} 8^k]
+    double *M, *L;          // FP64 level arrays of levels 1..levels (Kp per cell)
+    double *M0, *L0;        // level 0
+    const double *lat;      // level-0 lattice operator, transposed, FP64
+    const double *phi_uv;   // sorted far-field potential of the evaluation
+    double *phi_u;          // sorted far-field potential of the solute charges
+    double *nfuv, *nfsc, *nfdl;  // near-field u-v sums per solute atom
+    double *partials;       // reduction scratch
+    double *sc;             // scalar block of the box (see fmm_api.cpp)
+};
+
+__device__ inline int box_of(const int64_t *__restrict__ start, int nbox, int64_t b) {
+    int lo = 0, hi = nbox;  // start[lo] <= b < start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Stages of the solute-solvent pass (each returns the first HIP error):
+//   mask   zero every box's cell flags, then sorted solute flags ms and the
+//          flags of the leaves holding solute atoms and of all their ancestors
+//   p2m    FP64 P2M of the solute atoms of flagged leaves (sparse pass)
+//   m2m    step k = 1 .. levels: parents at level levels - k from flagged children
+//          (level 0: every box's M0, whatever the flags)
+//   lat    level-0 lattice operator L0 = A M0
+//   m2l    level l: flagged targets from flagged sources of their list; the
+//          FP64 operators with their plain lists (nil entries per parity class):
+//          the row-ordered full-list operators with rowpos (storage row ->
+//          operator row) and nbr = m2l_row_blocks, or the aliased operators of
+//          levels 1, 2 in storage order with rowpos NULL
+//   l2l    level l: flagged cells from their parents (level 1: from L0)
+//   l2p    far-field potential of the solute charges at the solute atoms
+//          (phi_u, 0 at the others)
+//   p2p_uv near-field u-v pair sums per solute atom (and soft-core sums)
+//   sums   A = sum_u q phi_uv, B = sum_u q phi_u, C = sum_v q phi_u,
+//          D = sum nf_uv, soft-core sums (sc[40..45]); moments of u (sc[24..28])
+//          and v (sc[32..36]); sc[20] = M0[0]
+// Block tables: `blocks(w)` blocks per box, as built by the host.
+hipError_t launch_uv_mask(const UvBox *b, int nbox, const int64_t *st_fill, int64_t nb_fill,
+                          const int64_t *st_atoms, int64_t nb_atoms, hipStream_t s);
+hipError_t launch_uv_p2m(const UvBox *b, int nbox, const int64_t *st_leaf, int64_t nb, hipStream_t s);
+hipError_t launch_uv_l2p(const UvBox *b, int nbox, const int64_t *st_atoms, int64_t nb, hipStream_t s);
+hipError_t launch_uv_lattice(const UvBox *b, int nbox, const int64_t *st_one, int64_t nb, hipStream_t s);
 // k_sparse.hip: ops = the 16 swizzled FP64 octant operators (M2M then L2L)
-// for M2M / L2L; for M2L the FP64 operators with their plain lists (nil
-// entries per parity class): the row-ordered full-list operators with rowpos
-// (storage row -> operator row) and nbr = m2l_row_blocks, or the aliased
-// operators in storage order with rowpos NULL
-hipError_t launch_m2m_sparse(int64_t nparent, const uint32_t *fparent, const uint32_t *fchild, const double *Mc,
-                             double *Mp, const void *ops, int K, int Kp, bool all, hipStream_t s);
-hipError_t launch_m2l_sparse(int level, const uint32_t *flag, const int32_t *il, const int32_t *offs,
-                             const double *ops, const int32_t *rowpos, int nbr, const double *M, double *L, int K,
-                             int Kp, int nil, hipStream_t s);
-hipError_t launch_l2l_sparse(int64_t nchild, const uint32_t *flag, const double *Lp, double *Lc, const void *ops,
-                             int K, int Kp, hipStream_t s);
+hipError_t launch_uv_m2m(const UvBox *b, int nbox, int step, const int64_t *st, int64_t nb, const void *ops,
+                         hipStream_t s);
+hipError_t launch_uv_m2l(const UvBox *b, int nbox, int level, const int64_t *st, int64_t nb, const int32_t *il,
+                         const int32_t *offs, const double *ops, const int32_t *rowpos, int nbr, int nil,
+                         hipStream_t s);
+hipError_t launch_uv_l2l(const UvBox *b, int nbox, int level, const int64_t *st, int64_t nb, const void *ops,
+                         hipStream_t s);
+// k_p2p.hip (T: type of xq)
+template <typename T>
+hipError_t launch_uv_p2p(const UvBox *b, int nbox, const int64_t *st_leaf, int64_t nb, hipStream_t s);
+// k_reduce.hip: st_red per box moments_blocks(n) blocks, st_one one block
+// (partials: 32 moments_blocks(n) doubles per box)
+hipError_t launch_uv_sums(const UvBox *b, int nbox, const int64_t *st_red, int64_t nb_red, const int64_t *st_one,
+                          int64_t nb_one, hipStream_t s);
 
 // k_m2l.hip
 // Levels with few target cells split the interaction list into slices
@@ -208,21 +264,6 @@ hipError_t launch_l2l_mfma(int64_t nparent, const Tin *Lparent, Tout *Lchild, co
 template <typename T>
 hipError_t launch_p2p(int64_t nleaf, int levels, const void *xqp, const int32_t *pstart, const int32_t *start,
                       double h, double *phi, T *field, int groups, int nsplit, int max_wg, hipStream_t s);
-// Soft-core near-field u-v pairs (lambda-coupled energy): 1/r -> 1/s,
-// s = (asc + r^c)^(1/c), asc = alpha lambda sigma^c, kd = alpha sigma^c / c;
-// per solute atom q_s sum q_j / s into out_sc and q_s sum q_j d(1/s)/dlambda
-// into out_dl
-struct SoftCore {
-    double asc, kd;
-    int c;
-    double *out_sc, *out_dl;
-};
-// ms: n bytes of scratch (the mask in sorted order); out_per_atom is written
-// at the solute atoms only; sc may be NULL (no soft-core sums)
-template <typename T>
-hipError_t launch_p2p_uv(int64_t n, int levels, const void *xq, const int32_t *start,
-                         const int32_t *perm, const uint8_t *mask, uint8_t *ms, double h, double *out_per_atom,
-                         const SoftCore *sc, hipStream_t s);
 
 // k_reduce.hip
 struct Moments {  // device-side FP64 results of the moment reduction
@@ -241,11 +282,5 @@ hipError_t launch_finalize(int64_t n, const int32_t *perm, const double *xs, dou
 template <typename T>
 hipError_t launch_parts_out(int64_t n, const int32_t *perm, const double *phi_s, const T *field_s,
                             const double *m0, double cq, double *phi, double *field, hipStream_t s);
-// out6: sum_u q phi_uv, sum_u q phi_u, sum_v q phi_u, sum_u nf_uv, and the
-// sums over u of nf_sc and nf_dl (0 when those are NULL)
-template <typename T>
-hipError_t launch_uv_sums(int64_t n, const int32_t *perm, const double *xs, const uint8_t *mask,
-                          const double *phi_uv, const double *phi_u, const double *nf_uv, const double *nf_sc,
-                          const double *nf_dl, double *partials, int nblocks, double *out6, hipStream_t s);
 
 }  // namespace fmm

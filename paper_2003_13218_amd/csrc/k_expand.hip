@@ -257,17 +257,21 @@ __device__ inline void leaf_local(const double *xs, int64_t s, uint32_t leaf, do
     z = (xs[4 * s + 2] - (((double)cz + 0.5) * h - hb)) / h;
 }
 
-// One wavefront per leaf; flagged leaves only.  Lane m accumulates the order-m
-// coefficients of every solute atom of the leaf (each lane owns its entries).
-__global__ __launch_bounds__(64) void k_p2m_sparse(int64_t nleaf, const double *__restrict__ xs,
-                                                   const int32_t *__restrict__ start,
-                                                   const int32_t *__restrict__ perm,
-                                                   const uint8_t *__restrict__ mask, const uint32_t *__restrict__ flag,
-                                                   double box, double h, int p, int Kp, double *__restrict__ M) {
-    const int64_t leaf = blockIdx.x;
-    if (leaf >= nleaf || !flag[leaf]) return;
+// cells of levels 1 .. l-1 (offset of level l in the concatenated level arrays)
+__device__ inline int64_t cells_before(int l) { return l <= 1 ? 0 : (((int64_t)1 << (3 * l)) - 8) / 7; }
+
+// One wavefront per leaf of every box (blocks of the box's leaf table);
+// flagged leaves only.  Lane m accumulates the order-m coefficients of every
+// solute atom of the leaf (each lane owns its entries).
+__global__ __launch_bounds__(64) void k_uv_p2m(const UvBox *__restrict__ boxes, int nbox,
+                                               const int64_t *__restrict__ st) {
+    const int w = box_of(st, nbox, blockIdx.x);
+    const UvBox &b = boxes[w];
+    const int64_t leaf = blockIdx.x - st[w];
+    const int L = b.levels, p = b.p, Kp = b.Kp;
+    if (!b.flag[1 + cells_before(L) + leaf]) return;
     const int m = threadIdx.x;
-    double *Ml = M + leaf * Kp;
+    double *Ml = b.M + (cells_before(L) + leaf) * Kp;
     if (m <= p)
         for (int n = m; n <= p; ++n) {
             if (m == 0) Ml[n * n] = 0.0;
@@ -279,11 +283,11 @@ __global__ __launch_bounds__(64) void k_p2m_sparse(int64_t nleaf, const double *
     if (m == 0)
         for (int k = (p + 1) * (p + 1); k < Kp; ++k) Ml[k] = 0.0;
     if (m > p) return;
-    for (int32_t s = start[leaf]; s < start[leaf + 1]; ++s) {
-        if (!mask[perm[s]]) continue;
+    for (int32_t s = b.start[leaf]; s < b.start[leaf + 1]; ++s) {
+        if (!b.ms[s]) continue;
         double x, y, z;
-        leaf_local(xs, s, (uint32_t)leaf, box, h, x, y, z);
-        const double q = xs[4 * s + 3];
+        leaf_local(b.xs, s, (uint32_t)leaf, b.box, b.h, x, y, z);
+        const double q = b.xs[4 * s + 3];
         regular_hat_column<double>(x, y, z, m, p, [&](int n, double re, double im) {
             if (m == 0) Ml[n * n] += q * re;
             else {
@@ -294,49 +298,36 @@ __global__ __launch_bounds__(64) void k_p2m_sparse(int64_t nleaf, const double *
     }
 }
 
-hipError_t launch_p2m_sparse(int64_t nleaf, const double *xs, const int32_t *start, const int32_t *perm,
-                             const uint8_t *mask, const uint32_t *flag, double box, int levels, int p, int Kp,
-                             double *M, hipStream_t s) {
-    const double h = box / (double)(1 << levels);
-    hipLaunchKernelGGL(k_p2m_sparse, dim3((unsigned)nleaf), dim3(64), 0, s, nleaf, xs, start, perm, mask, flag, box,
-                       h, p, Kp, M);
+hipError_t launch_uv_p2m(const UvBox *b, int nbox, const int64_t *st_leaf, int64_t nb, hipStream_t s) {
+    if (nb > 0) hipLaunchKernelGGL(k_uv_p2m, dim3((unsigned)nb), dim3(64), 0, s, b, nbox, st_leaf);
     return hipGetLastError();
 }
 
 // Potential of the leaf's local expansion at every solute atom (0 elsewhere),
-// one thread per sorted atom.
-__global__ void k_l2p_sparse(int64_t n, const double *__restrict__ xs, const uint32_t *__restrict__ key,
-                             const int32_t *__restrict__ perm, const uint8_t *__restrict__ mask, double box,
-                             double h, int p, int Kp, const double *__restrict__ L, double *__restrict__ phi) {
-    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
-         s += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t i = perm[s];
-        if (!mask[i]) {
-            phi[s] = 0.0;
-            continue;
-        }
-        const uint32_t leaf = key[i];
-        double x, y, z;
-        leaf_local(xs, s, leaf, box, h, x, y, z);
-        const double *Ll = L + (size_t)leaf * Kp;
-        double acc = 0.0;
-        regular_hat_foreach<double>(x, y, z, p, [&](int nn, int m, double re, double im) {
-            if (m == 0) acc += re * Ll[nn * nn];
-            else acc += re * Ll[nn * nn + 2 * m - 1] + im * Ll[nn * nn + 2 * m];
-        });
-        phi[s] = acc / h;
+// one thread per sorted atom of every box (blocks of 256 of the box's atom table).
+__global__ void k_uv_l2p(const UvBox *__restrict__ boxes, int nbox, const int64_t *__restrict__ st) {
+    const int w = box_of(st, nbox, blockIdx.x);
+    const UvBox &b = boxes[w];
+    const int64_t s = (blockIdx.x - st[w]) * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= b.n) return;
+    if (!b.ms[s]) {
+        b.phi_u[s] = 0.0;
+        return;
     }
+    const uint32_t leaf = b.key[b.perm[s]];
+    double x, y, z;
+    leaf_local(b.xs, s, leaf, b.box, b.h, x, y, z);
+    const double *Ll = b.L + (cells_before(b.levels) + leaf) * b.Kp;
+    double acc = 0.0;
+    regular_hat_foreach<double>(x, y, z, b.p, [&](int nn, int m, double re, double im) {
+        if (m == 0) acc += re * Ll[nn * nn];
+        else acc += re * Ll[nn * nn + 2 * m - 1] + im * Ll[nn * nn + 2 * m];
+    });
+    b.phi_u[s] = acc / b.h;
 }
 
-hipError_t launch_l2p_sparse(int64_t n, const double *xs, const uint32_t *key, const int32_t *perm,
-                             const uint8_t *mask, double box, int levels, int p, int Kp, const double *L, double *phi,
-                             hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    const double h = box / (double)(1 << levels);
-    int64_t g = (n + 255) / 256;
-    if (g > 65535) g = 65535;
-    hipLaunchKernelGGL(k_l2p_sparse, dim3((unsigned)g), dim3(256), 0, s, n, xs, key, perm, mask, box, h, p, Kp, L,
-                       phi);
+hipError_t launch_uv_l2p(const UvBox *b, int nbox, const int64_t *st_atoms, int64_t nb, hipStream_t s) {
+    if (nb > 0) hipLaunchKernelGGL(k_uv_l2p, dim3((unsigned)nb), dim3(256), 0, s, b, nbox, st_atoms);
     return hipGetLastError();
 }
 
@@ -366,6 +357,30 @@ __global__ __launch_bounds__(256) void k_lattice(const double *__restrict__ M0, 
     part[w][lane] = acc;
     __syncthreads();
     if (w == 0 && row < Kp) L0[row] = row < K ? ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane] : 0.0;
+}
+
+// the same for every box of a solute-solvent stage table (ceil(Kp / 64)
+// blocks per box)
+__global__ __launch_bounds__(256) void k_uv_lattice(const UvBox *__restrict__ boxes, int nbox,
+                                                   const int64_t *__restrict__ st) {
+    __shared__ double part[4][64];
+    const int w = box_of(st, nbox, blockIdx.x);
+    const UvBox &b = boxes[w];
+    const int K = b.K, Kp = b.Kp;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int row = (int)(blockIdx.x - st[w]) * 64 + lane;
+    double acc = 0.0;
+    if (row < K)
+        for (int c = wv; c < K; c += 4) acc += b.lat[(size_t)c * K + row] * b.M0[c];
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && row < Kp)
+        b.L0[row] = row < K ? ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane] : 0.0;
+}
+
+hipError_t launch_uv_lattice(const UvBox *b, int nbox, const int64_t *st_one, int64_t nb, hipStream_t s) {
+    if (nb > 0) hipLaunchKernelGGL(k_uv_lattice, dim3((unsigned)nb), dim3(256), 0, s, b, nbox, st_one);
+    return hipGetLastError();
 }
 
 hipError_t launch_lattice(const double *M0, double *L0, const double *AT, int p, int Kp, hipStream_t s) {

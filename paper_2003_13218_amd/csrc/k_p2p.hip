@@ -183,25 +183,19 @@ template hipError_t launch_p2p<float>(int64_t, int, const void *, const int32_t 
 template hipError_t launch_p2p<double>(int64_t, int, const void *, const int32_t *, const int32_t *, double,
                                        double *, double *, int, int, int, hipStream_t);
 
-// Near-field solute-solvent pairs: out[s] = q_s sum_{j in NF(s), solvent} q_j / r
-// for the solute atoms s (entries of solvent atoms are not written).  With
-// out_sc set, also the soft-core sums of the lambda-coupled energy, in FP64:
-// out_sc[s] = q_s sum q_j / s_ij and out_dl[s] = q_s sum q_j d(1/s_ij)/dlambda,
-// s = (asc + r^c)^(1/c) with asc = alpha lambda sigma^c, and
-// d(1/s)/dlambda = -kd s^(-c-1), kd = alpha sigma^c / c.
-// One workgroup per leaf.  The leaf's solute atoms are compacted (in order)
+// Near-field solute-solvent pairs: nfuv[s] = q_s sum_{j in NF(s), solvent} q_j / r
+// for the solute atoms s (ms[s] != 0; entries of solvent atoms are not
+// written).  With a soft-core exponent set, also the soft-core sums of the
+// lambda-coupled energy, in FP64: nfsc[s] = q_s sum q_j / s_ij and
+// nfdl[s] = q_s sum q_j d(1/s_ij)/dlambda, s = (asc + r^c)^(1/c) with
+// asc = alpha lambda sigma^c, and d(1/s)/dlambda = -kd s^(-c-1),
+// kd = alpha sigma^c / c.
+// One workgroup per leaf of every box.  The leaf's solute atoms are compacted (in order)
 // into LDS; for each of them the 256 threads split the 125 neighbour leaves,
 // two threads per leaf taking one half of its atoms each, sum their terms in
 // FP64, and a fixed LDS tree adds the 256 partial sums.  Leaves without solute
 // atoms read their mask bytes and return.
 constexpr int kUvBlock = 256;
-
-__global__ void k_sorted_mask(int64_t n, const int32_t *__restrict__ perm, const uint8_t *__restrict__ mask,
-                              uint8_t *__restrict__ ms) {
-    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
-         s += (int64_t)gridDim.x * blockDim.x)
-        ms[s] = mask[perm[s]] ? 1 : 0;
-}
 
 // r^c for a small positive integer c (r2 = r^2)
 __device__ inline double pow_int_r(double r2, int c) {
@@ -210,18 +204,25 @@ __device__ inline double pow_int_r(double r2, int c) {
     return x;
 }
 
+// blocks: one per leaf of every box (the box's leaf table)
 template <typename T>
-__global__ __launch_bounds__(kUvBlock) void k_p2p_uv(int levels, const T *__restrict__ xq,
-                                                     const int32_t *__restrict__ start,
-                                                     const uint8_t *__restrict__ ms, T h,
-                                                     double *__restrict__ out, double asc, double kd, int c,
-                                                     double *__restrict__ out_sc, double *__restrict__ out_dl) {
+__global__ __launch_bounds__(kUvBlock) void k_uv_p2p(const UvBox *__restrict__ boxes, int nbox,
+                                                     const int64_t *__restrict__ st) {
     __shared__ int32_t list[kUvBlock];
     __shared__ int wave_cnt[kUvBlock / 64];
     __shared__ double red[3][kUvBlock];
-    const bool soft = out_sc != nullptr;
+    const int w = box_of(st, nbox, blockIdx.x);
+    const UvBox &b = boxes[w];
+    const T *__restrict__ xq = reinterpret_cast<const T *>(b.xq);
+    const int32_t *__restrict__ start = b.start;
+    const uint8_t *__restrict__ ms = b.ms;
+    const int levels = b.levels;
+    const T h = (T)b.h;
+    const bool soft = b.soft_c > 0;
+    const int c = soft ? b.soft_c : 1;
+    const double asc = b.asc, kd = b.kd;
     const double inv_c = 1.0 / (double)c;
-    const uint32_t leaf = blockIdx.x;
+    const uint32_t leaf = (uint32_t)(blockIdx.x - st[w]);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int32_t s0 = start[leaf], s1 = start[leaf + 1];
     bool ready = false;  // neighbour range of this thread set up
@@ -230,24 +231,24 @@ __global__ __launch_bounds__(kUvBlock) void k_p2p_uv(int levels, const T *__rest
     for (int32_t base = s0; base < s1; base += kUvBlock) {
         const int32_t i = base + tid;
         const bool is_u = i < s1 && ms[i] != 0;
-        const uint64_t b = __ballot(is_u);
-        if (lane == 0) wave_cnt[wv] = __popcll(b);
+        const uint64_t bal = __ballot(is_u);
+        if (lane == 0) wave_cnt[wv] = __popcll(bal);
         __syncthreads();
         int off = 0, nu = 0;
-        for (int w = 0; w < kUvBlock / 64; ++w) {
-            if (w < wv) off += wave_cnt[w];
-            nu += wave_cnt[w];
+        for (int k = 0; k < kUvBlock / 64; ++k) {
+            if (k < wv) off += wave_cnt[k];
+            nu += wave_cnt[k];
         }
-        if (is_u) list[off + __popcll(b & ((1ull << lane) - 1ull))] = i;
+        if (is_u) list[off + __popcll(bal & ((1ull << lane) - 1ull))] = i;
         __syncthreads();
         if (nu > 0 && !ready) {
             ready = true;
-            const int c = tid >> 1;
-            if (c < 125) {
+            const int cc = tid >> 1;
+            if (cc < 125) {
                 uint32_t cx, cy, cz;
                 demorton3(leaf, cx, cy, cz);
                 const uint32_t nmask = (1u << levels) - 1u;
-                const int dx = c / 25 - kWS, dy = (c / 5) % 5 - kWS, dz = c % 5 - kWS;
+                const int dx = cc / 25 - kWS, dy = (cc / 5) % 5 - kWS, dz = cc % 5 - kWS;
                 const uint32_t sc = morton3((cx + dx) & nmask, (cy + dy) & nmask, (cz + dz) & nmask);
                 const int32_t a0 = start[sc], a1 = start[sc + 1];
                 const int32_t mid = a0 + (a1 - a0 + 1) / 2;
@@ -281,20 +282,20 @@ __global__ __launch_bounds__(kUvBlock) void k_p2p_uv(int levels, const T *__rest
             red[1][tid] = asc_sum;
             red[2][tid] = adl;
             __syncthreads();
-            for (int st = kUvBlock / 2; st > 0; st >>= 1) {
-                if (tid < st) {
-                    red[0][tid] += red[0][tid + st];
-                    red[1][tid] += red[1][tid + st];
-                    red[2][tid] += red[2][tid + st];
+            for (int sd = kUvBlock / 2; sd > 0; sd >>= 1) {
+                if (tid < sd) {
+                    red[0][tid] += red[0][tid + sd];
+                    red[1][tid] += red[1][tid + sd];
+                    red[2][tid] += red[2][tid + sd];
                 }
                 __syncthreads();
             }
             if (tid == 0) {
                 const double qa = (double)xq[4 * (int64_t)a + 3];
-                out[a] = qa * red[0][0];
+                b.nfuv[a] = qa * red[0][0];
                 if (soft) {
-                    out_sc[a] = qa * red[1][0];
-                    out_dl[a] = qa * red[2][0];
+                    b.nfsc[a] = qa * red[1][0];
+                    b.nfdl[a] = qa * red[2][0];
                 }
             }
             __syncthreads();
@@ -303,24 +304,11 @@ __global__ __launch_bounds__(kUvBlock) void k_p2p_uv(int levels, const T *__rest
 }
 
 template <typename T>
-hipError_t launch_p2p_uv(int64_t n, int levels, const void *xq, const int32_t *start, const int32_t *perm,
-                         const uint8_t *mask, uint8_t *ms, double h, double *out, const SoftCore *sc, hipStream_t s) {
-    if (sc && (sc->c < 1 || sc->c > 12)) return hipErrorInvalidValue;
-    if (n <= 0) return hipSuccess;
-    int64_t g = (n + 255) / 256;
-    if (g > 65535) g = 65535;
-    hipLaunchKernelGGL(k_sorted_mask, dim3((unsigned)g), dim3(256), 0, s, n, perm, mask, ms);
-    const int64_t nleaf = (int64_t)1 << (3 * levels);
-    hipLaunchKernelGGL(k_p2p_uv<T>, dim3((unsigned)nleaf), dim3(kUvBlock), 0, s, levels, (const T *)xq, start, ms,
-                       (T)h, out, sc ? sc->asc : 0.0, sc ? sc->kd : 0.0, sc ? sc->c : 1, sc ? sc->out_sc : nullptr,
-                       sc ? sc->out_dl : nullptr);
+hipError_t launch_uv_p2p(const UvBox *b, int nbox, const int64_t *st_leaf, int64_t nb, hipStream_t s) {
+    if (nb > 0) hipLaunchKernelGGL(k_uv_p2p<T>, dim3((unsigned)nb), dim3(kUvBlock), 0, s, b, nbox, st_leaf);
     return hipGetLastError();
 }
-template hipError_t launch_p2p_uv<float>(int64_t, int, const void *, const int32_t *, const int32_t *,
-                                         const uint8_t *, uint8_t *, double, double *, const SoftCore *,
-                                         hipStream_t);
-template hipError_t launch_p2p_uv<double>(int64_t, int, const void *, const int32_t *, const int32_t *,
-                                          const uint8_t *, uint8_t *, double, double *, const SoftCore *,
-                                          hipStream_t);
+template hipError_t launch_uv_p2p<float>(const UvBox *, int, const int64_t *, int64_t, hipStream_t);
+template hipError_t launch_uv_p2p<double>(const UvBox *, int, const int64_t *, int64_t, hipStream_t);
 
 }  // namespace fmm

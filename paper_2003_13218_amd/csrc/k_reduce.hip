@@ -227,56 +227,84 @@ template hipError_t launch_parts_out<float>(int64_t, const int32_t *, const doub
 template hipError_t launch_parts_out<double>(int64_t, const int32_t *, const double *, const double *,
                                              const double *, double, double *, double *, hipStream_t);
 
-// Solute-solvent sums (sorted order s, i = perm[s]):
-//   A = sum_u q phi_uv,  B = sum_u q phi_u,  C = sum_v q phi_u,  D = sum nf_uv
-template <typename T>
-__global__ __launch_bounds__(kRedBlock) void k_uv_sums(int64_t n, const int32_t *__restrict__ perm,
-                                                        const double *__restrict__ xs,
-                                                        const uint8_t *__restrict__ mask,
-                                                        const double *__restrict__ phi_uv,
-                                                        const double *__restrict__ phi_u,
-                                                        const double *__restrict__ nf_uv,
-                                                        const double *__restrict__ nf_sc,
-                                                        const double *__restrict__ nf_dl,
-                                                        double *__restrict__ partials) {
-    NSum v[6];
-    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
-         s += (int64_t)gridDim.x * blockDim.x) {
-        const double qi = xs[4 * s + 3];
-        if (mask[perm[s]]) {
-            v[0].add(qi * phi_uv[s]);
-            v[1].add(qi * phi_u[s]);
-            v[3].add(nf_uv[s]);
-            if (nf_sc) {
-                v[4].add(nf_sc[s]);
-                v[5].add(nf_dl[s]);
+// Solute-solvent sums of every box (sorted order s, solute flag ms[s]):
+//   A = sum_u q phi_uv, B = sum_u q phi_u, C = sum_v q phi_u, D = sum_u nf_uv,
+//   E = sum_u nf_sc, F = sum_u nf_dl (soft-core boxes), and the moments
+//   (Q, mu, S) of u and of v.  Blocks: the box's reduction table; each block
+// strides over the box's atoms and leaves 16 Neumaier pairs in the box's
+// partials; one block per box then adds them in block order.
+constexpr int kUvValues = 16;
+
+__global__ __launch_bounds__(kRedBlock) void k_uv_reduce(const UvBox *__restrict__ boxes, int nbox,
+                                                          const int64_t *__restrict__ st) {
+    const int w = box_of(st, nbox, blockIdx.x);
+    const UvBox &b = boxes[w];
+    const int64_t bi = blockIdx.x - st[w], nb = st[w + 1] - st[w];
+    const bool soft = b.soft_c > 0;
+    NSum v[kUvValues];
+    for (int64_t s = bi * kRedBlock + threadIdx.x; s < b.n; s += nb * kRedBlock) {
+        const double x = b.xs[4 * s], y = b.xs[4 * s + 1], z = b.xs[4 * s + 2], qi = b.xs[4 * s + 3];
+        const int o = b.ms[s] ? 6 : 11;  // moments of u at 6..10, of v at 11..15
+        if (b.ms[s]) {
+            v[0].add(qi * b.phi_uv[s]);
+            v[1].add(qi * b.phi_u[s]);
+            v[3].add(b.nfuv[s]);
+            if (soft) {
+                v[4].add(b.nfsc[s]);
+                v[5].add(b.nfdl[s]);
             }
         } else {
-            v[2].add(qi * phi_u[s]);
+            v[2].add(qi * b.phi_u[s]);
         }
+        v[o].add(qi);
+        v[o + 1].add(qi * x);
+        v[o + 2].add(qi * y);
+        v[o + 3].add(qi * z);
+        v[o + 4].add(qi * (x * x + y * y + z * z));
     }
-    block_reduce<6>(v);
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 6; ++k) {
-            partials[(blockIdx.x * 6 + k) * 2] = v[k].s;
-            partials[(blockIdx.x * 6 + k) * 2 + 1] = v[k].c;
-        }
+    // four passes of four values through the same LDS
+    for (int g = 0; g < kUvValues; g += 4) {
+        NSum part[4] = {v[g], v[g + 1], v[g + 2], v[g + 3]};
+        block_reduce<4>(part);
+        if (threadIdx.x == 0)
+            for (int k = 0; k < 4; ++k) {
+                b.partials[(bi * kUvValues + g + k) * 2] = part[k].s;
+                b.partials[(bi * kUvValues + g + k) * 2 + 1] = part[k].c;
+            }
+    }
 }
 
-template <typename T>
-hipError_t launch_uv_sums(int64_t n, const int32_t *perm, const double *xs, const uint8_t *mask,
-                          const double *phi_uv, const double *phi_u, const double *nf_uv, const double *nf_sc,
-                          const double *nf_dl, double *partials, int nblocks, double *out6, hipStream_t s) {
-    hipLaunchKernelGGL(k_uv_sums<T>, dim3(nblocks), dim3(kRedBlock), 0, s, n, perm, xs, mask, phi_uv, phi_u,
-                       nf_uv, nf_sc, nf_dl, partials);
-    hipLaunchKernelGGL(k_final_sum<6>, dim3(1), dim3(kRedBlock), 0, s, partials, nblocks, out6);
+// one block per box: the box's partials in block order, then its scalar block
+__global__ __launch_bounds__(kRedBlock) void k_uv_final(const UvBox *__restrict__ boxes, int nbox,
+                                                         const int64_t *__restrict__ st_red,
+                                                         const int64_t *__restrict__ st_one) {
+    const int w = box_of(st_one, nbox, blockIdx.x);
+    const UvBox &b = boxes[w];
+    const int64_t nb = st_red[w + 1] - st_red[w];
+    for (int g = 0; g < kUvValues; g += 4) {
+        NSum v[4];
+        for (int64_t k = threadIdx.x; k < nb; k += blockDim.x)
+            for (int j = 0; j < 4; ++j)
+                v[j].merge(b.partials[(k * kUvValues + g + j) * 2], b.partials[(k * kUvValues + g + j) * 2 + 1]);
+        block_reduce<4>(v);
+        if (threadIdx.x == 0)
+            for (int j = 0; j < 4; ++j) {
+                const int k = g + j;
+                const double val = v[j].value();
+                if (k < 6) b.sc[40 + k] = val;          // A, B, C, D, E, F
+                else if (k < 11) b.sc[24 + k - 6] = val;  // Q_u, mu_u, S_u
+                else b.sc[32 + k - 11] = val;             // Q_v, mu_v, S_v
+            }
+    }
+    if (threadIdx.x == 0) b.sc[20] = b.M0[0];  // monopole of the solute-charge tree
+}
+
+hipError_t launch_uv_sums(const UvBox *b, int nbox, const int64_t *st_red, int64_t nb_red, const int64_t *st_one,
+                          int64_t nb_one, hipStream_t s) {
+    if (nb_red <= 0 || nb_one <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_uv_reduce, dim3((unsigned)nb_red), dim3(kRedBlock), 0, s, b, nbox, st_red);
+    hipLaunchKernelGGL(k_uv_final, dim3((unsigned)nb_one), dim3(kRedBlock), 0, s, b, nbox, st_red, st_one);
     return hipGetLastError();
 }
-template hipError_t launch_uv_sums<float>(int64_t, const int32_t *, const double *, const uint8_t *,
-                                          const double *, const double *, const double *, const double *,
-                                          const double *, double *, int, double *, hipStream_t);
-template hipError_t launch_uv_sums<double>(int64_t, const int32_t *, const double *, const uint8_t *,
-                                           const double *, const double *, const double *, const double *,
-                                           const double *, double *, int, double *, hipStream_t);
 
 }  // namespace fmm

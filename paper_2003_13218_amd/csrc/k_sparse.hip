@@ -11,40 +11,48 @@
 // operators of the dense pass in their matrix-core swizzle.  One workgroup
 // per cell of the level (unflagged ones return at once), which keeps the
 // launch independent of the data (graph capture).
+//
+// Every stage runs for all boxes of a batch in one launch: block b belongs to
+// the box w of the stage's block table (box_of), and takes that box's arrays
+// from its UvBox entry.  A single-box plan is a batch of one.
 #include "fmm_internal.h"
 #include "morton.h"
 
 namespace fmm {
 
-// flag[key[i]] = 1 for every solute atom i (plain stores of 1: races benign)
-__global__ void k_flag_leaves(int64_t n, const uint8_t *__restrict__ mask, const uint32_t *__restrict__ key,
-                              uint32_t *__restrict__ flag) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        if (mask[i]) flag[key[i]] = 1u;
+// cells of levels 1 .. l-1 (offset of level l in the concatenated level arrays)
+__device__ inline int64_t lvl_off(int l) { return l <= 1 ? 0 : (((int64_t)1 << (3 * l)) - 8) / 7; }
+__device__ inline uint32_t *flags_at(const UvBox &b, int l) { return b.flag + (l == 0 ? 0 : 1 + lvl_off(l)); }
+
+// Mask stage.  k_uv_fill clears every flag of the box (level 0 and levels
+// 1 .. L); k_uv_mask writes the solute flag of every sorted atom and, for a
+// solute atom, the flags of its leaf and of all the leaf's ancestors (plain
+// stores of 1: concurrent writers store the same value).
+__global__ void k_uv_fill(const UvBox *__restrict__ boxes, int nbox, const int64_t *__restrict__ st) {
+    const int w = box_of(st, nbox, blockIdx.x);
+    const UvBox &b = boxes[w];
+    const int64_t nflag = 1 + lvl_off(b.levels + 1);
+    const int64_t i = (blockIdx.x - st[w]) * (int64_t)blockDim.x + threadIdx.x;
+    if (i < nflag) b.flag[i] = 0u;
 }
 
-// parent flags from child flags, one level
-__global__ void k_flag_up(int64_t ncell, const uint32_t *__restrict__ child, uint32_t *__restrict__ parent) {
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t f = 0;
-        for (int o = 0; o < 8; ++o) f |= child[8 * c + o];
-        parent[c] = f ? 1u : 0u;
-    }
+__global__ void k_uv_mask(const UvBox *__restrict__ boxes, int nbox, const int64_t *__restrict__ st) {
+    const int w = box_of(st, nbox, blockIdx.x);
+    const UvBox &b = boxes[w];
+    const int64_t s = (blockIdx.x - st[w]) * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= b.n) return;
+    const int32_t i = b.perm[s];
+    const bool u = (b.mask[i] != 0) != (b.invert != 0);
+    b.ms[s] = u ? 1 : 0;
+    if (!u) return;
+    uint32_t c = b.key[i];
+    for (int l = b.levels; l >= 0; --l, c >>= 3) flags_at(b, l)[c] = 1u;
 }
 
-hipError_t launch_flags(int64_t n, const uint8_t *mask, const uint32_t *key, int levels, uint32_t *const *flag,
-                        hipStream_t s) {
-    if (n > 0) {
-        int64_t g = (n + 255) / 256;
-        if (g > 65535) g = 65535;
-        hipLaunchKernelGGL(k_flag_leaves, dim3((unsigned)g), dim3(256), 0, s, n, mask, key, flag[levels]);
-    }
-    for (int l = levels - 1; l >= 0; --l) {
-        const int64_t nc = (int64_t)1 << (3 * l);
-        hipLaunchKernelGGL(k_flag_up, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, nc, flag[l + 1], flag[l]);
-    }
+hipError_t launch_uv_mask(const UvBox *b, int nbox, const int64_t *st_fill, int64_t nb_fill,
+                          const int64_t *st_atoms, int64_t nb_atoms, hipStream_t s) {
+    if (nb_fill > 0) hipLaunchKernelGGL(k_uv_fill, dim3((unsigned)nb_fill), dim3(256), 0, s, b, nbox, st_fill);
+    if (nb_atoms > 0) hipLaunchKernelGGL(k_uv_mask, dim3((unsigned)nb_atoms), dim3(256), 0, s, b, nbox, st_atoms);
     return hipGetLastError();
 }
 
@@ -79,15 +87,20 @@ __device__ inline double swz_dot(const double *__restrict__ ops, int oid, int ro
 }
 
 // M~(P) = sum over flagged children 8P + o of A_o M~(8P + o) with the swizzled
-// FP64 octant operators (M2M block: ids 0..7).  all != 0: every parent is
-// written (zero without flagged children), as the root must be whatever the
-// mask.
-__global__ __launch_bounds__(256) void k_m2m_sparse(const uint32_t *__restrict__ fparent,
-                                                    const uint32_t *__restrict__ fchild,
-                                                    const double *__restrict__ Mc, double *__restrict__ Mp,
-                                                    const double *__restrict__ ops, int K, int Kp, int all) {
-    const int64_t P = blockIdx.x;
-    if (!all && !fparent[P]) return;
+// FP64 octant operators (M2M block: ids 0..7), for the parents at level
+// levels - step of every box.  Level 0 (the box's M0) is written whatever
+// the flags, as the root must be whatever the mask.
+__global__ __launch_bounds__(256) void k_uv_m2m(const UvBox *__restrict__ boxes, int nbox, int step,
+                                                const int64_t *__restrict__ st, const double *__restrict__ ops) {
+    const int w = box_of(st, nbox, blockIdx.x);
+    const UvBox &b = boxes[w];
+    const int l = b.levels - step;
+    const int64_t P = blockIdx.x - st[w];
+    const int K = b.K, Kp = b.Kp;
+    if (l > 0 && !flags_at(b, l)[P]) return;
+    const uint32_t *fchild = flags_at(b, l + 1);
+    const double *Mc = b.M + lvl_off(l + 1) * Kp;
+    double *Mp = l == 0 ? b.M0 : b.M + lvl_off(l) * Kp;
     const int NB = Kp / 16;
     for (int row = threadIdx.x; row < Kp; row += blockDim.x) {
         double acc = 0.0;
@@ -98,10 +111,10 @@ __global__ __launch_bounds__(256) void k_m2m_sparse(const uint32_t *__restrict__
     }
 }
 
-hipError_t launch_m2m_sparse(int64_t nparent, const uint32_t *fparent, const uint32_t *fchild, const double *Mc,
-                             double *Mp, const void *ops, int K, int Kp, bool all, hipStream_t s) {
-    hipLaunchKernelGGL(k_m2m_sparse, dim3((unsigned)nparent), dim3(256), 0, s, fparent, fchild, Mc, Mp,
-                       (const double *)ops, K, Kp, all ? 1 : 0);
+hipError_t launch_uv_m2m(const UvBox *b, int nbox, int step, const int64_t *st, int64_t nb, const void *ops,
+                         hipStream_t s) {
+    if (nb > 0)
+        hipLaunchKernelGGL(k_uv_m2m, dim3((unsigned)nb), dim3(256), 0, s, b, nbox, step, st, (const double *)ops);
     return hipGetLastError();
 }
 
@@ -114,17 +127,22 @@ constexpr int kSparseBlock = 256;
 // their products.  rowpos: storage row -> operator row of the row-ordered
 // full-list operators (NBR row blocks), or NULL for operators in storage
 // order (the aliased levels).
-__global__ __launch_bounds__(kSparseBlock) void k_m2l_sparse(int level, const uint32_t *__restrict__ flag,
-                                                             const int32_t *__restrict__ il,
-                                                             const int32_t *__restrict__ offs,
-                                                             const double *__restrict__ ops,
-                                                             const int32_t *__restrict__ rowpos, int NBR,
-                                                             const double *__restrict__ M, double *__restrict__ L,
-                                                             int K, int Kp, int nil) {
+__global__ __launch_bounds__(kSparseBlock) void k_uv_m2l(const UvBox *__restrict__ boxes, int nbox, int level,
+                                                         const int64_t *__restrict__ st,
+                                                         const int32_t *__restrict__ il,
+                                                         const int32_t *__restrict__ offs,
+                                                         const double *__restrict__ ops,
+                                                         const int32_t *__restrict__ rowpos, int NBR, int nil) {
     __shared__ int32_t hit_oid[kILSize], hit_src[kILSize];
     __shared__ int wave_cnt[kSparseBlock / 64];
-    const uint32_t c = blockIdx.x;
+    const int w = box_of(st, nbox, blockIdx.x);
+    const UvBox &b = boxes[w];
+    const uint32_t c = (uint32_t)(blockIdx.x - st[w]);
+    const uint32_t *flag = flags_at(b, level);
     if (!flag[c]) return;
+    const int K = b.K, Kp = b.Kp;
+    const double *M = b.M + lvl_off(level) * Kp;
+    double *L = b.L + lvl_off(level) * Kp;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int NB = Kp / 16;
     const uint32_t nmask = (1u << level) - 1u;
@@ -168,23 +186,27 @@ __global__ __launch_bounds__(kSparseBlock) void k_m2l_sparse(int level, const ui
     }
 }
 
-hipError_t launch_m2l_sparse(int level, const uint32_t *flag, const int32_t *il, const int32_t *offs,
-                             const double *ops, const int32_t *rowpos, int nbr, const double *M, double *L, int K,
-                             int Kp, int nil, hipStream_t s) {
+hipError_t launch_uv_m2l(const UvBox *b, int nbox, int level, const int64_t *st, int64_t nb, const int32_t *il,
+                         const int32_t *offs, const double *ops, const int32_t *rowpos, int nbr, int nil,
+                         hipStream_t s) {
     if (nil < 1 || nil > kILSize) return hipErrorInvalidValue;
-    const int64_t nc = (int64_t)1 << (3 * level);
-    hipLaunchKernelGGL(k_m2l_sparse, dim3((unsigned)nc), dim3(kSparseBlock), 0, s, level, flag, il, offs, ops, rowpos,
-                       nbr, M, L, K, Kp, nil);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_uv_m2l, dim3((unsigned)nb), dim3(kSparseBlock), 0, s, b, nbox, level, st, il, offs, ops,
+                           rowpos, nbr, nil);
     return hipGetLastError();
 }
 
-// L~(c) += B_o L~(parent) for flagged cells c = 8P + o, with the swizzled FP64
-// octant operators (L2L block: ids 8..15)
-__global__ __launch_bounds__(256) void k_l2l_sparse(const uint32_t *__restrict__ flag,
-                                                    const double *__restrict__ Lp, double *__restrict__ Lc,
-                                                    const double *__restrict__ ops, int K, int Kp) {
-    const int64_t c = blockIdx.x;
-    if (!flag[c]) return;
+// L~(c) += B_o L~(parent) for flagged cells c = 8P + o of level `level`, with
+// the swizzled FP64 octant operators (L2L block: ids 8..15)
+__global__ __launch_bounds__(256) void k_uv_l2l(const UvBox *__restrict__ boxes, int nbox, int level,
+                                                const int64_t *__restrict__ st, const double *__restrict__ ops) {
+    const int w = box_of(st, nbox, blockIdx.x);
+    const UvBox &b = boxes[w];
+    const int64_t c = blockIdx.x - st[w];
+    if (!flags_at(b, level)[c]) return;
+    const int K = b.K, Kp = b.Kp;
+    const double *Lp = level == 1 ? b.L0 : b.L + lvl_off(level - 1) * Kp;
+    double *Lc = b.L + lvl_off(level) * Kp;
     const int NB = Kp / 16;
     const int o = (int)(c & 7);
     const double *lp = Lp + (c >> 3) * Kp;
@@ -192,10 +214,10 @@ __global__ __launch_bounds__(256) void k_l2l_sparse(const uint32_t *__restrict__
         Lc[c * Kp + row] += swz_dot(ops, 8 + o, row, NB, NB, K, lp, 0.0);
 }
 
-hipError_t launch_l2l_sparse(int64_t nchild, const uint32_t *flag, const double *Lp, double *Lc, const void *ops,
-                             int K, int Kp, hipStream_t s) {
-    hipLaunchKernelGGL(k_l2l_sparse, dim3((unsigned)nchild), dim3(256), 0, s, flag, Lp, Lc, (const double *)ops, K,
-                       Kp);
+hipError_t launch_uv_l2l(const UvBox *b, int nbox, int level, const int64_t *st, int64_t nb, const void *ops,
+                         hipStream_t s) {
+    if (nb > 0)
+        hipLaunchKernelGGL(k_uv_l2l, dim3((unsigned)nb), dim3(256), 0, s, b, nbox, level, st, (const double *)ops);
     return hipGetLastError();
 }
 
