@@ -11,8 +11,8 @@ FMM on the same box is timed beside it, and the oracle on a bounded sample on
 the host cores.  Prints ONE JSON line.
 
 Other workloads (each one JSON line):
-  --config C5 [--p P] [--prec fp64|mixed|bf16]   3,000,008 atoms, levels 6
-  --config C5 --sweep       p in (4, 8, 12, 16) x (fp64, mixed, bf16), one line each
+  --config C5 [--p P] [--prec fp64|mixed|bf16|split16]   3,000,008 atoms, levels 6
+  --config C5 --sweep       p in (4, 8, 12, 16) x (fp64, mixed, bf16, split16), one line each
   --config C4               32 charging windows (6k-48k atoms), one graph launch
                             of energies + forces and one of solute-solvent
                             energies per step, depths and P2P groups autotuned
@@ -33,8 +33,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 M2L_IL = 875  # interaction-list size per cell
-PEAK_TFLOPS = {"mixed": 157.3, "bf16": 2500.0, "fp64": 78.6}  # dense MFMA peaks of MI355X (FP32, BF16, FP64)
-PREC_NAMES = {"fp64": 0, "mixed": 1, "bf16": 2}
+# dense MFMA peaks of MI355X (FP32, BF16, FP64, FP16) by precision mode
+PEAK_TFLOPS = {"mixed": 157.3, "bf16": 2500.0, "fp64": 78.6, "split16": 2500.0}
+PREC_NAMES = {"fp64": 0, "mixed": 1, "bf16": 2, "split16": 3}
+DTYPES = {"mixed": "f32+f64", "fp64": "f64", "bf16": "bf16-m2l+f32+f64", "split16": "f16x3-m2l+f32+f64"}
 
 
 def leaf_kernel(prec_name, info):
@@ -43,13 +45,15 @@ def leaf_kernel(prec_name, info):
     reflected offsets) in info["m2l_launches"] launches (row-class groups)."""
     if prec_name == "bf16":
         return "k_m2l_bf16<false>"
+    if prec_name == "split16":
+        return f"k_m2l_lds<PolF16x3, false> x{info['m2l_launches']} (plain list, 875 offsets)"
     t = "double" if prec_name == "fp64" else "float"
     kind = "orbit" if info["m2l_scheme"] == 2 else "pair"
     return f"k_m2l_lds<{t}, false> x{info['m2l_launches']} ({kind} list, {info['m2l_entries']} entries)"
 
 
 def m2l_entries(prec_name, info):
-    return M2L_IL if prec_name == "bf16" else info["m2l_entries"]
+    return M2L_IL if prec_name in ("bf16", "split16") else info["m2l_entries"]
 
 
 def m2l_flops(p, level, entries):
@@ -212,9 +216,10 @@ def run_single(args, w, p, prec_name, steps, warmup, fp64_leg, cpu_leg, graph_le
     # issue including the class padding of the rows and the column padding.
     K = (p + 1) ** 2
     dense = m2l_flops(p, w.levels, M2L_IL)
-    rows = K if prec_name == "bf16" else info["m2l_rows"]
-    cols = info["Kp"] if prec_name != "bf16" else 32 * ((K + 31) // 32)
-    executed = flops_leaf * (rows * cols) / (K * K)
+    rows = {"bf16": info["Kp"], "split16": info["Kp"]}.get(prec_name, info["m2l_rows"])
+    cols = 32 * ((K + 31) // 32) if prec_name in ("bf16", "split16") else info["Kp"]
+    # split operands: three FP16 products per operand pair
+    executed = flops_leaf * (rows * cols) / (K * K) * (3 if prec_name == "split16" else 1)
     tflops = lambda f: f / (m2l_ms * 1e-3) / 1e12  # noqa: E731
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": recorded_traffic(kernel, workload),
@@ -234,7 +239,7 @@ def run_single(args, w, p, prec_name, steps, warmup, fp64_leg, cpu_leg, graph_le
         "value": value, "unit": "atom-evals/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": ms, "ms_per_call_median": round(ms_median, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"mixed": "f32+f64", "fp64": "f64", "bf16": "bf16-m2l+f32+f64"}[prec_name], "data": "synthetic",
+        "dtype": DTYPES[prec_name], "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.n} atoms ({desc}), b = {w.box} A, levels {w.levels}, p {p}, "
                                f"{prec_name} precision",
                    "n_atoms": w.n, "box": w.box, "levels": w.levels, "p": p, "precision": prec_name,
@@ -342,7 +347,7 @@ def run_batch(args):
         "metric": "atom-evals/s (energy+forces+solute-solvent energy), 32 charging windows, one graph launch each",
         "value": n * args.steps / dt, "unit": "atom-evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {"mixed": "f32+f64", "fp64": "f64", "bf16": "bf16-m2l+f32+f64"}[args.prec],
+        "vs_baseline": None, "dtype": DTYPES[args.prec],
         "data": "synthetic",
         "config": {"workload": f"C4: {len(ws)} windows, {n} atoms (6k-48k per box), p {p}, {args.prec} precision",
                    "n_atoms": n, "windows": len(ws), "p": p, "precision": args.prec, "uv_scheme": args.uv_scheme,
@@ -396,7 +401,7 @@ def main():
     w = workloads.config(args.config)
     if args.sweep:
         for p in (4, 8, 12, 16):
-            for prec in ("fp64", "mixed", "bf16"):
+            for prec in ("fp64", "mixed", "bf16", "split16"):
                 out = run_single(args, w, p, prec, args.steps, args.warmup, False, False)
                 print(json.dumps(out), flush=True)
         return

@@ -75,7 +75,15 @@ typedef enum {
      * does NOT meet the 1e-5 accuracy of the other modes: on water boxes
      * the RMS relative potential error is about 1.4e-2 and the force error
      * about 4e-4 at every order p */
-    FMM_MIXED_BF16_M2L = 2
+    FMM_MIXED_BF16_M2L = 2,
+    /* as FMM_MIXED, but the FP32 levels' M2L writes every operator and
+     * multipole entry as the sum of two FP16 numbers (hi + lo, with exact
+     * power-of-two row and column scales keeping them in FP16's range) and
+     * forms hi*hi + hi*lo + lo*hi on the FP16 matrix cores with FP32
+     * accumulation, partial sums flushed to FP64 after every offset: about
+     * 2^-22 relative per product against 2^-24 for FP32 operands, on the
+     * plain 875-offset interaction list */
+    FMM_MIXED_SPLIT16_M2L = 3
 } fmm_precision;
 
 /*

@@ -6,7 +6,7 @@ is its thin Python wrapper.  Importing this package does not load the library;
 ``binding.load()`` does, and raises if it has not been built.
 """
 from . import binding  # noqa: F401
-from .binding import (FMM_FP64, FMM_MIXED, FMM_MIXED_BF16_M2L, FMM_BOUNDARY_CONDUCTING,  # noqa: F401
+from .binding import (FMM_FP64, FMM_MIXED, FMM_MIXED_BF16_M2L, FMM_MIXED_SPLIT16_M2L, FMM_BOUNDARY_CONDUCTING,  # noqa: F401
                       FMM_BOUNDARY_VACUUM, FMM_UV_SYMMETRIC, FMM_UV_SPARSE, FMM_UV_SWAP, FmmError, Plan, fmm_bin, fmm_destroy,  # noqa: F401
                       fmm_energy_forces, fmm_last_error, fmm_lattice_tensor, fmm_plan,
                       fmm_plan_config, fmm_potential_parts, fmm_profile, fmm_profile_read,

@@ -22,6 +22,7 @@ FMM_ERR_STATE = -4
 FMM_FP64 = 0
 FMM_MIXED = 1
 FMM_MIXED_BF16_M2L = 2
+FMM_MIXED_SPLIT16_M2L = 3
 FMM_BOUNDARY_CONDUCTING = 0
 FMM_BOUNDARY_VACUUM = 1
 FMM_UV_SYMMETRIC = 0

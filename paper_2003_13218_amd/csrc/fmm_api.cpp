@@ -49,6 +49,7 @@ struct OpSet {
     int p = 0;
     Offsets offs;
     DeviceBuf ops32, ops64, opsbf, il, offv;  // M2L (FP32 / FP64 / bfloat16), interaction lists
+    DeviceBuf ops16, scale16;                 // M2L split into two FP16 parts; its row and column scales
     // symmetry-folded list entries of the FP32/FP64 M2L (m2l_scheme), the row
     // order of its operators (row -> storage row) and its inverse (storage
     // row -> row), and Kp zeros (the source of an absent image)
@@ -59,7 +60,8 @@ struct OpSet {
     // lists (8 x n^3 ids) and offsets (the residues of t modulo n)
     DeviceBuf alias_ops[2], alias_il[2], alias_off[2];
     ~OpSet() {
-        DeviceBuf *b[] = {&ops32, &ops64, &opsbf, &il, &offv, &pairs, &rowmap, &rowpos, &zeros, &tree32, &tree64,
+        DeviceBuf *b[] = {&ops32, &ops64, &opsbf, &ops16, &scale16, &il, &offv, &pairs, &rowmap, &rowpos, &zeros,
+                          &tree32, &tree64,
                           &alias_ops[0], &alias_ops[1],
                           &alias_il[0], &alias_il[1], &alias_off[0], &alias_off[1]};
         for (DeviceBuf *x : b) x->release();
@@ -358,7 +360,7 @@ static int upper_m2l_levels(fmm_plan_t pl) {
 // The M2L operator sets the plan's current mode needs; want64: the FP64
 // operators whatever the precision (sparse solute pass).
 struct OpNeeds {
-    bool alias, f64, f32, bf;
+    bool alias, f64, f32, bf, f16;
 };
 static OpNeeds m2l_needs(fmm_plan_t pl, bool want64) {
     OpNeeds n;
@@ -366,21 +368,33 @@ static OpNeeds m2l_needs(fmm_plan_t pl, bool want64) {
     n.f64 = n.alias || want64;
     n.f32 = pl->prec == FMM_MIXED;
     n.bf = pl->prec == FMM_MIXED_BF16_M2L;
+    n.f16 = pl->prec == FMM_MIXED_SPLIT16_M2L;
     return n;
 }
 static bool m2l_ops_ready(fmm_plan_t pl, bool want64) {
     const OpNeeds n = m2l_needs(pl, want64);
     return (!n.f64 || pl->op->ops64.ptr) && (!n.alias || pl->op->alias_ops[0].ptr) && (!n.f32 || pl->op->ops32.ptr) &&
-           (!n.bf || pl->op->opsbf.ptr);
+           (!n.bf || pl->op->opsbf.ptr) && (!n.f16 || pl->op->ops16.ptr);
 }
 
 static fmm_status ensure_m2l_ops(fmm_plan_t pl, bool want64 = false) {
     if (m2l_ops_ready(pl, want64)) return FMM_OK;
     const OpNeeds nd = m2l_needs(pl, want64);
-    const bool needalias = nd.alias, need64 = nd.f64, need32 = nd.f32, needbf = nd.bf;
+    const bool needalias = nd.alias, need64 = nd.f64, need32 = nd.f32, needbf = nd.bf, need16 = nd.f16;
     std::vector<double> rm;
     build_m2l_all(pl->p, pl->op->offs, rm);
     const size_t ne = m2l_ops_elems<float>(pl->p);
+    if (need16 && !pl->op->ops16.ptr) {
+        const size_t nh = m2l_split16_ops_elems(pl->p);
+        std::vector<uint16_t> sw(nh);
+        std::vector<float> sc((size_t)2 * pl->Kp);
+        swizzle_m2l_ops_split16(pl->p, rm.data(), sw.data(), sc.data(), sc.data() + pl->Kp);
+        if (!pl->op->ops16.ensure(nh * sizeof(uint16_t)) || !pl->op->scale16.ensure(sc.size() * sizeof(float)))
+            return fail(pl, FMM_ERR_NOMEM, "M2L operator allocation");
+        HIPCHK(pl, hipMemcpy(pl->op->ops16.ptr, sw.data(), nh * sizeof(uint16_t), hipMemcpyHostToDevice), "M2L upload");
+        HIPCHK(pl, hipMemcpy(pl->op->scale16.ptr, sc.data(), sc.size() * sizeof(float), hipMemcpyHostToDevice),
+               "M2L upload");
+    }
     if (needbf && !pl->op->opsbf.ptr) {
         const size_t nb = m2l_bf16_ops_elems(pl->p);
         std::vector<uint16_t> sw(nb);
@@ -532,7 +546,8 @@ extern "C" fmm_status fmm_plan(double box, int levels, int p, fmm_plan_t *out) {
 
 extern "C" fmm_status fmm_plan_config(fmm_plan_t pl, int precision, double kappa, void *hip_stream) {
     if (!pl) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan_config: plan is NULL");
-    if (precision != FMM_FP64 && precision != FMM_MIXED && precision != FMM_MIXED_BF16_M2L)
+    if (precision != FMM_FP64 && precision != FMM_MIXED && precision != FMM_MIXED_BF16_M2L &&
+        precision != FMM_MIXED_SPLIT16_M2L)
         return fail(pl, FMM_ERR_INVALID, "fmm_plan_config: unknown precision");
     if (!std::isfinite(kappa)) return fail(pl, FMM_ERR_INVALID, "fmm_plan_config: kappa must be finite");
     if (pl->is_batch) {
@@ -587,7 +602,8 @@ extern "C" fmm_status fmm_plan_info(fmm_plan_t pl, int64_t *info, int n) {
     if (n < 0 || (n > 0 && !info)) return fail(pl, FMM_ERR_INVALID, "fmm_plan_info: bad info array");
     const int64_t v[FMM_INFO_COUNT] = {pl->is_batch ? 0 : pl->levels, pl->p, pl->K, pl->Kp, pl->prec,
                                        m2l_scheme(pl->p), m2l_list_entries(pl->p),
-                                       m2l_launches(pl->p, pl->prec == FMM_FP64),
+                                       pl->prec == FMM_MIXED_SPLIT16_M2L ? m2l_split16_launches(pl->p)
+                                                                         : m2l_launches(pl->p, pl->prec == FMM_FP64),
                                        pl->is_batch ? pl->top_fp64 : top_fp64_levels(pl), pl->p2p_g,
                                        16 * (int64_t)m2l_row_blocks(pl->p)};
     for (int i = 0; i < n && i < FMM_INFO_COUNT; ++i) info[i] = v[i];
@@ -740,7 +756,7 @@ static fmm_status ensure_side_streams(fmm_plan_t pl) {
 }
 
 template <typename T>
-static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field) {
+static fmm_status far_field(fmm_plan_t pl, int64_t n, const void *xq, double *phi, T *field) {
     hipStream_t s = pl->stream;
     const int L = pl->levels, p = pl->p, Kp = pl->Kp;
     const int top = top_fp64_levels(pl);
@@ -807,6 +823,11 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
             e = launch_m2l<double>(l, o.ops64.as<double>(), o.pairs.as<int32_t>(), o.offv.as<int32_t>(),
                                    o.rowmap.as<int32_t>(), MD(l), flip.as<double>(), flip.bytes, o.zeros.as<double>(),
                                    LD(l), part.as<double>(), part.bytes, p, Kp, ls);
+        else if (!TD && pl->prec == FMM_MIXED_SPLIT16_M2L)
+            e = launch_m2l_split16(l, pl->op->ops16.ptr, pl->op->il.as<int32_t>(), pl->op->offv.as<int32_t>(),
+                                   reinterpret_cast<const float *>(MT(l)), flip.as<float>(), flip.bytes,
+                                   pl->op->scale16.as<float>() + Kp, pl->op->scale16.as<float>(),
+                                   reinterpret_cast<float *>(LT(l)), part.as<double>(), part.bytes, p, Kp, ls);
         else if (!TD && pl->prec == FMM_MIXED_BF16_M2L)
             e = launch_m2l_bf16(l, pl->op->opsbf.ptr, pl->op->il.as<int32_t>(), pl->op->offv.as<int32_t>(),
                                 reinterpret_cast<const float *>(MT(l)), reinterpret_cast<float *>(LT(l)),
@@ -840,7 +861,7 @@ static fmm_status far_field(fmm_plan_t pl, const void *xq, double *phi, T *field
     }
     stage_end(pl, FMM_STAGE_L2L);
     stage_begin(pl, FMM_STAGE_L2P);
-    HIPCHK(pl, launch_l2p<T>(level_cells(L), xq, pl->start.as<int32_t>(), LT(L), p, Kp, h_leaf, phi, field, s),
+    HIPCHK(pl, launch_l2p<T>(level_cells(L), xq, pl->start.as<int32_t>(), LT(L), p, Kp, h_leaf, phi, field, s, n),
            "L2P");
     stage_end(pl, FMM_STAGE_L2P);
     return FMM_OK;
@@ -908,7 +929,7 @@ static fmm_status run_fields(fmm_plan_t pl, int64_t n, const double *pos, const 
         return FMM_OK;
     };
     if ((st = near_field()) != FMM_OK) return st;
-    if ((st = far_field<T>(pl, pl->xq.ptr, pl->phi_ff.as<double>(), pl->field_ff.as<T>())) != FMM_OK) return st;
+    if ((st = far_field<T>(pl, n, pl->xq.ptr, pl->phi_ff.as<double>(), pl->field_ff.as<T>())) != FMM_OK) return st;
     if (fork) HIPCHK(pl, hipStreamWaitEvent(s, pl->ev_join, 0), "stream wait");
     return FMM_OK;
 }
@@ -1282,7 +1303,7 @@ static fmm_status enqueue_uv_dense(fmm_plan_t pl, const uint8_t *mask) {
     }
     HIPCHK(pl, launch_mask_charges(n, pl->perm.as<int32_t>(), mask, pl->prec == FMM_FP64, pl->xq.ptr, pl->xq_u.ptr, s),
            "mask charges");
-    return far_field<T>(pl, pl->xq_u.ptr, pl->phi_u.as<double>(), pl->field_u.as<T>());
+    return far_field<T>(pl, n, pl->xq_u.ptr, pl->phi_u.as<double>(), pl->field_u.as<T>());
 }
 
 // lam >= 0 with a soft-core set: also the soft-core near-field sums at lam

@@ -110,9 +110,10 @@ hipError_t launch_p2m(int64_t nleaf, const void *xq, const int32_t *start, T *M,
                       double inv_h, hipStream_t s);
 hipError_t launch_lattice(const double *M0, double *L0, const double *AT, int p, int Kp,
                           hipStream_t s);
+// natoms: atoms of the tree (sets the leaves per workgroup)
 template <typename T>
 hipError_t launch_l2p(int64_t nleaf, const void *xq, const int32_t *start, const T *L, int p,
-                      int Kp, double h, double *phi, T *field, hipStream_t s);
+                      int Kp, double h, double *phi, T *field, hipStream_t s, int64_t natoms);
 
 // ---------------------------------------------------------------------------
 // The solute-solvent pass of several boxes, one launch per stage for all of
@@ -197,7 +198,24 @@ hipError_t launch_uv_p2p(const UvBox *b, int nbox, const int64_t *st_leaf, int64
 hipError_t launch_uv_sums(const UvBox *b, int nbox, const int64_t *st_red, int64_t nb_red, const int64_t *st_one,
                           int64_t nb_one, hipStream_t s);
 
-// k_m2l.hip
+// m2l_layout.cpp (host) and k_m2l.hip (kernels)
+// Row blocks of 16 operator rows: at most kRowBlocksPerWave per launch of the
+// LDS kernel (176 rows: K <= 169, p <= 12, in one row group), at most
+// kMaxRowGroups launches per level.  FP32 orbit lists whose four row classes
+// fit kAllClassBlocks blocks run in one launch, the four source fragments
+// gathered once for all classes (measured on the 1M-atom box, p = 12: 8.22 vs
+// 8.42 ms for the level); FP64 keeps two launches (one launch of 12 FP64 row
+// blocks: 16.1 vs 14.5 ms).  The split-FP16 kernel takes at most
+// kSplit16RowBlocks blocks per launch (its FP64 flush accumulators and 32-byte
+// operator fragments fit the registers).
+constexpr int kRowBlocksPerWave = 11;
+constexpr int kMaxRowGroups = 16;
+constexpr int kAllClassBlocks = 12;
+constexpr int kSplit16RowBlocks = 6;
+inline bool one_launch(int blocks_per_class, bool fp64) { return !fp64 && 4 * blocks_per_class <= kAllClassBlocks; }
+// chunks of 32 coefficients (the k depth of the 16x16x32 BF16 / FP16 MFMA)
+inline int m2l_k32_chunks(int p) { return (num_coeffs(p) + 31) / 32; }
+
 // Levels with few target cells split the interaction list into slices
 // (split-K) whose partial sums go to `partial` and are added in a fixed order.
 // offs: 3 ints per operator id (the source cell is the target cell + offset,
@@ -247,6 +265,17 @@ size_t m2l_bf16_ops_elems(int p);
 void swizzle_m2l_ops_bf16(int p, const double *ops_rowmajor, uint16_t *out);
 hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const int32_t *offs, const float *M,
                            float *L, float *partial, size_t part_cap, int p, int Kp, hipStream_t s);
+// M2L operators split into two FP16 parts, with power-of-two row and column
+// scales (rscale, cscale: Kp floats each), in the lane order of
+// v_mfma_f32_16x16x32_f16: [1206][ceil(K/32)][Kp/16][64 lanes][hi 8, lo 8]
+size_t m2l_split16_ops_elems(int p);
+void swizzle_m2l_ops_split16(int p, const double *ops_rowmajor, uint16_t *out, float *rscale, float *cscale);
+int m2l_split16_launches(int p);
+// Mc: scratch for the column-scaled multipoles of the level (mc_cap bytes);
+// partial: FP64 split-K partials (part_cap bytes) or NULL
+hipError_t launch_m2l_split16(int level, const void *ops, const int32_t *il, const int32_t *offs, const float *M,
+                              float *Mc, size_t mc_cap, const float *cscale, const float *rscale, float *L,
+                              double *partial, size_t part_cap, int p, int Kp, hipStream_t s);
 // any nops row-major K x K operators into the matrix-core lane order
 template <typename T>
 void swizzle_ops(int p, int nops, const double *ops_rowmajor, T *out);

@@ -6,6 +6,9 @@
 // Storage and scaling conventions are those of fmm_internal.h: real storage
 // of the normalised harmonics, expansions at each level scaled by the cell
 // edge so that every operator is level- and box-independent.
+#include <algorithm>
+#include <cmath>
+
 #include "fmm_internal.h"
 #include "morton.h"
 
@@ -394,7 +397,10 @@ hipError_t launch_lattice(const double *M0, double *L0, const double *AT, int p,
 // from L~ by differentiating the regular harmonics:
 //   dz R_n^m = R_{n-1}^m,  (dx + i dy) R_n^m = R_{n-1}^{m+1},
 //   (dx - i dy) R_n^m = -R_{n-1}^{m-1}.
-// One wavefront per leaf; lanes take atoms.
+// A workgroup of 256 threads takes a group of consecutive leaves (chosen so
+// that the group holds about 256 atoms): it stages their L~ in LDS, derives
+// their G~ there, and every thread then evaluates one atom of the group (the
+// group's atoms are contiguous in sorted order).
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ inline void get_local(const T *Ls, int n, int m, T &re, T &im) {
@@ -411,89 +417,102 @@ __device__ inline void get_local(const T *Ls, int n, int m, T &re, T &im) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_l2p(int64_t nleaf, const T *__restrict__ xq,
-                                            const int32_t *__restrict__ start, const T *__restrict__ L,
-                                            int p, int K, int Kp, T inv_h, T inv_h2, double *__restrict__ phi,
-                                            T *__restrict__ field) {
+__global__ __launch_bounds__(256) void k_l2p(int64_t nleaf, const T *__restrict__ xq,
+                                             const int32_t *__restrict__ start, const T *__restrict__ L, int p,
+                                             int K, int Kp, T inv_h, T inv_h2, double *__restrict__ phi,
+                                             T *__restrict__ field, int gl) {
     extern __shared__ unsigned char smem_raw[];
-    T *Ls = reinterpret_cast<T *>(smem_raw);
+    T *sm = reinterpret_cast<T *>(smem_raw);
     const int Kg = p * p;
-    T *Gx = Ls + K;
-    T *Gy = Gx + Kg;
-    T *Gz = Gy + Kg;
+    const int per = K + 3 * Kg;  // per leaf: L~, then G~x, G~y, G~z
     const int tid = threadIdx.x;
-    for (int64_t leaf = blockIdx.x; leaf < nleaf; leaf += gridDim.x) {
-        const int32_t s0 = start[leaf], s1 = start[leaf + 1];
-        if (s1 <= s0) continue;  // uniform per block
-        for (int j = tid; j < K; j += 64) Ls[j] = L[leaf * Kp + j];
-        __syncthreads();
-        for (int j = tid; j < Kg; j += 64) {
-            const int n = degree_of(j);
-            const int r = j - n * n;
-            const int m = (r + 1) / 2;
-            T are, aim, bre, bim, cre, cim;
-            get_local(Ls, n + 1, m - 1, are, aim);
-            get_local(Ls, n + 1, m + 1, bre, bim);
-            get_local(Ls, n + 1, m, cre, cim);
-            const T fa = sqrt((T)((n - m + 2) * (n - m + 1)));
-            const T fb = sqrt((T)((n + m + 2) * (n + m + 1)));
-            const T fc = sqrt((T)((n + 1 + m) * (n + 1 - m)));
-            // complex G-hat values
-            const T gxr = (T)0.5 * (fa * are - fb * bre), gxi = (T)0.5 * (fa * aim - fb * bim);
-            // (i/2)(fa A + fb B)
-            const T gyr = (T)-0.5 * (fa * aim + fb * bim), gyi = (T)0.5 * (fa * are + fb * bre);
-            const T gzr = fc * cre, gzi = fc * cim;
+    const int64_t l0 = blockIdx.x * (int64_t)gl;
+    const int nl = (int)min((int64_t)gl, nleaf - l0);
+    const int32_t a0 = start[l0], a1 = start[l0 + nl];
+    if (a1 <= a0) return;  // uniform per block
+    for (int i = tid; i < nl * K; i += 256) {
+        const int li = i / K, j = i - li * K;
+        sm[li * per + j] = L[(l0 + li) * Kp + j];
+    }
+    __syncthreads();
+    for (int i = tid; i < nl * Kg; i += 256) {
+        const int li = i / Kg, j = i - li * Kg;
+        const T *Ls = sm + li * per;
+        T *Gx = sm + li * per + K, *Gy = Gx + Kg, *Gz = Gy + Kg;
+        const int n = degree_of(j);
+        const int r = j - n * n;
+        const int m = (r + 1) / 2;
+        T are, aim, bre, bim, cre, cim;
+        get_local(Ls, n + 1, m - 1, are, aim);
+        get_local(Ls, n + 1, m + 1, bre, bim);
+        get_local(Ls, n + 1, m, cre, cim);
+        const T fa = sqrt((T)((n - m + 2) * (n - m + 1)));
+        const T fb = sqrt((T)((n + m + 2) * (n + m + 1)));
+        const T fc = sqrt((T)((n + 1 + m) * (n + 1 - m)));
+        // complex G-hat values
+        const T gxr = (T)0.5 * (fa * are - fb * bre), gxi = (T)0.5 * (fa * aim - fb * bim);
+        // (i/2)(fa A + fb B)
+        const T gyr = (T)-0.5 * (fa * aim + fb * bim), gyi = (T)0.5 * (fa * are + fb * bre);
+        const T gzr = fc * cre, gzi = fc * cim;
+        if (m == 0) {
+            Gx[j] = gxr; Gy[j] = gyr; Gz[j] = gzr;
+        } else if (r & 1) {  // real part slot, factor 2
+            Gx[j] = 2 * gxr; Gy[j] = 2 * gyr; Gz[j] = 2 * gzr;
+        } else {
+            Gx[j] = 2 * gxi; Gy[j] = 2 * gyi; Gz[j] = 2 * gzi;
+        }
+    }
+    __syncthreads();
+    for (int32_t s = a0 + tid; s < a1; s += 256) {
+        int li = 0;  // the atom's leaf within the group
+        while (li + 1 < nl && start[l0 + li + 1] <= s) ++li;
+        const T *Ls = sm + li * per;
+        const T *Gx = Ls + K, *Gy = Gx + Kg, *Gz = Gy + Kg;
+        const T *a = xq + 4 * (int64_t)s;
+        const T x = a[0] * inv_h, y = a[1] * inv_h, z = a[2] * inv_h;
+        double ph = 0;  // potential accumulated in FP64 (see k_p2p)
+        T gx = 0, gy = 0, gz = 0;
+        regular_hat_foreach<T>(x, y, z, p, [&](int n, int m, T re, T im) {
             if (m == 0) {
-                Gx[j] = gxr; Gy[j] = gyr; Gz[j] = gzr;
-            } else if (r & 1) {  // real part slot, factor 2
-                Gx[j] = 2 * gxr; Gy[j] = 2 * gyr; Gz[j] = 2 * gzr;
+                const int k = n * n;
+                ph += (double)(re * Ls[k]);
+                if (n < p) { gx += re * Gx[k]; gy += re * Gy[k]; gz += re * Gz[k]; }
             } else {
-                Gx[j] = 2 * gxi; Gy[j] = 2 * gyi; Gz[j] = 2 * gzi;
-            }
-        }
-        __syncthreads();
-        for (int32_t s = s0 + tid; s < s1; s += 64) {
-            const T *a = xq + 4 * (int64_t)s;
-            const T x = a[0] * inv_h, y = a[1] * inv_h, z = a[2] * inv_h;
-            double ph = 0;  // potential accumulated in FP64 (see k_p2p)
-            T gx = 0, gy = 0, gz = 0;
-            regular_hat_foreach<T>(x, y, z, p, [&](int n, int m, T re, T im) {
-                if (m == 0) {
-                    const int k = n * n;
-                    ph += (double)(re * Ls[k]);
-                    if (n < p) { gx += re * Gx[k]; gy += re * Gy[k]; gz += re * Gz[k]; }
-                } else {
-                    const int k = n * n + 2 * m - 1;
-                    ph += (double)(re * Ls[k] + im * Ls[k + 1]);
-                    if (n < p) {
-                        gx += re * Gx[k] + im * Gx[k + 1];
-                        gy += re * Gy[k] + im * Gy[k + 1];
-                        gz += re * Gz[k] + im * Gz[k + 1];
-                    }
+                const int k = n * n + 2 * m - 1;
+                ph += (double)(re * Ls[k] + im * Ls[k + 1]);
+                if (n < p) {
+                    gx += re * Gx[k] + im * Gx[k + 1];
+                    gy += re * Gy[k] + im * Gy[k + 1];
+                    gz += re * Gz[k] + im * Gz[k + 1];
                 }
-            });
-            phi[s] = ph * (double)inv_h;
-            field[3 * (int64_t)s + 0] = -gx * inv_h2;
-            field[3 * (int64_t)s + 1] = -gy * inv_h2;
-            field[3 * (int64_t)s + 2] = -gz * inv_h2;
-        }
-        __syncthreads();
+            }
+        });
+        phi[s] = ph * (double)inv_h;
+        field[3 * (int64_t)s + 0] = -gx * inv_h2;
+        field[3 * (int64_t)s + 1] = -gy * inv_h2;
+        field[3 * (int64_t)s + 2] = -gz * inv_h2;
     }
 }
 
+// leaves per workgroup: about 256 atoms per group at the mean occupancy,
+// within 48 KB of LDS
 template <typename T>
 hipError_t launch_l2p(int64_t nleaf, const void *xq, const int32_t *start, const T *L, int p, int Kp,
-                      double h, double *phi, T *field, hipStream_t s) {
+                      double h, double *phi, T *field, hipStream_t s, int64_t natoms) {
     const int K = num_coeffs(p);
-    const size_t lds = (size_t)(K + 3 * p * p) * sizeof(T);
-    int64_t g = nleaf < 1048576 ? nleaf : 1048576;
-    hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)g), dim3(64), lds, s, nleaf, (const T *)xq, start, L, p, K,
-                       Kp, (T)(1.0 / h), (T)(1.0 / (h * h)), phi, field);
+    const size_t per = (size_t)(K + 3 * p * p) * sizeof(T);
+    const double occ = nleaf > 0 ? (double)natoms / (double)nleaf : 1.0;
+    int gl = (int)std::floor(256.0 / std::max(occ, 1.0));
+    gl = std::max(1, std::min(gl, (int)((48 * 1024) / per)));
+    gl = std::min(gl, 64);
+    const int64_t g = (nleaf + gl - 1) / gl;
+    hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)g), dim3(256), (size_t)gl * per, s, nleaf, (const T *)xq, start, L,
+                       p, K, Kp, (T)(1.0 / h), (T)(1.0 / (h * h)), phi, field, gl);
     return hipGetLastError();
 }
 template hipError_t launch_l2p<float>(int64_t, const void *, const int32_t *, const float *, int, int,
-                                      double, double *, float *, hipStream_t);
+                                      double, double *, float *, hipStream_t, int64_t);
 template hipError_t launch_l2p<double>(int64_t, const void *, const int32_t *, const double *, int, int,
-                                       double, double *, double *, hipStream_t);
+                                       double, double *, double *, hipStream_t, int64_t);
 
 }  // namespace fmm

@@ -22,6 +22,7 @@
 //     dispatch of workgroups to the 8 XCDs every XCD streams one class's 875
 //     operators through its own L2.
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
@@ -32,209 +33,6 @@
 #include "morton.h"
 
 namespace fmm {
-
-constexpr int kRowBlocksPerWave = 11;  // 176 rows: K <= 169 (p <= 12) in one row group
-constexpr int kMaxRowGroups = 16;
-// FP32 orbit lists whose four row classes fit this many blocks run in one
-// launch, the four source fragments gathered once for all classes (measured on
-// the 1M-atom box, p = 12: 8.22 vs 8.42 ms for the level); FP64 keeps two
-// launches (one launch of 12 FP64 row blocks: 16.1 vs 14.5 ms)
-constexpr int kAllClassBlocks = 12;
-static bool one_launch(int blocks_per_class, bool fp64) { return !fp64 && 4 * blocks_per_class <= kAllClassBlocks; }
-
-// ---------------------------------------------------------------------------
-// Symmetries of the M2L operators.  Reflecting the translation in any set of
-// axes changes an operator by signs only: for s in {+-1}^3
-//   O_{s t} = D_s O_t D_s,   D_s = diag(sigma_s(k)),
-// where for a coefficient of degree n, order m and real or imaginary part
-//   x -> -x multiplies it by (-1)^m, and by -1 more for an imaginary part,
-//   y -> -y by -1 for an imaginary part,   z -> -z by (-1)^(n+m).
-// (the irregular harmonics I_n^m(s t) are +-I_n^m(t) or their conjugates).
-// For a group H of reflections and a target whose list holds the images s t,
-//   sum_{s in H} O_{s t} M_s = sum_{s} D_s O_t D_s M_s,
-// and the rows of a character class chi of H (rows k with sigma_s(k) = chi(s)
-// for all s in H) receive  O_t (sum_s chi(s) D_s M_s):  one operator product
-// per orbit, class by class.  Two groups are used:
-//   scheme 1, H = {identity, -1}: classes even / odd degree; per parity class
-//     the 875 offsets form 302 pairs (t, -t) and 271 single offsets: 573
-//     entries, sources (t, -t);
-//   scheme 2, H = {identity, (-,-,+), (-,+,-), (+,-,-)} (two-axis flips):
-//     four classes; 305 orbits of 1 to 4 offsets, sources in the order of H.
-// Operators are stored with their rows grouped by class, each class padded to
-// whole 16-row blocks (so a matrix-core row block holds one class), columns in
-// storage order.  Scheme 2 needs four padded classes; it is taken where its
-// matrix-core work (entries x row blocks) is smaller, i.e. for p >= 5.
-// ---------------------------------------------------------------------------
-struct Coef {
-    int n, m;
-    bool im;
-};
-static Coef coef(int k) {
-    int n = 0;
-    while ((n + 1) * (n + 1) <= k) ++n;
-    const int r = k - n * n;
-    return Coef{n, (r + 1) / 2, r > 0 && (r % 2 == 0)};
-}
-static int row_class(int scheme, int k) {
-    const Coef c = coef(k);
-    if (scheme == 1) return c.n & 1;
-    return 2 * (c.m & 1) + ((c.n & 1) ^ (c.im ? 1 : 0));
-}
-static int class_rows(int p, int scheme, int cls) {
-    int r = 0;
-    for (int k = 0; k < num_coeffs(p); ++k) r += row_class(scheme, k) == cls;
-    return r;
-}
-static int scheme_blocks(int p, int scheme) {
-    int b = 0;
-    for (int c = 0; c < (scheme == 1 ? 2 : 4); ++c) b += (class_rows(p, scheme, c) + 15) / 16;
-    return b;
-}
-// launches of a full-list level: one for all classes (FP32, small orders), or
-// one per half of the classes (the two classes sharing their partial sums),
-// split into groups of at most 11 row blocks
-static int scheme_launches(int p, int scheme, bool fp64) {
-    if (scheme == 2) {
-        const int b0 = (class_rows(p, 2, 0) + 15) / 16;
-        bool equal = true;
-        for (int c = 1; c < 4; ++c) equal = equal && (class_rows(p, 2, c) + 15) / 16 == b0;
-        if (equal && one_launch(b0, fp64)) return 1;
-    }
-    int n = 0;
-    for (int h = 0; h < (scheme == 1 ? 1 : 2); ++h) {
-        const int c0 = (class_rows(p, scheme, 2 * h) + 15) / 16, c1 = (class_rows(p, scheme, 2 * h + 1) + 15) / 16;
-        if (c0 + c1 == 0) continue;
-        n += c0 + c1 <= 11 ? 1 : (c0 + 10) / 11 + (c1 + 10) / 11;
-    }
-    return n;
-}
-// The scheme with the smaller cost entries x (row blocks + multipole
-// fragments loaded per chunk over all launches): each launch gathers every
-// source of an entry (2 for pairs, 4 for orbits) for each column chunk.  On
-// the 3M-atom box this picks the pairs at p = 8 (41.8 vs 42.6 ms mixed, 71 vs
-// 79 ms FP64) and the orbits from p = 10 (84 vs 105 ms at p = 12).
-int m2l_scheme(int p) {
-    const int64_t c1 = (int64_t)kM2LPairEntries * (scheme_blocks(p, 1) + 2 * scheme_launches(p, 1, false));
-    const int64_t c2 = (int64_t)kM2LOrbitEntries * (scheme_blocks(p, 2) + 4 * scheme_launches(p, 2, false));
-    return c2 < c1 ? 2 : 1;
-}
-int m2l_launches(int p, bool fp64) { return scheme_launches(p, m2l_scheme(p), fp64); }
-int m2l_row_blocks(int p) { return scheme_blocks(p, m2l_scheme(p)); }
-int m2l_class_blocks(int p, int *blocks) {
-    const int sch = m2l_scheme(p), nc = sch == 1 ? 2 : 4;
-    for (int c = 0; c < nc; ++c) blocks[c] = (class_rows(p, sch, c) + 15) / 16;
-    return nc;
-}
-int m2l_list_entries(int p) { return m2l_scheme(p) == 1 ? kM2LPairEntries : kM2LOrbitEntries; }
-int m2l_list_width(int p) { return m2l_scheme(p) == 1 ? 2 : 4; }
-
-// The padding rows K .. Kp-1 of the storage order take the first unused
-// slots (their operator rows are zero), so the kernel writes every stored row.
-void m2l_row_map(int p, int32_t *map) {
-    const int sch = m2l_scheme(p);
-    int blocks[4], start[4];
-    const int nc = m2l_class_blocks(p, blocks);
-    const int nr = 16 * m2l_row_blocks(p);
-    for (int i = 0; i < nr; ++i) map[i] = -1;
-    for (int c = 0, at = 0; c < nc; ++c) {
-        start[c] = at;
-        at += 16 * blocks[c];
-    }
-    for (int k = 0; k < num_coeffs(p); ++k) map[start[row_class(sch, k)]++] = k;
-    int pad = num_coeffs(p);
-    for (int i = 0; i < nr && pad < padded_coeffs(p); ++i)
-        if (map[i] < 0) map[i] = pad++;
-}
-
-// List entries per parity class (m2l_list_width ints each, -1 for an absent
-// source): the orbits of the scheme's group within the class's list, each
-// orbit at the position of its first offset in list order, each offset in
-// exactly one entry.  False if the counts differ from the constants.
-bool build_m2l_list(int p, const int32_t *vec, const int32_t *il, int32_t *out) {
-    const int sch = m2l_scheme(p), W = m2l_list_width(p), NE = m2l_list_entries(p);
-    static const int H1[2][3] = {{1, 1, 1}, {-1, -1, -1}};
-    static const int H2[4][3] = {{1, 1, 1}, {-1, -1, 1}, {-1, 1, -1}, {1, -1, -1}};
-    for (int par = 0; par < 8; ++par) {
-        const int32_t *l = il + par * kILSize;
-        int32_t *o = out + (size_t)par * W * NE;
-        bool used[kNumOffsets] = {};
-        int ne = 0;
-        for (int i = 0; i < kILSize; ++i) {
-            const int a = l[i];
-            if (used[a]) continue;
-            if (ne == NE) return false;
-            for (int w = 0; w < W; ++w) {
-                const int *sg = sch == 1 ? H1[w] : H2[w];
-                int found = -1;
-                for (int jj = 0; jj < kILSize && found < 0; ++jj) {
-                    const int c = l[jj];
-                    if (!used[c] && vec[3 * c] == sg[0] * vec[3 * a] && vec[3 * c + 1] == sg[1] * vec[3 * a + 1] &&
-                        vec[3 * c + 2] == sg[2] * vec[3 * a + 2])
-                        found = c;
-                }
-                if (found >= 0) used[found] = true;
-                o[W * ne + w] = found;
-            }
-            ++ne;
-        }
-        if (ne != NE) return false;
-    }
-    return true;
-}
-
-template <typename T>
-size_t m2l_ops_elems(int p) {
-    const size_t Kp = (size_t)padded_coeffs(p);
-    return (size_t)kNumOffsets * (Kp / 16) * m2l_row_blocks(p) * 256;
-}
-template size_t m2l_ops_elems<float>(int);
-template size_t m2l_ops_elems<double>(int);
-
-// out[(((oid * NKC + kc) * NRB + rb) * 64 + lane) * 4 + j] =
-//     O_oid[row = 16 rb + lane % 16][col = 16 kc + 4 (lane / 16) + j]
-template <typename T>
-void swizzle_ops(int p, int nops, const double *ops, T *out) {
-    const int K = num_coeffs(p), Kp = padded_coeffs(p);
-    const int NB = Kp / 16;
-    for (int oid = 0; oid < nops; ++oid) {
-        const double *A = ops + (size_t)oid * K * K;
-        for (int kc = 0; kc < NB; ++kc)
-            for (int rb = 0; rb < NB; ++rb)
-                for (int lane = 0; lane < 64; ++lane)
-                    for (int j = 0; j < 4; ++j) {
-                        const int row = 16 * rb + (lane & 15);
-                        const int col = 16 * kc + 4 * (lane >> 4) + j;
-                        const double v = (row < K && col < K) ? A[(size_t)row * K + col] : 0.0;
-                        out[((((size_t)oid * NB + kc) * NB + rb) * 64 + lane) * 4 + j] = (T)v;
-                    }
-    }
-}
-template void swizzle_ops<float>(int, int, const double *, float *);
-template void swizzle_ops<double>(int, int, const double *, double *);
-
-// The M2L operators with their rows in the order of m2l_row_map:
-// out[(((oid * NKC + kc) * NBR + rb) * 64 + lane) * 4 + j] =
-//     O_oid[map[16 rb + lane % 16]][16 kc + 4 (lane / 16) + j]
-template <typename T>
-void swizzle_m2l_ops(int p, const double *ops, T *out) {
-    const int K = num_coeffs(p), NKC = padded_coeffs(p) / 16, NBR = m2l_row_blocks(p);
-    std::vector<int32_t> map((size_t)16 * NBR);
-    m2l_row_map(p, map.data());
-    for (int oid = 0; oid < kNumOffsets; ++oid) {
-        const double *A = ops + (size_t)oid * K * K;
-        for (int kc = 0; kc < NKC; ++kc)
-            for (int rb = 0; rb < NBR; ++rb)
-                for (int lane = 0; lane < 64; ++lane)
-                    for (int j = 0; j < 4; ++j) {
-                        const int row = map[16 * rb + (lane & 15)];
-                        const int col = 16 * kc + 4 * (lane >> 4) + j;
-                        const double v = (row >= 0 && row < K && col < K) ? A[(size_t)row * K + col] : 0.0;
-                        out[((((size_t)oid * NKC + kc) * NBR + rb) * 64 + lane) * 4 + j] = (T)v;
-                    }
-    }
-}
-template void swizzle_m2l_ops<float>(int, const double *, float *);
-template void swizzle_m2l_ops<double>(int, const double *, double *);
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_m2l(const T *__restrict__ ops, const int32_t *__restrict__ il,
@@ -388,6 +186,7 @@ template <typename T> struct PolMfma {  // FP32 or FP64 operands, v_mfma_*_16x16
     static constexpr int KW = 16;
     static constexpr bool kFlush64 = sizeof(T) == 4;
     static constexpr bool kPaired = true;  // list of (t, -t) entries, row-ordered operators
+    static constexpr int kMaxNRB = 12;     // largest row group instantiated
     __device__ static R load_b(const S *p, bool in) {
         return in ? *reinterpret_cast<const R *>(p) : R{0, 0, 0, 0};
     }
@@ -407,6 +206,7 @@ struct PolBf16 {  // BF16 operands, FP32 storage and accumulation, v_mfma_f32_16
     static constexpr int KW = 32;
     static constexpr bool kFlush64 = false;
     static constexpr bool kPaired = false;  // plain list, storage-ordered operators
+    static constexpr int kMaxNRB = 11;
     __device__ static R load_b(const S *p, bool in) {
         return in ? *reinterpret_cast<const R *>(p) : R{0, 0, 0, 0, 0, 0, 0, 0};
     }
@@ -418,6 +218,49 @@ struct PolBf16 {  // BF16 operands, FP32 storage and accumulation, v_mfma_f32_16
     }
     __device__ static Acc mma(const A &a, const B &b, Acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+// Split FP16 operands (precision mode FMM_MIXED_SPLIT16_M2L): operator and
+// multipole entries x are each written as x = hi + lo with hi = fp16(x) and
+// lo = fp16(x - hi), and the product as hi*hi + hi*lo + lo*hi on
+// v_mfma_f32_16x16x32_f16 with FP32 accumulation (the lo*lo term and the
+// rounding of lo leave a relative error of about 2^-22 per product, against
+// 2^-24 for FP32 operands).  FP16's range is kept by powers of two: column k
+// of the operators is multiplied by 2^{b_k} and the multipoles divided by it
+// (in a pre-pass over the level), row r by 2^{a_r} and the result divided by
+// it on output, both exact.  Operators in storage row order, plain list.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+struct F16Pair {
+    f16x8 hi, lo;
+};
+struct PolF16x3 {
+    using S = float;
+    using A = F16Pair;
+    using B = F16Pair;
+    using Acc = f32x4;
+    typedef float R __attribute__((ext_vector_type(8)));
+    static constexpr int KW = 32;
+    static constexpr bool kFlush64 = true;
+    static constexpr bool kPaired = false;
+    static constexpr int kMaxNRB = 6;
+    __device__ static R load_b(const S *p, bool in) {
+        return in ? *reinterpret_cast<const R *>(p) : R{0, 0, 0, 0, 0, 0, 0, 0};
+    }
+    __device__ static B to_b(const R &r) {
+        B b;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const _Float16 h = (_Float16)r[i];
+            b.hi[i] = h;
+            b.lo[i] = (_Float16)(r[i] - (float)h);
+        }
+        return b;
+    }
+    __device__ static Acc mma(const A &a, const B &b, Acc c) {
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a.lo, b.hi, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a.hi, b.lo, c, 0, 0, 0);
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a.hi, b.hi, c, 0, 0, 0);
     }
 };
 
@@ -436,7 +279,9 @@ __device__ inline double pick(double a, double b, uint32_t m) {
 // MFMA-equivalents) within 48 KB of double-buffered LDS and a few registers.
 template <typename P, int NRB> constexpr int stage_chunks() {
     constexpr int bytes = (int)sizeof(typename P::A);                   // per lane and row block
-    constexpr int cyc = std::is_same<P, PolBf16>::value ? 16 : (bytes == 16 ? 4 * 32 : 4 * 64);
+    constexpr int cyc = std::is_same<P, PolBf16>::value ? 16
+                        : std::is_same<P, PolF16x3>::value ? 3 * 16
+                                                          : (bytes == 16 ? 4 * 32 : 4 * 64);
     constexpr int want = (1280 + cyc * NRB - 1) / (cyc * NRB);
     constexpr int lds_cap = (48 * 1024) / (2 * NRB * 64 * bytes);
     constexpr int u = want < lds_cap ? want : lds_cap;
@@ -488,7 +333,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
     const typename P::A *__restrict__ ops, const int32_t *__restrict__ il, const int32_t *__restrict__ offs,
     const int32_t *__restrict__ rowmap, const typename P::S *__restrict__ M, const typename P::S *__restrict__ Mflip,
     const typename P::S *__restrict__ zeros, int64_t fstride, typename P::S *__restrict__ L, double *__restrict__ L64,
-    int nh_bits, int NB, int NKC, int Kp, int rb0, int nslices_arg) {
+    const float *__restrict__ rscale, int nh_bits, int NB, int NKC, int Kp, int rb0, int nslices_arg) {
     using S = typename P::S;
     using A = typename P::A;
     using B = typename P::B;
@@ -765,10 +610,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
             const int prow = 16 * (rb0 + rb) + Mfma<S>::row(lane, r);
             const int row = SYM != 0 ? rowmap[prow] : prow;
             if (row < 0) continue;
+            // split operands: undo the row's power-of-two scale (exact)
+            const double rs = std::is_same<P, PolF16x3>::value ? (double)rscale[row] : 1.0;
             if constexpr (OUT64)
-                L64[slice_off + (size_t)tcell * Kp + row] = hi[rb][r] + (double)acc[rb][r];
+                L64[slice_off + (size_t)tcell * Kp + row] = rs * (hi[rb][r] + (double)acc[rb][r]);
             else
-                L[slice_off + (size_t)tcell * Kp + row] = F64 ? (S)(hi[rb][r] + (double)acc[rb][r]) : (S)acc[rb][r];
+                L[slice_off + (size_t)tcell * Kp + row] =
+                    F64 ? (S)(rs * (hi[rb][r] + (double)acc[rb][r])) : (S)acc[rb][r];
         }
 }
 
@@ -823,7 +671,8 @@ template <typename P>
 static hipError_t launch_lds(const void *ops, const int32_t *il, const int32_t *offs, const int32_t *rowmap,
                              const typename P::S *M, const typename P::S *Mflip, const typename P::S *zeros,
                              int64_t fstride, typename P::S *out, double *out64, int nh_bits, int NB, int NKC, int Kp,
-                             int nslices, const RowGroup *groups, int ng, hipStream_t s) {
+                             int nslices, const RowGroup *groups, int ng, hipStream_t s,
+                             const float *rscale = nullptr) {
     using A = typename P::A;
     const int64_t ntile = (((int64_t)1 << (3 * nh_bits)) + 63) / 64;
     const int64_t grid = 8 * ntile * nslices;
@@ -835,15 +684,15 @@ static hipError_t launch_lds(const void *ops, const int32_t *il, const int32_t *
 #define FMM_M2L_LDS_LAUNCH(SYM, N, NE)                                                                          \
     if (nslices > 1)                                                                                            \
         hipLaunchKernelGGL((k_m2l_lds<P, true, N, stage_chunks<P, N>(), NE, SYM>), dim3((unsigned)grid),       \
-                           dim3(256), 0, s, o, il, offs, rowmap, M, Mflip, zeros, fstride, out, out64, nh_bits,   \
-                           NB, NKC, Kp, rb0, nslices);                                                          \
+                           dim3(256), 0, s, o, il, offs, rowmap, M, Mflip, zeros, fstride, out, out64, rscale,    \
+                           nh_bits, NB, NKC, Kp, rb0, nslices);                                                 \
     else                                                                                                        \
         hipLaunchKernelGGL((k_m2l_lds<P, false, N, stage_chunks<P, N>(), NE, SYM>), dim3((unsigned)grid),      \
-                           dim3(256), 0, s, o, il, offs, rowmap, M, Mflip, zeros, fstride, out, out64, nh_bits,   \
-                           NB, NKC, Kp, rb0, 1);
+                           dim3(256), 0, s, o, il, offs, rowmap, M, Mflip, zeros, fstride, out, out64, rscale,    \
+                           nh_bits, NB, NKC, Kp, rb0, 1);
 #define FMM_M2L_LDS_CASE(SYM, N, NE)                                                                            \
-    if (!launched && sym == SYM && nrb == N && ne == NE && (SYM == 0) == !P::kPaired) {                        \
-        if constexpr ((SYM == 0) == !P::kPaired) {                                                              \
+    if (!launched && sym == SYM && nrb == N && ne == NE && (SYM == 0) == !P::kPaired && N <= P::kMaxNRB) {    \
+        if constexpr ((SYM == 0) == !P::kPaired && N <= P::kMaxNRB) {                                           \
             FMM_M2L_LDS_LAUNCH(SYM, N, NE)                                                                      \
         }                                                                                                       \
         launched = true;                                                                                        \
@@ -916,75 +765,40 @@ __global__ void k_m2l_reduce(const P *__restrict__ partial, T *__restrict__ L, i
     }
 }
 
-// Slices per level: enough workgroups (>= ~512) to fill 256 CUs at two
-// resident workgroups each; levels >= 5 have enough targets on their own.
-// Level 4 (FP32 all-classes kernel, two workgroups per CU): 8 slices = 512
-// workgroups, one resident round; with the partials in FP64 the slicing no
-// longer changes the result (1M-atom box: 10.05 ms per step against 10.13 /
-// 10.23 with 16 / 32 slices, identical errors).
-int m2l_slices(int level) {
-    switch (level) {
-        case 1: return 64;
-        case 2: return 64;
-        case 3: return 64;
-        case 4: return 8;
-        default: return 1;
-    }
+// Mc[c][k] = M[c][k] cscale[k] for the cells of one level
+__global__ void k_col_scale(const float *__restrict__ M, float *__restrict__ Mc, const float *__restrict__ cscale,
+                            int64_t n, int Kp) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        Mc[i] = M[i] * cscale[i % Kp];
 }
 
-size_t m2l_flip_bytes(int level, int p, size_t elem) {
-    return (size_t)m2l_flip_copies(p) * ((size_t)1 << (3 * level)) * (size_t)padded_coeffs(p) * elem;
-}
+static_assert(kSplit16RowBlocks == PolF16x3::kMaxNRB, "row groups of the split kernel");
 
-size_t m2l_partial_bytes(int level, int p, int nil, size_t elem) {
-    const int nslices = std::min(m2l_slices(level), nil);
-    if (nslices <= 1) return 0;
-    // FP32 operands on the full list keep their split-K partials in FP64
-    const size_t pe = (elem == 4 && nil == kILSize) ? 8 : elem;
-    return (size_t)nslices * ((size_t)1 << (3 * level)) * (size_t)padded_coeffs(p) * pe;
-}
-
-// ---------------------------------------------------------------------------
-// M2L with BF16 operands (precision mode FMM_MIXED_BF16_M2L): the same
-// contraction L~_c += sum_t O_t M~_{c+t} on v_mfma_f32_16x16x32_bf16, which
-// takes 8 consecutive k values per lane: lane l holds
-//   A[l % 16][8 (l / 16) + i]  (operator rows, k)   and
-//   B[8 (l / 16) + i][l % 16]  (k, target columns),  i = 0..7,
-// and returns the 16x16 FP32 block with the layout of the FP32 instruction.
-// K is walked in chunks of 32 (NKC = ceil(K / 32)); the FP32 multipoles are
-// rounded to BF16 as they are loaded (coefficients past Kp read as 0).
-// Workgroup layout, LDS staging (U chunks per stage, double buffered) and
-// split-K are those of k_m2l_lds; accumulation stays in FP32 because the
-// BF16 operand rounding (2^-9 relative) dominates the error.
-// ---------------------------------------------------------------------------
-static inline uint16_t bf16_round(double v) {
-    const float f = (float)v;
-    uint32_t u;
-    std::memcpy(&u, &f, 4);
-    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-    return (uint16_t)(u >> 16);
-}
-
-static int bf16_chunks(int p) { return (num_coeffs(p) + 31) / 32; }
-
-size_t m2l_bf16_ops_elems(int p) {
-    return (size_t)kNumOffsets * bf16_chunks(p) * (padded_coeffs(p) / 16) * 64 * 8;
-}
-
-void swizzle_m2l_ops_bf16(int p, const double *ops, uint16_t *out) {
-    const int K = num_coeffs(p), NB = padded_coeffs(p) / 16, NKC = bf16_chunks(p);
-    for (int oid = 0; oid < kNumOffsets; ++oid) {
-        const double *A = ops + (size_t)oid * K * K;
-        for (int kc = 0; kc < NKC; ++kc)
-            for (int rb = 0; rb < NB; ++rb)
-                for (int lane = 0; lane < 64; ++lane)
-                    for (int i = 0; i < 8; ++i) {
-                        const int row = 16 * rb + (lane & 15);
-                        const int col = 32 * kc + 8 * (lane >> 4) + i;
-                        const double v = (row < K && col < K) ? A[(size_t)row * K + col] : 0.0;
-                        out[((((size_t)oid * NKC + kc) * NB + rb) * 64 + lane) * 8 + i] = bf16_round(v);
-                    }
-    }
+hipError_t launch_m2l_split16(int level, const void *ops, const int32_t *il, const int32_t *offs, const float *M,
+                              float *Mc, size_t mc_cap, const float *cscale, const float *rscale, float *L,
+                              double *partial, size_t part_cap, int p, int Kp, hipStream_t s) {
+    const int NB = Kp / 16;
+    const int nh_bits = level - 1;
+    const int64_t ncell = (int64_t)8 << (3 * nh_bits);
+    const int nslices = partial ? m2l_slices(level) : 1;
+    if (mc_cap < (size_t)ncell * Kp * sizeof(float)) return hipErrorInvalidValue;
+    if (nslices > 1 && part_cap < m2l_partial_bytes(level, p, kILSize, sizeof(float))) return hipErrorInvalidValue;
+    const int64_t n = ncell * Kp;
+    int64_t g = (n + 255) / 256;
+    if (g > 65535) g = 65535;
+    hipLaunchKernelGGL(k_col_scale, dim3((unsigned)g), dim3(256), 0, s, M, Mc, cscale, n, Kp);
+    RowGroup grp[kMaxRowGroups];
+    int ng = 0;
+    for (int r = 0; r < NB; r += kSplit16RowBlocks)
+        grp[ng++] = RowGroup{r, std::min(kSplit16RowBlocks, NB - r), 0, 0};
+    hipError_t e = launch_lds<PolF16x3>(ops, il, offs, nullptr, Mc, Mc, Mc, 0, L, nslices > 1 ? partial : nullptr,
+                                        nh_bits, NB, m2l_k32_chunks(p), Kp, nslices, grp, ng, s, rscale);
+    if (e != hipSuccess || nslices == 1) return e;
+    const int64_t elems = ncell * Kp;
+    g = (elems + 255) / 256;
+    if (g > 65535) g = 65535;
+    hipLaunchKernelGGL((k_m2l_reduce<double, float>), dim3((unsigned)g), dim3(256), 0, s, partial, L, nslices, elems);
+    return hipGetLastError();
 }
 
 hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const int32_t *offs, const float *M,
@@ -998,7 +812,7 @@ hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const 
     RowGroup grp[kMaxRowGroups];
     const int ng = row_groups(0, p, NB, false, grp);
     hipError_t e = launch_lds<PolBf16>(ops, il, offs, nullptr, M, M, M, 0, nslices > 1 ? partial : L, nullptr, nh_bits, NB,
-                                       bf16_chunks(p), Kp, nslices, grp, ng, s);
+                                       m2l_k32_chunks(p), Kp, nslices, grp, ng, s);
     if (e != hipSuccess || nslices == 1) return e;
     const int64_t elems = ((int64_t)8 << (3 * nh_bits)) * Kp;
     int64_t g = (elems + 255) / 256;

@@ -597,6 +597,33 @@ def test_c3_sample_bf16_m2l(fmm):
     assert ep > 1e-4
 
 
+def test_c3_sample_split16_m2l(fmm):
+    # split FP16 operands at the FP32 levels (4 and 5): every operator and
+    # multipole entry as hi + lo in FP16 with power-of-two scales, three FP16
+    # matrix-core products with FP32 accumulation, FP64 flush per offset.  The
+    # per-product error is about 2^-22 against 2^-24 for FP32 operands, so the
+    # mixed-mode tolerance 1e-5 must hold (measured: potential 3.2e-6, force
+    # 1.0e-6), and the error stays above the FP32 path's on the potential
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "c3_sample_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/c3_sample_oracle.npz not generated")
+    ref = np.load(path)
+    w = workloads.config("C3")
+    idx = ref["idx"]
+    plan = _plan(fmm, w.box, w.levels, w.p, fmm.FMM_MIXED_SPLIT16_M2L)
+    assert fmm.fmm_plan_info(plan)["m2l_launches"] == 2  # row groups of 6 and 5 blocks
+    _, f, ph = fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q), forces=True, phi=True)
+    ph = ph.cpu().numpy()[idx]
+    ef = rms_rel(f.cpu().numpy()[idx], ref["force"])
+    ep = rms_rel(ph, ref["phi"])
+    rms_phi = float(np.sqrt(np.mean(ref["phi"] ** 2)))
+    print(f"C3 split16 M2L: force rms rel {ef:.2e}, phi rms rel {ep:.2e}, "
+          f"ion {abs(ph[-1] - ref['phi'][-1]) / rms_phi:.2e} (rms units)")
+    assert ef < 1e-5 and ep < 1e-5
+    assert abs(ph[-1] - ref["phi"][-1]) < 1e-5 * rms_phi
+
+
 # ------------------------------------- the 3M-atom precision / order sweep box --
 def test_c5_sample_order_sweep(fmm):
     # 1,000,000 waters + 8 ions (net +3), levels 6: the error against the
@@ -616,7 +643,8 @@ def test_c5_sample_order_sweep(fmm):
         plan = fmm.fmm_plan(w.box, w.levels, p)
         # mixed first, then FP64 on the same plan (the order the benchmark
         # takes), then the BF16-operand M2L at the orders of the sweep
-        precs = (fmm.FMM_MIXED, fmm.FMM_FP64) + ((fmm.FMM_MIXED_BF16_M2L,) if p in (8, 12) else ())
+        precs = (fmm.FMM_MIXED, fmm.FMM_FP64) + ((fmm.FMM_MIXED_BF16_M2L, fmm.FMM_MIXED_SPLIT16_M2L)
+                                                 if p in (8, 12) else ())
         for prec in precs:
             fmm.fmm_plan_config(plan, prec)
             _, f, ph = fmm.fmm_energy_forces(plan, pos, q, forces=True, phi=True)
@@ -633,3 +661,6 @@ def test_c5_sample_order_sweep(fmm):
     for p in (8, 12):
         f_err, p_err = errs[p, 2]
         assert f_err < 2.0 ** -10 and 1e-4 < p_err < 2.0 ** -5
+        # split FP16 operands: the mixed-mode tolerance (measured 3.6e-6 and
+        # 3.4e-6 on the potential at p = 8 and 12)
+        assert max(errs[p, 3]) < 1e-5
