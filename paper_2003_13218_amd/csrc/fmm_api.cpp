@@ -824,9 +824,11 @@ static fmm_status far_field(fmm_plan_t pl, int64_t n, const void *xq, double *ph
                                    o.rowmap.as<int32_t>(), MD(l), flip.as<double>(), flip.bytes, o.zeros.as<double>(),
                                    LD(l), part.as<double>(), part.bytes, p, Kp, ls);
         else if (!TD && pl->prec == FMM_MIXED_SPLIT16_M2L)
-            e = launch_m2l_split16(l, pl->op->ops16.ptr, pl->op->il.as<int32_t>(), pl->op->offv.as<int32_t>(),
+            e = launch_m2l_split16(l, pl->op->ops16.ptr,
+                                   m2l_split16_folded(p) ? o.pairs.as<int32_t>() : o.il.as<int32_t>(),
+                                   o.offv.as<int32_t>(), o.rowmap.as<int32_t>(),
                                    reinterpret_cast<const float *>(MT(l)), flip.as<float>(), flip.bytes,
-                                   pl->op->scale16.as<float>() + Kp, pl->op->scale16.as<float>(),
+                                   o.scale16.as<float>() + Kp, o.scale16.as<float>(), o.zeros.as<float>(),
                                    reinterpret_cast<float *>(LT(l)), part.as<double>(), part.bytes, p, Kp, ls);
         else if (!TD && pl->prec == FMM_MIXED_BF16_M2L)
             e = launch_m2l_bf16(l, pl->op->opsbf.ptr, pl->op->il.as<int32_t>(), pl->op->offv.as<int32_t>(),

@@ -216,6 +216,23 @@ inline bool one_launch(int blocks_per_class, bool fp64) { return !fp64 && 4 * bl
 // chunks of 32 coefficients (the k depth of the 16x16x32 BF16 / FP16 MFMA)
 inline int m2l_k32_chunks(int p) { return (num_coeffs(p) + 31) / 32; }
 
+// One launch of the LDS-shared M2L kernel: operator rows [rb0, rb0 + nrb) in
+// blocks, the first ne blocks on the first source combination, kernel
+// variant sym (0 plain list, 1 pairs (t, -t), 2 / 3 orbit halves, 4 all orbit
+// classes; see k_m2l_lds).
+struct RowGroup {
+    int rb0, nrb, ne, sym;
+};
+// Row groups of the class-ordered operators of order p (scheme 1 or 2), or of
+// plain storage-ordered operators with NB row blocks (scheme 0), at most maxrb
+// blocks each; returns the count (<= kMaxRowGroups)
+int m2l_row_groups(int scheme, int p, int NB, bool fp64, RowGroup *g, int maxrb = kRowBlocksPerWave);
+// split-FP16 M2L: the row groups of its folded list (0 when the order's
+// classes do not fit the instantiated shapes, p > 12: the plain list is used),
+// whether it folds, and its launches per level
+int m2l_split16_fold_groups(int p, RowGroup *grp);
+bool m2l_split16_folded(int p);
+
 // Levels with few target cells split the interaction list into slices
 // (split-K) whose partial sums go to `partial` and are added in a fixed order.
 // offs: 3 ints per operator id (the source cell is the target cell + offset,
@@ -267,15 +284,22 @@ hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const 
                            float *L, float *partial, size_t part_cap, int p, int Kp, hipStream_t s);
 // M2L operators split into two FP16 parts, with power-of-two row and column
 // scales (rscale, cscale: Kp floats each), in the lane order of
-// v_mfma_f32_16x16x32_f16: [1206][ceil(K/32)][Kp/16][64 lanes][hi 8, lo 8]
+// v_mfma_f32_16x16x32_f16: [1206][ceil(K/32)][row blocks][64 lanes][hi 8,
+// lo 8], rows in the class order of m2l_row_map (m2l_row_blocks blocks) when
+// m2l_split16_folded(p), else in storage order (Kp / 16 blocks)
 size_t m2l_split16_ops_elems(int p);
 void swizzle_m2l_ops_split16(int p, const double *ops_rowmajor, uint16_t *out, float *rscale, float *cscale);
 int m2l_split16_launches(int p);
-// Mc: scratch for the column-scaled multipoles of the level (mc_cap bytes);
+// list / offs / rowmap: the folded list, offsets and row map of the FP32
+// kernel when m2l_split16_folded(p), else the plain list and offsets (rowmap
+// unused); ops in the matching layout (swizzle_m2l_ops_split16); Mc: scratch
+// for the column-scaled multipoles of the level and, folded, their
+// sign-flipped copies (mc_cap bytes); zeros: Kp zero floats (absent images);
 // partial: FP64 split-K partials (part_cap bytes) or NULL
-hipError_t launch_m2l_split16(int level, const void *ops, const int32_t *il, const int32_t *offs, const float *M,
-                              float *Mc, size_t mc_cap, const float *cscale, const float *rscale, float *L,
-                              double *partial, size_t part_cap, int p, int Kp, hipStream_t s);
+hipError_t launch_m2l_split16(int level, const void *ops, const int32_t *list, const int32_t *offs,
+                              const int32_t *rowmap, const float *M, float *Mc, size_t mc_cap, const float *cscale,
+                              const float *rscale, const float *zeros, float *L, double *partial, size_t part_cap,
+                              int p, int Kp, hipStream_t s);
 // any nops row-major K x K operators into the matrix-core lane order
 template <typename T>
 void swizzle_ops(int p, int nops, const double *ops_rowmajor, T *out);

@@ -187,6 +187,7 @@ template <typename T> struct PolMfma {  // FP32 or FP64 operands, v_mfma_*_16x16
     static constexpr bool kFlush64 = sizeof(T) == 4;
     static constexpr bool kPaired = true;  // list of (t, -t) entries, row-ordered operators
     static constexpr int kMaxNRB = 12;     // largest row group instantiated
+    template <int SYM, int N, int NE> static constexpr bool allow() { return SYM != 0; }
     __device__ static R load_b(const S *p, bool in) {
         return in ? *reinterpret_cast<const R *>(p) : R{0, 0, 0, 0};
     }
@@ -207,6 +208,7 @@ struct PolBf16 {  // BF16 operands, FP32 storage and accumulation, v_mfma_f32_16
     static constexpr bool kFlush64 = false;
     static constexpr bool kPaired = false;  // plain list, storage-ordered operators
     static constexpr int kMaxNRB = 11;
+    template <int SYM, int N, int NE> static constexpr bool allow() { return SYM == 0; }
     __device__ static R load_b(const S *p, bool in) {
         return in ? *reinterpret_cast<const R *>(p) : R{0, 0, 0, 0, 0, 0, 0, 0};
     }
@@ -234,7 +236,9 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 struct F16Pair {
     f16x8 hi, lo;
 };
-struct PolF16x3 {
+// FOLD: the symmetry-folded list with class-ordered operator rows (as the
+// FP32 / FP64 kernels), else the plain list with storage-ordered rows.
+template <bool FOLD> struct PolF16x3T {
     using S = float;
     using A = F16Pair;
     using B = F16Pair;
@@ -242,8 +246,15 @@ struct PolF16x3 {
     typedef float R __attribute__((ext_vector_type(8)));
     static constexpr int KW = 32;
     static constexpr bool kFlush64 = true;
-    static constexpr bool kPaired = false;
+    static constexpr bool kPaired = FOLD;
     static constexpr int kMaxNRB = 6;
+    // plain list: row groups of up to 6 blocks; folded list: the class halves
+    // of orders p <= 12 (1, 2 or 3 blocks per class), or the (t, -t) pair
+    // classes of one block each
+    template <int SYM, int N, int NE> static constexpr bool allow() {
+        if (!FOLD) return SYM == 0 && N <= kMaxNRB;
+        return (SYM == 1 && N == 2 && NE == 1) || ((SYM == 2 || SYM == 3) && N <= 6 && N % 2 == 0 && NE * 2 == N);
+    }
     __device__ static R load_b(const S *p, bool in) {
         return in ? *reinterpret_cast<const R *>(p) : R{0, 0, 0, 0, 0, 0, 0, 0};
     }
@@ -263,6 +274,11 @@ struct PolF16x3 {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(a.hi, b.hi, c, 0, 0, 0);
     }
 };
+using PolF16x3 = PolF16x3T<false>;
+using PolF16x3F = PolF16x3T<true>;
+template <typename P> constexpr bool is_split16() {
+    return std::is_same<P, PolF16x3>::value || std::is_same<P, PolF16x3F>::value;
+}
 
 // Per-element choice between two fragments by an all-ones / zero mask (bit
 // operations, so a run-time choice never becomes a branch).
@@ -277,14 +293,22 @@ __device__ inline double pick(double a, double b, uint32_t m) {
 
 // Chunks per LDS stage: enough matrix-core work per barrier (about 40 FP32
 // MFMA-equivalents) within 48 KB of double-buffered LDS and a few registers.
-template <typename P, int NRB> constexpr int stage_chunks() {
+// The folded split kernel holds 8 multipole values per lane for each of an
+// entry's 2 or 4 sources, twice (current and prefetched stage): at most 8
+// sources per stage keep that within 128 registers, at most 4 once six row
+// blocks of accumulators (FP32 and FP64) share the 256 registers of two
+// wavefronts per SIMD.
+template <typename P, int NRB, int SYM> constexpr int stage_chunks() {
     constexpr int bytes = (int)sizeof(typename P::A);                   // per lane and row block
     constexpr int cyc = std::is_same<P, PolBf16>::value ? 16
-                        : std::is_same<P, PolF16x3>::value ? 3 * 16
+                        : is_split16<P>() ? 3 * 16
                                                           : (bytes == 16 ? 4 * 32 : 4 * 64);
     constexpr int want = (1280 + cyc * NRB - 1) / (cyc * NRB);
     constexpr int lds_cap = (48 * 1024) / (2 * NRB * 64 * bytes);
-    constexpr int u = want < lds_cap ? want : lds_cap;
+    constexpr int nsrc = SYM == 0 ? 1 : (SYM == 1 ? 2 : 4);
+    constexpr int reg_cap = is_split16<P>() ? (NRB >= 6 ? 4 : 8) / nsrc : 6;
+    constexpr int u0 = want < lds_cap ? want : lds_cap;
+    constexpr int u = u0 < reg_cap ? u0 : reg_cap;
     return u < 1 ? 1 : (u > 6 ? 6 : u);
 }
 
@@ -325,7 +349,7 @@ template <typename P, int NRB> constexpr int stage_chunks() {
 // level of the 1M-atom box.  The FP64 half-class variants stay at two
 // wavefronts: squeezed to three they spill inside the stage and lose.
 template <typename P, int NRB, int SYM> constexpr int m2l_min_waves() {
-    return (sizeof(typename P::S) == 4 && SYM == 4 && NRB == 12) ? 2 : 1;
+    return ((sizeof(typename P::S) == 4 && SYM == 4 && NRB == 12) || (is_split16<P>() && SYM != 0)) ? 2 : 1;
 }
 
 template <typename P, bool SPLIT, int NRB, int U, int NE, int SYM>
@@ -341,6 +365,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
     using R = typename P::R;
     constexpr bool F64 = P::kFlush64;
     constexpr int NSRC = SYM == 0 ? 1 : (SYM == 1 ? 2 : 4);       // sources per list entry
+    constexpr int NRV = (int)(sizeof(R) / sizeof(S));              // coefficients per lane and source
     static_assert(SYM != 4 || NRB == 4 * NE, "all four classes: NE blocks each");
     constexpr int NENT = SYM == 0 ? kILSize : (SYM == 1 ? kM2LPairEntries : kM2LOrbitEntries);
     constexpr int CHUNK = NRB * 64;             // fragments per chunk
@@ -509,16 +534,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
             } else if constexpr (SYM == 4) {
                 // all four classes of the orbit list (NE blocks each):
                 // (w0 + w1) +- (w2 + w3), (w0 - w1) +- (w2 - w3)
-                B v[4];
+                R w[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                for (int j = 0; j < NRV; ++j) {
                     const S xp = bcur[u][0][j] + bcur[u][1][j], xm = bcur[u][0][j] - bcur[u][1][j];
                     const S yp = bcur[u][2][j] + bcur[u][3][j], ym = bcur[u][2][j] - bcur[u][3][j];
-                    v[0][j] = xp + yp;
-                    v[1][j] = xp - yp;
-                    v[2][j] = xm + ym;
-                    v[3][j] = xm - ym;
+                    w[0][j] = xp + yp;
+                    w[1][j] = xp - yp;
+                    w[2][j] = xm + ym;
+                    w[3][j] = xm - ym;
                 }
+                const B v[4] = {P::to_b(w[0]), P::to_b(w[1]), P::to_b(w[2]), P::to_b(w[3])};
 #pragma unroll
                 for (int rb = 0; rb < NRB; ++rb) acc[rb] = P::mma(a[rb], v[rb / NE], acc[rb]);
                 // 16-byte fragments: read one row-block pair ahead of the eight
@@ -538,25 +564,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
                 // the class combinations sum_s chi(s) D_s M_s of the entry:
                 // pairs: w0 +- w1; orbits: (w0 +- w1) + (w2 +- w3) for the
                 // first class of the half, (w0 +- w1) - (w2 +- w3) for the second
-                B v1, v2;
+                R w1, w2;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                for (int j = 0; j < NRV; ++j) {
                     if constexpr (SYM == 1) {
-                        v1[j] = bcur[u][0][j] + bcur[u][1][j];
-                        v2[j] = bcur[u][0][j] - bcur[u][1][j];
+                        w1[j] = bcur[u][0][j] + bcur[u][1][j];
+                        w2[j] = bcur[u][0][j] - bcur[u][1][j];
                     } else {
                         const S x = SYM == 2 ? bcur[u][0][j] + bcur[u][1][j] : bcur[u][0][j] - bcur[u][1][j];
                         const S y = SYM == 2 ? bcur[u][2][j] + bcur[u][3][j] : bcur[u][2][j] - bcur[u][3][j];
-                        v1[j] = x + y;
-                        v2[j] = x - y;
+                        w1[j] = x + y;
+                        w2[j] = x - y;
                     }
                 }
+                const B v1 = P::to_b(w1), v2 = P::to_b(w2);
 #pragma unroll
                 for (int rb = 0; rb < NRB; ++rb) acc[rb] = P::mma(a[rb], rb < NE ? v1 : v2, acc[rb]);
                 // FP64 orbit halves: each row block's 32-byte fragment (two
                 // reads) issued two row blocks ahead of its four MFMAs (FP64
                 // leaf level of the 1M-atom box 13.78 -> 13.56 ms)
-                if constexpr (sizeof(A) == 32 && SYM >= 2) {
+                if constexpr (std::is_same<S, double>::value && SYM >= 2) {
                     __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);  // LDS reads
 #pragma unroll
                     for (int g = 0; g < NRB; ++g) {
@@ -611,57 +638,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
             const int row = SYM != 0 ? rowmap[prow] : prow;
             if (row < 0) continue;
             // split operands: undo the row's power-of-two scale (exact)
-            const double rs = std::is_same<P, PolF16x3>::value ? (double)rscale[row] : 1.0;
+            const double rs = is_split16<P>() ? (double)rscale[row] : 1.0;
             if constexpr (OUT64)
                 L64[slice_off + (size_t)tcell * Kp + row] = rs * (hi[rb][r] + (double)acc[rb][r]);
             else
                 L[slice_off + (size_t)tcell * Kp + row] =
                     F64 ? (S)(rs * (hi[rb][r] + (double)acc[rb][r])) : (S)acc[rb][r];
         }
-}
-
-// One launch of the LDS-shared kernel: operator rows [rb0, rb0 + nrb) in
-// blocks, the first ne blocks on the first source combination, kernel
-// variant sym (see k_m2l_lds).
-struct RowGroup {
-    int rb0, nrb, ne, sym;
-};
-
-// Row groups of the class-ordered operators of order p (scheme 1 or 2), or of
-// plain storage-ordered operators with NB row blocks (scheme 0).  A group
-// holds at most kRowBlocksPerWave blocks and one or two classes of the same
-// half (the two classes that share the partial sums w0 +- w1 and w2 +- w3).
-static int row_groups(int scheme, int p, int NB, bool fp64, RowGroup *g) {
-    int ng = 0;
-    auto chunks = [&](int from, int n, bool first, int sym) {
-        for (int r = 0; r < n; r += kRowBlocksPerWave) {
-            const int k = std::min(kRowBlocksPerWave, n - r);
-            g[ng++] = RowGroup{from + r, k, first ? k : 0, sym};
-        }
-    };
-    if (scheme == 0) {
-        chunks(0, NB, false, 0);
-        return ng;
-    }
-    int b[4];
-    const int nc = m2l_class_blocks(p, b);
-    if (nc == 4 && b[0] == b[1] && b[0] == b[2] && b[0] == b[3] && one_launch(b[0], fp64)) {
-        g[ng++] = RowGroup{0, 4 * b[0], b[0], 4};
-        return ng;
-    }
-    int at = 0;
-    for (int h = 0; h < nc / 2; ++h) {
-        const int c0 = b[2 * h], c1 = b[2 * h + 1], sym = scheme == 1 ? 1 : 2 + h;
-        if (c0 + c1 == 0) continue;
-        if (c0 + c1 <= kRowBlocksPerWave) {
-            g[ng++] = RowGroup{at, c0 + c1, c0, sym};
-        } else {
-            chunks(at, c0, true, sym);
-            chunks(at + c0, c1, false, sym);
-        }
-        at += c0 + c1;
-    }
-    return ng;
 }
 
 // Launches the LDS-shared kernel for every row group (NRB, U, NE and the
@@ -683,16 +666,16 @@ static hipError_t launch_lds(const void *ops, const int32_t *il, const int32_t *
         bool launched = false;
 #define FMM_M2L_LDS_LAUNCH(SYM, N, NE)                                                                          \
     if (nslices > 1)                                                                                            \
-        hipLaunchKernelGGL((k_m2l_lds<P, true, N, stage_chunks<P, N>(), NE, SYM>), dim3((unsigned)grid),       \
+        hipLaunchKernelGGL((k_m2l_lds<P, true, N, stage_chunks<P, N, SYM>(), NE, SYM>), dim3((unsigned)grid),       \
                            dim3(256), 0, s, o, il, offs, rowmap, M, Mflip, zeros, fstride, out, out64, rscale,    \
                            nh_bits, NB, NKC, Kp, rb0, nslices);                                                 \
     else                                                                                                        \
-        hipLaunchKernelGGL((k_m2l_lds<P, false, N, stage_chunks<P, N>(), NE, SYM>), dim3((unsigned)grid),      \
+        hipLaunchKernelGGL((k_m2l_lds<P, false, N, stage_chunks<P, N, SYM>(), NE, SYM>), dim3((unsigned)grid),      \
                            dim3(256), 0, s, o, il, offs, rowmap, M, Mflip, zeros, fstride, out, out64, rscale,    \
                            nh_bits, NB, NKC, Kp, rb0, 1);
 #define FMM_M2L_LDS_CASE(SYM, N, NE)                                                                            \
-    if (!launched && sym == SYM && nrb == N && ne == NE && (SYM == 0) == !P::kPaired && N <= P::kMaxNRB) {    \
-        if constexpr ((SYM == 0) == !P::kPaired && N <= P::kMaxNRB) {                                           \
+    if (!launched && sym == SYM && nrb == N && ne == NE && P::template allow<SYM, N, NE>()) {                \
+        if constexpr (P::template allow<SYM, N, NE>()) {                                                        \
             FMM_M2L_LDS_LAUNCH(SYM, N, NE)                                                                      \
         }                                                                                                       \
         launched = true;                                                                                        \
@@ -774,30 +757,67 @@ __global__ void k_col_scale(const float *__restrict__ M, float *__restrict__ Mc,
 
 static_assert(kSplit16RowBlocks == PolF16x3::kMaxNRB, "row groups of the split kernel");
 
-hipError_t launch_m2l_split16(int level, const void *ops, const int32_t *il, const int32_t *offs, const float *M,
-                              float *Mc, size_t mc_cap, const float *cscale, const float *rscale, float *L,
-                              double *partial, size_t part_cap, int p, int Kp, hipStream_t s) {
-    const int NB = Kp / 16;
+// Scaled and sign-flipped copies of the level's multipoles for the folded
+// split kernel: Mc[0] = cscale M, Mc[1 + f] = D_f (cscale M) for the group
+// elements of the scheme's list entries (the signs of k_m2l_flip)
+__device__ inline int flip_sign(int scheme, int f, int k);
+__global__ void k_m2l_flip_scaled(const float *__restrict__ M, float *__restrict__ Mc, const float *__restrict__ cscale,
+                                  int64_t ncell, int Kp, int scheme, int ncopy) {
+    const int k = threadIdx.x;
+    if (k >= Kp) return;
+    bool neg[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) neg[f] = f < ncopy && flip_sign(scheme, f, k) < 0;
+    const float cs = cscale[k];
+    const int64_t n = ncell * Kp;
+    for (int64_t c = blockIdx.x; c < ncell; c += gridDim.x) {
+        const int64_t i = c * Kp + k;
+        const float v = M[i] * cs;
+        Mc[i] = v;
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+            if (f < ncopy) Mc[(size_t)(f + 1) * n + i] = neg[f] ? -v : v;
+    }
+}
+
+hipError_t launch_m2l_split16(int level, const void *ops, const int32_t *list, const int32_t *offs,
+                              const int32_t *rowmap, const float *M, float *Mc, size_t mc_cap, const float *cscale,
+                              const float *rscale, const float *zeros, float *L, double *partial, size_t part_cap,
+                              int p, int Kp, hipStream_t s) {
     const int nh_bits = level - 1;
     const int64_t ncell = (int64_t)8 << (3 * nh_bits);
-    const int nslices = partial ? m2l_slices(level) : 1;
-    if (mc_cap < (size_t)ncell * Kp * sizeof(float)) return hipErrorInvalidValue;
-    if (nslices > 1 && part_cap < m2l_partial_bytes(level, p, kILSize, sizeof(float))) return hipErrorInvalidValue;
     const int64_t n = ncell * Kp;
+    const int nslices = partial ? m2l_slices(level) : 1;
+    RowGroup grp[kMaxRowGroups];
+    int ng = m2l_split16_fold_groups(p, grp);
+    const bool fold = ng > 0;
+    const int copies = fold ? 1 + m2l_flip_copies(p) : 1;
+    if (mc_cap < (size_t)copies * n * sizeof(float)) return hipErrorInvalidValue;
+    if (nslices > 1 && part_cap < m2l_partial_bytes(level, p, kILSize, sizeof(float))) return hipErrorInvalidValue;
+    if (Kp > 1024) return hipErrorInvalidValue;
+    hipError_t e;
+    if (fold) {
+        if (!rowmap || !zeros) return hipErrorInvalidValue;
+        const int fb = (Kp + 63) / 64 * 64;
+        const int64_t g = ncell < 16384 ? ncell : 16384;
+        hipLaunchKernelGGL(k_m2l_flip_scaled, dim3((unsigned)g), dim3(fb), 0, s, M, Mc, cscale, ncell, Kp,
+                           m2l_scheme(p), m2l_flip_copies(p));
+        e = launch_lds<PolF16x3F>(ops, list, offs, rowmap, Mc, Mc + n, zeros, n, L, nslices > 1 ? partial : nullptr,
+                                  nh_bits, m2l_row_blocks(p), m2l_k32_chunks(p), Kp, nslices, grp, ng, s, rscale);
+    } else {
+        int64_t g = (n + 255) / 256;
+        if (g > 65535) g = 65535;
+        hipLaunchKernelGGL(k_col_scale, dim3((unsigned)g), dim3(256), 0, s, M, Mc, cscale, n, Kp);
+        const int NB = Kp / 16;
+        for (int r = 0; r < NB; r += kSplit16RowBlocks)
+            grp[ng++] = RowGroup{r, std::min(kSplit16RowBlocks, NB - r), 0, 0};
+        e = launch_lds<PolF16x3>(ops, list, offs, nullptr, Mc, Mc, Mc, 0, L, nslices > 1 ? partial : nullptr, nh_bits,
+                                 NB, m2l_k32_chunks(p), Kp, nslices, grp, ng, s, rscale);
+    }
+    if (e != hipSuccess || nslices == 1) return e;
     int64_t g = (n + 255) / 256;
     if (g > 65535) g = 65535;
-    hipLaunchKernelGGL(k_col_scale, dim3((unsigned)g), dim3(256), 0, s, M, Mc, cscale, n, Kp);
-    RowGroup grp[kMaxRowGroups];
-    int ng = 0;
-    for (int r = 0; r < NB; r += kSplit16RowBlocks)
-        grp[ng++] = RowGroup{r, std::min(kSplit16RowBlocks, NB - r), 0, 0};
-    hipError_t e = launch_lds<PolF16x3>(ops, il, offs, nullptr, Mc, Mc, Mc, 0, L, nslices > 1 ? partial : nullptr,
-                                        nh_bits, NB, m2l_k32_chunks(p), Kp, nslices, grp, ng, s, rscale);
-    if (e != hipSuccess || nslices == 1) return e;
-    const int64_t elems = ncell * Kp;
-    g = (elems + 255) / 256;
-    if (g > 65535) g = 65535;
-    hipLaunchKernelGGL((k_m2l_reduce<double, float>), dim3((unsigned)g), dim3(256), 0, s, partial, L, nslices, elems);
+    hipLaunchKernelGGL((k_m2l_reduce<double, float>), dim3((unsigned)g), dim3(256), 0, s, partial, L, nslices, n);
     return hipGetLastError();
 }
 
@@ -810,7 +830,7 @@ hipError_t launch_m2l_bf16(int level, const void *ops, const int32_t *il, const 
     if (nslices > 1 && part_cap < (size_t)nslices * ((size_t)8 << (3 * nh_bits)) * (size_t)Kp * sizeof(float))
         return hipErrorInvalidValue;
     RowGroup grp[kMaxRowGroups];
-    const int ng = row_groups(0, p, NB, false, grp);
+    const int ng = m2l_row_groups(0, p, NB, false, grp);
     hipError_t e = launch_lds<PolBf16>(ops, il, offs, nullptr, M, M, M, 0, nslices > 1 ? partial : L, nullptr, nh_bits, NB,
                                        m2l_k32_chunks(p), Kp, nslices, grp, ng, s);
     if (e != hipSuccess || nslices == 1) return e;
@@ -886,7 +906,7 @@ hipError_t launch_m2l(int level, const T *ops, const int32_t *list, const int32_
         hipLaunchKernelGGL(k_m2l_flip<T>, dim3((unsigned)g), dim3(fb), 0, s, M, Mflip, ncell, Kp, scheme,
                            m2l_flip_copies(p));
         RowGroup grp[kMaxRowGroups];
-        const int ng = row_groups(scheme, p, m2l_row_blocks(p), sizeof(T) == 8, grp);
+        const int ng = m2l_row_groups(scheme, p, m2l_row_blocks(p), sizeof(T) == 8, grp);
         // FP32 operands: FP64 split-K partials (the buffer holds doubles)
         part64 = (sizeof(T) == 4 && nslices > 1) ? reinterpret_cast<double *>(partial) : nullptr;
         const hipError_t e = launch_lds<PolMfma<T>>(ops, list, offs, rowmap, M, Mflip, zeros, n,

@@ -308,12 +308,22 @@ static double f16_value(uint16_t b) {
     return (b & 0x8000) ? -v : v;
 }
 
+// row blocks of the split operators: class-ordered for the folded list
+static int split16_row_blocks(int p) { return m2l_split16_folded(p) ? m2l_row_blocks(p) : padded_coeffs(p) / 16; }
+
 size_t m2l_split16_ops_elems(int p) {
-    return (size_t)kNumOffsets * m2l_k32_chunks(p) * (padded_coeffs(p) / 16) * 64 * 16;
+    return (size_t)kNumOffsets * m2l_k32_chunks(p) * split16_row_blocks(p) * 64 * 16;
 }
 
 void swizzle_m2l_ops_split16(int p, const double *ops, uint16_t *out, float *rscale, float *cscale) {
-    const int K = num_coeffs(p), Kp = padded_coeffs(p), NB = Kp / 16, NKC = m2l_k32_chunks(p);
+    const int K = num_coeffs(p), Kp = padded_coeffs(p), NB = split16_row_blocks(p), NKC = m2l_k32_chunks(p);
+    // operator row of each position (class order when folded; -1: padding)
+    std::vector<int32_t> map((size_t)16 * NB);
+    if (m2l_split16_folded(p)) {
+        m2l_row_map(p, map.data());
+    } else {
+        for (int i = 0; i < 16 * NB; ++i) map[i] = i;
+    }
     std::vector<int> b(Kp, 0), a(Kp, 0);
     for (int k = 0; k < K; ++k) {
         int n = 0;
@@ -341,10 +351,11 @@ void swizzle_m2l_ops_split16(int p, const double *ops, uint16_t *out, float *rsc
             for (int rb = 0; rb < NB; ++rb)
                 for (int lane = 0; lane < 64; ++lane)
                     for (int i = 0; i < 8; ++i) {
-                        const int row = 16 * rb + (lane & 15);
+                        const int row = map[16 * rb + (lane & 15)];
                         const int col = 32 * kc + 8 * (lane >> 4) + i;
                         double v = 0.0;
-                        if (row < K && col < K) v = std::ldexp(A[(size_t)row * K + col], a[row] + b[col]);
+                        if (row >= 0 && row < K && col < K)
+                            v = std::ldexp(A[(size_t)row * K + col], a[row] + b[col]);
                         const uint16_t hi = f16_bits(v);
                         const uint16_t lo = f16_bits(v - f16_value(hi));
                         const size_t at = ((((size_t)oid * NKC + kc) * NB + rb) * 64 + lane) * 16;
@@ -355,6 +366,69 @@ void swizzle_m2l_ops_split16(int p, const double *ops, uint16_t *out, float *rsc
 }
 
 
-int m2l_split16_launches(int p) { return (padded_coeffs(p) / 16 + kSplit16RowBlocks - 1) / kSplit16RowBlocks; }
+// Row groups of the class-ordered operators of order p (scheme 1 or 2), or of
+// plain storage-ordered operators with NB row blocks (scheme 0).  A group
+// holds at most kRowBlocksPerWave blocks and one or two classes of the same
+// half (the two classes that share the partial sums w0 +- w1 and w2 +- w3).
+int m2l_row_groups(int scheme, int p, int NB, bool fp64, RowGroup *g, int maxrb) {
+    int ng = 0;
+    auto chunks = [&](int from, int n, bool first, int sym) {
+        for (int r = 0; r < n; r += maxrb) {
+            const int k = std::min(maxrb, n - r);
+            g[ng++] = RowGroup{from + r, k, first ? k : 0, sym};
+        }
+    };
+    if (scheme == 0) {
+        chunks(0, NB, false, 0);
+        return ng;
+    }
+    int b[4];
+    const int nc = m2l_class_blocks(p, b);
+    if (nc == 4 && b[0] == b[1] && b[0] == b[2] && b[0] == b[3] && one_launch(b[0], fp64)) {
+        g[ng++] = RowGroup{0, 4 * b[0], b[0], 4};
+        return ng;
+    }
+    int at = 0;
+    for (int h = 0; h < nc / 2; ++h) {
+        const int c0 = b[2 * h], c1 = b[2 * h + 1], sym = scheme == 1 ? 1 : 2 + h;
+        if (c0 + c1 == 0) continue;
+        if (c0 + c1 <= maxrb) {
+            g[ng++] = RowGroup{at, c0 + c1, c0, sym};
+        } else {
+            chunks(at, c0, true, sym);
+            chunks(at + c0, c1, false, sym);
+        }
+        at += c0 + c1;
+    }
+    return ng;
+}
+
+
+// The row groups of the folded split kernel for order p (class halves, at most
+// kSplit16RowBlocks blocks), or 0 when an order's classes do not fit the
+// instantiated shapes (p > 12: the plain list is used)
+int m2l_split16_fold_groups(int p, RowGroup *grp) {
+    const int scheme = m2l_scheme(p);
+    const int ng = m2l_row_groups(scheme, p, m2l_row_blocks(p), true, grp, kSplit16RowBlocks);
+    for (int i = 0; i < ng; ++i) {
+        const RowGroup &g = grp[i];
+        const bool ok = (g.sym == 1 && g.nrb == 2 && g.ne == 1) ||
+                        ((g.sym == 2 || g.sym == 3) && g.nrb <= 6 && g.nrb % 2 == 0 && 2 * g.ne == g.nrb);
+        if (!ok) return 0;
+    }
+    return ng;
+}
+
+bool m2l_split16_folded(int p) {
+    RowGroup grp[kMaxRowGroups];
+    return m2l_split16_fold_groups(p, grp) > 0;
+}
+
+int m2l_split16_launches(int p) {
+    RowGroup grp[kMaxRowGroups];
+    const int ng = m2l_split16_fold_groups(p, grp);
+    return ng > 0 ? ng : (padded_coeffs(p) / 16 + kSplit16RowBlocks - 1) / kSplit16RowBlocks;
+}
+
 
 }  // namespace fmm

@@ -190,6 +190,31 @@ def test_c1_orders_with_several_row_groups(fmm, p, prec):
     assert rms_rel(ph.cpu().numpy(), o["phi"]) < tol
 
 
+@pytest.mark.parametrize("p", [4, 5, 8, 12, 16])
+def test_split16_layouts_every_level(fmm, p):
+    # the split-FP16 M2L at all four levels of the 10,000-water box (FP64 top
+    # levels switched off), in each of its operator layouts: the folded orbit
+    # list with (t, -t) pair classes of one row block (p = 4), class halves of
+    # one, two and three row blocks (p = 5, 8, 12), and the plain list (p = 16).
+    # Against FP64 on the same plan (same truncation) the difference is the
+    # operand rounding alone; a wrong row, sign or scale would be of order 1.
+    w, o = ewald_full("C2")
+    plan = _plan(fmm, w.box, w.levels, p, fmm.FMM_FP64)
+    pos, q = _t(w.pos), _t(w.q)
+    e64, f64, ph64 = fmm.fmm_energy_forces(plan, pos, q, forces=True, phi=True)
+    fmm.fmm_plan_config(plan, fmm.FMM_MIXED_SPLIT16_M2L)
+    fmm.fmm_plan_tuning(plan, fp64_levels=0)
+    e, f, ph = fmm.fmm_energy_forces(plan, pos, q, forces=True, phi=True)
+    fmm.fmm_destroy(plan)
+    f64, ph64 = f64.cpu().numpy(), ph64.cpu().numpy()
+    ef, ep = rms_rel(f.cpu().numpy(), f64), rms_rel(ph.cpu().numpy(), ph64)
+    print(f"split16 p={p} every level: vs FP64 force {ef:.2e} phi {ep:.2e} energy {abs(e - e64) / abs(e64):.2e}")
+    assert ef < 1e-5 and ep < 1e-5 and abs(e - e64) < 1e-6 * abs(e64)
+    if p >= 8:
+        assert rms_rel(f.cpu().numpy(), o["force"]) < 1e-5
+        assert rms_rel(ph.cpu().numpy(), o["phi"]) < 1e-5
+
+
 @pytest.mark.parametrize("prec,tol", [(0, 1e-6), (1, 1e-5)])
 def test_c2_energy_forces(fmm, prec, tol):
     w, o = ewald_full("C2")
@@ -599,11 +624,11 @@ def test_c3_sample_bf16_m2l(fmm):
 
 def test_c3_sample_split16_m2l(fmm):
     # split FP16 operands at the FP32 levels (4 and 5): every operator and
-    # multipole entry as hi + lo in FP16 with power-of-two scales, three FP16
-    # matrix-core products with FP32 accumulation, FP64 flush per offset.  The
-    # per-product error is about 2^-22 against 2^-24 for FP32 operands, so the
-    # mixed-mode tolerance 1e-5 must hold (measured: potential 3.2e-6, force
-    # 1.0e-6), and the error stays above the FP32 path's on the potential
+    # (orbit-combined) multipole entry as hi + lo in FP16 with power-of-two
+    # scales, three FP16 matrix-core products with FP32 accumulation, FP64
+    # flush per offset.  The per-product error is about 2^-22 against 2^-24
+    # for FP32 operands, so the mixed-mode tolerance 1e-5 must hold (measured
+    # unfolded: potential 3.2e-6, force 1.0e-6)
     import os
     path = os.path.join(os.path.dirname(__file__), "golden", "c3_sample_oracle.npz")
     if not os.path.exists(path):
@@ -612,7 +637,7 @@ def test_c3_sample_split16_m2l(fmm):
     w = workloads.config("C3")
     idx = ref["idx"]
     plan = _plan(fmm, w.box, w.levels, w.p, fmm.FMM_MIXED_SPLIT16_M2L)
-    assert fmm.fmm_plan_info(plan)["m2l_launches"] == 2  # row groups of 6 and 5 blocks
+    assert fmm.fmm_plan_info(plan)["m2l_launches"] == 2  # the two class halves of 6 blocks
     _, f, ph = fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q), forces=True, phi=True)
     ph = ph.cpu().numpy()[idx]
     ef = rms_rel(f.cpu().numpy()[idx], ref["force"])
