@@ -42,18 +42,17 @@ DTYPES = {"mixed": "f32+f64", "fp64": "f64", "bf16": "bf16-m2l+f32+f64", "split1
 def leaf_kernel(prec_name, info):
     """Name of the finest-level M2L kernel; info = fmm_plan_info of the plan.
     The FP32/FP64 kernel takes the symmetry-folded list (pairs or orbits of
-    reflected offsets) in info["m2l_launches"] launches (row-class groups)."""
+    reflected offsets) in info["m2l_launches"] launches (row-class groups), the
+    split-FP16 one the orbit list at p = 11, 12 and the plain list otherwise."""
     if prec_name == "bf16":
         return "k_m2l_bf16<false>"
-    if prec_name == "split16":
-        return f"k_m2l_lds<PolF16x3, false> x{info['m2l_launches']} (plain list, 875 offsets)"
-    t = "double" if prec_name == "fp64" else "float"
-    kind = "orbit" if info["m2l_scheme"] == 2 else "pair"
+    t = {"fp64": "double", "split16": "PolF16x3"}.get(prec_name, "float")
+    kind = {2: "orbit", 1: "pair", 0: "plain"}[info["m2l_scheme"]]
     return f"k_m2l_lds<{t}, false> x{info['m2l_launches']} ({kind} list, {info['m2l_entries']} entries)"
 
 
 def m2l_entries(prec_name, info):
-    return M2L_IL if prec_name in ("bf16", "split16") else info["m2l_entries"]
+    return info["m2l_entries"]
 
 
 def m2l_flops(p, level, entries):
@@ -216,7 +215,7 @@ def run_single(args, w, p, prec_name, steps, warmup, fp64_leg, cpu_leg, graph_le
     # issue including the class padding of the rows and the column padding.
     K = (p + 1) ** 2
     dense = m2l_flops(p, w.levels, M2L_IL)
-    rows = {"bf16": info["Kp"], "split16": info["Kp"]}.get(prec_name, info["m2l_rows"])
+    rows = info["m2l_rows"]
     cols = 32 * ((K + 31) // 32) if prec_name in ("bf16", "split16") else info["Kp"]
     # split operands: three FP16 products per operand pair
     executed = flops_leaf * (rows * cols) / (K * K) * (3 if prec_name == "split16" else 1)

@@ -80,9 +80,10 @@ typedef enum {
      * multipole entry as the sum of two FP16 numbers (hi + lo, with exact
      * power-of-two row and column scales keeping them in FP16's range) and
      * forms hi*hi + hi*lo + lo*hi on the FP16 matrix cores with FP32
-     * accumulation, partial sums flushed to FP64 after every offset: about
-     * 2^-22 relative per product against 2^-24 for FP32 operands, on the
-     * plain 875-offset interaction list */
+     * accumulation, partial sums flushed to FP64 after every list entry: about
+     * 2^-22 relative per product against 2^-24 for FP32 operands.  Orders
+     * 11 and 12 run the folded orbit list (all four row classes in one
+     * launch), the others the plain 875-offset list */
     FMM_MIXED_SPLIT16_M2L = 3
 } fmm_precision;
 
@@ -394,19 +395,20 @@ fmm_status fmm_profile_read(fmm_plan_t plan, double *ms, int64_t *calls);
  * Writes min(n, FMM_INFO_COUNT) int64 values to info (host):
  *   [0] levels (0 for a batch plan: see fmm_batch_levels)   [1] p
  *   [2] K = (p+1)^2   [3] Kp (K padded to 16)   [4] precision mode
- *   [5] symmetry folding of the FP32/FP64 M2L interaction lists:
+ *   [5]-[7] and [10] describe the finest level's M2L in the plan's current
+ *   precision mode (FP32 in the mixed modes, FP64 in FMM_FP64):
+ *   [5] symmetry folding of its interaction list: 0 = none (the 875 offsets:
+ *       the BF16 M2L, and the split-FP16 one except at p = 11, 12),
  *       1 = (t, -t) pairs, 2 = orbits of the two-axis flips (the operators of
  *       reflected offsets differ by signs only, so each pair or orbit is one
  *       operator product per row class)
- *   [6] M2L list entries per cell under that folding (573 or 305; the BF16
- *       M2L always takes the 875 offsets)
- *   [7] launches of the M2L kernel per full-list level in the plan's
- *       precision (the finest level: FP32 in the mixed modes)
+ *   [6] list entries per cell under that folding (875, 573 or 305)
+ *   [7] launches of the M2L kernel per full-list level
  *   [8] tree levels run in FP64 (1 .. [8]; all of them in FMM_FP64; for a
  *       batch plan the fmm_plan_tuning setting)
  *   [9] near-field source groups set by fmm_plan_tuning (0 = automatic)
- *   [10] operator rows the matrix cores run per list entry of the FP32/FP64
- *       M2L (each row class padded to whole 16-row blocks; >= K)
+ *   [10] operator rows the matrix cores run per list entry (folded: each row
+ *       class padded to whole 16-row blocks; plain: Kp; >= K)
  */
 #define FMM_INFO_COUNT 11
 fmm_status fmm_plan_info(fmm_plan_t plan, int64_t *info, int n);

@@ -600,12 +600,18 @@ extern "C" fmm_status fmm_plan_tuning(fmm_plan_t pl, int fp64_levels, int p2p_gr
 extern "C" fmm_status fmm_plan_info(fmm_plan_t pl, int64_t *info, int n) {
     if (!pl) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan_info: plan is NULL");
     if (n < 0 || (n > 0 && !info)) return fail(pl, FMM_ERR_INVALID, "fmm_plan_info: bad info array");
+    // the finest level's M2L in the plan's mode: the folded list of the FP32 /
+    // FP64 kernels, the plain list of the BF16 kernel, and for the split
+    // operands whichever of the two that order takes
+    const bool plain = pl->prec == FMM_MIXED_BF16_M2L ||
+                       (pl->prec == FMM_MIXED_SPLIT16_M2L && !m2l_split16_folded(pl->p));
+    int64_t launches = m2l_launches(pl->p, pl->prec == FMM_FP64);
+    if (pl->prec == FMM_MIXED_SPLIT16_M2L) launches = m2l_split16_launches(pl->p);
+    if (pl->prec == FMM_MIXED_BF16_M2L) launches = 1;
     const int64_t v[FMM_INFO_COUNT] = {pl->is_batch ? 0 : pl->levels, pl->p, pl->K, pl->Kp, pl->prec,
-                                       m2l_scheme(pl->p), m2l_list_entries(pl->p),
-                                       pl->prec == FMM_MIXED_SPLIT16_M2L ? m2l_split16_launches(pl->p)
-                                                                         : m2l_launches(pl->p, pl->prec == FMM_FP64),
-                                       pl->is_batch ? pl->top_fp64 : top_fp64_levels(pl), pl->p2p_g,
-                                       16 * (int64_t)m2l_row_blocks(pl->p)};
+                                       plain ? 0 : m2l_scheme(pl->p), plain ? kILSize : m2l_list_entries(pl->p),
+                                       launches, pl->is_batch ? pl->top_fp64 : top_fp64_levels(pl), pl->p2p_g,
+                                       plain ? pl->Kp : 16 * (int64_t)m2l_row_blocks(pl->p)};
     for (int i = 0; i < n && i < FMM_INFO_COUNT; ++i) info[i] = v[i];
     return FMM_OK;
 }

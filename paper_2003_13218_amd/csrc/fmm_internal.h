@@ -206,8 +206,9 @@ hipError_t launch_uv_sums(const UvBox *b, int nbox, const int64_t *st_red, int64
 // gathered once for all classes (measured on the 1M-atom box, p = 12: 8.22 vs
 // 8.42 ms for the level); FP64 keeps two launches (one launch of 12 FP64 row
 // blocks: 16.1 vs 14.5 ms).  The split-FP16 kernel takes at most
-// kSplit16RowBlocks blocks per launch (its FP64 flush accumulators and 32-byte
-// operator fragments fit the registers).
+// kSplit16RowBlocks blocks per launch on the plain list (its FP64 flush
+// accumulators and 32-byte operator fragments at two wavefronts per SIMD), and
+// all kAllClassBlocks blocks in one launch on the orbit list (one wavefront).
 constexpr int kRowBlocksPerWave = 11;
 constexpr int kMaxRowGroups = 16;
 constexpr int kAllClassBlocks = 12;
@@ -227,9 +228,9 @@ struct RowGroup {
 // plain storage-ordered operators with NB row blocks (scheme 0), at most maxrb
 // blocks each; returns the count (<= kMaxRowGroups)
 int m2l_row_groups(int scheme, int p, int NB, bool fp64, RowGroup *g, int maxrb = kRowBlocksPerWave);
-// split-FP16 M2L: the row groups of its folded list (0 when the order's
-// classes do not fit the instantiated shapes, p > 12: the plain list is used),
-// whether it folds, and its launches per level
+// split-FP16 M2L: the row group of its folded list (the four classes of three
+// blocks each in one launch, p = 11, 12; 0 for other orders, which take the
+// plain list), whether it folds, and its launches per level
 int m2l_split16_fold_groups(int p, RowGroup *grp);
 bool m2l_split16_folded(int p);
 

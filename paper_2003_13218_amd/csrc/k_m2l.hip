@@ -248,12 +248,11 @@ template <bool FOLD> struct PolF16x3T {
     static constexpr bool kFlush64 = true;
     static constexpr bool kPaired = FOLD;
     static constexpr int kMaxNRB = 6;
-    // plain list: row groups of up to 6 blocks; folded list: the class halves
-    // of orders p <= 12 (1, 2 or 3 blocks per class), or the (t, -t) pair
-    // classes of one block each
+    // plain list: row groups of up to 6 blocks; folded list: the four orbit
+    // classes of three blocks each in one launch
     template <int SYM, int N, int NE> static constexpr bool allow() {
         if (!FOLD) return SYM == 0 && N <= kMaxNRB;
-        return (SYM == 1 && N == 2 && NE == 1) || ((SYM == 2 || SYM == 3) && N <= 6 && N % 2 == 0 && NE * 2 == N);
+        return SYM == 4 && N == 12 && NE == 3;
     }
     __device__ static R load_b(const S *p, bool in) {
         return in ? *reinterpret_cast<const R *>(p) : R{0, 0, 0, 0, 0, 0, 0, 0};
@@ -291,13 +290,15 @@ __device__ inline double pick(double a, double b, uint32_t m) {
                                             ((unsigned long long)__double_as_longlong(b) & ~mm)));
 }
 
+// Stages whose loads are in flight while one runs.  The folded split kernel
+// runs one wavefront per SIMD, so no other wavefront covers the latency of a
+// stage's gathers: it prefetches two stages ahead, one chunk per stage (1M-atom
+// box, finest level: 5.98 ms against 6.22 ms one stage ahead).
+template <typename P, int SYM> constexpr int prefetch_depth() { return (is_split16<P>() && SYM != 0) ? 2 : 1; }
+
 // Chunks per LDS stage: enough matrix-core work per barrier (about 40 FP32
-// MFMA-equivalents) within 48 KB of double-buffered LDS and a few registers.
-// The folded split kernel holds 8 multipole values per lane for each of an
-// entry's 2 or 4 sources, twice (current and prefetched stage): at most 8
-// sources per stage keep that within 128 registers, at most 4 once six row
-// blocks of accumulators (FP32 and FP64) share the 256 registers of two
-// wavefronts per SIMD.
+// MFMA-equivalents) within 48 KB of double-buffered LDS and a few registers
+// (the folded split kernel: one, see prefetch_depth).
 template <typename P, int NRB, int SYM> constexpr int stage_chunks() {
     constexpr int bytes = (int)sizeof(typename P::A);                   // per lane and row block
     constexpr int cyc = std::is_same<P, PolBf16>::value ? 16
@@ -306,7 +307,7 @@ template <typename P, int NRB, int SYM> constexpr int stage_chunks() {
     constexpr int want = (1280 + cyc * NRB - 1) / (cyc * NRB);
     constexpr int lds_cap = (48 * 1024) / (2 * NRB * 64 * bytes);
     constexpr int nsrc = SYM == 0 ? 1 : (SYM == 1 ? 2 : 4);
-    constexpr int reg_cap = is_split16<P>() ? (NRB >= 6 ? 4 : 8) / nsrc : 6;
+    constexpr int reg_cap = is_split16<P>() ? (SYM != 0 ? 1 : 8 / nsrc) : 6;
     constexpr int u0 = want < lds_cap ? want : lds_cap;
     constexpr int u = u0 < reg_cap ? u0 : reg_cap;
     return u < 1 ? 1 : (u > 6 ? 6 : u);
@@ -347,9 +348,12 @@ template <typename P, int NRB, int SYM> constexpr int stage_chunks() {
 // (237 once the operator fragment reads interleave with the MFMAs, below) two
 // wavefronts per SIMD hide each other's waits: 8.2 -> 6.7 ms for the finest
 // level of the 1M-atom box.  The FP64 half-class variants stay at two
-// wavefronts: squeezed to three they spill inside the stage and lose.
+// wavefronts: squeezed to three they spill inside the stage and lose.  The
+// folded split kernel (all classes, 32-byte fragments, FP64 flush
+// accumulators, two stages of prefetch) holds about 410 registers and runs one
+// wavefront per SIMD.
 template <typename P, int NRB, int SYM> constexpr int m2l_min_waves() {
-    return ((sizeof(typename P::S) == 4 && SYM == 4 && NRB == 12) || (is_split16<P>() && SYM != 0)) ? 2 : 1;
+    return (sizeof(typename P::S) == 4 && !is_split16<P>() && SYM == 4 && NRB == 12) ? 2 : 1;
 }
 
 template <typename P, bool SPLIT, int NRB, int U, int NE, int SYM>
@@ -366,6 +370,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
     constexpr bool F64 = P::kFlush64;
     constexpr int NSRC = SYM == 0 ? 1 : (SYM == 1 ? 2 : 4);       // sources per list entry
     constexpr int NRV = (int)(sizeof(R) / sizeof(S));              // coefficients per lane and source
+    constexpr int DB = prefetch_depth<P, SYM>();                   // stages in flight
     static_assert(SYM != 4 || NRB == 4 * NE, "all four classes: NE blocks each");
     constexpr int NENT = SYM == 0 ? kILSize : (SYM == 1 ? kM2LPairEntries : kM2LOrbitEntries);
     constexpr int CHUNK = NRB * 64;             // fragments per chunk
@@ -474,7 +479,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
     const int e_last = min(tid + 256 * (PC - 1), CHUNK - 1);
     const bool last_in = tid + 256 * (PC - 1) < CHUNK;
 
-    // prologue: stage 0 into LDS buffer 0
+    // prologue: stage 0 into LDS buffer 0 (and, two stages deep, stage 1's
+    // operators into registers)
     R bcur[U][NSRC];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -486,19 +492,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
         for (int f = 0; f < NSRC; ++f) bcur[u][f] = frag_b(pc, pc.src[f]);
         advance(pc);
     }
-    // drain every prologue load: otherwise the compiler's wait bookkeeping
-    // carries them into the loop and waits on all loads before the MFMAs
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
 
-    // One stage: prefetch the next one (operators to registers, multipole
-    // fragments to bnext), run this one from LDS buffer cur and bcur, publish
-    // the prefetched operators in LDS buffer cur ^ 1.  The loop below calls it
-    // twice per iteration with the two fragment sets swapped, so no register
-    // copy moves bnext into bcur.
-    auto stage = [&](const int cur, R (&bcur)[U][NSRC], R (&bnext)[U][NSRC]) __attribute__((always_inline)) {
-        // prefetch the next stage (past the end: harmless re-reads)
-        A pre[U][PC];
+    // prefetch of a later stage: operators to registers (pre), multipole
+    // fragments to bnext (past the end: harmless re-reads)
+    auto issue = [&](A (&pre)[U][PC], R (&bnext)[U][NSRC]) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -511,10 +508,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
             asm volatile("" ::: "memory");
             advance(pc);
         }
-        // keep the prefetch loads ahead of the matrix-core work (the
-        // scheduler would otherwise sink them towards their use at the end)
-        if constexpr (sizeof(A) == 16) __builtin_amdgcn_sched_barrier(0);
-        // this stage on the matrix cores
+    };
+    // one stage on the matrix cores from LDS buffer cur and bcur
+    auto compute = [&](const int cur, R (&bcur)[U][NSRC]) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             A a[NRB];
@@ -604,24 +600,80 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
                 }
             }
         }
-        // publish the prefetched stage: for 16-byte fragments after all of this
-        // stage's MFMAs, so the waits for the prefetch loads come as late as
-        // possible; FP64 stages are long enough that the compiler's placement
-        // of the LDS writes among the MFMAs hides their latency (measured)
-        if constexpr (sizeof(A) == 16) __builtin_amdgcn_sched_barrier(0);
+    };
+    // the prefetched operators of the next stage into LDS buffer nxt
+    auto publish = [&](const int nxt, A (&pre)[U][PC]) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll
-            for (int v = 0; v < PC - 1; ++v) lds[cur ^ 1][u * CHUNK + tid + 256 * v] = pre[u][v];
-            if (last_in) lds[cur ^ 1][u * CHUNK + e_last] = pre[u][PC - 1];
+            for (int v = 0; v < PC - 1; ++v) lds[nxt][u * CHUNK + tid + 256 * v] = pre[u][v];
+            if (last_in) lds[nxt][u * CHUNK + e_last] = pre[u][PC - 1];
         }
-        __syncthreads();
     };
-    R bnext[U][NSRC];
-    for (int st = 0; st < nstage; st += 2) {
-        stage(0, bcur, bnext);
-        if (st + 1 == nstage) break;
-        stage(1, bnext, bcur);
+
+    if constexpr (DB == 1) {
+        // drain every prologue load: otherwise the compiler's wait bookkeeping
+        // carries them into the loop and waits on all loads before the MFMAs
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        // One stage: prefetch the next one, run this one, publish the
+        // prefetched operators in LDS buffer cur ^ 1.  The loop below calls it
+        // twice per iteration with the two fragment sets swapped, so no
+        // register copy moves bnext into bcur.
+        auto stage = [&](const int cur, R (&bcur)[U][NSRC], R (&bnext)[U][NSRC]) __attribute__((always_inline)) {
+            A pre[U][PC];
+            issue(pre, bnext);
+            // keep the prefetch loads ahead of the matrix-core work (the
+            // scheduler would otherwise sink them towards their use at the end)
+            if constexpr (sizeof(A) == 16) __builtin_amdgcn_sched_barrier(0);
+            compute(cur, bcur);
+            // publish the prefetched stage: for 16-byte fragments after all of this
+            // stage's MFMAs, so the waits for the prefetch loads come as late as
+            // possible; FP64 stages are long enough that the compiler's placement
+            // of the LDS writes among the MFMAs hides their latency (measured)
+            if constexpr (sizeof(A) == 16) __builtin_amdgcn_sched_barrier(0);
+            publish(cur ^ 1, pre);
+            __syncthreads();
+        };
+        R bnext[U][NSRC];
+        for (int st = 0; st < nstage; st += 2) {
+            stage(0, bcur, bnext);
+            if (st + 1 == nstage) break;
+            stage(1, bnext, bcur);
+        }
+    } else {
+        // Two stages deep: stage s + 2's loads are issued while stage s runs
+        // and stage s + 1's are in flight, so a gather's latency may span two
+        // stages.  Three multipole fragment sets rotate (b0, b1, b2) and two
+        // operator register sets (p0, p1); six stages per loop iteration keep
+        // every set's role a compile-time constant.
+        A p0[U][PC], p1[U][PC];
+        R b1[U][NSRC], b2[U][NSRC];
+        issue(p1, b1);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        auto stage = [&](const int cur, R (&buse)[U][NSRC], R (&bissue)[U][NSRC], A (&pissue)[U][PC],
+                         A (&pwrite)[U][PC]) __attribute__((always_inline)) {
+            issue(pissue, bissue);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(cur, buse);
+            __builtin_amdgcn_sched_barrier(0);
+            publish(cur ^ 1, pwrite);
+            __syncthreads();
+        };
+        for (int st = 0; st < nstage; st += 6) {
+            stage(0, bcur, b2, p0, p1);
+            if (st + 1 == nstage) break;
+            stage(1, b1, bcur, p1, p0);
+            if (st + 2 == nstage) break;
+            stage(0, b2, b1, p0, p1);
+            if (st + 3 == nstage) break;
+            stage(1, bcur, b2, p1, p0);
+            if (st + 4 == nstage) break;
+            stage(0, b1, bcur, p0, p1);
+            if (st + 5 == nstage) break;
+            stage(1, b2, b1, p1, p0);
+        }
     }
 
     if (!valid) return;

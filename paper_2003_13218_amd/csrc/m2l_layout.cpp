@@ -404,19 +404,21 @@ int m2l_row_groups(int scheme, int p, int NB, bool fp64, RowGroup *g, int maxrb)
 }
 
 
-// The row groups of the folded split kernel for order p (class halves, at most
-// kSplit16RowBlocks blocks), or 0 when an order's classes do not fit the
-// instantiated shapes (p > 12: the plain list is used)
+// The row group of the folded split kernel for order p: the four row classes
+// of the two-axis flips in one launch when each takes three row blocks
+// (p = 11, 12), else 0 and the plain list is used.  The split operands cost
+// about 4.5 vector instructions per multipole value converted, and the orbit
+// list converts four class combinations per entry (1220 per column chunk and
+// parity class against 875 on the plain list), so folding only pays where it
+// saves the most matrix work: the finest level of the 3M-atom box takes
+// 18.9 ms on the plain list against 21.5 ms folded at p = 8, and 72.9 against
+// 46.9 ms at p = 12.
 int m2l_split16_fold_groups(int p, RowGroup *grp) {
-    const int scheme = m2l_scheme(p);
-    const int ng = m2l_row_groups(scheme, p, m2l_row_blocks(p), true, grp, kSplit16RowBlocks);
-    for (int i = 0; i < ng; ++i) {
-        const RowGroup &g = grp[i];
-        const bool ok = (g.sym == 1 && g.nrb == 2 && g.ne == 1) ||
-                        ((g.sym == 2 || g.sym == 3) && g.nrb <= 6 && g.nrb % 2 == 0 && 2 * g.ne == g.nrb);
-        if (!ok) return 0;
-    }
-    return ng;
+    int b[4];
+    if (m2l_scheme(p) != 2 || m2l_class_blocks(p, b) != 4) return 0;
+    if (b[0] != 3 || b[1] != 3 || b[2] != 3 || b[3] != 3) return 0;
+    grp[0] = RowGroup{0, 12, 3, 4};
+    return 1;
 }
 
 bool m2l_split16_folded(int p) {

@@ -157,6 +157,15 @@ def test_plan_info_folding(fmm):
         assert info["levels"] == 2
         fmm.fmm_plan_config(plan, fmm.FMM_MIXED)
         assert fmm.fmm_plan_info(plan)["m2l_launches"] == l32, p
+        # the 16-bit modes: the BF16 M2L on the plain list, the split-FP16 one
+        # folded (all four classes, one launch) only at p = 11, 12
+        fmm.fmm_plan_config(plan, fmm.FMM_MIXED_BF16_M2L)
+        info = fmm.fmm_plan_info(plan)
+        assert (info["m2l_scheme"], info["m2l_entries"], info["m2l_rows"]) == (0, 875, info["Kp"]), p
+        fmm.fmm_plan_config(plan, fmm.FMM_MIXED_SPLIT16_M2L)
+        info = fmm.fmm_plan_info(plan)
+        want = (2, 305, 1, 192) if p == 12 else (0, 875, (info["Kp"] // 16 + 5) // 6, info["Kp"])
+        assert (info["m2l_scheme"], info["m2l_entries"], info["m2l_launches"], info["m2l_rows"]) == want, p
         fmm.fmm_destroy(plan)
 
 
@@ -190,12 +199,12 @@ def test_c1_orders_with_several_row_groups(fmm, p, prec):
     assert rms_rel(ph.cpu().numpy(), o["phi"]) < tol
 
 
-@pytest.mark.parametrize("p", [4, 5, 8, 12, 16])
+@pytest.mark.parametrize("p", [4, 8, 11, 12, 16])
 def test_split16_layouts_every_level(fmm, p):
     # the split-FP16 M2L at all four levels of the 10,000-water box (FP64 top
-    # levels switched off), in each of its operator layouts: the folded orbit
-    # list with (t, -t) pair classes of one row block (p = 4), class halves of
-    # one, two and three row blocks (p = 5, 8, 12), and the plain list (p = 16).
+    # levels switched off), in each of its operator layouts: the plain list in
+    # one, two and three row groups (p = 4, 8, 16) and the folded orbit list,
+    # all four classes of three row blocks in one launch (p = 11, 12).
     # Against FP64 on the same plan (same truncation) the difference is the
     # operand rounding alone; a wrong row, sign or scale would be of order 1.
     w, o = ewald_full("C2")
@@ -637,7 +646,7 @@ def test_c3_sample_split16_m2l(fmm):
     w = workloads.config("C3")
     idx = ref["idx"]
     plan = _plan(fmm, w.box, w.levels, w.p, fmm.FMM_MIXED_SPLIT16_M2L)
-    assert fmm.fmm_plan_info(plan)["m2l_launches"] == 2  # the two class halves of 6 blocks
+    assert fmm.fmm_plan_info(plan)["m2l_launches"] == 1  # the four orbit classes of 3 blocks
     _, f, ph = fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q), forces=True, phi=True)
     ph = ph.cpu().numpy()[idx]
     ef = rms_rel(f.cpu().numpy()[idx], ref["force"])
