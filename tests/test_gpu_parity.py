@@ -64,21 +64,29 @@ def test_binning_bit_exact(fmm, levels):
 
 
 # ---------------------------------------------------------------------- a9 --
+# Near-field tolerances (potential, field): FP64 1e-14 (measured at most
+# 2.5e-15); FP32 1e-6 on the potential (each leaf's partial sum goes to FP64;
+# measured at most 1.7e-7) and 2e-6 on the field, whose terms are summed in
+# FP32 over every source of the 125 leaves: 1.3e-6 measured with 60 atoms per
+# leaf (7,500 sources per target), 5.6e-7 at the water density.
+P2P_TOL = {0: (1e-14, 1e-14), 1: (1e-6, 2e-6)}
+
+
 @pytest.mark.parametrize("name", ["C1", "C2"])
-@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-6)])
-def test_p2p_matches_direct_nearfield(fmm, name, prec, tol):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_p2p_matches_direct_nearfield(fmm, name, prec):
     w = workloads.config(name)
     plan = _plan(fmm, w.box, w.levels, 2, prec)
     pn, fn, _, _ = fmm.fmm_potential_parts(plan, _t(w.pos), _t(w.q))
     phi, field = oracle.nearfield(w.pos, w.q, w.box, w.levels)
     ep, ef = rms_rel(pn.cpu().numpy(), phi), rms_rel(fn.cpu().numpy(), field)
     print(f"P2P {name} prec={prec}: phi rms rel {ep:.2e}, field rms rel {ef:.2e}")
-    assert ep < tol and ef < tol
+    assert ep < P2P_TOL[prec][0] and ef < P2P_TOL[prec][1]
 
 
 @pytest.mark.parametrize("occ", [2, 4, 20, 60])
-@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 2e-6)])
-def test_p2p_uneven_leaves(fmm, occ, prec, tol):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_p2p_uneven_leaves(fmm, occ, prec):
     # Leaf counts from empty to several times the mean, at mean occupancies
     # that select each source-group count of the near-field kernel (16, 8, 4,
     # 2 groups): full target chunks, half-size last chunks with twice the
@@ -103,7 +111,7 @@ def test_p2p_uneven_leaves(fmm, occ, prec, tol):
     phi, field = oracle.nearfield(pos, q, box, levels)
     ep, ef = rms_rel(pn.cpu().numpy(), phi), rms_rel(fn.cpu().numpy(), field)
     print(f"P2P uneven occ={occ} prec={prec}: phi rms rel {ep:.2e}, field rms rel {ef:.2e}")
-    assert ep < tol and ef < tol
+    assert ep < P2P_TOL[prec][0] and ef < P2P_TOL[prec][1]
 
 
 def test_p2p_shallow_tree_repeats_images(fmm):
