@@ -205,14 +205,15 @@ hipError_t launch_uv_sums(const UvBox *b, int nbox, const int64_t *st_red, int64
 // fit kAllClassBlocks blocks run in one launch, the four source fragments
 // gathered once for all classes (measured on the 1M-atom box, p = 12: 8.22 vs
 // 8.42 ms for the level); FP64 keeps two launches (one launch of 12 FP64 row
-// blocks: 16.1 vs 14.5 ms).  The split-FP16 kernel takes at most
-// kSplit16RowBlocks blocks per launch on the plain list (its FP64 flush
-// accumulators and 32-byte operator fragments at two wavefronts per SIMD), and
-// all kAllClassBlocks blocks in one launch on the orbit list (one wavefront).
+// blocks: 16.1 vs 14.5 ms).  The split-FP16 M2L takes at most
+// kSplit16RowBlocks blocks per launch on the plain list (k_m2l_f16rows: three
+// blocks per wavefront, with their FP64 flush accumulators for 64 targets, at
+// two wavefronts per SIMD), and all kAllClassBlocks blocks in one launch on
+// the orbit list (one wavefront per SIMD).
 constexpr int kRowBlocksPerWave = 11;
 constexpr int kMaxRowGroups = 16;
 constexpr int kAllClassBlocks = 12;
-constexpr int kSplit16RowBlocks = 6;
+constexpr int kSplit16RowBlocks = 12;
 inline bool one_launch(int blocks_per_class, bool fp64) { return !fp64 && 4 * blocks_per_class <= kAllClassBlocks; }
 // chunks of 32 coefficients (the k depth of the 16x16x32 BF16 / FP16 MFMA)
 inline int m2l_k32_chunks(int p) { return (num_coeffs(p) + 31) / 32; }
@@ -233,6 +234,9 @@ int m2l_row_groups(int scheme, int p, int NB, bool fp64, RowGroup *g, int maxrb 
 // plain list), whether it folds, and its launches per level
 int m2l_split16_fold_groups(int p, RowGroup *grp);
 bool m2l_split16_folded(int p);
+// row groups of the plain split-FP16 kernel for NB row blocks: as few as fit
+// kSplit16RowBlocks each, of equal size (the first ones one block more)
+int m2l_split16_plain_groups(int NB, RowGroup *grp);
 
 // Levels with few target cells split the interaction list into slices
 // (split-K) whose partial sums go to `partial` and are added in a fixed order.

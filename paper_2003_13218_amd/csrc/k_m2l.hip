@@ -236,9 +236,16 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 struct F16Pair {
     f16x8 hi, lo;
 };
-// FOLD: the symmetry-folded list with class-ordered operator rows (as the
-// FP32 / FP64 kernels), else the plain list with storage-ordered rows.
-template <bool FOLD> struct PolF16x3T {
+__device__ inline f32x4 mma_split16(const F16Pair &a, const F16Pair &b, f32x4 c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a.lo, b.hi, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a.hi, b.lo, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a.hi, b.hi, c, 0, 0, 0);
+}
+// Folded orbit list with class-ordered operator rows (as the FP32 / FP64
+// kernels), the four orbit classes of three blocks each in one launch: the
+// class combinations of an entry's four sources are formed in FP32 and split
+// into hi and lo inside the kernel.
+struct PolF16x3F {
     using S = float;
     using A = F16Pair;
     using B = F16Pair;
@@ -246,14 +253,9 @@ template <bool FOLD> struct PolF16x3T {
     typedef float R __attribute__((ext_vector_type(8)));
     static constexpr int KW = 32;
     static constexpr bool kFlush64 = true;
-    static constexpr bool kPaired = FOLD;
-    static constexpr int kMaxNRB = 6;
-    // plain list: row groups of up to 6 blocks; folded list: the four orbit
-    // classes of three blocks each in one launch
-    template <int SYM, int N, int NE> static constexpr bool allow() {
-        if (!FOLD) return SYM == 0 && N <= kMaxNRB;
-        return SYM == 4 && N == 12 && NE == 3;
-    }
+    static constexpr bool kPaired = true;
+    static constexpr int kMaxNRB = 12;
+    template <int SYM, int N, int NE> static constexpr bool allow() { return SYM == 4 && N == 12 && NE == 3; }
     __device__ static R load_b(const S *p, bool in) {
         return in ? *reinterpret_cast<const R *>(p) : R{0, 0, 0, 0, 0, 0, 0, 0};
     }
@@ -267,17 +269,9 @@ template <bool FOLD> struct PolF16x3T {
         }
         return b;
     }
-    __device__ static Acc mma(const A &a, const B &b, Acc c) {
-        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a.lo, b.hi, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a.hi, b.lo, c, 0, 0, 0);
-        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a.hi, b.hi, c, 0, 0, 0);
-    }
+    __device__ static Acc mma(const A &a, const B &b, Acc c) { return mma_split16(a, b, c); }
 };
-using PolF16x3 = PolF16x3T<false>;
-using PolF16x3F = PolF16x3T<true>;
-template <typename P> constexpr bool is_split16() {
-    return std::is_same<P, PolF16x3>::value || std::is_same<P, PolF16x3F>::value;
-}
+template <typename P> constexpr bool is_split16() { return std::is_same<P, PolF16x3F>::value; }
 
 // Per-element choice between two fragments by an all-ones / zero mask (bit
 // operations, so a run-time choice never becomes a branch).
@@ -369,7 +363,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(m2l_min_wav
     using R = typename P::R;
     constexpr bool F64 = P::kFlush64;
     constexpr int NSRC = SYM == 0 ? 1 : (SYM == 1 ? 2 : 4);       // sources per list entry
-    constexpr int NRV = (int)(sizeof(R) / sizeof(S));              // coefficients per lane and source
+    constexpr int NRV = P::KW / 4;                                 // coefficients per lane and source
     constexpr int DB = prefetch_depth<P, SYM>();                   // stages in flight
     static_assert(SYM != 4 || NRB == 4 * NE, "all four classes: NE blocks each");
     constexpr int NENT = SYM == 0 ? kILSize : (SYM == 1 ? kM2LPairEntries : kM2LOrbitEntries);
@@ -833,14 +827,241 @@ __global__ void k_m2l_reduce(const P *__restrict__ partial, T *__restrict__ L, i
     }
 }
 
-// Mc[c][k] = M[c][k] cscale[k] for the cells of one level
-__global__ void k_col_scale(const float *__restrict__ M, float *__restrict__ Mc, const float *__restrict__ cscale,
-                            int64_t n, int Kp) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        Mc[i] = M[i] * cscale[i % Kp];
+// The level's multipoles scaled by cscale and split for the plain split-FP16
+// kernel: x = M[c][k] cscale[k] as hi = fp16(x), lo = fp16(x - hi), one
+// thread per group of 8 coefficients, written as 8 hi then 8 lo values in the
+// group's 32 bytes (the layout k_m2l_f16rows loads).
+__global__ void k_col_split(const float *__restrict__ M, float *__restrict__ Mc, const float *__restrict__ cscale,
+                            int64_t ngroup, int Kp) {
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < ngroup;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i0 = 8 * g;
+        const int k0 = (int)(i0 % Kp);
+        F16Pair v;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float x = M[i0 + i] * cscale[k0 + i];
+            const _Float16 h = (_Float16)x;
+            v.hi[i] = h;
+            v.lo[i] = (_Float16)(x - (float)h);
+        }
+        *reinterpret_cast<F16Pair *>(Mc + i0) = v;
+    }
 }
 
-static_assert(kSplit16RowBlocks == PolF16x3::kMaxNRB, "row groups of the split kernel");
+// ---------------------------------------------------------------------------
+// Split-FP16 M2L on the plain list with the rows split over the wavefronts.
+// With the split operands (32-byte fragments, three MFMAs per fragment pair)
+// the LDS-shared kernel above, where every wavefront reads the whole operator
+// chunk from LDS for its own 16 targets, is paced by LDS bandwidth rather than
+// by the matrix cores.  Here a workgroup still owns 64 target cells of one
+// parity class, but wavefront w owns RW row blocks, rows 16 (rb0 + RW w) ..,
+// for all 64 targets (four column blocks of 16):
+//   * its operator fragments come from global memory (L2) straight into
+//     registers, one stage ahead: no other wavefront reads them;
+//   * the multipole fragments of the 64 targets are the operand shared
+//     through LDS: wavefront w gathers the chunk's fragment of its 16 targets
+//     (one 32-byte load per lane of the pairs written by k_col_split) into a
+//     double-buffered LDS stage and every wavefront reads all four, one
+//     barrier per stage;
+//   * each operator fragment feeds 4 column blocks x 3 MFMAs.
+// Accumulation as in k_m2l_lds: FP32 on the matrix cores over one offset's
+// chunks, then into FP64.  Row blocks past the group (the last wavefront when
+// the group is not a multiple of 4) run on a clamped fragment and are not
+// stored, so every MFMA is unconditional.  SPLIT: split-K over offset slices
+// into FP64 partials, as in k_m2l_lds.
+// ---------------------------------------------------------------------------
+template <bool SPLIT, int RW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_m2l_f16rows(
+    const F16Pair *__restrict__ ops, const int32_t *__restrict__ il, const int32_t *__restrict__ offs,
+    const float *__restrict__ Mc, float *__restrict__ L, double *__restrict__ L64, const float *__restrict__ rscale,
+    int nh_bits, int NB, int NKC, int Kp, int rb0, int nrb, int nslices_arg) {
+    __shared__ uint4 lds[2][2][256];  // [stage buffer][hi, lo plane][column block x 64 + lane]
+    const int nslices = SPLIT ? nslices_arg : 1;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int parity = blockIdx.x & 7;
+    const int rest = blockIdx.x >> 3;
+    const int slice = rest % nslices;
+    const int tile = rest / nslices;
+    const uint32_t ntarget = 1u << (3 * nh_bits);
+
+    // the target whose multipole fragments this lane gathers (column block wid)
+    const uint32_t Pg = (uint32_t)tile * 64 + (uint32_t)wid * 16 + (lane & 15);
+    uint32_t tx, ty, tz;
+    demorton3(Pg < ntarget ? Pg : 0u, tx, ty, tz);
+    tx = 2 * tx + ((parity >> 2) & 1);
+    ty = 2 * ty + ((parity >> 1) & 1);
+    tz = 2 * tz + (parity & 1);
+    const int kq = 8 * (lane >> 4);
+    // source cell by dilated-integer addition (as in k_m2l_lds)
+    const uint32_t lvl = (8u << (3 * nh_bits)) - 1u;
+    const uint32_t zm = 0x09249249u & lvl, ym = (0x09249249u << 1) & lvl, xm = (0x09249249u << 2) & lvl;
+    const uint32_t tdx = (spread3(tx) << 2) | ~xm, tdy = (spread3(ty) << 1) | ~ym, tdz = spread3(tz) | ~zm;
+    auto source = [&](int oid) {
+        const uint32_t cx = (tdx + (spread3((uint32_t)offs[3 * oid]) << 2)) & xm;
+        const uint32_t cy = (tdy + (spread3((uint32_t)offs[3 * oid + 1]) << 1)) & ym;
+        const uint32_t cz = (tdz + spread3((uint32_t)offs[3 * oid + 2])) & zm;
+        return Mc + (size_t)(cx | cy | cz) * Kp + kq;
+    };
+
+    // this wavefront's row blocks (fragment row block, clamped into the group)
+    const int wr0 = RW * wid;
+    int rbf[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) rbf[r] = rb0 + min(wr0 + r, nrb - 1);
+
+    const int t0 = slice * kILSize / nslices, t1 = (slice + 1) * kILSize / nslices;
+    const int nstage = (t1 - t0) * NKC;
+    const int32_t *ilp = il + parity * kILSize;
+    // prefetch cursor (offset t, column chunk kc); past the end of the list it
+    // stays on the last offset and the multipole fragment is zero
+    int pt = t0, pkc = 0;
+    const float *psrc = Mc;
+    size_t pbase = 0;
+    auto set_t = [&](int t) {
+        pt = t;
+        pkc = 0;
+        const int oid = ilp[min(t, t1 - 1)];
+        psrc = source(oid);
+        pbase = (size_t)oid * NKC * NB * 64 + lane;
+    };
+    auto advance = [&]() {
+        if (++pkc == NKC) set_t(pt + 1);
+        else pbase += (size_t)NB * 64;
+    };
+    auto load_a = [&](F16Pair (&a)[RW]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = 0; r < RW; ++r) a[r] = ops[pbase + (size_t)rbf[r] * 64];
+    };
+    auto load_b = [&]() __attribute__((always_inline)) -> F16Pair {
+        F16Pair b;
+        if (pt < t1 && 32 * pkc + kq < Kp) {
+            b = *reinterpret_cast<const F16Pair *>(psrc + 32 * pkc);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) b.hi[i] = b.lo[i] = (_Float16)0.0f;
+        }
+        return b;
+    };
+    auto put_b = [&](int buf, const F16Pair &b) __attribute__((always_inline)) {
+        uint4 w[2];
+        __builtin_memcpy(w, &b, sizeof(b));
+        lds[buf][0][tid] = w[0];
+        lds[buf][1][tid] = w[1];
+    };
+
+    f32x4 acc[RW][4];
+    double hi[RW][4][4];
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            acc[r][c] = f32x4{0, 0, 0, 0};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) hi[r][c][e] = 0.0;
+        }
+
+    F16Pair a0[RW], a1[RW];
+    set_t(t0);
+    load_a(a0);
+    {
+        const F16Pair b = load_b();
+        advance();
+        put_b(0, b);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    int kc = 0;
+    // one stage: prefetch the next chunk (operators to registers, this lane's
+    // multipole fragment to bn), run this chunk from LDS buffer cur and acur,
+    // publish bn in the other buffer
+    auto stage = [&](const int cur, F16Pair (&acur)[RW], F16Pair (&anext)[RW]) __attribute__((always_inline)) {
+        load_a(anext);
+        const F16Pair bn = load_b();
+        advance();
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            uint4 w[2] = {lds[cur][0][c * 64 + lane], lds[cur][1][c * 64 + lane]};
+            F16Pair b;
+            __builtin_memcpy(&b, w, sizeof(b));
+#pragma unroll
+            for (int r = 0; r < RW; ++r) acc[r][c] = mma_split16(acur[r], b, acc[r][c]);
+        }
+        if (++kc == NKC) {
+            kc = 0;
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) hi[r][c][e] += (double)acc[r][c][e];
+                    acc[r][c] = f32x4{0, 0, 0, 0};
+                }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        put_b(cur ^ 1, bn);
+        __syncthreads();
+    };
+    for (int st = 0; st < nstage; st += 2) {
+        stage(0, a0, a1);
+        if (st + 1 == nstage) break;
+        stage(1, a1, a0);
+    }
+
+    const size_t slice_off = (size_t)slice * ((size_t)8 << (3 * nh_bits)) * Kp;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        if (wr0 + r >= nrb) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t P = (uint32_t)tile * 64 + (uint32_t)c * 16 + (lane & 15);
+            if (P >= ntarget) continue;
+            const size_t tcell = 8 * (size_t)P + (size_t)parity;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = 16 * (rb0 + wr0 + r) + 4 * (lane >> 4) + e;
+                const double v = (double)rscale[row] * (hi[r][c][e] + (double)acc[r][c][e]);
+                if constexpr (SPLIT)
+                    L64[slice_off + tcell * Kp + row] = v;
+                else
+                    L[tcell * Kp + row] = (float)v;
+            }
+        }
+    }
+}
+
+// Launches k_m2l_f16rows for every row group (at most 12 blocks each: RW <= 3)
+static hipError_t launch_f16rows(const void *ops, const int32_t *il, const int32_t *offs, const float *Mc, float *L,
+                                 double *part, const float *rscale, int nh_bits, int NB, int NKC, int Kp, int nslices,
+                                 const RowGroup *grp, int ng, hipStream_t s) {
+    const int64_t ntile = (((int64_t)1 << (3 * nh_bits)) + 63) / 64;
+    const int64_t grid = 8 * ntile * nslices;
+    const F16Pair *o = reinterpret_cast<const F16Pair *>(ops);
+    for (int gi = 0; gi < ng; ++gi) {
+        const int rb0 = grp[gi].rb0, nrb = grp[gi].nrb;
+        const int RW = (nrb + 3) / 4;
+#define FMM_F16ROWS(R)                                                                                          \
+    if (RW == R) {                                                                                              \
+        if (nslices > 1)                                                                                        \
+            hipLaunchKernelGGL((k_m2l_f16rows<true, R>), dim3((unsigned)grid), dim3(256), 0, s, o, il, offs, Mc,  \
+                               L, part, rscale, nh_bits, NB, NKC, Kp, rb0, nrb, nslices);                        \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_m2l_f16rows<false, R>), dim3((unsigned)grid), dim3(256), 0, s, o, il, offs, Mc, \
+                               L, part, rscale, nh_bits, NB, NKC, Kp, rb0, nrb, 1);                             \
+    }
+        if (RW < 1 || RW > 3) return hipErrorInvalidValue;
+        FMM_F16ROWS(1)
+        FMM_F16ROWS(2)
+        FMM_F16ROWS(3)
+#undef FMM_F16ROWS
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+static_assert(kSplit16RowBlocks == 12, "row groups of k_m2l_f16rows: at most 3 blocks per wavefront");
 
 // Scaled and sign-flipped copies of the level's multipoles for the folded
 // split kernel: Mc[0] = cscale M, Mc[1 + f] = D_f (cscale M) for the group
@@ -890,14 +1111,13 @@ hipError_t launch_m2l_split16(int level, const void *ops, const int32_t *list, c
         e = launch_lds<PolF16x3F>(ops, list, offs, rowmap, Mc, Mc + n, zeros, n, L, nslices > 1 ? partial : nullptr,
                                   nh_bits, m2l_row_blocks(p), m2l_k32_chunks(p), Kp, nslices, grp, ng, s, rscale);
     } else {
-        int64_t g = (n + 255) / 256;
+        int64_t g = (n / 8 + 255) / 256;
         if (g > 65535) g = 65535;
-        hipLaunchKernelGGL(k_col_scale, dim3((unsigned)g), dim3(256), 0, s, M, Mc, cscale, n, Kp);
+        hipLaunchKernelGGL(k_col_split, dim3((unsigned)g), dim3(256), 0, s, M, Mc, cscale, n / 8, Kp);
         const int NB = Kp / 16;
-        for (int r = 0; r < NB; r += kSplit16RowBlocks)
-            grp[ng++] = RowGroup{r, std::min(kSplit16RowBlocks, NB - r), 0, 0};
-        e = launch_lds<PolF16x3>(ops, list, offs, nullptr, Mc, Mc, Mc, 0, L, nslices > 1 ? partial : nullptr, nh_bits,
-                                 NB, m2l_k32_chunks(p), Kp, nslices, grp, ng, s, rscale);
+        ng = m2l_split16_plain_groups(NB, grp);
+        e = launch_f16rows(ops, list, offs, Mc, L, nslices > 1 ? partial : nullptr, rscale, nh_bits, NB,
+                           m2l_k32_chunks(p), Kp, nslices, grp, ng, s);
     }
     if (e != hipSuccess || nslices == 1) return e;
     int64_t g = (n + 255) / 256;

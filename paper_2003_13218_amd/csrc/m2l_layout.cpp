@@ -276,8 +276,8 @@ void swizzle_m2l_ops_bf16(int p, const double *ops, uint16_t *out) {
 }
 
 // ---------------------------------------------------------------------------
-// Split FP16 operators (PolF16x3): per storage row r and column k the powers
-// of two 2^{a_r} and 2^{b_k}, b_k = round(3/4 n(k)) (the multipoles of degree
+// Split FP16 operators (k_m2l_f16rows, PolF16x3F): per storage row r and
+// column k the powers of two 2^{a_r} and 2^{b_k}, b_k = round(3/4 n(k)) (the multipoles of degree
 // n fall off about as 0.87^n, the operators' columns as 3^-n: this keeps both
 // near the middle of FP16's range), a_r chosen so that the row's largest
 // scaled entry over all offsets lies in [2^9, 2^10).  cscale[k] = 2^{-b_k}
@@ -421,6 +421,16 @@ int m2l_split16_fold_groups(int p, RowGroup *grp) {
     return 1;
 }
 
+int m2l_split16_plain_groups(int NB, RowGroup *grp) {
+    const int ng = (NB + kSplit16RowBlocks - 1) / kSplit16RowBlocks;
+    for (int i = 0, r = 0; i < ng; ++i) {
+        const int nrb = NB / ng + (i < NB % ng ? 1 : 0);
+        grp[i] = RowGroup{r, nrb, 0, 0};
+        r += nrb;
+    }
+    return ng;
+}
+
 bool m2l_split16_folded(int p) {
     RowGroup grp[kMaxRowGroups];
     return m2l_split16_fold_groups(p, grp) > 0;
@@ -429,7 +439,7 @@ bool m2l_split16_folded(int p) {
 int m2l_split16_launches(int p) {
     RowGroup grp[kMaxRowGroups];
     const int ng = m2l_split16_fold_groups(p, grp);
-    return ng > 0 ? ng : (padded_coeffs(p) / 16 + kSplit16RowBlocks - 1) / kSplit16RowBlocks;
+    return ng > 0 ? ng : m2l_split16_plain_groups(padded_coeffs(p) / 16, grp);
 }
 
 

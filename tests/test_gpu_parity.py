@@ -172,7 +172,7 @@ def test_plan_info_folding(fmm):
         assert (info["m2l_scheme"], info["m2l_entries"], info["m2l_rows"]) == (0, 875, info["Kp"]), p
         fmm.fmm_plan_config(plan, fmm.FMM_MIXED_SPLIT16_M2L)
         info = fmm.fmm_plan_info(plan)
-        want = (2, 305, 1, 192) if p == 12 else (0, 875, (info["Kp"] // 16 + 5) // 6, info["Kp"])
+        want = (2, 305, 1, 192) if p == 12 else (0, 875, (info["Kp"] // 16 + 11) // 12, info["Kp"])
         assert (info["m2l_scheme"], info["m2l_entries"], info["m2l_launches"], info["m2l_rows"]) == want, p
         fmm.fmm_destroy(plan)
 
@@ -210,9 +210,11 @@ def test_c1_orders_with_several_row_groups(fmm, p, prec):
 @pytest.mark.parametrize("p", [4, 8, 11, 12, 16])
 def test_split16_layouts_every_level(fmm, p):
     # the split-FP16 M2L at all four levels of the 10,000-water box (FP64 top
-    # levels switched off), in each of its operator layouts: the plain list in
-    # one, two and three row groups (p = 4, 8, 16) and the folded orbit list,
-    # all four classes of three row blocks in one launch (p = 11, 12).
+    # levels switched off), in each of its operator layouts: the plain list on
+    # the rows-per-wavefront kernel in one row group of 2 or 6 blocks (p = 4,
+    # 8: one and two blocks per wavefront, clamped rows on the last ones) and
+    # two groups of 10 and 9 blocks (p = 16), and the folded orbit list, all
+    # four classes of three row blocks in one launch (p = 11, 12).
     # Against FP64 on the same plan (same truncation) the difference is the
     # operand rounding alone; a wrong row, sign or scale would be of order 1.
     w, o = ewald_full("C2")
