@@ -46,9 +46,20 @@ def leaf_kernel(prec_name, info):
     split-FP16 one the orbit list at p = 11, 12 and the plain list otherwise."""
     if prec_name == "bf16":
         return "k_m2l_bf16<false>"
-    t = {"fp64": "double", "split16": "PolF16x3"}.get(prec_name, "float")
     kind = {2: "orbit", 1: "pair", 0: "plain"}[info["m2l_scheme"]]
+    if prec_name == "split16" and kind == "plain":
+        return f"k_m2l_f16rows<false> x{info['m2l_launches']} (plain list, {info['m2l_entries']} entries)"
+    t = {"fp64": "double", "split16": "PolF16x3F"}.get(prec_name, "float")
     return f"k_m2l_lds<{t}, false> x{info['m2l_launches']} ({kind} list, {info['m2l_entries']} entries)"
+
+
+def split16_plain_rows(Kp):
+    """Operator rows the plain split-FP16 kernel runs per level: row groups of
+    12 blocks of 16 and a last one of the rest, each spread over 4 wavefronts of
+    equal block count (the last ones repeat a block they do not store)."""
+    nb = Kp // 16
+    sizes = [min(12, nb - r) for r in range(0, nb, 12)]
+    return sum(16 * 4 * ((n + 3) // 4) for n in sizes)
 
 
 def m2l_entries(prec_name, info):
@@ -216,6 +227,8 @@ def run_single(args, w, p, prec_name, steps, warmup, fp64_leg, cpu_leg, graph_le
     K = (p + 1) ** 2
     dense = m2l_flops(p, w.levels, M2L_IL)
     rows = info["m2l_rows"]
+    if prec_name == "split16" and info["m2l_scheme"] == 0:
+        rows = split16_plain_rows(info["Kp"])
     cols = 32 * ((K + 31) // 32) if prec_name in ("bf16", "split16") else info["Kp"]
     # split operands: three FP16 products per operand pair
     executed = flops_leaf * (rows * cols) / (K * K) * (3 if prec_name == "split16" else 1)

@@ -235,7 +235,7 @@ int m2l_row_groups(int scheme, int p, int NB, bool fp64, RowGroup *g, int maxrb 
 int m2l_split16_fold_groups(int p, RowGroup *grp);
 bool m2l_split16_folded(int p);
 // row groups of the plain split-FP16 kernel for NB row blocks: as few as fit
-// kSplit16RowBlocks each, of equal size (the first ones one block more)
+// kSplit16RowBlocks each, all full but the last
 int m2l_split16_plain_groups(int NB, RowGroup *grp);
 
 // Levels with few target cells split the interaction list into slices

@@ -422,12 +422,12 @@ int m2l_split16_fold_groups(int p, RowGroup *grp) {
 }
 
 int m2l_split16_plain_groups(int NB, RowGroup *grp) {
-    const int ng = (NB + kSplit16RowBlocks - 1) / kSplit16RowBlocks;
-    for (int i = 0, r = 0; i < ng; ++i) {
-        const int nrb = NB / ng + (i < NB % ng ? 1 : 0);
-        grp[i] = RowGroup{r, nrb, 0, 0};
-        r += nrb;
-    }
+    // full groups first: a group of n blocks runs 4 ceil(n / 4) of them (its
+    // four wavefronts take equal shares), so with 12 = 3 x 4 only the last
+    // group is padded and the total, 4 ceil(NB / 4), is the least possible
+    int ng = 0;
+    for (int r = 0; r < NB; r += kSplit16RowBlocks)
+        grp[ng++] = RowGroup{r, std::min(kSplit16RowBlocks, NB - r), 0, 0};
     return ng;
 }
 

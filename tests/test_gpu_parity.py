@@ -213,7 +213,7 @@ def test_split16_layouts_every_level(fmm, p):
     # levels switched off), in each of its operator layouts: the plain list on
     # the rows-per-wavefront kernel in one row group of 2 or 6 blocks (p = 4,
     # 8: one and two blocks per wavefront, clamped rows on the last ones) and
-    # two groups of 10 and 9 blocks (p = 16), and the folded orbit list, all
+    # two groups of 12 and 7 blocks (p = 16), and the folded orbit list, all
     # four classes of three row blocks in one launch (p = 11, 12).
     # Against FP64 on the same plan (same truncation) the difference is the
     # operand rounding alone; a wrong row, sign or scale would be of order 1.
