@@ -53,15 +53,6 @@ def leaf_kernel(prec_name, info):
     return f"k_m2l_lds<{t}, false> x{info['m2l_launches']} ({kind} list, {info['m2l_entries']} entries)"
 
 
-def split16_plain_rows(Kp):
-    """Operator rows the plain split-FP16 kernel runs per level: row groups of
-    12 blocks of 16 and a last one of the rest, each spread over 4 wavefronts of
-    equal block count (the last ones repeat a block they do not store)."""
-    nb = Kp // 16
-    sizes = [min(12, nb - r) for r in range(0, nb, 12)]
-    return sum(16 * 4 * ((n + 3) // 4) for n in sizes)
-
-
 def m2l_entries(prec_name, info):
     return info["m2l_entries"]
 
@@ -227,8 +218,6 @@ def run_single(args, w, p, prec_name, steps, warmup, fp64_leg, cpu_leg, graph_le
     K = (p + 1) ** 2
     dense = m2l_flops(p, w.levels, M2L_IL)
     rows = info["m2l_rows"]
-    if prec_name == "split16" and info["m2l_scheme"] == 0:
-        rows = split16_plain_rows(info["Kp"])
     cols = 32 * ((K + 31) // 32) if prec_name in ("bf16", "split16") else info["Kp"]
     # split operands: three FP16 products per operand pair
     executed = flops_leaf * (rows * cols) / (K * K) * (3 if prec_name == "split16" else 1)

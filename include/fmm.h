@@ -408,7 +408,8 @@ fmm_status fmm_profile_read(fmm_plan_t plan, double *ms, int64_t *calls);
  *       batch plan the fmm_plan_tuning setting)
  *   [9] near-field source groups set by fmm_plan_tuning (0 = automatic)
  *   [10] operator rows the matrix cores run per list entry (folded: each row
- *       class padded to whole 16-row blocks; plain: Kp; >= K)
+ *       class padded to whole 16-row blocks; plain: Kp, and for the plain
+ *       split-FP16 kernel 64 ceil(n / 4) per row group of n blocks; >= K)
  */
 #define FMM_INFO_COUNT 11
 fmm_status fmm_plan_info(fmm_plan_t plan, int64_t *info, int n);

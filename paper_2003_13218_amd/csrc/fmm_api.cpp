@@ -608,10 +608,19 @@ extern "C" fmm_status fmm_plan_info(fmm_plan_t pl, int64_t *info, int n) {
     int64_t launches = m2l_launches(pl->p, pl->prec == FMM_FP64);
     if (pl->prec == FMM_MIXED_SPLIT16_M2L) launches = m2l_split16_launches(pl->p);
     if (pl->prec == FMM_MIXED_BF16_M2L) launches = 1;
+    // rows run per entry: the plain split-FP16 kernel gives each of its four
+    // wavefronts an equal number of row blocks per group (m2l_split16_plain_groups)
+    int64_t rows = plain ? pl->Kp : 16 * (int64_t)m2l_row_blocks(pl->p);
+    if (pl->prec == FMM_MIXED_SPLIT16_M2L && plain) {
+        RowGroup grp[kMaxRowGroups];
+        const int ng = m2l_split16_plain_groups(pl->Kp / 16, grp);
+        rows = 0;
+        for (int i = 0; i < ng; ++i) rows += 64 * (int64_t)((grp[i].nrb + 3) / 4);
+    }
     const int64_t v[FMM_INFO_COUNT] = {pl->is_batch ? 0 : pl->levels, pl->p, pl->K, pl->Kp, pl->prec,
                                        plain ? 0 : m2l_scheme(pl->p), plain ? kILSize : m2l_list_entries(pl->p),
                                        launches, pl->is_batch ? pl->top_fp64 : top_fp64_levels(pl), pl->p2p_g,
-                                       plain ? pl->Kp : 16 * (int64_t)m2l_row_blocks(pl->p)};
+                                       rows};
     for (int i = 0; i < n && i < FMM_INFO_COUNT; ++i) info[i] = v[i];
     return FMM_OK;
 }
