@@ -298,8 +298,9 @@ int m2l_split16_launches(int p);
 // list / offs / rowmap: the folded list, offsets and row map of the FP32
 // kernel when m2l_split16_folded(p), else the plain list and offsets (rowmap
 // unused); ops in the matching layout (swizzle_m2l_ops_split16); Mc: scratch
-// for the column-scaled multipoles of the level and, folded, their
-// sign-flipped copies (mc_cap bytes); zeros: Kp zero floats (absent images);
+// for the column-scaled multipoles of the level (plain list: as FP16 hi / lo
+// pairs, the same size) and, folded, their sign-flipped copies (mc_cap
+// bytes); zeros: Kp zero floats (absent images);
 // partial: FP64 split-K partials (part_cap bytes) or NULL
 hipError_t launch_m2l_split16(int level, const void *ops, const int32_t *list, const int32_t *offs,
                               const int32_t *rowmap, const float *M, float *Mc, size_t mc_cap, const float *cscale,

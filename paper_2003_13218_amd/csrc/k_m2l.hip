@@ -231,7 +231,8 @@ struct PolBf16 {  // BF16 operands, FP32 storage and accumulation, v_mfma_f32_16
 // 2^-24 for FP32 operands).  FP16's range is kept by powers of two: column k
 // of the operators is multiplied by 2^{b_k} and the multipoles divided by it
 // (in a pre-pass over the level), row r by 2^{a_r} and the result divided by
-// it on output, both exact.  Operators in storage row order, plain list.
+// it on output, both exact.  Two kernels take them: k_m2l_lds with the policy
+// below (folded orbit list, p = 11, 12) and k_m2l_f16rows (plain list).
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 struct F16Pair {
     f16x8 hi, lo;
@@ -300,8 +301,7 @@ template <typename P, int NRB, int SYM> constexpr int stage_chunks() {
                                                           : (bytes == 16 ? 4 * 32 : 4 * 64);
     constexpr int want = (1280 + cyc * NRB - 1) / (cyc * NRB);
     constexpr int lds_cap = (48 * 1024) / (2 * NRB * 64 * bytes);
-    constexpr int nsrc = SYM == 0 ? 1 : (SYM == 1 ? 2 : 4);
-    constexpr int reg_cap = is_split16<P>() ? (SYM != 0 ? 1 : 8 / nsrc) : 6;
+    constexpr int reg_cap = is_split16<P>() ? 1 : 6;
     constexpr int u0 = want < lds_cap ? want : lds_cap;
     constexpr int u = u0 < reg_cap ? u0 : reg_cap;
     return u < 1 ? 1 : (u > 6 ? 6 : u);
