@@ -192,6 +192,32 @@ def test_c1_mixed_shallow_trees(fmm, levels):
     assert rms_rel(ph.cpu().numpy(), o["phi"]) < 1e-5
 
 
+@pytest.mark.parametrize("levels,p", [(1, 8), (2, 8), (1, 12), (2, 12)])
+def test_c1_split16_shallow_trees(fmm, levels, p):
+    # the split-FP16 M2L where a level has 1 or 8 target cells per parity
+    # class (one partly filled tile, split-K slices over the whole list):
+    # the plain-list kernel (p = 8) and the folded one (p = 12), FP64 top
+    # levels switched off so that every level takes them
+    # Against FP64 on the same plan the difference is the operand rounding
+    # alone (a wrong row, tile or slice would be of order 1); against the
+    # oracle the truncation error of the order is added.
+    w, o = ewald_full("C1")
+    pos, q = _t(w.pos), _t(w.q)
+    plan = _plan(fmm, w.box, levels, p, fmm.FMM_FP64)
+    e64, f64, ph64 = fmm.fmm_energy_forces(plan, pos, q, forces=True, phi=True)
+    fmm.fmm_plan_config(plan, fmm.FMM_MIXED_SPLIT16_M2L)
+    fmm.fmm_plan_tuning(plan, fp64_levels=0)
+    e, f, ph = fmm.fmm_energy_forces(plan, pos, q, forces=True, phi=True)
+    fmm.fmm_destroy(plan)
+    f, ph, f64, ph64 = f.cpu().numpy(), ph.cpu().numpy(), f64.cpu().numpy(), ph64.cpu().numpy()
+    ef, ep = rms_rel(f, f64), rms_rel(ph, ph64)
+    E = o["terms"]["total"]
+    print(f"C1 split16 levels={levels} p={p}: vs FP64 E {abs(e - e64) / abs(e64):.2e} force {ef:.2e} "
+          f"phi {ep:.2e}; vs oracle force {rms_rel(f, o['force']):.2e}")
+    assert abs(e - e64) < 1e-6 * abs(e64) and ef < 1e-5 and ep < 1e-5
+    assert abs(e - E) / abs(E) < 1e-5 and rms_rel(f, o["force"]) < 1e-4 and rms_rel(ph, o["phi"]) < 1e-4
+
+
 @pytest.mark.parametrize("p,prec", [(7, 0), (9, 1), (13, 0), (14, 1), (20, 0)])
 def test_c1_orders_with_several_row_groups(fmm, p, prec):
     # layouts of the folded M2L not met elsewhere: orbit lists with one row
