@@ -2,7 +2,7 @@
 allocate) against fmm_energy_forces through the C ABI: the same kernels on the
 same plan, so energies, forces and potentials must agree bit for bit; two
 calls in a row on the shared device scratch, the second with fewer atoms, in
-both precision modes; a workspace beyond the scratch is refused before any GPU
+every precision mode; a workspace beyond the scratch is refused before any GPU
 work."""
 import numpy as np
 import pytest
@@ -17,7 +17,7 @@ def _t(a):
     return torch.tensor(np.ascontiguousarray(a), device="cuda")
 
 
-@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("prec", [1, 0, 3, 2])
 def test_noalloc_matches_energy_forces(fmm, prec):
     import torch
     w = workloads.config("C2")  # 30,001 atoms, levels 4, p 10
