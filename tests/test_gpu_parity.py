@@ -544,6 +544,25 @@ def test_error_falls_with_order(fmm):
     assert errs[4] < errs[2] < errs[0]
 
 
+def test_uv_error_falls_with_order(fmm):
+    # the same experiment for the solute-solvent energy (eq. FMMcalc) of the
+    # ion: its error against the oracle's Ewald form drops with p as well, not
+    # monotonically at this size (measured 2.2e-2, 3.0e-5, 5.8e-5, 1.5e-5,
+    # 3.8e-7 for p = 2..10: W is the interaction of one ion with its
+    # surroundings, about 1e-3 of the total, so its relative error is larger)
+    w = workloads.config("PA")
+    W = oracle.ewald_uv(w.pos, w.q, w.mask, w.box)["total"]
+    mask = _t(w.mask)
+    errs = []
+    for p in (2, 4, 6, 8, 10):
+        plan = _plan(fmm, w.box, w.levels, p, fmm.FMM_FP64)
+        fmm.fmm_energy_forces(plan, _t(w.pos), _t(w.q), forces=False)
+        errs.append(abs(fmm.fmm_solute_solvent_energy(plan, mask) - W) / abs(W))
+        fmm.fmm_destroy(plan)
+    print("relative solute-solvent energy error vs p (2,4,6,8,10):", errs)
+    assert errs[0] > 1e-3 and max(errs[1:4]) < 1e-4 and errs[4] < 1e-6
+
+
 # ------------------------------------------------ the 1M-atom benchmark box --
 @pytest.mark.parametrize("prec,tol", [(1, 1e-5), (0, 1e-6)])
 def test_c3_sample_parity(fmm, prec, tol):
