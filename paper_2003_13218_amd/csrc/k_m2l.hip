@@ -852,11 +852,11 @@ __global__ void k_col_split(const float *__restrict__ M, float *__restrict__ Mc,
 // ---------------------------------------------------------------------------
 // Split-FP16 M2L on the plain list with the rows split over the wavefronts.
 // With the split operands (32-byte fragments, three MFMAs per fragment pair)
-// the LDS-shared kernel above, where every wavefront reads the whole operator
-// chunk from LDS for its own 16 targets, is paced by LDS bandwidth rather than
-// by the matrix cores.  Here a workgroup still owns 64 target cells of one
-// parity class, but wavefront w owns RW row blocks, rows 16 (rb0 + RW w) ..,
-// for all 64 targets (four column blocks of 16):
+// the LDS-shared kernel above makes every wavefront read the whole operator
+// chunk from LDS for its own 16 targets: 22 of its 28 LDS instructions per
+// stage.  Here a workgroup still owns 64 target cells of one parity class, but
+// wavefront w owns RW row blocks, rows 16 (rb0 + RW w) .., for all 64 targets
+// (four column blocks of 16):
 //   * its operator fragments come from global memory (L2) straight into
 //     registers, one stage ahead: no other wavefront reads them;
 //   * the multipole fragments of the 64 targets are the operand shared
@@ -869,7 +869,10 @@ __global__ void k_col_split(const float *__restrict__ M, float *__restrict__ Mc,
 // chunks, then into FP64.  Row blocks past the group (the last wavefront when
 // the group is not a multiple of 4) run on a clamped fragment and are not
 // stored, so every MFMA is unconditional.  SPLIT: split-K over offset slices
-// into FP64 partials, as in k_m2l_lds.
+// into FP64 partials, as in k_m2l_lds.  What paces it (3M-atom box, p = 16):
+// the operator fragments missing L2 (the 64 workgroups of an XCD walk the same
+// chunks but drift apart), about 6.5 TB/s of reads, with the matrix cores busy
+// 44% of the time.
 // ---------------------------------------------------------------------------
 template <bool SPLIT, int RW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_m2l_f16rows(
