@@ -90,6 +90,59 @@ __device__ inline void regular_hat_foreach(T x, T y, T z, int p, F &&f) {
     }
 }
 
+// The same recurrences for a compile-time order P, fully unrolled: every
+// coefficient index is then a constant, and so is every recurrence constant,
+// written here as the formula of build_rec_tables (harmonics_host.cpp) in FP64
+// and rounded once to T, i.e. the value of the uploaded tables, which the
+// compiler folds into the instructions instead of loading it.
+template <typename T>
+__device__ __forceinline__ T rec_a(int n, int m) {
+    return (T)((double)(2 * n - 1) / __builtin_sqrt((double)((n + m) * (n - m))));
+}
+template <typename T>
+__device__ __forceinline__ T rec_b(int n, int m) {
+    return (T)__builtin_sqrt((double)((n + m - 1) * (n - m - 1)) / (double)((n + m) * (n - m)));
+}
+template <typename T>
+__device__ __forceinline__ T rec_c(int m) {
+    return (T)__builtin_sqrt((double)(2 * m - 1) / (double)(2 * m));
+}
+template <typename T>
+__device__ __forceinline__ T rec_d(int m) {
+    return (T)__builtin_sqrt((double)(2 * m + 1));
+}
+template <typename T, int P, typename F>
+__device__ __forceinline__ void regular_hat_unrolled(T x, T y, T z, F &&f) {
+    const T r2 = x * x + y * y + z * z;
+    T mre = 1, mim = 0;
+#pragma unroll
+    for (int m = 0; m <= P; ++m) {
+        if (m > 0) {
+            const T c = -rec_c<T>(m);
+            const T nre = c * (x * mre - y * mim);
+            const T nim = c * (x * mim + y * mre);
+            mre = nre;
+            mim = nim;
+        }
+        f(m, m, mre, mim);
+        if (m + 1 <= P) {
+            T p2re = mre, p2im = mim;
+            const T dm = rec_d<T>(m) * z;
+            T p1re = dm * mre, p1im = dm * mim;
+            f(m + 1, m, p1re, p1im);
+#pragma unroll
+            for (int n = m + 2; n <= P; ++n) {
+                const T a = rec_a<T>(n, m) * z, b = rec_b<T>(n, m) * r2;
+                const T cre = a * p1re - b * p2re;
+                const T cim = a * p1im - b * p2im;
+                f(n, m, cre, cim);
+                p2re = p1re; p2im = p1im;
+                p1re = cre; p1im = cim;
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // P2M (eq. P2M): M~_n^m(leaf) = sum_j q_j conj(R^_n^m((r_j - c)/h)).
 // One thread per (leaf, pair of orders {m, P - m}): the two columns n >= m of
@@ -416,15 +469,17 @@ __device__ inline void get_local(const T *Ls, int n, int m, T &re, T &im) {
     }
 }
 
-template <typename T>
+template <typename T, int P>
 __global__ __launch_bounds__(256) void k_l2p(int64_t nleaf, const T *__restrict__ xq,
-                                             const int32_t *__restrict__ start, const T *__restrict__ L, int p,
-                                             int K, int Kp, T inv_h, T inv_h2, double *__restrict__ phi,
-                                             T *__restrict__ field, int gl) {
+                                             const int32_t *__restrict__ start, const T *__restrict__ L, int Kp,
+                                             T inv_h, T inv_h2, double *__restrict__ phi, T *__restrict__ field,
+                                             int gl) {
+    constexpr int K = (P + 1) * (P + 1);
+    constexpr int Kg = P * P;
+    constexpr int per = K + 3 * Kg;  // per leaf: L~, then G~x, G~y, G~z
     extern __shared__ unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
-    const int Kg = p * p;
-    const int per = K + 3 * Kg;  // per leaf: L~, then G~x, G~y, G~z
+    int32_t *sst = reinterpret_cast<int32_t *>(smem_raw + (size_t)gl * per * sizeof(T));  // the group's leaf starts
     const int tid = threadIdx.x;
     const int64_t l0 = blockIdx.x * (int64_t)gl;
     const int nl = (int)min((int64_t)gl, nleaf - l0);
@@ -434,6 +489,7 @@ __global__ __launch_bounds__(256) void k_l2p(int64_t nleaf, const T *__restrict_
         const int li = i / K, j = i - li * K;
         sm[li * per + j] = L[(l0 + li) * Kp + j];
     }
+    if (tid <= nl) sst[tid] = start[l0 + tid];
     __syncthreads();
     for (int i = tid; i < nl * Kg; i += 256) {
         const int li = i / Kg, j = i - li * Kg;
@@ -465,22 +521,24 @@ __global__ __launch_bounds__(256) void k_l2p(int64_t nleaf, const T *__restrict_
     __syncthreads();
     for (int32_t s = a0 + tid; s < a1; s += 256) {
         int li = 0;  // the atom's leaf within the group
-        while (li + 1 < nl && start[l0 + li + 1] <= s) ++li;
+        while (li + 1 < nl && sst[li + 1] <= s) ++li;
         const T *Ls = sm + li * per;
         const T *Gx = Ls + K, *Gy = Gx + Kg, *Gz = Gy + Kg;
         const T *a = xq + 4 * (int64_t)s;
         const T x = a[0] * inv_h, y = a[1] * inv_h, z = a[2] * inv_h;
         double ph = 0;  // potential accumulated in FP64 (see k_p2p)
         T gx = 0, gy = 0, gz = 0;
-        regular_hat_foreach<T>(x, y, z, p, [&](int n, int m, T re, T im) {
+        // with P a compile-time constant every index below is one too: the
+        // expansions are read from LDS at fixed offsets from the leaf's base
+        regular_hat_unrolled<T, P>(x, y, z, [&](int n, int m, T re, T im) {
             if (m == 0) {
                 const int k = n * n;
                 ph += (double)(re * Ls[k]);
-                if (n < p) { gx += re * Gx[k]; gy += re * Gy[k]; gz += re * Gz[k]; }
+                if (n < P) { gx += re * Gx[k]; gy += re * Gy[k]; gz += re * Gz[k]; }
             } else {
                 const int k = n * n + 2 * m - 1;
                 ph += (double)(re * Ls[k] + im * Ls[k + 1]);
-                if (n < p) {
+                if (n < P) {
                     gx += re * Gx[k] + im * Gx[k + 1];
                     gy += re * Gy[k] + im * Gy[k + 1];
                     gz += re * Gz[k] + im * Gz[k + 1];
@@ -496,19 +554,35 @@ __global__ __launch_bounds__(256) void k_l2p(int64_t nleaf, const T *__restrict_
 
 // leaves per workgroup: about 256 atoms per group at the mean occupancy,
 // within 48 KB of LDS
-template <typename T>
-hipError_t launch_l2p(int64_t nleaf, const void *xq, const int32_t *start, const T *L, int p, int Kp,
-                      double h, double *phi, T *field, hipStream_t s, int64_t natoms) {
-    const int K = num_coeffs(p);
-    const size_t per = (size_t)(K + 3 * p * p) * sizeof(T);
+template <typename T, int P>
+static hipError_t launch_l2p_p(int64_t nleaf, const void *xq, const int32_t *start, const T *L, int Kp, double h,
+                               double *phi, T *field, hipStream_t s, int64_t natoms) {
+    constexpr int K = (P + 1) * (P + 1);
+    const size_t per = (size_t)(K + 3 * P * P) * sizeof(T);
     const double occ = nleaf > 0 ? (double)natoms / (double)nleaf : 1.0;
     int gl = (int)std::floor(256.0 / std::max(occ, 1.0));
     gl = std::max(1, std::min(gl, (int)((48 * 1024) / per)));
     gl = std::min(gl, 64);
     const int64_t g = (nleaf + gl - 1) / gl;
-    hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)g), dim3(256), (size_t)gl * per, s, nleaf, (const T *)xq, start, L,
-                       p, K, Kp, (T)(1.0 / h), (T)(1.0 / (h * h)), phi, field, gl);
+    const size_t lds = (size_t)gl * per + (size_t)(gl + 1) * sizeof(int32_t);
+    hipLaunchKernelGGL((k_l2p<T, P>), dim3((unsigned)g), dim3(256), lds, s, nleaf, (const T *)xq, start, L, Kp,
+                       (T)(1.0 / h), (T)(1.0 / (h * h)), phi, field, gl);
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_l2p(int64_t nleaf, const void *xq, const int32_t *start, const T *L, int p, int Kp,
+                      double h, double *phi, T *field, hipStream_t s, int64_t natoms) {
+    switch (p) {
+#define FMM_L2P_CASE(P) \
+    case P: return launch_l2p_p<T, P>(nleaf, xq, start, L, Kp, h, phi, field, s, natoms);
+        FMM_L2P_CASE(0) FMM_L2P_CASE(1) FMM_L2P_CASE(2) FMM_L2P_CASE(3) FMM_L2P_CASE(4) FMM_L2P_CASE(5)
+        FMM_L2P_CASE(6) FMM_L2P_CASE(7) FMM_L2P_CASE(8) FMM_L2P_CASE(9) FMM_L2P_CASE(10) FMM_L2P_CASE(11)
+        FMM_L2P_CASE(12) FMM_L2P_CASE(13) FMM_L2P_CASE(14) FMM_L2P_CASE(15) FMM_L2P_CASE(16) FMM_L2P_CASE(17)
+        FMM_L2P_CASE(18) FMM_L2P_CASE(19) FMM_L2P_CASE(20)
+#undef FMM_L2P_CASE
+        default: return hipErrorInvalidValue;
+    }
 }
 template hipError_t launch_l2p<float>(int64_t, const void *, const int32_t *, const float *, int, int,
                                       double, double *, float *, hipStream_t, int64_t);
