@@ -469,8 +469,15 @@ __device__ inline void get_local(const T *Ls, int n, int m, T &re, T &im) {
     }
 }
 
+// FP64 at the middle orders: capped at three wavefronts per SIMD (left to
+// itself the compiler keeps about 180 registers at p = 12, two wavefronts)
+template <typename T, int P> constexpr int l2p_min_waves() {
+    return (sizeof(T) == 8 && P >= 9 && P <= 12) ? 3 : 1;
+}
+
 template <typename T, int P>
-__global__ __launch_bounds__(256) void k_l2p(int64_t nleaf, const T *__restrict__ xq,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(l2p_min_waves<T, P>()))) void k_l2p(
+    int64_t nleaf, const T *__restrict__ xq,
                                              const int32_t *__restrict__ start, const T *__restrict__ L, int Kp,
                                              T inv_h, T inv_h2, double *__restrict__ phi, T *__restrict__ field,
                                              int gl) {
