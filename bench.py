@@ -16,6 +16,7 @@ Other workloads (each one JSON line):
   --config C4               32 charging windows (6k-48k atoms), one graph launch
                             of energies + forces and one of solute-solvent
                             energies per step, depths and P2P groups autotuned
+                            (--autotune-cache FILE: taken from / stored in FILE)
 --gpus > 1 is refused: this build runs on one GPU.
 """
 from __future__ import annotations
@@ -317,7 +318,11 @@ def run_batch(args):
     F.fmm_plan_options(plan, F.FMM_BOUNDARY_CONDUCTING, uv_scheme)
     model_levels, _ = F.fmm_batch_levels(plan)
     t0 = time.perf_counter()
-    levels, groups = F.fmm_autotune_batch(plan, off, pos, q)
+    cache_hit = None
+    if args.autotune_cache:
+        cache_hit, levels, groups = F.fmm_autotune_batch_cached(plan, off, pos, q, args.autotune_cache)
+    else:
+        levels, groups = F.fmm_autotune_batch(plan, off, pos, q)
     t_tune = time.perf_counter() - t0
     for _ in range(args.warmup):
         F.fmm_energy_forces_batch(plan, off, pos, q)
@@ -362,7 +367,8 @@ def run_batch(args):
         "config": {"workload": f"C4: {len(ws)} windows, {n} atoms (6k-48k per box), p {p}, {args.prec} precision",
                    "n_atoms": n, "windows": len(ws), "p": p, "precision": args.prec, "uv_scheme": args.uv_scheme,
                    "model_levels": model_levels.tolist(), "tuned_levels": levels.tolist(),
-                   "tuned_p2p_groups": groups.tolist(), "autotune_s": round(t_tune, 2)},
+                   "tuned_p2p_groups": groups.tolist(), "autotune_s": round(t_tune, 2),
+                   "autotune_cache_hit": cache_hit},
         "split_ms": split,
         "energies": E.tolist(), "e_uv": U.tolist(), f"e_uv_{other}": U_other.tolist(),
         "roofline": None,
@@ -383,6 +389,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
+    ap.add_argument("--autotune-cache", default="",
+                    help="C4: depths and P2P groups through this cache file (tuned and stored on a miss)")
     ap.add_argument("--cpu-reference", action="store_true",
                     help="also time the oracle at reference accuracy (1e-12; minutes)")
     ap.add_argument("--copy-bytes", type=int, default=0,

@@ -334,6 +334,7 @@ fmm_status fmm_lattice_tensor(fmm_plan_t plan, double *out, int64_t cap);
  *   is captured on the first call and replayed while offsets, the three
  *   pointers and the precision stay the same (inputs may change in place).
  *   Empty boxes give 0.  Caches the per-box state for
+ *   fmm_solute_solvent_energy_batch and fmm_lambda_energy_batch.
  *
  * fmm_solute_solvent_energy_batch -- e_uv[w] (host out, nbox) of every box
  *   (see fmm_solute_solvent_energy) for mask (device, same rows as pos),
@@ -346,6 +347,24 @@ fmm_status fmm_lattice_tensor(fmm_plan_t plan, double *out, int64_t cap);
  *   rows as pos x 3, or NULL.  fmm_batch_levels reports the chosen depths and
  *   P2P group counts (0 = from the leaf occupancy), host nbox ints each, either
  *   may be NULL.
+ *
+ * fmm_batch_set_tuning -- sets every box's depth (levels[w] in [1, 10]) and
+ *   P2P source-group count (p2p_groups[w]: 0, 1, 2, 4, 8 or 16), host nbox ints
+ *   each; NULL keeps that setting.  Every value is checked before any box
+ *   changes (FMM_ERR_INVALID).  Waits for the device; the next batch call
+ *   captures its graph anew.
+ *
+ * fmm_autotune_batch_cached -- fmm_autotune_batch with a cache file
+ *   (cache_path: a text file, created if absent, one line per tuned batch).
+ *   The key of a line is the device architecture, p, the precision mode, the
+ *   FP64 top levels and every box's edge and atom count (from offsets).  On
+ *   a key found in the file the stored depths and group counts are applied
+ *   as by fmm_batch_set_tuning, nothing is timed and *hit = 1; otherwise the
+ *   batch is tuned, the result appended as one line and *hit = 0 (hit may be
+ *   NULL).  Lines that do not parse are skipped; the last valid line of a
+ *   key wins.  If the file cannot be written the tuning stays applied and
+ *   the call returns FMM_ERR_INVALID.  Concurrent writers may interleave
+ *   lines but each line is one write.
  *
  * Single-box calls (fmm_energy_forces, fmm_bin, ...) reject a batch plan and
  * the *_batch calls reject a single-box plan (FMM_ERR_INVALID).
@@ -362,6 +381,9 @@ fmm_status fmm_lambda_energy_batch(fmm_plan_t plan, const uint8_t *mask, const d
 fmm_status fmm_autotune_batch(fmm_plan_t plan, const int64_t *offsets, const double *pos, const double *q,
                               double *forces_scratch);
 fmm_status fmm_batch_levels(fmm_plan_t plan, int *levels, int *p2p_groups);
+fmm_status fmm_batch_set_tuning(fmm_plan_t plan, const int *levels, const int *p2p_groups);
+fmm_status fmm_autotune_batch_cached(fmm_plan_t plan, const int64_t *offsets, const double *pos, const double *q,
+                                     double *forces_scratch, const char *cache_path, int *hit);
 
 /*
  * Stage timing.  fmm_profile(plan, 1) creates HIP events on the plan's stream

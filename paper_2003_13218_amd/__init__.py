@@ -14,4 +14,4 @@ from .binding import (FMM_FP64, FMM_MIXED, FMM_MIXED_BF16_M2L, FMM_MIXED_SPLIT16
                       fmm_solute_solvent_energy_batch, fmm_autotune_batch, fmm_batch_levels,
                       fmm_lambda_energy, fmm_lambda_energy_batch, fmm_plan_options,
                       fmm_plan_softcore, fmm_plan_info, fmm_plan_tuning,
-                      fmm_energy_forces_noalloc)
+                      fmm_energy_forces_noalloc, fmm_batch_set_tuning, fmm_autotune_batch_cached)

@@ -35,7 +35,7 @@ EXPORTED = (
     "fmm_last_error", "fmm_destroy", "fmm_version", "fmm_plan_batch", "fmm_energy_forces_batch",
     "fmm_solute_solvent_energy_batch", "fmm_autotune_batch", "fmm_batch_levels", "fmm_lambda_energy",
     "fmm_lambda_energy_batch", "fmm_plan_options", "fmm_plan_softcore", "fmm_plan_info", "fmm_plan_tuning",
-    "fmm_energy_forces_noalloc",
+    "fmm_energy_forces_noalloc", "fmm_batch_set_tuning", "fmm_autotune_batch_cached",
 )
 
 STAGES = ("sort", "gather", "p2m", "m2m", "lattice", "m2l", "m2l_leaf", "l2l", "l2p", "p2p", "final", "total")
@@ -102,6 +102,10 @@ def load():
         lib.fmm_autotune_batch.restype = ci
         lib.fmm_batch_levels.argtypes = [vp, vp, vp]
         lib.fmm_batch_levels.restype = ci
+        lib.fmm_batch_set_tuning.argtypes = [vp, vp, vp]
+        lib.fmm_batch_set_tuning.restype = ci
+        lib.fmm_autotune_batch_cached.argtypes = [vp, vp, vp, vp, vp, ctypes.c_char_p, vp]
+        lib.fmm_autotune_batch_cached.restype = ci
         lib.fmm_lambda_energy.argtypes = [vp, vp, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
         lib.fmm_lambda_energy.restype = ci
         lib.fmm_lambda_energy_batch.argtypes = [vp, vp, vp, vp, vp]
@@ -366,11 +370,41 @@ def fmm_autotune_batch(plan: Plan, offsets, pos, q):
     import numpy as np
     import torch
     off = _host(offsets, np.int64)
+    if off.size != plan.nbox + 1:
+        raise ValueError(f"offsets needs {plan.nbox + 1} entries")
     scratch = torch.empty((int(q.shape[0]), 3), dtype=torch.float64, device=q.device)
     _check(load().fmm_autotune_batch(plan.handle, off.ctypes.data_as(ctypes.c_void_p),
                                      _dptr(pos, torch.float64, (3,), "pos"), _dptr(q, torch.float64, (), "q"),
                                      _dptr(scratch, torch.float64, (3,))), plan)
     return fmm_batch_levels(plan)
+
+
+def fmm_batch_set_tuning(plan: Plan, levels=None, p2p_groups=None):
+    """Sets each box's tree depth and P2P source groups (None keeps a setting)."""
+    import numpy as np
+    lv = None if levels is None else _host(levels, np.int32)
+    g = None if p2p_groups is None else _host(p2p_groups, np.int32)
+    for a, name in ((lv, "levels"), (g, "p2p_groups")):
+        if a is not None and a.shape != (plan.nbox,):
+            raise ValueError(f"{name} must hold one value per box ({plan.nbox})")
+    _check(load().fmm_batch_set_tuning(plan.handle, None if lv is None else lv.ctypes.data_as(ctypes.c_void_p),
+                                       None if g is None else g.ctypes.data_as(ctypes.c_void_p)), plan)
+
+
+def fmm_autotune_batch_cached(plan: Plan, offsets, pos, q, cache_path):
+    """fmm_autotune_batch through a cache file; returns (hit, levels, p2p_groups)."""
+    import numpy as np
+    import torch
+    off = _host(offsets, np.int64)
+    if off.size != plan.nbox + 1:
+        raise ValueError(f"offsets needs {plan.nbox + 1} entries")
+    scratch = torch.empty((int(q.shape[0]), 3), dtype=torch.float64, device=q.device)
+    hit = ctypes.c_int(0)
+    _check(load().fmm_autotune_batch_cached(plan.handle, off.ctypes.data_as(ctypes.c_void_p),
+                                            _dptr(pos, torch.float64, (3,), "pos"), _dptr(q, torch.float64, (), "q"),
+                                            _dptr(scratch, torch.float64, (3,)), os.fsencode(cache_path),
+                                            ctypes.byref(hit)), plan)
+    return (bool(hit.value),) + tuple(fmm_batch_levels(plan))
 
 
 def fmm_destroy(plan: Plan):

@@ -578,8 +578,7 @@ extern "C" fmm_status fmm_plan_tuning(fmm_plan_t pl, int fp64_levels, int p2p_gr
     if (!pl) return fail(nullptr, FMM_ERR_INVALID, "fmm_plan_tuning: plan is NULL");
     if (fp64_levels < -1 || fp64_levels > kMaxLevels)
         return fail(pl, FMM_ERR_INVALID, "fmm_plan_tuning: fp64_levels must be in [-1, 10]");
-    if (p2p_groups != -1 && p2p_groups != 0 && p2p_groups != 1 && p2p_groups != 2 && p2p_groups != 4 &&
-        p2p_groups != 8 && p2p_groups != kMaxP2PGroups)
+    if (p2p_groups != -1 && !valid_p2p_groups(p2p_groups))
         return fail(pl, FMM_ERR_INVALID, "fmm_plan_tuning: p2p_groups must be -1, 0, 1, 2, 4, 8 or 16");
     auto set = [&](fmm_plan_t b) {
         if (fp64_levels >= 0) b->top_fp64 = fp64_levels;
@@ -1896,6 +1895,32 @@ extern "C" fmm_status fmm_lambda_energy_batch(fmm_plan_t pl, const uint8_t *mask
     return FMM_OK;
 }
 
+// Box w of a batch at depth L with g P2P source groups (0: from the leaf
+// occupancy).  A new depth means a new sub-plan, sharing the box-independent
+// operators and taking over the box's settings.
+static fmm_status batch_set_box(fmm_plan_t pl, size_t w, int L, int g) {
+    fmm_plan_t cur = pl->sub[w];
+    if (L != cur->levels) {
+        fmm_plan_t b = nullptr;
+        fmm_status st = plan_create(cur->box, L, pl->p, pl->op, true, &b);
+        if (st != FMM_OK) return fail(pl, st, "box " + std::to_string(w) + ": " + g_plan_error);
+        b->top_fp64 = cur->top_fp64;
+        b->boundary = cur->boundary;
+        b->uv_scheme = cur->uv_scheme;
+        b->sc_alpha = cur->sc_alpha;
+        b->sc_sigma = cur->sc_sigma;
+        b->sc_c = cur->sc_c;
+        b->prec = pl->prec;
+        b->stream = pl->sub_stream[w];
+        fmm_destroy(cur);
+        pl->sub[w] = b;
+        cur = b;
+    }
+    cur->p2p_g = g;
+    cur->have_state = false;
+    return FMM_OK;
+}
+
 // Autotuner: for every non-empty box, time whole evaluations (energy and
 // forces, hipEvent-timed on the box's stream after one warm-up) for the tree
 // depths L-1, L, L+1 around the current one and the P2P source-group counts
@@ -1964,30 +1989,70 @@ extern "C" fmm_status fmm_autotune_batch(fmm_plan_t pl, const int64_t *offsets, 
             if (b != cur) fmm_destroy(b);
         }
         if (st != FMM_OK) break;
-        if (best_L != cur->levels) {
-            fmm_plan_t b = nullptr;
-            if ((st = plan_create(cur->box, best_L, pl->p, pl->op, true, &b)) != FMM_OK) {
-                pl->err = "autotune box " + std::to_string(w) + ": " + g_plan_error;
-                break;
-            }
-            b->top_fp64 = cur->top_fp64;
-            b->boundary = cur->boundary;
-            b->uv_scheme = cur->uv_scheme;
-            b->sc_alpha = cur->sc_alpha;
-            b->sc_sigma = cur->sc_sigma;
-            b->sc_c = cur->sc_c;
-            b->prec = pl->prec;
-            b->stream = pl->sub_stream[w];
-            fmm_destroy(cur);
-            pl->sub[w] = b;
-            cur = b;
-        }
-        cur->p2p_g = best_g;
-        cur->have_state = false;
+        st = batch_set_box(pl, w, best_L, best_g);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return st;
+}
+
+extern "C" fmm_status fmm_batch_set_tuning(fmm_plan_t pl, const int *levels, const int *p2p_groups) {
+    if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    if (!pl->is_batch) return fail(pl, FMM_ERR_INVALID, "fmm_batch_set_tuning: not a batch plan");
+    for (size_t w = 0; w < pl->sub.size(); ++w) {
+        if (levels && (levels[w] < 1 || levels[w] > kMaxLevels))
+            return fail(pl, FMM_ERR_INVALID, "fmm_batch_set_tuning: levels must be in [1, 10]");
+        if (p2p_groups && !valid_p2p_groups(p2p_groups[w]))
+            return fail(pl, FMM_ERR_INVALID, "fmm_batch_set_tuning: p2p_groups must be 0, 1, 2, 4, 8 or 16");
+    }
+    HIPCHK(pl, hipSetDevice(pl->device), "hipSetDevice");
+    HIPCHK(pl, hipDeviceSynchronize(), "synchronize");  // no queued work still uses a sub-plan
+    batch_drop_graphs(pl);
+    pl->batch_state = false;
+    for (size_t w = 0; w < pl->sub.size(); ++w) {
+        const fmm_status st = batch_set_box(pl, w, levels ? levels[w] : pl->sub[w]->levels,
+                                            p2p_groups ? p2p_groups[w] : pl->sub[w]->p2p_g);
+        if (st != FMM_OK) return st;
+    }
+    return FMM_OK;
+}
+
+extern "C" fmm_status fmm_autotune_batch_cached(fmm_plan_t pl, const int64_t *offsets, const double *pos,
+                                                const double *q, double *forces_scratch, const char *cache_path,
+                                                int *hit) {
+    if (hit) *hit = 0;
+    if (!pl) return fail(nullptr, FMM_ERR_INVALID, "plan is NULL");
+    if (!pl->is_batch) return fail(pl, FMM_ERR_INVALID, "fmm_autotune_batch_cached: not a batch plan");
+    if (!cache_path || !*cache_path) return fail(pl, FMM_ERR_INVALID, "fmm_autotune_batch_cached: no cache path");
+    fmm_status st = check_batch_offsets(pl, offsets);
+    if (st != FMM_OK) return st;
+    const size_t nb = pl->sub.size();
+    hipDeviceProp_t prop;
+    HIPCHK(pl, hipGetDeviceProperties(&prop, pl->device), "hipGetDeviceProperties");
+    std::vector<double> edge(nb);
+    std::vector<int64_t> natoms(nb);
+    for (size_t w = 0; w < nb; ++w) {
+        edge[w] = pl->sub[w]->box;
+        natoms[w] = offsets[w + 1] - offsets[w];
+    }
+    const std::string key = tuning_cache_key(prop.gcnArchName, pl->p, (int)pl->prec, pl->sub[0]->top_fp64, nb,
+                                             edge.data(), natoms.data());
+    std::vector<int> lv, gr;
+    if (tuning_cache_lookup(cache_path, key, nb, lv, gr)) {
+        if ((st = fmm_batch_set_tuning(pl, lv.data(), gr.data())) != FMM_OK) return st;
+        if (hit) *hit = 1;
+        return FMM_OK;
+    }
+    if ((st = fmm_autotune_batch(pl, offsets, pos, q, forces_scratch)) != FMM_OK) return st;
+    lv.assign(nb, 0);
+    gr.assign(nb, 0);
+    for (size_t w = 0; w < nb; ++w) {
+        lv[w] = pl->sub[w]->levels;
+        gr[w] = pl->sub[w]->p2p_g;
+    }
+    if (!tuning_cache_append(cache_path, key, lv, gr))
+        return fail(pl, FMM_ERR_INVALID, "fmm_autotune_batch_cached: cannot write the cache file");
+    return FMM_OK;
 }
 
 extern "C" const char *fmm_version(void) { return "libfmm 0.1 (gfx950)"; }

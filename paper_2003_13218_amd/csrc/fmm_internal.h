@@ -18,6 +18,8 @@ constexpr int kM2LPairEntries = 573;   // list entries per class, scheme 1: 302 
 constexpr int kM2LOrbitEntries = 305;  // list entries per class, scheme 2: orbits of the two-axis flips
 constexpr int kMaxP = 20;
 constexpr int kMaxP2PGroups = 16;  // largest source-group count of the P2P kernel
+// source-group counts of the P2P kernel (0: chosen from the leaf occupancy)
+constexpr bool valid_p2p_groups(int g) { return g == 0 || g == 1 || g == 2 || g == 4 || g == 8 || g == kMaxP2PGroups; }
 constexpr int kMaxLevels = 10;
 
 // ---------------------------------------------------------------------------
@@ -341,5 +343,13 @@ hipError_t launch_finalize(int64_t n, const int32_t *perm, const double *xs, dou
 template <typename T>
 hipError_t launch_parts_out(int64_t n, const int32_t *perm, const double *phi_s, const T *field_s,
                             const double *m0, double cq, double *phi, double *field, hipStream_t s);
+
+// tuning_cache.cpp: the autotune cache file of batch plans (host code)
+std::string tuning_cache_key(const std::string &arch, int p, int prec, int fp64_levels, size_t nbox,
+                             const double *box, const int64_t *natoms);
+bool tuning_cache_lookup(const char *path, const std::string &key, size_t nbox, std::vector<int> &levels,
+                         std::vector<int> &groups);
+bool tuning_cache_append(const char *path, const std::string &key, const std::vector<int> &levels,
+                         const std::vector<int> &groups);
 
 }  // namespace fmm

@@ -125,6 +125,54 @@ def test_batch_autotune_keeps_results(fmm, windows):
         assert abs(E[k] - e) <= 1e-6 * abs(e)
 
 
+def test_batch_autotune_cache_and_set_tuning(fmm, windows, tmp_path):
+    # fmm_autotune_batch_cached: a miss tunes and appends one line; a second
+    # plan of the same batch finds it and takes the same depths and group
+    # counts without timing, so its energies and forces equal the first
+    # plan's bit for bit.  fmm_batch_set_tuning applies given settings the
+    # same way and rejects out-of-range ones before changing any box.
+    ws = windows[:3]
+    off, pos, q, _ = _concat(ws)
+    tp, tq = _t(pos), _t(q)
+    path = str(tmp_path / "autotune.txt")
+
+    def new_plan():
+        b = fmm.fmm_plan_batch([w.box for w in ws], 10, natoms=[w.n for w in ws])
+        fmm.fmm_plan_config(b, fmm.FMM_MIXED)
+        return b
+
+    plan = new_plan()
+    hit, L1, G1 = fmm.fmm_autotune_batch_cached(plan, off, tp, tq, path)
+    assert not hit and set(G1.tolist()) <= {2, 4, 8}
+    assert len(open(path).read().splitlines()) == 1
+    E1, F1 = fmm.fmm_energy_forces_batch(plan, off, tp, tq)
+    F1 = F1.cpu().numpy()
+
+    plan2 = new_plan()
+    hit, L2, G2 = fmm.fmm_autotune_batch_cached(plan2, off, tp, tq, path)
+    assert hit and L2.tolist() == L1.tolist() and G2.tolist() == G1.tolist()
+    assert len(open(path).read().splitlines()) == 1
+    E2, F2 = fmm.fmm_energy_forces_batch(plan2, off, tp, tq)
+    np.testing.assert_array_equal(E2, E1)
+    np.testing.assert_array_equal(F2.cpu().numpy(), F1)
+
+    plan3 = new_plan()
+    L0, G0 = fmm.fmm_batch_levels(plan3)
+    for bad in (dict(levels=[0] * 3), dict(levels=[11] * 3), dict(p2p_groups=[3] * 3),
+                dict(levels=L1, p2p_groups=[4, 4, 5])):
+        with pytest.raises(fmm.FmmError):
+            fmm.fmm_batch_set_tuning(plan3, **bad)
+        L, G = fmm.fmm_batch_levels(plan3)
+        assert L.tolist() == L0.tolist() and G.tolist() == G0.tolist()
+    fmm.fmm_batch_set_tuning(plan3, L1, G1)
+    L3, G3 = fmm.fmm_batch_levels(plan3)
+    assert L3.tolist() == L1.tolist() and G3.tolist() == G1.tolist()
+    E3, _ = fmm.fmm_energy_forces_batch(plan3, off, tp, tq)
+    np.testing.assert_array_equal(E3, E1)
+    for b in (plan, plan2, plan3):
+        fmm.fmm_destroy(b)
+
+
 def test_batch_edge_cases(fmm, windows):
     import torch
     ws = windows[:2]

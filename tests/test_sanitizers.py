@@ -3,8 +3,9 @@
 The oracle (oracle/ewald.c) and the library's host-side plan precompute (the
 operator builders, the lattice tensor of eq. 12, the interaction lists and
 their symmetry folding, the matrix-core swizzles; csrc/harmonics_host.cpp and
-csrc/m2l_layout.cpp) are built with -fsanitize=address,undefined and driven
-over small inputs and every order p the benchmarks use: any out-of-bounds
+csrc/m2l_layout.cpp) and the batch autotune cache file (csrc/tuning_cache.cpp)
+are built with -fsanitize=address,undefined and driven over small inputs and
+every order p the benchmarks use: any out-of-bounds
 access, use after free, leak or undefined arithmetic aborts the driver.  No
 GPU code is built or run here (the host files are compiled host-only).
 """
@@ -97,6 +98,52 @@ HOST_DRIVER = textwrap.dedent(r"""
 """)
 
 
+CACHE_DRIVER = textwrap.dedent(r"""
+    #include "fmm_internal.h"
+    #include <cstdio>
+    #include <vector>
+    using namespace fmm;
+    int main(int argc, char **argv) {
+        if (argc < 2) return 2;
+        const char *path = argv[1];
+        int bad = 0;
+        const double box[3] = {30.5, 41.25, 52.0};
+        const int64_t na[3] = {1000, 2500, 0}, nb[3] = {1000, 2501, 0};
+        const std::string k = tuning_cache_key("gfx950:sramecc+ x\t", 10, 1, 3, 3, box, na);
+        const std::string k2 = tuning_cache_key("gfx950:sramecc+ x\t", 10, 1, 3, 3, box, nb);
+        if (k.find('\t') != std::string::npos || k.find(' ', 15) == std::string::npos || k == k2) ++bad;
+        std::vector<int> lv, gr;
+        if (tuning_cache_lookup(path, k, 3, lv, gr)) ++bad;  // no file yet
+        FILE *fp = std::fopen(path, "wb");
+        if (!fp) return 3;
+        std::fprintf(fp, "foreign line\n\n%s\n", k.c_str());
+        std::fprintf(fp, "%s\t3,3\t4,4,4\n", k.c_str());        // too few depths
+        std::fprintf(fp, "%s\t3,11,3\t4,4,4\n", k.c_str());     // depth out of range
+        std::fprintf(fp, "%s\t3,3,3\t4,5,4\n", k.c_str());      // not a group count
+        std::fprintf(fp, "%s\t3,3,3,\t4,4,4\n", k.c_str());     // trailing comma
+        std::fprintf(fp, "%sX\t3,3,3\t4,4,4\n", k.c_str());     // longer key
+        std::fclose(fp);
+        if (tuning_cache_lookup(path, k, 3, lv, gr)) ++bad;
+        if (!tuning_cache_append(path, k, {3, 2, 4}, {4, 8, 0})) ++bad;
+        if (!tuning_cache_lookup(path, k, 3, lv, gr) || lv != std::vector<int>{3, 2, 4} ||
+            gr != std::vector<int>{4, 8, 0}) ++bad;
+        if (tuning_cache_lookup(path, k2, 3, lv, gr)) ++bad;  // another batch
+        if (!tuning_cache_append(path, k2, {1, 1, 1}, {16, 16, 16})) ++bad;
+        if (!tuning_cache_append(path, k, {2, 2, 2}, {2, 2, 2})) ++bad;
+        fp = std::fopen(path, "ab");
+        if (!fp) return 3;
+        std::fprintf(fp, "%s\t5,5,5\t16,16,16", k.c_str());  // torn append: no line feed
+        std::fclose(fp);
+        if (!tuning_cache_lookup(path, k, 3, lv, gr) || lv != std::vector<int>{2, 2, 2} ||
+            gr != std::vector<int>{2, 2, 2}) ++bad;  // the last complete line wins
+        if (!tuning_cache_lookup(path, k2, 3, lv, gr) || lv != std::vector<int>{1, 1, 1}) ++bad;
+        if (tuning_cache_append("/nonexistent-dir/x/cache.txt", k, {1, 1, 1}, {0, 0, 0})) ++bad;
+        std::printf("tuning cache bad=%d\n", bad);
+        return bad;
+    }
+""")
+
+
 def _run(cmd, env=None, **kw):
     r = subprocess.run(cmd, capture_output=True, text=True, env=env or ENV, **kw)
     assert r.returncode == 0, f"{' '.join(cmd)}\n{r.stdout[-3000:]}\n{r.stderr[-3000:]}"
@@ -133,3 +180,23 @@ def test_host_precompute_under_sanitizers(tmp_path):
     _run([hipcc, *HIP_SAN, *objs, "-o", str(exe), "-lpthread"])
     r = _run([str(exe)], timeout=600)
     assert "host precompute bad=0" in r.stdout
+
+
+def test_tuning_cache_under_sanitizers(tmp_path):
+    # the autotune cache file of batch plans (csrc/tuning_cache.cpp): keys,
+    # round trip, last line wins, foreign / malformed / torn lines skipped
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    drv = tmp_path / "cache_drv.cpp"
+    drv.write_text(CACHE_DRIVER)
+    objs = []
+    for path in (os.path.join(CSRC, "tuning_cache.cpp"), str(drv)):
+        obj = tmp_path / (os.path.basename(path) + ".o")
+        _run([hipcc, "-x", "hip", "--cuda-host-only", "-std=c++17", "-I", CSRC, "-I", os.path.join(ROOT, "include"),
+              *HIP_SAN, "-c", path, "-o", str(obj)])
+        objs.append(str(obj))
+    exe = tmp_path / "cache_san"
+    _run([hipcc, *HIP_SAN, *objs, "-o", str(exe), "-lpthread"])
+    r = _run([str(exe), str(tmp_path / "autotune.txt")], timeout=120)
+    assert "tuning cache bad=0" in r.stdout
