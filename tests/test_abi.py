@@ -62,6 +62,10 @@ def test_calls_on_null_plan_are_rejected():
     assert lib.fmm_solute_solvent_energy(None, None, ctypes.byref(e)) == -1
     assert lib.fmm_plan_config(None, 0, 0.0, None) == -1
     assert lib.fmm_profile(None, 1) == -1
+    hit = ctypes.c_int(7)
+    assert lib.fmm_batch_set_tuning(None, None, None) == -1
+    assert lib.fmm_autotune_batch_cached(None, None, None, None, None, b"x", ctypes.byref(hit)) == -1
+    assert hit.value == 0
 
 
 def test_plan_without_gpu_reports_device_error():
