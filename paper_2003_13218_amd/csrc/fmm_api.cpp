@@ -938,7 +938,8 @@ static fmm_status run_fields(fmm_plan_t pl, int64_t n, const double *pos, const 
         nsplit = std::max(1, std::min(nsplit, 8));
         while (nsplit > 1 && nleaf * nsplit >= ((int64_t)1 << 31)) nsplit /= 2;  // wavefront ids stay int
         HIPCHK(pl, launch_p2p<T>(nleaf, pl->levels, pl->xqp.ptr, pl->pstart.as<int32_t>(), pl->start.as<int32_t>(),
-                                 h_leaf, pl->phi_nf.as<double>(), pl->field_nf.as<T>(), groups, nsplit, 0, ns),
+                                 h_leaf, pl->phi_nf.as<double>(), pl->field_nf.as<T>(), groups, nsplit, 0,
+                                 n + (int64_t)groups * nleaf, ns),
                "P2P");
         stage_end(pl, FMM_STAGE_P2P, ns);
         if (fork) HIPCHK(pl, hipEventRecord(pl->ev_join, ns), "event record");

@@ -324,7 +324,8 @@ hipError_t launch_l2l_mfma(int64_t nparent, const Tin *Lparent, Tout *Lchild, co
 // k_p2p.hip
 template <typename T>
 hipError_t launch_p2p(int64_t nleaf, int levels, const void *xqp, const int32_t *pstart, const int32_t *start,
-                      double h, double *phi, T *field, int groups, int nsplit, int max_wg, hipStream_t s);
+                      double h, double *phi, T *field, int groups, int nsplit, int max_wg, int64_t nsrc_max,
+                      hipStream_t s);
 
 // k_reduce.hip
 struct Moments {  // device-side FP64 results of the moment reduction

@@ -19,6 +19,8 @@
 // the ~125 n terms of a potential; the field terms fall off as 1/r^2 and are
 // summed in the mode's precision.  The G partial sums of a target are
 // combined with cross-lane shuffles at the end.
+#include <type_traits>
+
 #include "fmm_internal.h"
 #include "morton.h"
 
@@ -57,22 +59,61 @@ __device__ inline void p2p_pair(const typename Vec4<T>::type &b, T ox, T oy, T o
     fz += qr3 * dz;
 }
 
-// Potential and field at (ox, oy, oz) from the sources bp[0], bp[G], ... of a
-// leaf holding n (padded) sources.  n is a multiple of G, or of G / 2 when
-// HALF: then a last half group may remain, whose upper lanes (g >= G / 2) read
-// the same group's lower half again and drop it.  SELF: the sources are the
-// target's own leaf; skip the source at selfp.
-template <typename T, int G, bool SELF, bool HALF>
-__device__ inline void p2p_leaf(const typename Vec4<T>::type *__restrict__ bp, int n, int g, T ox, T oy, T oz,
-                                const typename Vec4<T>::type *selfp, double &ph, T &fx, T &fy, T &fz) {
+// BUF: the sources of one leaf read through a raw buffer descriptor (base
+// address, no stride, the leaf's bytes as its size; GFX9 data-format word):
+// a load takes the lane's byte offset in a vector register and the
+// wave-uniform position in the leaf in a scalar register, so stepping through
+// the leaf is one scalar add and no lane computes a 64-bit address.  Taken for
+// FP64 sources (1M-atom box, FP64 near field 8.8 -> 8.4 ms); FP32 sources stay
+// on global loads, with which that kernel measured faster (2.55 against 2.73
+// ms) although it issues more vector instructions.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ inline __amdgpu_buffer_rsrc_t leaf_rsrc(const void *base, uint32_t nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)nbytes, 0x00020000);
+}
+__device__ inline Vec4<double>::type load_src(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+    const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(voff + 16u), (int)soff, 0);
+    auto d = [](unsigned lo, unsigned hi) {
+        return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    };
+    return Vec4<double>::type{d(a.x, a.y), d(a.z, a.w), d(b.x, b.y), d(b.z, b.w)};
+}
+
+// Potential and field at (ox, oy, oz) from the sources base[g], base[g + G],
+// ... of a leaf holding n (padded) sources starting at base.  n is a multiple
+// of G, or of G / 2 when HALF: then a last half group may remain, whose upper
+// lanes (g >= G / 2) read the same group's lower half again and drop it.
+// SELF: the sources are the target's own leaf; skip source index self_i.
+template <typename T, int G, bool SELF, bool HALF, bool BUF>
+__device__ inline void p2p_leaf(const typename Vec4<T>::type *__restrict__ base, int n, int g, T ox, T oy, T oz,
+                                int self_i, double &ph, T &fx, T &fy, T &fz) {
+    using V4 = typename Vec4<T>::type;
     T pc = 0;
     const int nk = n / G;
+    if constexpr (BUF) {
+        static_assert(std::is_same<T, double>::value, "buffer loads of FP64 sources");
+        constexpr uint32_t SZ = sizeof(V4);
+        const __amdgpu_buffer_rsrc_t r = leaf_rsrc(base, (uint32_t)n * SZ);
+        const uint32_t voff = (uint32_t)g * SZ;
 #pragma unroll 4
-    for (int k = 0; k < nk; ++k) p2p_pair<T>(bp[k * G], ox, oy, oz, SELF && bp + k * G == selfp, pc, fx, fy, fz);
-    if (HALF && n != nk * G) {  // wave-uniform
-        const bool in = g < G / 2;
-        const typename Vec4<T>::type *b = bp + nk * G - (in ? 0 : G / 2);
-        p2p_pair<T>(*b, ox, oy, oz, !in || (SELF && b == selfp), pc, fx, fy, fz);
+        for (int k = 0; k < nk; ++k)
+            p2p_pair<T>(load_src(r, voff, (uint32_t)k * G * SZ), ox, oy, oz, SELF && k * G + g == self_i, pc, fx, fy,
+                        fz);
+        if (HALF && n != nk * G) {  // wave-uniform
+            const bool in = g < G / 2;
+            const int i = nk * G + g - (in ? 0 : G / 2);
+            p2p_pair<T>(load_src(r, (uint32_t)i * SZ, 0u), ox, oy, oz, !in || (SELF && i == self_i), pc, fx, fy, fz);
+        }
+    } else {
+        const V4 *bp = base + g;
+#pragma unroll 4
+        for (int k = 0; k < nk; ++k) p2p_pair<T>(bp[k * G], ox, oy, oz, SELF && k * G + g == self_i, pc, fx, fy, fz);
+        if (HALF && n != nk * G) {  // wave-uniform
+            const bool in = g < G / 2;
+            const int i = nk * G + g - (in ? 0 : G / 2);
+            p2p_pair<T>(base[i], ox, oy, oz, !in || (SELF && i == self_i), pc, fx, fy, fz);
+        }
     }
     ph += (double)pc;
 }
@@ -80,7 +121,7 @@ __device__ inline void p2p_leaf(const typename Vec4<T>::type *__restrict__ bp, i
 // One chunk of up to 64 / G targets of a leaf (first target tb) against its
 // 125 near-field leaves, G source groups per target; results stored by the
 // lanes of group 0.
-template <typename T, int G, bool HALF>
+template <typename T, int G, bool HALF, bool BUF>
 __device__ inline void p2p_chunk(const typename Vec4<T>::type *__restrict__ X, const int32_t *__restrict__ pstart,
                                  uint32_t cx, uint32_t cy, uint32_t cz, uint32_t nmask, int32_t s0, int32_t cnt,
                                  int32_t p0, int32_t pcnt, int32_t tb, T h, int lane, double *__restrict__ phi,
@@ -93,14 +134,14 @@ __device__ inline void p2p_chunk(const typename Vec4<T>::type *__restrict__ X, c
     const V4 ti = X[p0 + tl];
     double ph = 0;
     T fx = 0, fy = 0, fz = 0;
-    p2p_leaf<T, G, true, HALF>(X + p0 + g, pcnt, g, ti.x, ti.y, ti.z, X + p0 + tl, ph, fx, fy, fz);
+    p2p_leaf<T, G, true, HALF, BUF>(X + p0, pcnt, g, ti.x, ti.y, ti.z, tl, ph, fx, fy, fz);
     for (int c = 0; c < 125; ++c) {
         if (c == 62) continue;  // offset (0, 0, 0): done above
         const int dx = c / 25 - kWS, dy = (c / 5) % 5 - kWS, dz = c % 5 - kWS;
         const uint32_t sc = morton3((cx + dx) & nmask, (cy + dy) & nmask, (cz + dz) & nmask);
         const int32_t j0 = pstart[sc];
-        p2p_leaf<T, G, false, HALF>(X + j0 + g, pstart[sc + 1] - j0, g, ti.x - (T)dx * h, ti.y - (T)dy * h,
-                                    ti.z - (T)dz * h, nullptr, ph, fx, fy, fz);
+        p2p_leaf<T, G, false, HALF, BUF>(X + j0, pstart[sc + 1] - j0, g, ti.x - (T)dx * h, ti.y - (T)dy * h,
+                                    ti.z - (T)dz * h, -1, ph, fx, fy, fz);
     }
 #pragma unroll
     for (int m = 1; m < G; m <<= 1) {
@@ -118,7 +159,7 @@ __device__ inline void p2p_chunk(const typename Vec4<T>::type *__restrict__ X, c
     }
 }
 
-template <typename T, int G>
+template <typename T, int G, bool BUF>
 __global__ __launch_bounds__(256) void k_p2p(int64_t nleaf, int levels, const T *__restrict__ xqp,
                                              const int32_t *__restrict__ pstart, const int32_t *__restrict__ start,
                                              T h, double *__restrict__ phi, T *__restrict__ field, int nsplit) {
@@ -150,27 +191,40 @@ __global__ __launch_bounds__(256) void k_p2p(int64_t nleaf, int levels, const T 
         const int32_t p0 = pstart[leaf], pcnt = pstart[leaf + 1] - p0;
         for (int32_t tb = part * TS; tb < cnt; tb += nsplit * TS) {
             if (kHalfTail && cnt - tb <= TS / 2)
-                p2p_chunk<T, (kHalfTail ? 2 * G : G), true>(X, pstart, cx, cy, cz, nmask, s0, cnt, p0, pcnt, tb, h,
+                p2p_chunk<T, (kHalfTail ? 2 * G : G), true, BUF>(X, pstart, cx, cy, cz, nmask, s0, cnt, p0, pcnt, tb, h,
                                                             lane, phi, field);
             else
-                p2p_chunk<T, G, false>(X, pstart, cx, cy, cz, nmask, s0, cnt, p0, pcnt, tb, h, lane, phi, field);
+                p2p_chunk<T, G, false, BUF>(X, pstart, cx, cy, cz, nmask, s0, cnt, p0, pcnt, tb, h, lane, phi,
+                                            field);
         }
     }
 }
 
-// max_wg > 0 caps the grid (the kernel loops over the remaining items)
+// max_wg > 0 caps the grid (the kernel loops over the remaining items);
+// nsrc_max bounds the padded source count (buffer loads need every leaf's
+// byte size and offsets below 2^31)
 template <typename T>
 hipError_t launch_p2p(int64_t nleaf, int levels, const void *xqp, const int32_t *pstart, const int32_t *start,
-                      double h, double *phi, T *field, int groups, int nsplit, int max_wg, hipStream_t s) {
+                      double h, double *phi, T *field, int groups, int nsplit, int max_wg, int64_t nsrc_max,
+                      hipStream_t s) {
     if (nsplit < 1 || nsplit > 64) return hipErrorInvalidValue;
     int64_t grid = (nleaf * nsplit + 3) / 4;
     if (max_wg > 0 && grid > max_wg) grid = max_wg;
     const T *x = (const T *)xqp;
+    const bool buf = std::is_same<T, double>::value && nsrc_max >= 0 &&
+                     nsrc_max * (int64_t)sizeof(typename Vec4<T>::type) < ((int64_t)1 << 31);
     switch (groups) {
-#define FMM_P2P_CASE(G)                                                                                    \
-    case G:                                                                                                \
-        hipLaunchKernelGGL((k_p2p<T, G>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x, pstart, \
-                           start, (T)h, phi, field, nsplit);                                              \
+#define FMM_P2P_CASE(G)                                                                                        \
+    case G:                                                                                                    \
+        if constexpr (std::is_same<T, double>::value) {                                                        \
+            if (buf) {                                                                                         \
+                hipLaunchKernelGGL((k_p2p<T, G, true>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x, \
+                                   pstart, start, (T)h, phi, field, nsplit);                                   \
+                break;                                                                                         \
+            }                                                                                                  \
+        }                                                                                                      \
+        hipLaunchKernelGGL((k_p2p<T, G, false>), dim3((unsigned)grid), dim3(256), 0, s, nleaf, levels, x,      \
+                           pstart, start, (T)h, phi, field, nsplit);                                           \
         break;
         FMM_P2P_CASE(1) FMM_P2P_CASE(2) FMM_P2P_CASE(4) FMM_P2P_CASE(8) FMM_P2P_CASE(16)
 #undef FMM_P2P_CASE
@@ -179,9 +233,9 @@ hipError_t launch_p2p(int64_t nleaf, int levels, const void *xqp, const int32_t 
     return hipGetLastError();
 }
 template hipError_t launch_p2p<float>(int64_t, int, const void *, const int32_t *, const int32_t *, double,
-                                      double *, float *, int, int, int, hipStream_t);
+                                      double *, float *, int, int, int, int64_t, hipStream_t);
 template hipError_t launch_p2p<double>(int64_t, int, const void *, const int32_t *, const int32_t *, double,
-                                       double *, double *, int, int, int, hipStream_t);
+                                       double *, double *, int, int, int, int64_t, hipStream_t);
 
 // Near-field solute-solvent pairs: nfuv[s] = q_s sum_{j in NF(s), solvent} q_j / r
 // for the solute atoms s (ms[s] != 0; entries of solvent atoms are not
