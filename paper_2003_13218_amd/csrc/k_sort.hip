@@ -40,6 +40,31 @@ hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) {
 }
 
 // key[i] and per-leaf counts; flag |= 1 for a non-finite position or charge.
+// Wave-aggregated increment of ctr[k]: the active lanes of a wavefront that
+// share a key add their number once, and each lane gets the counter's old
+// value plus its rank among them (its slot).  Neighbouring atoms usually
+// share a leaf, so a wavefront's 64 increments become a few atomics.  Every
+// pass serves the key of the first remaining lane, so the loop ends after at
+// most 64 passes.
+__device__ inline uint32_t wave_agg_inc(uint32_t *ctr, uint32_t k) {
+    const int lane = threadIdx.x & 63;
+    uint32_t slot = 0;
+    bool done = false;
+    while (!done) {
+        const uint32_t lk = __builtin_amdgcn_readfirstlane(k);
+        const unsigned long long m = __ballot(k == lk);
+        if (k == lk) {
+            const int leader = __ffsll((long long)m) - 1;
+            uint32_t old = 0;
+            if (lane == leader) old = atomicAdd(&ctr[k], (uint32_t)__popcll(m));
+            old = __shfl(old, leader);
+            slot = old + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            done = true;
+        }
+    }
+    return slot;
+}
+
 __global__ void k_bin(int64_t n, const double *__restrict__ pos, const double *__restrict__ q,
                       double box, double scale, uint32_t nc, uint32_t *__restrict__ key,
                       uint32_t *__restrict__ count, int *__restrict__ flag) {
@@ -58,7 +83,7 @@ __global__ void k_bin(int64_t n, const double *__restrict__ pos, const double *_
         const uint32_t cz = leaf_coord(wrap_coord(z, box), scale, nc);
         const uint32_t k = morton3(cx, cy, cz);
         key[i] = k;
-        atomicAdd(&count[k], 1u);
+        (void)wave_agg_inc(count, k);
     }
 }
 
@@ -197,7 +222,7 @@ __global__ void k_scatter(int64_t n, const uint32_t *__restrict__ key, const int
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t k = key[i];
-        const uint32_t slot = atomicAdd(&cursor[k], 1u);
+        const uint32_t slot = wave_agg_inc(cursor, k);
         perm[start[k] + (int32_t)slot] = (int32_t)i;
     }
 }
