@@ -858,23 +858,28 @@ static fmm_status far_field(fmm_plan_t pl, int64_t n, const void *xq, double *ph
         HIPCHK(pl, e, "M2L");
         if (l == L) stage_end(pl, FMM_STAGE_M2L_LEAF);
     }
+    // L2L into level l (from level l - 1; level 1 from the lattice's L0)
+    auto l2l = [&](int l, hipStream_t ls) -> hipError_t {
+        if (l == 1)
+            return top >= 1 ? launch_l2l_mfma<double, double>(1, pl->L0.as<double>(), LD(1), l2l_ops(true), p, Kp, ls)
+                            : launch_l2l_mfma<double, T>(1, pl->L0.as<double>(), LT(1), l2l_ops(true), p, Kp, ls);
+        const int64_t np = level_cells(l - 1);  // parents
+        if (l <= top) return launch_l2l_mfma<double, double>(np, LD(l - 1), LD(l), l2l_ops(true), p, Kp, ls);
+        if (l - 1 <= top) return launch_l2l_mfma<double, T>(np, LD(l - 1), LT(l), l2l_ops(true), p, Kp, ls);
+        return launch_l2l_mfma<T, T>(np, LT(l - 1), LT(l), l2l_ops(TD), p, Kp, ls);
+    };
+    // The upper tree's own L2L steps (into levels 1 .. lup, whose M2L ran on
+    // the second side stream) follow its M2L there, before the join, so after
+    // the leaf M2L the plan stream only pushes down into levels lup + 1 .. L
+    // (the L2L stage timing covers those).
+    for (int l = 1; l <= lup; ++l) HIPCHK(pl, l2l(l, su), "L2L");
     if (lup > 0) {
         HIPCHK(pl, hipEventRecord(pl->ev_up_join, pl->side_up), "event record");
         HIPCHK(pl, hipStreamWaitEvent(s, pl->ev_up_join, 0), "stream wait");
     }
     stage_end(pl, FMM_STAGE_M2L);
     stage_begin(pl, FMM_STAGE_L2L);
-    HIPCHK(pl, (top >= 1 ? launch_l2l_mfma<double, double>(1, pl->L0.as<double>(), LD(1), l2l_ops(true), p, Kp, s)
-                         : launch_l2l_mfma<double, T>(1, pl->L0.as<double>(), LT(1), l2l_ops(true), p, Kp, s)),
-           "L2L");
-    for (int l = 2; l <= L; ++l) {
-        const int64_t np = level_cells(l - 1);  // parents
-        hipError_t e;
-        if (l <= top) e = launch_l2l_mfma<double, double>(np, LD(l - 1), LD(l), l2l_ops(true), p, Kp, s);
-        else if (l - 1 <= top) e = launch_l2l_mfma<double, T>(np, LD(l - 1), LT(l), l2l_ops(true), p, Kp, s);
-        else e = launch_l2l_mfma<T, T>(np, LT(l - 1), LT(l), l2l_ops(TD), p, Kp, s);
-        HIPCHK(pl, e, "L2L");
-    }
+    for (int l = lup + 1; l <= L; ++l) HIPCHK(pl, l2l(l, s), "L2L");
     stage_end(pl, FMM_STAGE_L2L);
     stage_begin(pl, FMM_STAGE_L2P);
     HIPCHK(pl, launch_l2p<T>(level_cells(L), xq, pl->start.as<int32_t>(), LT(L), p, Kp, h_leaf, phi, field, s, n),
